@@ -1,0 +1,266 @@
+"""Plain FP64 reference of the F-statistic search path (TEST INFRASTRUCTURE ONLY).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this module.  The GPU library never calls it and it never calls the
+GPU library.
+
+The steps follow the paper's flow for one band and frame (Sect. 2, Fig. 3):
+for each sky position, recover the direction, compute the two amplitude
+modulations and the phase modulation, demodulate, resample with the FFT and
+splines; then for each spindown, demodulate the spindown, Fourier-transform
+both amplitude-demodulated series with 2x Fourier interpolation, form the
+F-statistic on every bin and register bins above the threshold as candidates
+of five numbers (sky position, frequency, spindown, F).
+
+The paper defers every formula to its references (Sect. 1.1), so each step
+below states the reading it uses:
+
+* sky direction n = (cos d cos a, cos d sin a, sin d); Roemer delay
+  D_i = n.(r_i - r_0) from the detector-to-SSB ephemeris (Sect. 2);
+* amplitude modulations a(t), b(t): the closed forms of Jaranowski, Krolak &
+  Schutz (1998) for a right-angle interferometer at latitude lat, arm
+  bisector at gamma counter-clockwise from East, local sidereal angle
+  phi_r + Omega_r t;
+* phase demodulation by exp(-i 2 pi f_off D_i);
+* resampling "with the FFT and splines" (Sect. 2) read as: 2x band-limited
+  upsampling by spectral zero-padding of a length nfft/2 DFT, then a natural
+  cubic spline through the upsampled points evaluated at the detector times
+  of a uniform barycentric grid, s_j = j - D_j/dt (first-order inverse of
+  tau = t + D), zero outside the data;
+* spindown demodulation exp(-i pi fdot (j dt)^2), reference time at the
+  segment start;
+* "Fourier transform twice as long" (Sect. 2) read as zero-padding of the N
+  samples to nfft = the smallest power of two >= 2N;
+* 2F_k = 2/(N sigma^2) (|Fa_k|^2/A + |Fb_k|^2/B), A = <a^2>, B = <b^2>
+  (simplified form, the cross term <ab> dropped); the full form with <ab> is
+  provided as well;
+* candidates: every bin with 2F strictly above the threshold.
+
+Every floating-point step is FP64.  numpy's FFT and scipy's banded solver are
+used as library primitives.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.linalg
+
+SIDEREAL_DAY = 86164.0905                  # s
+OMEGA_R = 2.0 * math.pi / SIDEREAL_DAY     # Earth rotation rate, rad/s
+
+
+def next_pow2_at_least(v: int) -> int:
+    m = 1
+    while m < v:
+        m *= 2
+    return m
+
+
+def default_nfft(n: int) -> int:
+    """Length of the 2x interpolated Fourier transform (Sect. 2): nextpow2(2N)."""
+    return next_pow2_at_least(2 * n)
+
+
+# ---------------------------------------------------------------- sky stage
+def sky_direction(alpha: float, delta: float) -> np.ndarray:
+    """Unit vector towards equatorial (alpha, delta) (Sect. 2: sky position recovered)."""
+    return np.array([math.cos(delta) * math.cos(alpha),
+                     math.cos(delta) * math.sin(alpha),
+                     math.sin(delta)])
+
+
+def roemer_delay(r: np.ndarray, nhat: np.ndarray) -> np.ndarray:
+    """Phase modulation delay D_i = n.(r_i - r_0) in seconds (Sect. 2, ephemeris file)."""
+    nr = nhat[0] * r[0] + nhat[1] * r[1] + nhat[2] * r[2]
+    return nr - nr[0]
+
+
+def amplitude_modulation(n: int, dt: float, alpha: float, delta: float,
+                         lat: float, gamma: float, phi_r: float):
+    """The two amplitude modulations a(t), b(t) (Sect. 2; JKS 1998 closed forms)."""
+    t = np.arange(n, dtype=np.float64) * dt
+    x = alpha - phi_r - OMEGA_R * t
+    s2g, c2g = math.sin(2 * gamma), math.cos(2 * gamma)
+    sl, cl = math.sin(lat), math.cos(lat)
+    s2l, c2l = math.sin(2 * lat), math.cos(2 * lat)
+    sd, cd = math.sin(delta), math.cos(delta)
+    s2d, c2d = math.sin(2 * delta), math.cos(2 * delta)
+    a = (s2g * (3 - c2l) * (3 - c2d) * np.cos(2 * x) / 16.0
+         - c2g * sl * (3 - c2d) * np.sin(2 * x) / 4.0
+         + s2g * s2l * s2d * np.cos(x) / 4.0
+         - c2g * cl * s2d * np.sin(x) / 2.0
+         + 0.75 * s2g * cl * cl * cd * cd)
+    b = (c2g * sl * sd * np.cos(2 * x)
+         + s2g * (3 - c2l) * sd * np.sin(2 * x) / 4.0
+         + c2g * cl * cd * np.cos(x)
+         + s2g * s2l * cd * np.sin(x) / 2.0)
+    return a, b
+
+
+def antenna_averages(a: np.ndarray, b: np.ndarray):
+    """A = <a^2>, B = <b^2>, C = <ab>, means over the N detector samples."""
+    n = a.shape[0]
+    return float(np.dot(a, a) / n), float(np.dot(b, b) / n), float(np.dot(a, b) / n)
+
+
+def demodulate(x: np.ndarray, a: np.ndarray, b: np.ndarray, delay: np.ndarray, f_off: float):
+    """Amplitude and phase demodulation (Sect. 2, Fig. 3):
+    za = x a exp(-i psi), zb = x b exp(-i psi), psi = 2 pi f_off D reduced mod 2 pi."""
+    cyc = f_off * delay
+    cyc = cyc - np.floor(cyc)
+    e = np.exp(-2j * math.pi * cyc)
+    return x * a * e, x * b * e
+
+
+def fft_upsample2(z: np.ndarray, nfft: int) -> np.ndarray:
+    """Band-limited 2x upsampling by spectral zero-padding (the FFT part of the resampling).
+
+    M = nfft/2; Z = DFT_M(z zero-padded to M); U of length nfft holds Z[0:M/2) at
+    the start and Z[M/2:M) at the end (the Nyquist term whole on the negative
+    side); u = 2 IDFT_nfft(U) so that u[2i] = z[i].
+    """
+    m = nfft // 2
+    if z.shape[0] > m:
+        raise ValueError("segment longer than nfft/2")
+    zz = np.fft.fft(z, m)
+    u_spec = np.zeros(nfft, dtype=np.complex128)
+    u_spec[: m // 2] = zz[: m // 2]
+    u_spec[nfft - m + m // 2:] = zz[m // 2:]
+    return 2.0 * np.fft.ifft(u_spec)
+
+
+def natural_spline_moments(u: np.ndarray) -> np.ndarray:
+    """Second derivatives of the natural cubic spline through (p, u_p), unit spacing.
+
+    m_0 = m_{L-1} = 0 and m_{p-1} + 4 m_p + m_{p+1} = 6 (u_{p+1} - 2 u_p + u_{p-1}).
+    """
+    L = u.shape[0]
+    m = np.zeros(L, dtype=u.dtype)
+    if L <= 2:
+        return m
+    rhs = 6.0 * (u[2:] - 2.0 * u[1:-1] + u[:-2])
+    k = L - 2
+    ab = np.empty((3, k))
+    ab[0, :] = 1.0
+    ab[1, :] = 4.0
+    ab[2, :] = 1.0
+    m[1:-1] = scipy.linalg.solve_banded((1, 1), ab, rhs)
+    return m
+
+
+def natural_spline_eval(u: np.ndarray, m: np.ndarray, pos: np.ndarray) -> np.ndarray:
+    """Evaluate the spline (knots at 0..L-1, moments m) at positions inside [0, L-1]."""
+    L = u.shape[0]
+    p = np.clip(np.floor(pos).astype(np.int64), 0, L - 2)
+    t = pos - p
+    w = 1.0 - t
+    return (w * u[p] + t * u[p + 1]
+            + ((w ** 3 - w) * m[p] + (t ** 3 - t) * m[p + 1]) / 6.0)
+
+
+def resample(z: np.ndarray, delay: np.ndarray, dt: float, nfft: int) -> np.ndarray:
+    """Resampling onto the uniform barycentric grid tau_j = j dt (Sect. 2: FFT and splines).
+
+    The value at tau_j is read at the detector sample position s_j = j - D_j/dt,
+    i.e. at 2 s_j on the 2x upsampled grid; zero where s_j is outside [0, N-1].
+    """
+    n = z.shape[0]
+    u = fft_upsample2(z, nfft)
+    mom = natural_spline_moments(u)
+    s = np.arange(n, dtype=np.float64) - delay / dt
+    inside = (s >= 0.0) & (s <= n - 1)
+    out = np.zeros(n, dtype=np.complex128)
+    out[inside] = natural_spline_eval(u, mom, 2.0 * s[inside])
+    return out
+
+
+def sky_stage(seg, alpha: float, delta: float, nfft: int):
+    """Everything done once per sky position (Sect. 2: reused in the spindown loop)."""
+    nhat = sky_direction(alpha, delta)
+    delay = roemer_delay(seg.r, nhat)
+    a, b = amplitude_modulation(seg.n, seg.dt, alpha, delta, seg.lat, seg.gamma, seg.phi_r)
+    A, B, C = antenna_averages(a, b)
+    za, zb = demodulate(seg.x, a, b, delay, seg.f_off)
+    return {
+        "delay": delay, "a": a, "b": b, "A": A, "B": B, "C": C, "za": za, "zb": zb,
+        "za_t": resample(za, delay, seg.dt, nfft),
+        "zb_t": resample(zb, delay, seg.dt, nfft),
+    }
+
+
+# ----------------------------------------------------------- spindown stage
+def spindown_demodulate(zt: np.ndarray, fdot: float, dt: float) -> np.ndarray:
+    """Spindown demodulation (Sect. 2, inner loop): multiply by exp(-i pi fdot (j dt)^2)."""
+    t = np.arange(zt.shape[0], dtype=np.float64) * dt
+    cyc = 0.5 * fdot * t * t
+    cyc = cyc - np.floor(cyc)
+    return zt * np.exp(-2j * math.pi * cyc)
+
+
+def fourier_transform(y: np.ndarray, nfft: int) -> np.ndarray:
+    """F_k = sum_{j<N} y_j exp(-2 pi i j k / nfft): the FFT with 2x interpolation (Sect. 2)."""
+    return np.fft.fft(y, nfft)
+
+
+def two_f(fa: np.ndarray, fb: np.ndarray, A: float, B: float, n: int, sigma2: float) -> np.ndarray:
+    """2F = 2/(N sigma^2) (|Fa|^2/A + |Fb|^2/B) (simplified F-statistic, <ab> dropped)."""
+    return (2.0 / (n * sigma2)) * ((fa.real ** 2 + fa.imag ** 2) / A
+                                   + (fb.real ** 2 + fb.imag ** 2) / B)
+
+
+def two_f_full(fa, fb, A, B, C, n, sigma2):
+    """2F with the cross term: 2/(N sigma^2) (B|Fa|^2 + A|Fb|^2 - 2C Re(Fa conj Fb)) / (AB - C^2)."""
+    num = (B * np.abs(fa) ** 2 + A * np.abs(fb) ** 2 - 2.0 * C * (fa * np.conj(fb)).real)
+    return (2.0 / (n * sigma2)) * num / (A * B - C * C)
+
+
+def template_two_f(seg, sky, fdot: float, nfft: int, k_min: int = 0, k_max: int = -1,
+                   full: bool = False) -> np.ndarray:
+    """2F over bins [k_min, k_max) for one (sky, spindown) template."""
+    if k_max < 0:
+        k_max = nfft // 2
+    fa = fourier_transform(spindown_demodulate(sky["za_t"], fdot, seg.dt), nfft)[k_min:k_max]
+    fb = fourier_transform(spindown_demodulate(sky["zb_t"], fdot, seg.dt), nfft)[k_min:k_max]
+    if full:
+        return two_f_full(fa, fb, sky["A"], sky["B"], sky["C"], seg.n, seg.sigma2)
+    return two_f(fa, fb, sky["A"], sky["B"], seg.n, seg.sigma2)
+
+
+# ---------------------------------------------------------------- candidates
+CANDIDATE_DTYPE = np.dtype([("segment", np.int32), ("sky", np.int32), ("fdot_idx", np.int32),
+                            ("bin", np.int32), ("f_hz", np.float64), ("fdot", np.float64),
+                            ("alpha", np.float64), ("delta", np.float64), ("twoF", np.float64)])
+
+
+def search(seg, alpha, delta, fdot, threshold: float, nfft: int = 0, k_min: int = 0,
+           k_max: int = -1, segment_index: int = 0, full: bool = False,
+           skies=None, fdot_indices=None):
+    """Threshold crossings of every (sky, spindown) template (Sect. 2, Fig. 3).
+
+    Each candidate is the paper's five numbers (frequency, spindown, sky
+    position, 2F) plus its integer key (segment, sky, spindown index, bin);
+    the result is sorted by key.  `skies` / `fdot_indices` restrict the search
+    to a subset of the lists (same indices as the full search).
+    """
+    if nfft <= 0:
+        nfft = default_nfft(seg.n)
+    if k_max < 0:
+        k_max = nfft // 2
+    alpha = np.asarray(alpha, dtype=np.float64)
+    delta = np.asarray(delta, dtype=np.float64)
+    fdot = np.asarray(fdot, dtype=np.float64)
+    skies = range(alpha.shape[0]) if skies is None else skies
+    fdot_indices = range(fdot.shape[0]) if fdot_indices is None else fdot_indices
+    rows = []
+    for i in skies:
+        sky = sky_stage(seg, float(alpha[i]), float(delta[i]), nfft)
+        for s in fdot_indices:
+            tf = template_two_f(seg, sky, float(fdot[s]), nfft, k_min, k_max, full)
+            ks = np.nonzero(tf > threshold)[0]
+            for k in ks:
+                kk = int(k) + k_min
+                rows.append((segment_index, i, s, kk, seg.f_off + kk / (nfft * seg.dt),
+                             float(fdot[s]), float(alpha[i]), float(delta[i]), float(tf[k])))
+    out = np.array(rows, dtype=CANDIDATE_DTYPE)
+    return np.sort(out, order=["segment", "sky", "fdot_idx", "bin"])

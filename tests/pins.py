@@ -1,0 +1,220 @@
+"""Checks that pin the oracle to mathematics outside itself.
+
+Each function returns a measured discrepancy; the tests assert bounds on it,
+and the mutation tests plant mistakes in the oracle and assert that at least
+one of these checks then fails.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.interpolate
+import scipy.stats
+
+from oracle import fstat_oracle as oracle
+import synth
+
+
+# ---- P0: amplitude modulations vs the detector tensor ------------------------------
+def p0_amplitude_vs_tensor(seed: int = 0, trials: int = 40) -> float:
+    """max |a - D:e+(psi=0)|, |b - D:ex(psi=0)| over random sky, time and detector."""
+    rng = np.random.default_rng(seed)
+    err = 0.0
+    for _ in range(trials):
+        alpha = rng.uniform(0, 2 * math.pi)
+        delta = math.asin(rng.uniform(-1, 1))
+        lat = rng.uniform(-1.5, 1.5)
+        gamma = rng.uniform(0, math.pi)
+        phi_r = rng.uniform(0, 2 * math.pi)
+        n, dt = 64, rng.uniform(100.0, 3000.0)
+        a, b = oracle.amplitude_modulation(n, dt, alpha, delta, lat, gamma, phi_r)
+        t = np.arange(n) * dt
+        fp, fx = synth.antenna_response(t, alpha, delta, 0.0, lat, gamma, phi_r)
+        err = max(err, float(np.max(np.abs(a - fp))), float(np.max(np.abs(b - fx))))
+    return err
+
+
+# ---- P4: the Fourier transform step vs a brute-force DFT ---------------------------
+def p4_fft_vs_bruteforce(n: int = 37, nfft: int = 128, seed: int = 1) -> float:
+    rng = np.random.default_rng(seed)
+    y = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    got = oracle.fourier_transform(y, nfft)
+    j = np.arange(n)
+    ref = np.array([np.sum(y * np.exp(-2j * math.pi * j * k / nfft)) for k in range(nfft)])
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+
+
+def p4_tone_peak_bin(nfft: int = 256, k0: int = 37) -> int:
+    """A tone exp(+2 pi i k0 j / nfft) must peak at bin k0 (forward sign -i)."""
+    j = np.arange(nfft // 2)
+    f = oracle.fourier_transform(np.exp(2j * math.pi * k0 * j / nfft), nfft)
+    return int(np.argmax(np.abs(f)))
+
+
+# ---- upsampling: u[2i] = z[i] and the odd points vs the trigonometric interpolant --------
+def upsample_errors(n: int = 24, nfft: int = 64, seed: int = 2):
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    u = oracle.fft_upsample2(z, nfft)
+    even_err = float(np.max(np.abs(u[0::2][:n] - z)))
+    # brute force: periodic trigonometric interpolant of zp (z zero-padded to M) with
+    # frequencies -M/2 .. M/2-1, evaluated at half-integer sample positions
+    m = nfft // 2
+    zp = np.zeros(m, dtype=complex)
+    zp[:n] = z
+    i = np.arange(m)
+    freqs = np.concatenate([np.arange(0, m // 2), np.arange(-m // 2, 0)])
+    coef = np.array([np.sum(zp * np.exp(-2j * math.pi * q * i / m)) / m for q in freqs])
+    pos = np.arange(nfft) / 2.0
+    interp = np.array([np.sum(coef * np.exp(2j * math.pi * freqs * p / m)) for p in pos])
+    odd_err = float(np.max(np.abs(u - interp)))
+    return even_err, odd_err
+
+
+# ---- P5: the natural cubic spline --------------------------------------------------------
+def p5_spline_vs_scipy(L: int = 300, seed: int = 3) -> float:
+    rng = np.random.default_rng(seed)
+    u = rng.standard_normal(L) + 1j * rng.standard_normal(L)
+    pos = rng.uniform(0, L - 1, 1000)
+    pos = np.concatenate([pos, [0.0, L - 1.0, 1.0, L - 2.0]])
+    mom = oracle.natural_spline_moments(u)
+    got = oracle.natural_spline_eval(u, mom, pos)
+    x = np.arange(L, dtype=float)
+    ref = (scipy.interpolate.CubicSpline(x, u.real, bc_type="natural")(pos)
+           + 1j * scipy.interpolate.CubicSpline(x, u.imag, bc_type="natural")(pos))
+    return float(np.max(np.abs(got - ref)))
+
+
+def p5_spline_linear_exact(L: int = 200) -> float:
+    u = 3.0 - 0.25 * np.arange(L) + 1j * (0.5 * np.arange(L) - 7.0)
+    mom = oracle.natural_spline_moments(u)
+    pos = np.linspace(0, L - 1, 777)
+    got = oracle.natural_spline_eval(u, mom, pos)
+    return float(np.max(np.abs(got - (3.0 - 0.25 * pos + 1j * (0.5 * pos - 7.0)))))
+
+
+# ---- resampling of a smooth tone with a known delay --------------------------------------
+def resample_tone_error(n: int = 4096, dt: float = 2.0, f0: float = 0.01, nfft: int = 0) -> float:
+    """z_i = exp(2 pi i f0 i dt) resampled with delay D must give exp(2 pi i f0 (j dt - D_j))."""
+    nfft = nfft or oracle.default_nfft(n)
+    t = np.arange(n) * dt
+    delay = 300.0 * np.sin(2 * math.pi * t / (n * dt * 3.0)) + 20.0 * np.sin(2 * math.pi * t / 86164.0)
+    delay = delay - delay[0]
+    z = np.exp(2j * math.pi * f0 * t)
+    zt = oracle.resample(z, delay, dt, nfft)
+    s = np.arange(n) - delay / dt
+    inside = (s >= 0) & (s <= n - 1)
+    # stay away from the ends, where the periodic band-limited interpolant wraps
+    core = inside & (s > 64) & (s < n - 65)
+    ref = np.exp(2j * math.pi * f0 * (t - delay))
+    outside_ok = np.all(zt[~inside] == 0)
+    return float(np.max(np.abs(zt[core] - ref[core]))) if outside_ok else float("inf")
+
+
+# ---- P2 / P1: noiseless injection -------------------------------------------------------
+def jks_amplitudes(inj: synth.Injection):
+    ap = inj.h0 * (1 + inj.cosi ** 2) / 2.0
+    ax = inj.h0 * inj.cosi
+    c2, s2 = math.cos(2 * inj.psi), math.sin(2 * inj.psi)
+    cp, sp = math.cos(inj.phi0), math.sin(inj.phi0)
+    a1 = ap * c2 * cp - ax * s2 * sp
+    a2 = ap * s2 * cp + ax * c2 * sp
+    a3 = -ap * c2 * sp - ax * s2 * cp
+    a4 = -ap * s2 * sp + ax * c2 * cp
+    return a1, a2, a3, a4
+
+
+def closed_form_two_f(inj, A, B, C, n, sigma2=1.0):
+    """Noiseless simplified 2F at the matched template: (N/2)[((A1A+A2C)^2+(A3A+A4C)^2)/A + ...]."""
+    a1, a2, a3, a4 = jks_amplitudes(inj)
+    return (n / (2.0 * sigma2)) * (((a1 * A + a2 * C) ** 2 + (a3 * A + a4 * C) ** 2) / A
+                                   + ((a1 * C + a2 * B) ** 2 + (a3 * C + a4 * B) ** 2) / B)
+
+
+def on_grid_injection(n: int, dt: float = 2.0, f_off: float = 100.0, fdot: float = -4e-10,
+                      alpha: float = 1.1, delta: float = 0.3, frac: float = 0.113, snr: float = 10.0,
+                      psi: float = 0.7, cosi: float = 0.35, phi0: float = 2.1):
+    nfft = oracle.default_nfft(n)
+    k0 = int(round(frac * nfft))
+    inj = synth.Injection(f=k0 / (nfft * dt), fdot=fdot, alpha=alpha, delta=delta, psi=psi,
+                          cosi=cosi, phi0=phi0, snr=snr)
+    seg = synth.make_segment(n, dt, f_off, 1.0, None, [inj])
+    return seg, seg.injections[0], k0, nfft
+
+
+def p2_closed_form(n: int, **kw):
+    """(oracle 2F at the injection bin, closed form, peak bin, expected bin)."""
+    seg, inj, k0, nfft = on_grid_injection(n, **kw)
+    sky = oracle.sky_stage(seg, inj.alpha, inj.delta, nfft)
+    tf = oracle.template_two_f(seg, sky, inj.fdot, nfft)
+    cf = closed_form_two_f(inj, sky["A"], sky["B"], sky["C"], n, seg.sigma2)
+    return float(tf[k0]), float(cf), int(np.argmax(tf)), k0
+
+
+def direct_two_f(seg, alpha, delta, f_narrow, fdot):
+    """2F from the direct detector-time sum, no resampling and no FFT:
+    Fa = sum_i x_i a_i exp(-i[2 pi (f tau_i + fdot tau_i^2/2) + 2 pi f_off D_i]),
+    with a, b from the detector tensor (psi = 0)."""
+    t = np.arange(seg.n) * seg.dt
+    k = np.array([math.cos(delta) * math.cos(alpha), math.cos(delta) * math.sin(alpha), math.sin(delta)])
+    d = k @ seg.r - k @ seg.r[:, 0]
+    tau = t + d
+    a, b = synth.antenna_response(t, alpha, delta, 0.0, seg.lat, seg.gamma, seg.phi_r)
+    cyc = f_narrow * tau + 0.5 * fdot * tau * tau + seg.f_off * d
+    cyc = cyc - np.floor(cyc)
+    e = np.exp(-2j * math.pi * cyc)
+    fa = np.sum(seg.x * a * e)
+    fb = np.sum(seg.x * b * e)
+    A, B = float(np.mean(a * a)), float(np.mean(b * b))
+    return (2.0 / (seg.n * seg.sigma2)) * (abs(fa) ** 2 / A + abs(fb) ** 2 / B)
+
+
+def p1_direct_vs_resampled(n: int, frac: float = 0.2071, **kw):
+    """Off-bin injection; (oracle 2F, direct-sum 2F) at the oracle's peak bin."""
+    nfft = oracle.default_nfft(n)
+    dt = 2.0
+    inj = synth.Injection(f=frac / (2 * dt) + 0.37 / (nfft * dt), fdot=-6e-10, alpha=4.0, delta=-0.6,
+                          psi=2.0, cosi=-0.5, phi0=0.3, snr=10.0)
+    seg = synth.make_segment(n, dt, 230.5, 1.0, None, [inj])
+    sky = oracle.sky_stage(seg, inj.alpha, inj.delta, nfft)
+    tf = oracle.template_two_f(seg, sky, inj.fdot, nfft)
+    k = int(np.argmax(tf))
+    return float(tf[k]), float(direct_two_f(seg, inj.alpha, inj.delta, k / (nfft * dt), inj.fdot))
+
+
+# ---- P3: noise statistics ---------------------------------------------------------------
+def p3_noise_stats(n: int = synth.N_FULL, realisations: int = 6, seed: int = 77):
+    """2F over pure-noise segments (independent realisations, one template each).
+
+    Bins from 1% to 75% of the band: at the top of the band the cubic spline of
+    the resampling attenuates the noise by a few percent.  Every third bin is
+    used for the KS test (the zero-padding to nfft ~ 3N correlates neighbours).
+    """
+    nfft = oracle.default_nfft(n)
+    lo, hi = nfft // 200, (3 * nfft) // 8
+    vals = []
+    for r in range(realisations):
+        seg = synth.make_segment(n, 2.0, 100.0, 1.0, seed + r, [])
+        sky = oracle.sky_stage(seg, 2.3 + 0.7 * r, -0.4 + 0.1 * r, nfft)
+        vals.append(oracle.template_two_f(seg, sky, -1e-10 * r, nfft)[lo:hi])
+    v = np.concatenate(vals)
+    sparse = np.concatenate([x[0::3] for x in vals])
+    ks = scipy.stats.kstest(sparse[::2], scipy.stats.chi2(4).cdf)
+    return float(v.mean()), float(v.var()), float(np.mean(v > 20.0)), sparse.size, float(ks.pvalue)
+
+
+# ---- P6: linearity ----------------------------------------------------------------------
+def p6_linearity(n: int = 4096, seed: int = 5) -> float:
+    rng = np.random.default_rng(seed)
+    s1 = synth.make_segment(n, 2.0, 150.0, 1.0, seed, [])
+    s2 = synth.make_segment(n, 2.0, 150.0, 1.0, seed + 1, [])
+    s12 = synth.make_segment(n, 2.0, 150.0, 1.0, None, [])
+    s12.x = s1.x + 0.5 * s2.x
+    nfft = oracle.default_nfft(n)
+    al, de, fd = rng.uniform(0, 6), rng.uniform(-1, 1), -3e-10
+    f = []
+    for s in (s1, s2, s12):
+        sky = oracle.sky_stage(s, al, de, nfft)
+        f.append(oracle.fourier_transform(oracle.spindown_demodulate(sky["za_t"], fd, s.dt), nfft))
+    return float(np.max(np.abs(f[2] - (f[0] + 0.5 * f[1]))) / np.max(np.abs(f[2])))
