@@ -1,0 +1,191 @@
+/*
+ * fstat.h - C ABI of the MI355X (gfx950) F-statistic search library.
+ *
+ * The library evaluates the F-statistic of an all-sky search for periodic
+ * gravitational waves over a grid of (sky position, spindown) templates and
+ * registers every frequency bin above a threshold as a candidate.  The
+ * operation is the core loop of the paper's search code (Sect. 2, Fig. 3):
+ * per sky position, amplitude and phase demodulation and resampling; per
+ * spindown, spindown demodulation, two FFTs with 2x Fourier interpolation,
+ * the F-statistic on every bin, and threshold crossings as candidates of
+ * five numbers (sky position, frequency, spindown, F).
+ *
+ * Conventions shared by every call:
+ *  - Every call returns an fstat_status; nothing aborts or throws across the
+ *    ABI.  fstat_last_error() gives a text for the last failure on a plan.
+ *  - "device" pointers are HIP device memory (for example from PyTorch);
+ *    "host" pointers are ordinary process memory.
+ *  - The caller owns every input buffer and keeps it alive and unchanged
+ *    until the stream work that reads it has completed.  The library never
+ *    frees caller memory.  The plan owns its kernels' tables, its candidate
+ *    buffer and (unless the caller supplies one) its workspace.
+ *  - Calls on one plan are not thread-safe; distinct plans are independent.
+ *  - Stream arguments are hipStream_t passed as void*; NULL is the null stream.
+ */
+#ifndef FSTAT_H
+#define FSTAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fstat_plan_s* fstat_plan_t;
+
+typedef enum {
+  FSTAT_OK = 0,
+  FSTAT_E_INVAL = 1,            /* an argument is out of range or inconsistent */
+  FSTAT_E_NOMEM = 2,            /* a device or host allocation failed */
+  FSTAT_E_ADMISSION = 3,        /* a segment's minimum workspace exceeds the budget */
+  FSTAT_E_OVERFLOW = 4,         /* more candidates than the buffer holds (true count reported) */
+  FSTAT_E_DEVICE = 5,           /* a HIP runtime call failed (no usable GPU, launch error) */
+  FSTAT_E_STATE = 6,            /* call not valid in the plan's current state */
+  FSTAT_E_NOT_IMPLEMENTED = 7
+} fstat_status;
+
+/* Arithmetic of the path.  FP64: every step in double precision.  MIXED:
+ * time of arrival, phases, spline positions and reductions in FP64; the
+ * demodulated series, resampling values, FFTs and F in FP32. */
+typedef enum { FSTAT_PREC_FP64 = 0, FSTAT_PREC_MIXED = 1 } fstat_precision;
+
+/* F-statistic form.  SIMPLIFIED: 2F = 2/(N sigma^2) (|Fa|^2/A + |Fb|^2/B),
+ * A = <a^2>, B = <b^2>.  FULL adds the cross term C = <ab>:
+ * 2F = 2/(N sigma^2) (B|Fa|^2 + A|Fb|^2 - 2C Re(Fa Fb*)) / (AB - C^2). */
+typedef enum { FSTAT_FORM_SIMPLIFIED = 0, FSTAT_FORM_FULL = 1 } fstat_form;
+
+/* One data segment: one (frame, band) pair of the paper (Sect. 2, Eq. 1). */
+typedef struct {
+  int64_t n;            /* samples, >= 2048 */
+  double dt;            /* sampling interval, s, > 0 */
+  double f_off;         /* lower band edge, Hz (Eq. 1); the series is heterodyned by it */
+  double sigma2;        /* noise variance of x, > 0 */
+  const double* x;      /* device, n doubles: the narrowband series */
+  const double* r_ssb;  /* device, 3*n doubles: detector-to-SSB vector in light-seconds,
+                           component-major (x[0..n), y[0..n), z[0..n)), equatorial frame;
+                           the content of the paper's ephemeris file (Sect. 2) */
+  double lat;           /* detector latitude, rad */
+  double gamma;         /* arm-bisector orientation, rad counter-clockwise from local East */
+  double phi_r;         /* local sidereal angle of the detector at the first sample, rad */
+} fstat_segment;
+
+typedef struct {
+  int32_t nfft;                   /* FFT length, power of two >= 2n; 0 = nextpow2(2n) per segment */
+  int32_t k_min, k_max;           /* searched bins [k_min, k_max); 0,0 = [0, nfft/2) */
+  double threshold_2F;            /* a bin is a candidate when 2F > threshold (strict) */
+  int32_t precision;              /* fstat_precision */
+  int32_t form;                   /* fstat_form */
+  int64_t candidate_capacity;     /* entries of the device candidate buffer, >= 1 */
+  size_t workspace_budget_bytes;  /* admission limit for the workspace; 0 = no limit */
+  int32_t templates_per_launch;   /* spindown templates per FFT launch; 1 = one template per
+                                     launch; 0 = the library's choice */
+  int32_t skies_per_batch;        /* sky positions prepared together; 0 = the library's choice */
+  int32_t use_graph;              /* 1: replay each sky batch's launches as a captured HIP graph */
+} fstat_options;
+
+/* The paper's five numbers of a candidate (Sect. 2). */
+typedef struct { double f_hz, fdot, alpha, delta, twoF; } fstat_candidate;
+
+/* Integer key of a candidate: which search call, segment, sky index, spindown
+ * index and frequency bin produced it; bins are f_hz = f_off + bin/(nfft dt). */
+typedef struct { int32_t search, segment, sky, fdot_idx, bin, reserved; } fstat_candidate_key;
+
+/* Fill *opt with defaults: nfft 0, all bins, threshold 20, MIXED, SIMPLIFIED,
+ * capacity 1<<24, no budget, library-chosen batching, graphs on. */
+void fstat_options_default(fstat_options* opt);
+
+/* Create a plan for nseg segments (host array, copied).  Validates every
+ * argument, chooses FFT factorizations and batch sizes, and performs the
+ * admission check: FSTAT_E_ADMISSION when even one sky and one template of
+ * the largest segment need more workspace than workspace_budget_bytes.
+ * Allocates the plan's tables and candidate buffer on the current device.
+ * On failure *out_plan is NULL. */
+fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_options* opt,
+                        fstat_plan_t* out_plan);
+
+/* Workspace bytes the plan needs (its chosen batch sizes). */
+fstat_status fstat_plan_workspace_size(fstat_plan_t plan, size_t* bytes);
+
+/* Hand the plan a caller-owned device workspace of at least
+ * fstat_plan_workspace_size bytes, 256-byte aligned.  Without this call the
+ * plan allocates its own on first use. */
+fstat_status fstat_plan_set_workspace(fstat_plan_t plan, void* dev_ptr, size_t bytes);
+
+/* Enqueue the search of every (sky, spindown) template on one segment
+ * (segment >= 0) or on every segment of the plan (segment = -1) with the
+ * same template lists.  alpha, delta (nsky) and fdot (nfdot) are device
+ * arrays of doubles.  Asynchronous on `stream`; candidates are appended to
+ * the plan's device buffer and tagged with this call's search index.  The
+ * lists may be released once the stream has passed this work. */
+fstat_status fstat_search_batch(fstat_plan_t plan, int32_t segment,
+                                const double* alpha, const double* delta, int32_t nsky,
+                                const double* fdot, int32_t nfdot, void* stream);
+
+/* Wait for the plan's work, then copy out and drain the candidates found
+ * since the previous call, sorted by key (search, segment, sky, fdot_idx,
+ * bin).  out / keys are host arrays of `capacity` entries (either may be
+ * NULL).  *n_found receives the true number of crossings, also when it
+ * exceeds the device buffer or `capacity`; then FSTAT_E_OVERFLOW is
+ * returned and the first min(capacity, stored) entries in key order are
+ * written. */
+fstat_status fstat_candidates(fstat_plan_t plan, fstat_candidate* out, fstat_candidate_key* keys,
+                              int64_t capacity, int64_t* n_found);
+
+/* Enqueue 2F over bins [k_min, k_max) of every template of one segment into
+ * the device array out, laid out [sky][fdot][bin - k_min], float for MIXED
+ * and double for FP64.  Same kernels as the search, with the threshold
+ * stage replaced by a store.  Asynchronous on `stream`. */
+fstat_status fstat_twoF_spectrum(fstat_plan_t plan, int32_t segment,
+                                 const double* alpha, const double* delta, int32_t nsky,
+                                 const double* fdot, int32_t nfdot, void* out, void* stream);
+
+/* Per-sky intermediates of one sky position, for stage-by-stage checks.
+ * Device outputs (complex values interleaved re, im; float for MIXED,
+ * double for FP64), any may be NULL:
+ *   abc    3 doubles: A = <a^2>, B = <b^2>, C = <ab>
+ *   za, zb n complex: amplitude- and phase-demodulated series
+ *   ua, ub nfft complex: 2x upsampled series
+ *   zta, ztb n complex: resampled series on the barycentric grid
+ * Asynchronous on `stream`. */
+fstat_status fstat_sky_stages(fstat_plan_t plan, int32_t segment, double alpha, double delta,
+                              double* abc, void* za, void* zb, void* ua, void* ub,
+                              void* zta, void* ztb, void* stream);
+
+/* Per-kernel timing.  When enabled, the plan brackets each launch of the
+ * kernel classes below with HIP events on the launch stream;
+ * fstat_profile_read waits for them and reports the number of launches and
+ * their summed duration since the last reset. */
+typedef enum {
+  FSTAT_KERNEL_SKY_PREP = 0,      /* demodulation + antenna sums */
+  FSTAT_KERNEL_RESAMPLE = 1,      /* upsampling FFTs + spline */
+  FSTAT_KERNEL_TEMPLATE_A = 2,    /* spindown chirp + first FFT pass */
+  FSTAT_KERNEL_TEMPLATE_B = 3,    /* second FFT pass + F + threshold + compaction */
+  FSTAT_KERNEL_COUNT = 4
+} fstat_kernel_class;
+fstat_status fstat_profile_enable(fstat_plan_t plan, int32_t on);
+fstat_status fstat_profile_read(fstat_plan_t plan, int32_t kernel_class, int64_t* launches,
+                                double* total_ms, int32_t reset);
+
+/* Plan facts: FFT length and factors P x Q used for a segment, and the
+ * batch sizes in force.  Any output pointer may be NULL. */
+fstat_status fstat_plan_info(fstat_plan_t plan, int32_t segment, int32_t* nfft, int32_t* p,
+                             int32_t* q, int32_t* templates_per_launch, int32_t* skies_per_batch);
+
+/* Release the plan and everything it owns (waits for its work first).
+ * NULL is accepted; a second destroy of the same handle is undefined, as
+ * for free(). */
+fstat_status fstat_destroy(fstat_plan_t plan);
+
+/* Static text for a status code. */
+const char* fstat_strerror(fstat_status status);
+
+/* Text of the last failure on this plan ("" if none); the global text of
+ * the last failed fstat_plan when plan is NULL.  Valid until the next call. */
+const char* fstat_last_error(fstat_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSTAT_H */

@@ -1,0 +1,816 @@
+// Host side of the F-statistic search library: plans, admission, launch
+// orchestration, candidate drain, per-kernel timing.  C ABI in include/fstat.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <utility>
+#include <vector>
+
+#include "../../include/fstat.h"
+#include "fstat_kernels.hpp"
+
+using namespace fstat;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr int LOG_MIN = 10, LOG_MAX = 20;  // supported FFT lengths 2^10 .. 2^20
+
+struct SegInfo {
+  fstat_segment s;
+  int nfft, M;                 // template FFT length and upsampling FFT length nfft/2
+  int logL, P, Q;              // nfft = P * Q
+  int PM, QM;                  // M = PM * QM
+  int kmin, kmax;
+};
+
+struct SearchRecord {
+  int nsky = 0, nfdot = 0;
+  double* host = nullptr;      // pinned: alpha[nsky], delta[nsky], fdot[nfdot]
+};
+
+struct ProfRec {
+  int cls;
+  hipEvent_t a, b;
+};
+
+struct Tables {
+  void* dev = nullptr;         // one allocation for both precisions
+  size_t off_tw1024[2] = {0, 0};
+  size_t off_lo[2][LOG_MAX + 1] = {};
+  size_t off_hi[2][LOG_MAX + 1] = {};
+  size_t off_g[2] = {0, 0};
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct fstat_plan_s {
+  std::vector<SegInfo> segs;
+  fstat_options opt;
+  bool fp64 = false;
+  int device = 0;
+  int Sb = 1, B = 1;           // skies per batch, templates per launch
+  size_t cx_bytes = 8;
+  // workspace
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+  size_t off_sp = 0, off_part = 0, off_zt = 0, off_shared = 0;
+  int nblk_max = 0;
+  long n_max = 0, L_max = 0, M_max = 0;
+  // tables and candidates
+  Tables tab;
+  CandEntry* d_cand = nullptr;
+  unsigned long long* d_count = nullptr;
+  int search_count = 0;
+  std::vector<SearchRecord> searches;
+  hipStream_t last_stream = nullptr;
+  bool used_stream = false;
+  // profiling
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<ProfRec> prof;
+  std::string last_error;
+};
+
+// ------------------------------------------------------------------ helpers
+static fstat_status fail(fstat_plan_t plan, fstat_status st, const std::string& msg) {
+  if (plan) plan->last_error = msg;
+  else g_last_error = msg;
+  return st;
+}
+
+static fstat_status hip_fail(fstat_plan_t plan, hipError_t e, const char* what) {
+  std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(plan, e == hipErrorOutOfMemory ? FSTAT_E_NOMEM : FSTAT_E_DEVICE, msg);
+}
+
+#define HIP_TRY(plan, expr, what)                  \
+  do {                                             \
+    hipError_t e_ = (expr);                        \
+    if (e_ != hipSuccess) return hip_fail(plan, e_, what); \
+  } while (0)
+
+static int ilog2_exact(long v) {
+  int e = 0;
+  while ((1L << e) < v) ++e;
+  return ((1L << e) == v) ? e : -1;
+}
+
+static long next_pow2(long v) {
+  long m = 1;
+  while (m < v) m <<= 1;
+  return m;
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+template <typename F>
+static void with_len(int len, F&& f) {
+  switch (len) {
+    case 32: f(std::integral_constant<int, 32>{}); break;
+    case 64: f(std::integral_constant<int, 64>{}); break;
+    case 128: f(std::integral_constant<int, 128>{}); break;
+    case 256: f(std::integral_constant<int, 256>{}); break;
+    case 512: f(std::integral_constant<int, 512>{}); break;
+    case 1024: f(std::integral_constant<int, 1024>{}); break;
+    default: break;
+  }
+}
+
+template <typename T>
+static int tw_of(int len) {
+  int tw = 0;
+  with_len(len, [&](auto c) { tw = tile_width<T, decltype(c)::value>(); });
+  return tw;
+}
+
+// Workspace layout for Sb skies and B templates (bytes).
+static size_t layout(fstat_plan_t p, int Sb, int B, bool commit) {
+  const size_t cx = p->cx_bytes;
+  size_t off = 0;
+  const size_t o_sp = off;
+  off = align256(off + (size_t)Sb * sizeof(SkyParams));
+  const size_t o_part = off;
+  off = align256(off + (size_t)Sb * p->nblk_max * 3 * sizeof(double));
+  const size_t o_zt = off;
+  off = align256(off + (size_t)Sb * 2 * p->n_max * cx);
+  const size_t o_sh = off;
+  // per-sky scratch: za [2][M], Z [2][M], tmp [2][L], u [2][L]; aliased by the
+  // template intermediate [B][2][L] (per-sky scratch is dead once zt is built)
+  const size_t sky_scratch = (size_t)Sb * (4 * p->M_max + 4 * p->L_max) * cx;
+  const size_t tmpl = (size_t)B * 2 * p->L_max * cx;
+  off = align256(off + std::max(sky_scratch, tmpl));
+  if (commit) {
+    p->off_sp = o_sp;
+    p->off_part = o_part;
+    p->off_zt = o_zt;
+    p->off_shared = o_sh;
+  }
+  return off;
+}
+
+template <typename T>
+static void fill_tables(std::vector<unsigned char>& buf, Tables& tb, int which, int kt) {
+  auto put = [&](size_t count) {
+    size_t off = align256(buf.size());
+    buf.resize(off + count * sizeof(cx<T>));
+    return off;
+  };
+  auto wexp = [](long m, long L) {
+    // exp(-2 pi i m / L) evaluated in double precision, then rounded to T
+    const double a = 2.0 * M_PI * (double)m / (double)L;
+    cx<T> w;
+    w.re = (T)std::cos(a);
+    w.im = (T)(-std::sin(a));
+    return w;
+  };
+  size_t o = put(1024);
+  tb.off_tw1024[which] = o;
+  for (int m = 0; m < 1024; ++m) reinterpret_cast<cx<T>*>(buf.data() + o)[m] = wexp(m, 1024);
+  for (int e = LOG_MIN; e <= LOG_MAX; ++e) {
+    const long L = 1L << e;
+    size_t lo = put(1024);
+    tb.off_lo[which][e] = lo;
+    for (int m = 0; m < 1024; ++m) reinterpret_cast<cx<T>*>(buf.data() + lo)[m] = wexp(m, L);
+    const long nh = std::max(1L, L / 1024);
+    size_t hi = put(nh);
+    tb.off_hi[which][e] = hi;
+    for (long m = 0; m < nh; ++m) reinterpret_cast<cx<T>*>(buf.data() + hi)[m] = wexp((1024 * m) % L, L);
+  }
+  size_t og = align256(buf.size());
+  buf.resize(og + (kt + 1) * sizeof(T));
+  tb.off_g[which] = og;
+  const double z = std::sqrt(3.0) - 2.0;
+  for (int k = 0; k <= kt; ++k)
+    reinterpret_cast<T*>(buf.data() + og)[k] = (T)(std::pow(z, k) / (2.0 * std::sqrt(3.0)));
+}
+
+constexpr int KT_F32 = 16, KT_F64 = 32;
+
+static SegConst seg_const(const SegInfo& si) {
+  SegConst sc;
+  sc.n = (int)si.s.n;
+  sc.nfft = si.nfft;
+  sc.dt = si.s.dt;
+  sc.f_off = si.s.f_off;
+  sc.sigma2 = si.s.sigma2;
+  sc.lat = si.s.lat;
+  sc.gamma = si.s.gamma;
+  sc.phi_r = si.s.phi_r;
+  sc.x = si.s.x;
+  sc.r = si.s.r_ssb;
+  return sc;
+}
+
+// ------------------------------------------------------------- profiling
+static hipEvent_t take_event(fstat_plan_t p) {
+  if (!p->ev_pool.empty()) {
+    hipEvent_t e = p->ev_pool.back();
+    p->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct ProfScope {
+  fstat_plan_t p;
+  int cls;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  ProfScope(fstat_plan_t p_, int cls_, hipStream_t st_) : p(p_), cls(cls_), st(st_) {
+    if (p->profiling) {
+      a = take_event(p);
+      if (a) (void)hipEventRecord(a, st);
+    }
+  }
+  ~ProfScope() {
+    if (p->profiling && a) {
+      hipEvent_t b = take_event(p);
+      if (b) {
+        (void)hipEventRecord(b, st);
+        p->prof.push_back({cls, a, b});
+      } else {
+        p->ev_pool.push_back(a);
+      }
+    }
+  }
+};
+
+// ------------------------------------------------------------- launches
+template <typename T>
+struct Dev {
+  fstat_plan_t p;
+  const cx<T>* tw1024;
+  const T* g;
+  const cx<T>* lo(int e) const {
+    return (const cx<T>*)((const char*)p->tab.dev + p->tab.off_lo[sizeof(T) == 8][e]);
+  }
+  const cx<T>* hi(int e) const {
+    return (const cx<T>*)((const char*)p->tab.dev + p->tab.off_hi[sizeof(T) == 8][e]);
+  }
+  explicit Dev(fstat_plan_t p_) : p(p_) {
+    const int w = sizeof(T) == 8;
+    tw1024 = (const cx<T>*)((const char*)p->tab.dev + p->tab.off_tw1024[w]);
+    g = (const T*)((const char*)p->tab.dev + p->tab.off_g[w]);
+  }
+  SkyParams* sp() const { return (SkyParams*)((char*)p->ws + p->off_sp); }
+  double* part() const { return (double*)((char*)p->ws + p->off_part); }
+  cx<T>* zt() const { return (cx<T>*)((char*)p->ws + p->off_zt); }
+  cx<T>* shared() const { return (cx<T>*)((char*)p->ws + p->off_shared); }
+};
+
+// forward or inverse L-point FFT of `items` pairs of series, two passes
+template <typename T, bool INV, int SRC>
+static hipError_t fft_two_pass(const Dev<T>& d, int logL, int P, int Q, const cx<T>* in, long ld_in,
+                               int nvalid, cx<T>* tmp, cx<T>* out, long ld_out, int items, T scale,
+                               hipStream_t st) {
+  const int L = 1 << logL;
+  hipError_t err = hipSuccess;
+  with_len(Q, [&](auto c) {
+    constexpr int QQ = decltype(c)::value;
+    const int ntiles = P / tile_width<T, QQ>();
+    hipLaunchKernelGGL((k_fft_pass_a<T, QQ, INV, SRC>), dim3(ntiles * items), dim3(NT), 0, st, in, ld_in,
+                       nvalid, tmp, P, L, d.tw1024, d.lo(logL), d.hi(logL));
+    err = hipGetLastError();
+  });
+  if (err != hipSuccess) return err;
+  with_len(P, [&](auto c) {
+    constexpr int PP = decltype(c)::value;
+    const int ntiles = Q / tile_width<T, PP>();
+    hipLaunchKernelGGL((k_fft_pass_b<T, PP, INV>), dim3(ntiles * items), dim3(NT), 0, st, tmp, out, ld_out, Q,
+                       L, scale, d.tw1024);
+    err = hipGetLastError();
+  });
+  return err;
+}
+
+// Per-sky stage for skies [sky0, sky0 + nb) of segment si; leaves zt and SkyParams.
+template <typename T>
+static fstat_status run_sky_batch(fstat_plan_t p, const Dev<T>& d, const SegInfo& si, const double* alpha,
+                                  const double* delta, int sky0, int nb, hipStream_t st) {
+  const SegConst sc = seg_const(si);
+  const int n = sc.n, L = si.nfft, M = si.M;
+  const int nblk = (n + NT - 1) / NT;
+  cx<T>* za = d.shared();                          // [nb][2][M]
+  cx<T>* Z = za + (size_t)nb * 2 * M;              // [nb][2][M]
+  cx<T>* tmp = Z + (size_t)nb * 2 * M;             // [nb][2][L]
+  cx<T>* u = tmp + (size_t)nb * 2 * L;             // [nb][2][L]
+  {
+    ProfScope ps(p, FSTAT_KERNEL_SKY_PREP, st);
+    hipLaunchKernelGGL(k_sky_setup, dim3((nb + 63) / 64), dim3(64), 0, st, alpha, delta, sky0, nb, sc, d.sp());
+    hipLaunchKernelGGL((k_sky_demod<T>), dim3(nblk, nb), dim3(NT), 0, st, sc, d.sp(), za, (long)M, d.part());
+    hipLaunchKernelGGL(k_sky_finalize, dim3(nb), dim3(NT), 0, st, sc, d.sp(), d.part(), nblk,
+                       p->opt.form == FSTAT_FORM_FULL ? 1 : 0);
+    HIP_TRY(p, hipGetLastError(), "sky stage launch");
+  }
+  {
+    ProfScope ps(p, FSTAT_KERNEL_RESAMPLE, st);
+    HIP_TRY(p, (fft_two_pass<T, false, SRC_PLAIN>(d, si.logL - 1, si.PM, si.QM, za, M, n, tmp, Z, M, nb, (T)1, st)),
+            "upsampling forward FFT");
+    HIP_TRY(p, (fft_two_pass<T, true, SRC_UPSPEC>(d, si.logL, si.P, si.Q, Z, M, 0, tmp, u, L, nb, (T)(2.0 / L), st)),
+            "upsampling inverse FFT");
+    constexpr int KT = sizeof(T) == 8 ? KT_F64 : KT_F32;
+    hipLaunchKernelGGL((k_spline<T, KT>), dim3(nblk, nb), dim3(NT), 0, st, sc, d.sp(), u, d.zt(), (long)n, d.g);
+    HIP_TRY(p, hipGetLastError(), "spline launch");
+  }
+  return FSTAT_OK;
+}
+
+// Template stage for the nb skies of the current batch: nb * nfdot templates in launches of B.
+template <typename T>
+static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo& si, int sky0, int nb,
+                                  const double* fdot, int nfdot, int mode, OutArgs oa, hipStream_t st) {
+  TmplArgs ta;
+  ta.n = (int)si.s.n;
+  ta.P = si.P;
+  ta.Q = si.Q;
+  ta.L = si.nfft;
+  ta.nfdot = nfdot;
+  ta.sky0 = sky0;
+  ta.dt = si.s.dt;
+  ta.fdot = fdot;
+  ta.ldzt = si.s.n;
+  const int total = nb * nfdot;
+  cx<T>* tbuf = d.shared();
+  for (int t0 = 0; t0 < total; t0 += p->B) {
+    const int nt = std::min(p->B, total - t0);
+    ta.t0 = t0;
+    hipError_t err = hipSuccess;
+    {
+      ProfScope ps(p, FSTAT_KERNEL_TEMPLATE_A, st);
+      with_len(si.Q, [&](auto c) {
+        constexpr int QQ = decltype(c)::value;
+        const int ntiles = si.P / tile_width<T, QQ>();
+        hipLaunchKernelGGL((k_tmpl_pass_a<T, QQ>), dim3(ntiles * nt), dim3(NT), 0, st, ta, d.zt(), tbuf, d.tw1024,
+                           d.lo(si.logL), d.hi(si.logL));
+        err = hipGetLastError();
+      });
+    }
+    HIP_TRY(p, err, "template pass A launch");
+    {
+      ProfScope ps(p, FSTAT_KERNEL_TEMPLATE_B, st);
+      with_len(si.P, [&](auto c) {
+        constexpr int PP = decltype(c)::value;
+        const int ntiles = si.Q / tile_width<T, PP>();
+        if (mode == 0)
+          hipLaunchKernelGGL((k_tmpl_pass_b<T, PP, 0>), dim3(ntiles * nt), dim3(NT), 0, st, ta, d.sp(), tbuf, oa,
+                             d.tw1024);
+        else
+          hipLaunchKernelGGL((k_tmpl_pass_b<T, PP, 1>), dim3(ntiles * nt), dim3(NT), 0, st, ta, d.sp(), tbuf, oa,
+                             d.tw1024);
+        err = hipGetLastError();
+      });
+    }
+    HIP_TRY(p, err, "template pass B launch");
+  }
+  return FSTAT_OK;
+}
+
+static fstat_status ensure_workspace(fstat_plan_t p) {
+  if (p->ws) return FSTAT_OK;
+  const size_t need = layout(p, p->Sb, p->B, true);
+  void* w = nullptr;
+  HIP_TRY(p, hipMalloc(&w, need), "workspace allocation");
+  p->ws = w;
+  p->ws_bytes = need;
+  p->ws_owned = true;
+  return FSTAT_OK;
+}
+
+template <typename T>
+static fstat_status search_impl(fstat_plan_t p, int segment, const double* alpha, const double* delta, int nsky,
+                                const double* fdot, int nfdot, int mode, void* spectrum, hipStream_t st) {
+  Dev<T> d(p);
+  OutArgs oa;
+  oa.threshold = p->opt.threshold_2F;
+  oa.search = p->search_count;
+  oa.cand = p->d_cand;
+  oa.count = p->d_count;
+  oa.capacity = p->opt.candidate_capacity;
+  oa.spectrum = spectrum;
+  const int s0 = segment < 0 ? 0 : segment;
+  const int s1 = segment < 0 ? (int)p->segs.size() : segment + 1;
+  for (int s = s0; s < s1; ++s) {
+    const SegInfo& si = p->segs[s];
+    oa.segment = s;
+    oa.k_min = si.kmin;
+    oa.k_max = si.kmax;
+    for (int sky0 = 0; sky0 < nsky; sky0 += p->Sb) {
+      const int nb = std::min(p->Sb, nsky - sky0);
+      fstat_status r = run_sky_batch<T>(p, d, si, alpha, delta, sky0, nb, st);
+      if (r != FSTAT_OK) return r;
+      r = run_templates<T>(p, d, si, sky0, nb, fdot, nfdot, mode, oa, st);
+      if (r != FSTAT_OK) return r;
+    }
+  }
+  return FSTAT_OK;
+}
+
+// ------------------------------------------------------------------ C ABI
+// (C linkage comes from the declarations in fstat.h)
+
+void fstat_options_default(fstat_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->nfft = 0;
+  opt->k_min = 0;
+  opt->k_max = 0;
+  opt->threshold_2F = 20.0;
+  opt->precision = FSTAT_PREC_MIXED;
+  opt->form = FSTAT_FORM_SIMPLIFIED;
+  opt->candidate_capacity = 1LL << 24;
+  opt->workspace_budget_bytes = 0;
+  opt->templates_per_launch = 0;
+  opt->skies_per_batch = 0;
+  opt->use_graph = 1;
+}
+
+const char* fstat_strerror(fstat_status st) {
+  switch (st) {
+    case FSTAT_OK: return "success";
+    case FSTAT_E_INVAL: return "invalid argument";
+    case FSTAT_E_NOMEM: return "out of memory";
+    case FSTAT_E_ADMISSION: return "segment does not fit the workspace budget";
+    case FSTAT_E_OVERFLOW: return "candidate buffer overflow";
+    case FSTAT_E_DEVICE: return "HIP device error";
+    case FSTAT_E_STATE: return "invalid plan state";
+    case FSTAT_E_NOT_IMPLEMENTED: return "not implemented";
+  }
+  return "unknown status";
+}
+
+const char* fstat_last_error(fstat_plan_t plan) {
+  return plan ? plan->last_error.c_str() : g_last_error.c_str();
+}
+
+fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_options* opt_in,
+                        fstat_plan_t* out_plan) {
+  if (!out_plan) return fail(nullptr, FSTAT_E_INVAL, "out_plan is NULL");
+  *out_plan = nullptr;
+  if (!segs || nseg <= 0) return fail(nullptr, FSTAT_E_INVAL, "need at least one segment");
+  fstat_options opt;
+  if (opt_in) opt = *opt_in;
+  else fstat_options_default(&opt);
+  if (opt.precision != FSTAT_PREC_FP64 && opt.precision != FSTAT_PREC_MIXED)
+    return fail(nullptr, FSTAT_E_INVAL, "unknown precision");
+  if (opt.form != FSTAT_FORM_SIMPLIFIED && opt.form != FSTAT_FORM_FULL)
+    return fail(nullptr, FSTAT_E_INVAL, "unknown form");
+  if (opt.candidate_capacity < 1) return fail(nullptr, FSTAT_E_INVAL, "candidate_capacity must be >= 1");
+  if (opt.templates_per_launch < 0 || opt.skies_per_batch < 0)
+    return fail(nullptr, FSTAT_E_INVAL, "batch sizes must be >= 0");
+  if (!(std::isfinite(opt.threshold_2F))) return fail(nullptr, FSTAT_E_INVAL, "threshold must be finite");
+  if (opt.k_min < 0 || opt.k_max < 0 || (opt.k_max != 0 && opt.k_max <= opt.k_min))
+    return fail(nullptr, FSTAT_E_INVAL, "bad bin range");
+
+  auto p = new (std::nothrow) fstat_plan_s();
+  if (!p) return fail(nullptr, FSTAT_E_NOMEM, "plan allocation");
+  p->opt = opt;
+  p->fp64 = opt.precision == FSTAT_PREC_FP64;
+  p->cx_bytes = p->fp64 ? 16 : 8;
+  for (int i = 0; i < nseg; ++i) {
+    const fstat_segment& s = segs[i];
+    char msg[160];
+    if (s.n < 1024 || s.n > (1L << (LOG_MAX - 1))) {
+      std::snprintf(msg, sizeof msg, "segment %d: n=%lld outside [1024, %ld]", i, (long long)s.n, 1L << (LOG_MAX - 1));
+      delete p;
+      return fail(nullptr, FSTAT_E_INVAL, msg);
+    }
+    if (!(s.dt > 0) || !std::isfinite(s.dt) || !(s.sigma2 > 0) || !std::isfinite(s.sigma2) ||
+        !std::isfinite(s.f_off) || !std::isfinite(s.lat) || !std::isfinite(s.gamma) || !std::isfinite(s.phi_r)) {
+      std::snprintf(msg, sizeof msg, "segment %d: dt and sigma2 must be > 0 and all parameters finite", i);
+      delete p;
+      return fail(nullptr, FSTAT_E_INVAL, msg);
+    }
+    if (!s.x || !s.r_ssb) {
+      std::snprintf(msg, sizeof msg, "segment %d: x and r_ssb must be device pointers", i);
+      delete p;
+      return fail(nullptr, FSTAT_E_INVAL, msg);
+    }
+    SegInfo si;
+    si.s = s;
+    const long nf = opt.nfft ? opt.nfft : next_pow2(2 * s.n);
+    const int e = ilog2_exact(nf);
+    if (e < 0 || nf < 2 * s.n || e < LOG_MIN + 1 || e > LOG_MAX) {
+      std::snprintf(msg, sizeof msg, "segment %d: nfft=%ld must be a power of two in [2n, 2^%d]", i, nf, LOG_MAX);
+      delete p;
+      return fail(nullptr, FSTAT_E_INVAL, msg);
+    }
+    si.nfft = (int)nf;
+    si.M = (int)(nf / 2);
+    si.logL = e;
+    si.P = 1 << ((e + 1) / 2);
+    si.Q = 1 << (e / 2);
+    si.PM = 1 << (e / 2);
+    si.QM = 1 << ((e - 1) / 2);
+    si.kmin = opt.k_min;
+    si.kmax = opt.k_max ? opt.k_max : si.nfft / 2;
+    if (si.kmax > si.nfft) {
+      std::snprintf(msg, sizeof msg, "segment %d: k_max=%d beyond nfft=%d", i, si.kmax, si.nfft);
+      delete p;
+      return fail(nullptr, FSTAT_E_INVAL, msg);
+    }
+    p->segs.push_back(si);
+    p->n_max = std::max(p->n_max, (long)s.n);
+    p->L_max = std::max(p->L_max, (long)si.nfft);
+    p->M_max = std::max(p->M_max, (long)si.M);
+  }
+  p->nblk_max = (int)((p->n_max + NT - 1) / NT);
+
+  // batch sizes: requested or defaults, shrunk to the budget (admission)
+  int Sb = opt.skies_per_batch ? opt.skies_per_batch : (p->fp64 ? 4 : 8);
+  int B = opt.templates_per_launch ? opt.templates_per_launch : (p->fp64 ? 16 : 64);
+  const size_t budget = opt.workspace_budget_bytes;
+  if (budget) {
+    if (layout(p, 1, 1, false) > budget) {
+      char msg[200];
+      std::snprintf(msg, sizeof msg, "largest segment needs %zu workspace bytes with one sky and one template; budget %zu",
+                    layout(p, 1, 1, false), budget);
+      delete p;
+      return fail(nullptr, FSTAT_E_ADMISSION, msg);
+    }
+    while (layout(p, Sb, B, false) > budget && (Sb > 1 || B > 1)) {
+      if (B > 1 && (B >= 2 * Sb || Sb == 1)) B = (B + 1) / 2;
+      else Sb = (Sb + 1) / 2;
+    }
+  }
+  p->Sb = Sb;
+  p->B = B;
+  layout(p, Sb, B, true);
+
+  // device resources
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev <= 0) {
+    delete p;
+    return fail(nullptr, FSTAT_E_DEVICE, "no HIP device available");
+  }
+  (void)hipGetDevice(&p->device);
+  std::vector<unsigned char> tb;
+  fill_tables<float>(tb, p->tab, 0, KT_F32);
+  fill_tables<double>(tb, p->tab, 1, KT_F64);
+  p->tab.bytes = tb.size();
+  if ((e = hipMalloc(&p->tab.dev, tb.size())) != hipSuccess ||
+      (e = hipMemcpy(p->tab.dev, tb.data(), tb.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMalloc((void**)&p->d_cand, (size_t)opt.candidate_capacity * sizeof(CandEntry))) != hipSuccess ||
+      (e = hipMalloc((void**)&p->d_count, sizeof(unsigned long long))) != hipSuccess ||
+      (e = hipMemset(p->d_count, 0, sizeof(unsigned long long))) != hipSuccess) {
+    std::string msg = std::string("plan device allocation: ") + hipGetErrorString(e);
+    fstat_destroy(p);
+    return fail(nullptr, e == hipErrorOutOfMemory ? FSTAT_E_NOMEM : FSTAT_E_DEVICE, msg);
+  }
+  *out_plan = p;
+  return FSTAT_OK;
+}
+
+fstat_status fstat_plan_workspace_size(fstat_plan_t plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(plan, FSTAT_E_INVAL, "NULL argument");
+  *bytes = layout(plan, plan->Sb, plan->B, false);
+  return FSTAT_OK;
+}
+
+fstat_status fstat_plan_set_workspace(fstat_plan_t plan, void* dev_ptr, size_t bytes) {
+  if (!plan) return fail(plan, FSTAT_E_INVAL, "NULL plan");
+  const size_t need = layout(plan, plan->Sb, plan->B, false);
+  if (!dev_ptr || bytes < need || ((uintptr_t)dev_ptr & 255))
+    return fail(plan, FSTAT_E_INVAL, "workspace NULL, too small or not 256-byte aligned");
+  if (plan->ws_owned && plan->ws) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(plan->ws);
+  }
+  plan->ws = dev_ptr;
+  plan->ws_bytes = bytes;
+  plan->ws_owned = false;
+  layout(plan, plan->Sb, plan->B, true);
+  return FSTAT_OK;
+}
+
+static fstat_status check_lists(fstat_plan_t plan, int32_t segment, const double* alpha, const double* delta,
+                                int32_t nsky, const double* fdot, int32_t nfdot) {
+  if (!plan) return fail(plan, FSTAT_E_INVAL, "NULL plan");
+  if (segment < -1 || segment >= (int32_t)plan->segs.size()) return fail(plan, FSTAT_E_INVAL, "segment out of range");
+  if (nsky <= 0 || nfdot <= 0) return fail(plan, FSTAT_E_INVAL, "nsky and nfdot must be > 0");
+  if (!alpha || !delta || !fdot) return fail(plan, FSTAT_E_INVAL, "template lists must be device pointers");
+  if ((long long)nsky * nfdot > (1LL << 30)) return fail(plan, FSTAT_E_INVAL, "too many templates in one call");
+  return FSTAT_OK;
+}
+
+fstat_status fstat_search_batch(fstat_plan_t plan, int32_t segment, const double* alpha, const double* delta,
+                                int32_t nsky, const double* fdot, int32_t nfdot, void* stream) {
+  fstat_status r = check_lists(plan, segment, alpha, delta, nsky, fdot, nfdot);
+  if (r != FSTAT_OK) return r;
+  r = ensure_workspace(plan);
+  if (r != FSTAT_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  SearchRecord rec;
+  rec.nsky = nsky;
+  rec.nfdot = nfdot;
+  const size_t nd = 2 * (size_t)nsky + nfdot;
+  HIP_TRY(plan, hipHostMalloc((void**)&rec.host, nd * sizeof(double), hipHostMallocDefault), "pinned list copy");
+  plan->searches.push_back(rec);
+  HIP_TRY(plan, hipMemcpyAsync(rec.host, alpha, nsky * sizeof(double), hipMemcpyDeviceToHost, st), "list copy");
+  HIP_TRY(plan, hipMemcpyAsync(rec.host + nsky, delta, nsky * sizeof(double), hipMemcpyDeviceToHost, st), "list copy");
+  HIP_TRY(plan, hipMemcpyAsync(rec.host + 2 * nsky, fdot, nfdot * sizeof(double), hipMemcpyDeviceToHost, st),
+          "list copy");
+  plan->last_stream = st;
+  plan->used_stream = true;
+  r = plan->fp64 ? search_impl<double>(plan, segment, alpha, delta, nsky, fdot, nfdot, 0, nullptr, st)
+                 : search_impl<float>(plan, segment, alpha, delta, nsky, fdot, nfdot, 0, nullptr, st);
+  plan->search_count++;
+  return r;
+}
+
+fstat_status fstat_twoF_spectrum(fstat_plan_t plan, int32_t segment, const double* alpha, const double* delta,
+                                 int32_t nsky, const double* fdot, int32_t nfdot, void* out, void* stream) {
+  fstat_status r = check_lists(plan, segment, alpha, delta, nsky, fdot, nfdot);
+  if (r != FSTAT_OK) return r;
+  if (segment < 0) return fail(plan, FSTAT_E_INVAL, "spectrum needs one segment");
+  if (!out) return fail(plan, FSTAT_E_INVAL, "out is NULL");
+  r = ensure_workspace(plan);
+  if (r != FSTAT_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  plan->last_stream = st;
+  plan->used_stream = true;
+  return plan->fp64 ? search_impl<double>(plan, segment, alpha, delta, nsky, fdot, nfdot, 1, out, st)
+                    : search_impl<float>(plan, segment, alpha, delta, nsky, fdot, nfdot, 1, out, st);
+}
+
+template <typename T>
+static fstat_status sky_stages_impl(fstat_plan_t plan, const SegInfo& si, const double* ad, double* abc, void* za,
+                                    void* zb, void* ua, void* ub, void* zta, void* ztb, hipStream_t st) {
+  Dev<T> d(plan);
+  fstat_status r = run_sky_batch<T>(plan, d, si, ad, ad + 1, 0, 1, st);
+  if (r != FSTAT_OK) return r;
+  const size_t n = si.s.n, M = si.M, L = si.nfft, cb = sizeof(cx<T>);
+  cx<T>* zab = d.shared();
+  cx<T>* u = zab + 4 * M + 2 * L;
+  auto cp = [&](void* dst, const void* src, size_t bytes) {
+    return dst ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st) : hipSuccess;
+  };
+  HIP_TRY(plan, cp(za, zab, n * cb), "stage copy");
+  HIP_TRY(plan, cp(zb, zab + M, n * cb), "stage copy");
+  HIP_TRY(plan, cp(ua, u, L * cb), "stage copy");
+  HIP_TRY(plan, cp(ub, u + L, L * cb), "stage copy");
+  HIP_TRY(plan, cp(zta, d.zt(), n * cb), "stage copy");
+  HIP_TRY(plan, cp(ztb, d.zt() + n, n * cb), "stage copy");
+  if (abc) {
+    SkyParams* sp = d.sp();
+    HIP_TRY(plan, hipMemcpyAsync(abc, &sp->A, 3 * sizeof(double), hipMemcpyDeviceToDevice, st), "stage copy");
+  }
+  return FSTAT_OK;
+}
+
+fstat_status fstat_sky_stages(fstat_plan_t plan, int32_t segment, double alpha, double delta, double* abc, void* za,
+                              void* zb, void* ua, void* ub, void* zta, void* ztb, void* stream) {
+  if (!plan) return fail(plan, FSTAT_E_INVAL, "NULL plan");
+  if (segment < 0 || segment >= (int32_t)plan->segs.size()) return fail(plan, FSTAT_E_INVAL, "segment out of range");
+  fstat_status r = ensure_workspace(plan);
+  if (r != FSTAT_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  // the sky position goes through a small device array, as for a search
+  double* ad = nullptr;
+  HIP_TRY(plan, hipMalloc(&ad, 2 * sizeof(double)), "sky position");
+  double h[2] = {alpha, delta};
+  hipError_t e = hipMemcpyAsync(ad, h, sizeof h, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    (void)hipFree(ad);
+    return hip_fail(plan, e, "sky position copy");
+  }
+  const SegInfo& si = plan->segs[segment];
+  r = plan->fp64 ? sky_stages_impl<double>(plan, si, ad, abc, za, zb, ua, ub, zta, ztb, st)
+                 : sky_stages_impl<float>(plan, si, ad, abc, za, zb, ua, ub, zta, ztb, st);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(ad);
+  plan->last_stream = st;
+  plan->used_stream = true;
+  return r;
+}
+
+fstat_status fstat_candidates(fstat_plan_t plan, fstat_candidate* out, fstat_candidate_key* keys, int64_t capacity,
+                              int64_t* n_found) {
+  if (!plan || !n_found) return fail(plan, FSTAT_E_INVAL, "NULL argument");
+  if (capacity < 0) return fail(plan, FSTAT_E_INVAL, "capacity < 0");
+  *n_found = 0;
+  if (plan->used_stream) HIP_TRY(plan, hipStreamSynchronize(plan->last_stream), "stream synchronize");
+  HIP_TRY(plan, hipDeviceSynchronize(), "device synchronize");
+  unsigned long long count = 0;
+  HIP_TRY(plan, hipMemcpy(&count, plan->d_count, sizeof count, hipMemcpyDeviceToHost), "count copy");
+  const long long stored = std::min<long long>((long long)count, plan->opt.candidate_capacity);
+  std::vector<CandEntry> ent((size_t)stored);
+  if (stored > 0)
+    HIP_TRY(plan, hipMemcpy(ent.data(), plan->d_cand, (size_t)stored * sizeof(CandEntry), hipMemcpyDeviceToHost),
+            "candidate copy");
+  HIP_TRY(plan, hipMemset(plan->d_count, 0, sizeof(unsigned long long)), "count reset");
+  std::sort(ent.begin(), ent.end(), [](const CandEntry& a, const CandEntry& b) {
+    if (a.search != b.search) return a.search < b.search;
+    if (a.segment != b.segment) return a.segment < b.segment;
+    if (a.sky != b.sky) return a.sky < b.sky;
+    if (a.fdot_idx != b.fdot_idx) return a.fdot_idx < b.fdot_idx;
+    return a.bin < b.bin;
+  });
+  const long long nout = std::min<long long>(stored, capacity);
+  for (long long i = 0; i < nout; ++i) {
+    const CandEntry& c = ent[(size_t)i];
+    if (keys) {
+      keys[i].search = c.search;
+      keys[i].segment = c.segment;
+      keys[i].sky = c.sky;
+      keys[i].fdot_idx = c.fdot_idx;
+      keys[i].bin = c.bin;
+      keys[i].reserved = 0;
+    }
+    if (out) {
+      const SegInfo& si = plan->segs[c.segment];
+      const SearchRecord& sr = plan->searches[(size_t)c.search - (plan->search_count - plan->searches.size())];
+      out[i].f_hz = si.s.f_off + (double)c.bin / ((double)si.nfft * si.s.dt);
+      out[i].fdot = sr.host[2 * sr.nsky + c.fdot_idx];
+      out[i].alpha = sr.host[c.sky];
+      out[i].delta = sr.host[sr.nsky + c.sky];
+      out[i].twoF = c.twoF;
+    }
+  }
+  for (auto& sr : plan->searches) (void)hipHostFree(sr.host);
+  plan->searches.clear();
+  *n_found = (int64_t)count;
+  if ((long long)count > plan->opt.candidate_capacity || (long long)count > capacity)
+    return fail(plan, FSTAT_E_OVERFLOW, "more candidates than buffer capacity");
+  return FSTAT_OK;
+}
+
+fstat_status fstat_profile_enable(fstat_plan_t plan, int32_t on) {
+  if (!plan) return fail(plan, FSTAT_E_INVAL, "NULL plan");
+  plan->profiling = on != 0;
+  return FSTAT_OK;
+}
+
+fstat_status fstat_profile_read(fstat_plan_t plan, int32_t kernel_class, int64_t* launches, double* total_ms,
+                                int32_t reset) {
+  if (!plan || kernel_class < 0 || kernel_class >= FSTAT_KERNEL_COUNT)
+    return fail(plan, FSTAT_E_INVAL, "bad arguments");
+  int64_t cnt = 0;
+  double tot = 0.0;
+  for (auto& pr : plan->prof) {
+    if (pr.cls != kernel_class) continue;
+    HIP_TRY(plan, hipEventSynchronize(pr.b), "event synchronize");
+    float ms = 0.f;
+    HIP_TRY(plan, hipEventElapsedTime(&ms, pr.a, pr.b), "event elapsed");
+    tot += ms;
+    ++cnt;
+  }
+  if (launches) *launches = cnt;
+  if (total_ms) *total_ms = tot;
+  if (reset) {
+    std::vector<ProfRec> keep;
+    for (auto& pr : plan->prof) {
+      if (pr.cls == kernel_class) {
+        plan->ev_pool.push_back(pr.a);
+        plan->ev_pool.push_back(pr.b);
+      } else {
+        keep.push_back(pr);
+      }
+    }
+    plan->prof.swap(keep);
+  }
+  return FSTAT_OK;
+}
+
+fstat_status fstat_plan_info(fstat_plan_t plan, int32_t segment, int32_t* nfft, int32_t* p, int32_t* q,
+                             int32_t* templates_per_launch, int32_t* skies_per_batch) {
+  if (!plan || segment < 0 || segment >= (int32_t)plan->segs.size())
+    return fail(plan, FSTAT_E_INVAL, "bad arguments");
+  const SegInfo& si = plan->segs[segment];
+  if (nfft) *nfft = si.nfft;
+  if (p) *p = si.P;
+  if (q) *q = si.Q;
+  if (templates_per_launch) *templates_per_launch = plan->B;
+  if (skies_per_batch) *skies_per_batch = plan->Sb;
+  return FSTAT_OK;
+}
+
+fstat_status fstat_destroy(fstat_plan_t plan) {
+  if (!plan) return FSTAT_OK;
+  if (plan->tab.dev || plan->ws || plan->d_cand) (void)hipDeviceSynchronize();
+  for (auto& pr : plan->prof) {
+    (void)hipEventDestroy(pr.a);
+    (void)hipEventDestroy(pr.b);
+  }
+  for (auto e : plan->ev_pool) (void)hipEventDestroy(e);
+  for (auto& sr : plan->searches) (void)hipHostFree(sr.host);
+  if (plan->ws_owned && plan->ws) (void)hipFree(plan->ws);
+  if (plan->tab.dev) (void)hipFree(plan->tab.dev);
+  if (plan->d_cand) (void)hipFree(plan->d_cand);
+  if (plan->d_count) (void)hipFree(plan->d_count);
+  delete plan;
+  return FSTAT_OK;
+}
+

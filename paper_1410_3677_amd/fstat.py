@@ -1,0 +1,227 @@
+"""Thin ctypes binding of the C ABI in include/fstat.h (argument marshalling only).
+
+Every step of the search runs in the HIP library libfstat.so; this module
+only converts Python/PyTorch arguments into the C structs and pointers.  It
+raises if the library is missing: there is no fallback implementation.
+PyTorch provides device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfstat.so")
+
+# status codes
+OK, E_INVAL, E_NOMEM, E_ADMISSION, E_OVERFLOW, E_DEVICE, E_STATE, E_NOT_IMPLEMENTED = range(8)
+PREC_FP64, PREC_MIXED = 0, 1
+FORM_SIMPLIFIED, FORM_FULL = 0, 1
+KERNEL_SKY_PREP, KERNEL_RESAMPLE, KERNEL_TEMPLATE_A, KERNEL_TEMPLATE_B = range(4)
+KERNEL_NAMES = ("sky_prep", "resample", "template_a", "template_b")
+
+EXPORTED = ("fstat_options_default", "fstat_plan", "fstat_plan_workspace_size", "fstat_plan_set_workspace",
+            "fstat_search_batch", "fstat_candidates", "fstat_twoF_spectrum", "fstat_sky_stages",
+            "fstat_profile_enable", "fstat_profile_read", "fstat_plan_info", "fstat_destroy",
+            "fstat_strerror", "fstat_last_error")
+
+
+class fstat_segment(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("dt", ctypes.c_double), ("f_off", ctypes.c_double),
+                ("sigma2", ctypes.c_double), ("x", ctypes.c_void_p), ("r_ssb", ctypes.c_void_p),
+                ("lat", ctypes.c_double), ("gamma", ctypes.c_double), ("phi_r", ctypes.c_double)]
+
+
+class fstat_options(ctypes.Structure):
+    _fields_ = [("nfft", ctypes.c_int32), ("k_min", ctypes.c_int32), ("k_max", ctypes.c_int32),
+                ("threshold_2F", ctypes.c_double), ("precision", ctypes.c_int32), ("form", ctypes.c_int32),
+                ("candidate_capacity", ctypes.c_int64), ("workspace_budget_bytes", ctypes.c_size_t),
+                ("templates_per_launch", ctypes.c_int32), ("skies_per_batch", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
+
+
+class fstat_candidate(ctypes.Structure):
+    _fields_ = [("f_hz", ctypes.c_double), ("fdot", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("delta", ctypes.c_double), ("twoF", ctypes.c_double)]
+
+
+class fstat_candidate_key(ctypes.Structure):
+    _fields_ = [("search", ctypes.c_int32), ("segment", ctypes.c_int32), ("sky", ctypes.c_int32),
+                ("fdot_idx", ctypes.c_int32), ("bin", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+CANDIDATE_NP = np.dtype([("f_hz", "<f8"), ("fdot", "<f8"), ("alpha", "<f8"), ("delta", "<f8"), ("twoF", "<f8")])
+KEY_NP = np.dtype([("search", "<i4"), ("segment", "<i4"), ("sky", "<i4"), ("fdot_idx", "<i4"), ("bin", "<i4"),
+                   ("reserved", "<i4")])
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libfstat.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1410_3677_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i32, i64, dbl, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "fstat_options_default": (None, [ctypes.POINTER(fstat_options)]),
+        "fstat_plan": (i32, [ctypes.POINTER(fstat_segment), i32, ctypes.POINTER(fstat_options), ctypes.POINTER(P)]),
+        "fstat_plan_workspace_size": (i32, [P, ctypes.POINTER(sz)]),
+        "fstat_plan_set_workspace": (i32, [P, P, sz]),
+        "fstat_search_batch": (i32, [P, i32, P, P, i32, P, i32, P]),
+        "fstat_candidates": (i32, [P, P, P, i64, ctypes.POINTER(i64)]),
+        "fstat_twoF_spectrum": (i32, [P, i32, P, P, i32, P, i32, P, P]),
+        "fstat_sky_stages": (i32, [P, i32, dbl, dbl, P, P, P, P, P, P, P, P]),
+        "fstat_profile_enable": (i32, [P, i32]),
+        "fstat_profile_read": (i32, [P, i32, ctypes.POINTER(i64), ctypes.POINTER(dbl), i32]),
+        "fstat_plan_info": (i32, [P, i32] + [ctypes.POINTER(i32)] * 5),
+        "fstat_destroy": (i32, [P]),
+        "fstat_strerror": (ctypes.c_char_p, [i32]),
+        "fstat_last_error": (ctypes.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class FstatError(RuntimeError):
+    def __init__(self, status: int, text: str):
+        super().__init__(f"fstat status {status}: {text}")
+        self.status = status
+
+
+def _check(st: int, plan_handle=None):
+    if st != OK:
+        lib = load()
+        detail = lib.fstat_last_error(plan_handle).decode()
+        raise FstatError(st, f"{lib.fstat_strerror(st).decode()} ({detail})")
+
+
+def options_default() -> fstat_options:
+    o = fstat_options()
+    load().fstat_options_default(ctypes.byref(o))
+    return o
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    return int(getattr(stream, "cuda_stream", stream))
+
+
+class Plan:
+    """An fstat plan over device-resident segments.
+
+    segments: sequence of dicts with keys n, dt, f_off, sigma2, x (device float64 tensor),
+    r (device float64 tensor of shape (3, n)), lat, gamma, phi_r.
+    """
+
+    def __init__(self, segments: Sequence[dict], options: Optional[fstat_options] = None,
+                 workspace_from_torch: bool = True, **opts):
+        import torch
+        self.lib = load()
+        o = options if options is not None else options_default()
+        for k, v in opts.items():
+            setattr(o, k, v)
+        self.options = o
+        self._keep = []
+        arr = (fstat_segment * len(segments))()
+        for i, s in enumerate(segments):
+            x, r = s["x"], s["r"]
+            assert x.dtype == torch.float64 and r.dtype == torch.float64 and x.is_cuda and r.is_cuda
+            assert x.is_contiguous() and r.is_contiguous() and r.numel() == 3 * s["n"] and x.numel() == s["n"]
+            self._keep += [x, r]
+            arr[i] = fstat_segment(int(s["n"]), float(s["dt"]), float(s["f_off"]), float(s["sigma2"]),
+                                   _ptr(x), _ptr(r), float(s["lat"]), float(s["gamma"]), float(s["phi_r"]))
+        h = ctypes.c_void_p()
+        _check(self.lib.fstat_plan(arr, len(segments), ctypes.byref(o), ctypes.byref(h)))
+        self.handle = h
+        self.nseg = len(segments)
+        self.fp64 = o.precision == PREC_FP64
+        self.workspace = None
+        if workspace_from_torch:
+            nbytes = ctypes.c_size_t()
+            _check(self.lib.fstat_plan_workspace_size(h, ctypes.byref(nbytes)), h)
+            self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device="cuda")
+            base = _ptr(self.workspace)
+            aligned = (base + 255) & ~255
+            _check(self.lib.fstat_plan_set_workspace(h, aligned, int(nbytes.value)), h)
+
+    def info(self, segment: int = 0) -> dict:
+        v = [ctypes.c_int32() for _ in range(5)]
+        _check(self.lib.fstat_plan_info(self.handle, segment, *[ctypes.byref(x) for x in v]), self.handle)
+        return dict(zip(("nfft", "p", "q", "templates_per_launch", "skies_per_batch"), [x.value for x in v]))
+
+    def search_batch(self, segment: int, alpha, delta, fdot, stream=None):
+        self._keep_lists = (alpha, delta, fdot)
+        _check(self.lib.fstat_search_batch(self.handle, segment, _ptr(alpha), _ptr(delta), int(alpha.numel()),
+                                           _ptr(fdot), int(fdot.numel()), _stream_handle(stream)), self.handle)
+
+    def candidates(self, capacity: Optional[int] = None, allow_overflow: bool = False):
+        """Drain the candidates: (records, keys, n_found) as numpy structured arrays."""
+        n = ctypes.c_int64()
+        if capacity is None:
+            capacity = int(self.options.candidate_capacity)
+        recs = np.zeros(capacity, dtype=CANDIDATE_NP)
+        keys = np.zeros(capacity, dtype=KEY_NP)
+        st = self.lib.fstat_candidates(self.handle, recs.ctypes.data, keys.ctypes.data, capacity, ctypes.byref(n))
+        if st == E_OVERFLOW and allow_overflow:
+            m = min(capacity, n.value, int(self.options.candidate_capacity))
+            return recs[:m], keys[:m], n.value
+        _check(st, self.handle)
+        return recs[: n.value], keys[: n.value], n.value
+
+    def twoF_spectrum(self, segment: int, alpha, delta, fdot, out, stream=None):
+        _check(self.lib.fstat_twoF_spectrum(self.handle, segment, _ptr(alpha), _ptr(delta), int(alpha.numel()),
+                                            _ptr(fdot), int(fdot.numel()), _ptr(out), _stream_handle(stream)),
+               self.handle)
+
+    def sky_stages(self, segment: int, alpha: float, delta: float, abc=None, za=None, zb=None, ua=None, ub=None,
+                   zta=None, ztb=None, stream=None):
+        _check(self.lib.fstat_sky_stages(self.handle, segment, float(alpha), float(delta), _ptr(abc), _ptr(za),
+                                         _ptr(zb), _ptr(ua), _ptr(ub), _ptr(zta), _ptr(ztb),
+                                         _stream_handle(stream)), self.handle)
+
+    def profile_enable(self, on: bool = True):
+        _check(self.lib.fstat_profile_enable(self.handle, 1 if on else 0), self.handle)
+
+    def profile_read(self, kernel_class: int, reset: bool = False):
+        n, ms = ctypes.c_int64(), ctypes.c_double()
+        _check(self.lib.fstat_profile_read(self.handle, kernel_class, ctypes.byref(n), ctypes.byref(ms),
+                                           1 if reset else 0), self.handle)
+        return n.value, ms.value
+
+    def destroy(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.fstat_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def segment_to_device(seg) -> dict:
+    """Copy a synthetic segment (object with n, dt, f_off, sigma2, x, r, lat, gamma, phi_r) to the GPU."""
+    import torch
+    return dict(n=seg.n, dt=seg.dt, f_off=seg.f_off, sigma2=seg.sigma2,
+                x=torch.as_tensor(np.ascontiguousarray(seg.x), dtype=torch.float64, device="cuda"),
+                r=torch.as_tensor(np.ascontiguousarray(seg.r), dtype=torch.float64, device="cuda"),
+                lat=seg.lat, gamma=seg.gamma, phi_r=seg.phi_r)

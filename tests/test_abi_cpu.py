@@ -1,0 +1,126 @@
+"""C-ABI checks that need no GPU: symbols, option defaults, argument validation, admission.
+
+Validation and admission run on the host before any device call, so these
+paths are exercised here with placeholder (never dereferenced) pointers.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1410_3677_amd import fstat as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fstat.h")
+FAKE_PTR = 0x10000  # placeholder device address; validation never dereferences it
+
+pytestmark = pytest.mark.skipif(not os.path.exists(F.LIB_PATH), reason="libfstat.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fstat_[A-Za-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = F.load()
+    names = declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(F.EXPORTED)
+
+
+def test_strerror_texts():
+    lib = F.load()
+    assert lib.fstat_strerror(F.OK) == b"success"
+    assert b"budget" in lib.fstat_strerror(F.E_ADMISSION)
+    assert b"overflow" in lib.fstat_strerror(F.E_OVERFLOW)
+    assert lib.fstat_strerror(99) == b"unknown status"
+
+
+def test_option_defaults():
+    o = F.options_default()
+    assert o.nfft == 0 and o.k_min == 0 and o.k_max == 0
+    assert o.threshold_2F == 20.0
+    assert o.precision == F.PREC_MIXED and o.form == F.FORM_SIMPLIFIED
+    assert o.candidate_capacity == 1 << 24
+    assert o.workspace_budget_bytes == 0
+
+
+def _seg(n=86164, **kw):
+    s = F.fstat_segment(n, 2.0, 100.0, 1.0, FAKE_PTR, FAKE_PTR, 0.81, 3.0, 0.0)
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+def _plan(segs, **opts):
+    lib = F.load()
+    o = F.options_default()
+    for k, v in opts.items():
+        setattr(o, k, v)
+    arr = (F.fstat_segment * len(segs))(*segs)
+    h = ctypes.c_void_p()
+    st = lib.fstat_plan(arr, len(segs), ctypes.byref(o), ctypes.byref(h))
+    return st, h, lib.fstat_last_error(None).decode()
+
+
+@pytest.mark.parametrize("seg,opts,needle", [
+    (dict(n=500), {}, "n=500"),
+    (dict(dt=0.0), {}, "dt"),
+    (dict(sigma2=-1.0), {}, "sigma2"),
+    (dict(f_off=float("nan")), {}, "finite"),
+    (dict(x=None), {}, "device pointers"),
+    (dict(), dict(nfft=100000), "power of two"),
+    (dict(), dict(nfft=131072), "power of two"),   # < 2n
+    (dict(), dict(precision=7), "precision"),
+    (dict(), dict(form=3), "form"),
+    (dict(), dict(candidate_capacity=0), "capacity"),
+    (dict(), dict(k_min=10, k_max=5), "bin range"),
+    (dict(), dict(k_max=1 << 20), "k_max"),
+    (dict(), dict(threshold_2F=float("inf")), "threshold"),
+])
+def test_invalid_arguments_are_rejected(seg, opts, needle):
+    st, h, msg = _plan([_seg(**seg)], **opts)
+    assert st == F.E_INVAL
+    assert h.value is None
+    assert needle in msg
+
+
+def test_no_segments_is_rejected():
+    lib = F.load()
+    h = ctypes.c_void_p()
+    assert lib.fstat_plan(None, 0, None, ctypes.byref(h)) == F.E_INVAL
+    assert lib.fstat_plan((F.fstat_segment * 1)(_seg()), 1, None, None) == F.E_INVAL
+
+
+def test_admission_rejects_segment_larger_than_budget():
+    # a 2^19-point segment needs ~27 MB of workspace even with one sky and one template
+    st, h, msg = _plan([_seg(n=20000), _seg(n=172328)], workspace_budget_bytes=8 << 20)
+    assert st == F.E_ADMISSION
+    assert h.value is None
+    assert "budget" in msg
+
+
+def test_null_handles_are_rejected_not_crashing():
+    lib = F.load()
+    n = ctypes.c_int64()
+    assert lib.fstat_candidates(None, None, None, 0, ctypes.byref(n)) == F.E_INVAL
+    assert lib.fstat_search_batch(None, 0, FAKE_PTR, FAKE_PTR, 1, FAKE_PTR, 1, None) == F.E_INVAL
+    assert lib.fstat_profile_enable(None, 1) == F.E_INVAL
+    assert lib.fstat_destroy(None) == F.OK
+    sz = ctypes.c_size_t()
+    assert lib.fstat_plan_workspace_size(None, ctypes.byref(sz)) == F.E_INVAL
+
+
+def test_valid_plan_without_gpu_reports_device_error():
+    # on a host without a GPU the only failure left after validation is the device
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    st, h, msg = _plan([_seg()])
+    assert st == F.E_DEVICE
+    assert h.value is None

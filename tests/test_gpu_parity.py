@@ -1,0 +1,244 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle, element by element.
+
+Tolerances: FP64 path 1e-10 relative; mixed path 1e-4 relative with the noise
+mean 4 as floor (|2F_gpu - 2F_ora| / max(2F_ora, 4)).  Candidate key sets must
+be equal outside a guard band of 1e-4 * threshold around the threshold
+(FP64: 1e-9 * threshold), where a bin can flip legitimately.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch as _torch  # imported at collection: the first import on a fresh box is slow
+
+import synth
+from oracle import fstat_oracle as ora
+from tests import pins
+from tests.gpu_util import (compare_candidates, gpu_spectrum, make_plan, note, oracle_spectrum, rel_err_floor)
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-10
+TOL_MIXED = 1e-4
+GUARD_FP64 = 1e-9
+GUARD_MIXED = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return synth.workload(1)
+
+
+@pytest.fixture(scope="module")
+def full():
+    return synth.workload(2)
+
+
+def _stages(torch, plan, seg, al, de, fp64):
+    n, nfft = seg.n, synth.nfft_for(seg.n)
+    ct = torch.complex128 if fp64 else torch.complex64
+    abc = torch.zeros(3, dtype=torch.float64, device="cuda")
+    bufs = [torch.zeros(m, dtype=ct, device="cuda") for m in (n, n, nfft, nfft, n, n)]
+    plan.sky_stages(0, al, de, abc, *bufs)
+    torch.cuda.synchronize()
+    return abc.cpu().numpy(), [b.cpu().numpy().astype(np.complex128) for b in bufs]
+
+
+def _stage_errors(torch, seg, al, de, fp64):
+    plan = make_plan([seg], precision=0 if fp64 else 1)
+    abc, (za, zb, ua, ub, zta, ztb) = _stages(torch, plan, seg, al, de, fp64)
+    ref = ora.sky_stage(seg, al, de, synth.nfft_for(seg.n))
+    ua_ref = ora.fft_upsample2(ref["za"], synth.nfft_for(seg.n))
+    ub_ref = ora.fft_upsample2(ref["zb"], synth.nfft_for(seg.n))
+
+    def rel(a, b):
+        return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    errs = dict(A=abs(abc[0] - ref["A"]) / ref["A"], B=abs(abc[1] - ref["B"]) / ref["B"],
+                C=abs(abc[2] - ref["C"]) / math.sqrt(ref["A"] * ref["B"]),
+                za=rel(za, ref["za"]), zb=rel(zb, ref["zb"]), ua=rel(ua, ua_ref), ub=rel(ub, ub_ref),
+                zta=rel(zta, ref["za_t"]), ztb=rel(ztb, ref["zb_t"]))
+    plan.destroy()
+    return errs
+
+
+def phase_conditioning(seg) -> float:
+    """Phase error of one FP64 rounding of the demodulation phase 2 pi f_off n.r(t).
+
+    |r| is about 500 light-seconds, so two correct FP64 evaluations of the phase
+    (different summation or FMA order) differ by a few times 2 pi f_off |r| 2^-53
+    (3.5e-11 rad at 100 Hz); every demodulated value inherits it as relative error.
+    """
+    return 2 * math.pi * (seg.f_off + 0.25) * float(np.max(np.abs(seg.r))) * 2.0 ** -53
+
+
+def test_sky_stages_fp64_tiny(torch, tiny):
+    note("sky stages fp64 n=4096")
+    seg = tiny.segments[0]
+    e = _stage_errors(torch, seg, float(tiny.alpha[3]), float(tiny.delta[3]), True)
+    note(str(e))
+    assert e["A"] < 1e-13 and e["B"] < 1e-13 and e["C"] < 1e-13
+    tol = 8 * phase_conditioning(seg) + 1e-13
+    assert max(e.values()) < tol
+
+
+def test_sky_stages_mixed_full(torch, full):
+    note("sky stages mixed n=86164")
+    e = _stage_errors(torch, full.segments[0], float(full.alpha[17]), float(full.delta[17]), False)
+    note(str(e))
+    assert e["A"] < 1e-12 and e["B"] < 1e-12 and e["C"] < 1e-12   # FP64 reductions
+    assert e["za"] < 1e-6 and e["zb"] < 1e-6                        # FP32 rounding of the values
+    assert e["ua"] < 2e-6 and e["ub"] < 2e-6
+    assert e["zta"] < 5e-6 and e["ztb"] < 5e-6
+
+
+def test_spectrum_fp64_tiny(torch, tiny):
+    note("spectrum fp64 config-1 grid 8x4")
+    seg = tiny.segments[0]
+    nfft = synth.nfft_for(seg.n)
+    plan = make_plan([seg], precision=0)
+    got = gpu_spectrum(plan, 0, tiny.alpha, tiny.delta, tiny.fdot, nfft // 2, True)
+    ref = oracle_spectrum(seg, tiny.alpha, tiny.delta, tiny.fdot, nfft)
+    err = rel_err_floor(got, ref)
+    note(f"max rel err {err:.3e}")
+    assert err < TOL_FP64
+
+
+def test_candidates_fp64_tiny(torch, tiny):
+    note("candidates fp64 config-1 grid 8x4")
+    seg = tiny.segments[0]
+    nfft = synth.nfft_for(seg.n)
+    plan = make_plan([seg], precision=0)
+    from tests.gpu_util import dev
+    plan.search_batch(0, dev(tiny.alpha), dev(tiny.delta), dev(tiny.fdot))
+    recs, keys, n = plan.candidates()
+    ref = oracle_spectrum(seg, tiny.alpha, tiny.delta, tiny.fdot, nfft)
+    ng, no, flips, mism, err = compare_candidates(
+        np.stack([keys["sky"], keys["fdot_idx"], keys["bin"]], 1), recs["twoF"], ref, tiny.threshold, GUARD_FP64)
+    note(f"gpu {ng} oracle {no} flips {flips} mismatches {len(mism)} err {err:.3e}")
+    assert no > 0 and not mism and err < TOL_FP64
+    np.testing.assert_allclose(recs["f_hz"], seg.f_off + keys["bin"] / (nfft * seg.dt), rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(recs["alpha"], tiny.alpha[keys["sky"]])
+    np.testing.assert_array_equal(recs["fdot"], tiny.fdot[keys["fdot_idx"]])
+
+
+def test_full_form_fp64_tiny(torch, tiny):
+    note("full F form fp64")
+    seg = tiny.segments[0]
+    nfft = synth.nfft_for(seg.n)
+    plan = make_plan([seg], precision=0, form=1)
+    al, de, fd = tiny.alpha[:3], tiny.delta[:3], tiny.fdot[:2]
+    got = gpu_spectrum(plan, 0, al, de, fd, nfft // 2, True)
+    ref = oracle_spectrum(seg, al, de, fd, nfft, full=True)
+    assert rel_err_floor(got, ref) < TOL_FP64
+
+
+def test_spectrum_mixed_full_segment(torch, full):
+    note("spectrum mixed n=86164, 2 sky x 3 spindowns")
+    seg = full.segments[0]
+    nfft = synth.nfft_for(seg.n)
+    plan = make_plan([seg])
+    al, de, fd = full.alpha[[0, 101]], full.delta[[0, 101]], full.fdot[[0, 31, 63]]
+    got = gpu_spectrum(plan, 0, al, de, fd, nfft // 2, False)
+    ref = oracle_spectrum(seg, al, de, fd, nfft)
+    err = rel_err_floor(got, ref)
+    note(f"max rel err {err:.3e}")
+    assert err < TOL_MIXED
+
+
+def test_candidates_mixed_full_segment(torch, full):
+    note("candidates mixed n=86164, 2 sky x 3 spindowns")
+    seg = full.segments[0]
+    nfft = synth.nfft_for(seg.n)
+    plan = make_plan([seg])
+    from tests.gpu_util import dev
+    al, de, fd = full.alpha[[5, 77]], full.delta[[5, 77]], full.fdot[[1, 40, 62]]
+    plan.search_batch(0, dev(al), dev(de), dev(fd))
+    recs, keys, n = plan.candidates()
+    ref = oracle_spectrum(seg, al, de, fd, nfft)
+    ng, no, flips, mism, err = compare_candidates(
+        np.stack([keys["sky"], keys["fdot_idx"], keys["bin"]], 1), recs["twoF"], ref, full.threshold, GUARD_MIXED)
+    note(f"gpu {ng} oracle {no} flips {flips} mismatches {len(mism)} err {err:.3e}")
+    assert no > 50 and not mism and err < TOL_MIXED
+
+
+def test_injection_recovered_mixed(torch):
+    note("noiseless on-grid injection, mixed")
+    seg, inj, k0, nfft = pins.on_grid_injection(synth.N_FULL)
+    plan = make_plan([seg])
+    got = gpu_spectrum(plan, 0, np.array([inj.alpha]), np.array([inj.delta]), np.array([inj.fdot]), nfft // 2, False)
+    sky = ora.sky_stage(seg, inj.alpha, inj.delta, nfft)
+    cf = pins.closed_form_two_f(inj, sky["A"], sky["B"], sky["C"], seg.n)
+    assert int(np.argmax(got[0, 0])) == k0
+    assert abs(got[0, 0, k0] - cf) / cf < 1e-3
+
+
+@pytest.mark.parametrize("n", [1500, 4096, 20000, 45000])
+def test_ragged_lengths_mixed(torch, n):
+    note(f"ragged length n={n}")
+    rng = np.random.default_rng(n)
+    injs = synth.draw_injections(rng, 1, 15.0, 15.0)
+    f_off = float(synth.band_offset(int(rng.integers(0, 1000))))
+    seg = synth.make_segment(n, 2.0, f_off, 1.0, 4000 + n, injs)
+    nfft = synth.nfft_for(n)
+    plan = make_plan([seg])
+    al, de = np.array([0.3, injs[0].alpha]), np.array([-0.2, injs[0].delta])
+    fd = np.array([0.0, injs[0].fdot])
+    got = gpu_spectrum(plan, 0, al, de, fd, nfft // 2, False)
+    ref = oracle_spectrum(seg, al, de, fd, nfft)
+    err = rel_err_floor(got, ref)
+    note(f"n={n} nfft={nfft} max rel err {err:.3e}")
+    assert err < TOL_MIXED
+
+
+def test_bin_range_matches_full_spectrum(torch, tiny):
+    seg = tiny.segments[0]
+    nfft = synth.nfft_for(seg.n)
+    full_plan = make_plan([seg], precision=0)
+    part_plan = make_plan([seg], precision=0, k_min=1000, k_max=3001)
+    al, de, fd = tiny.alpha[:2], tiny.delta[:2], tiny.fdot[:2]
+    a = gpu_spectrum(full_plan, 0, al, de, fd, nfft // 2, True)
+    b = gpu_spectrum(part_plan, 0, al, de, fd, 2001, True)
+    np.testing.assert_array_equal(a[:, :, 1000:3001], b)
+
+
+def test_plain_launches_equal_batched(torch, full):
+    note("one template per launch vs batched")
+    seg = full.segments[0]
+    from tests.gpu_util import dev
+    al, de, fd = dev(full.alpha[:3]), dev(full.delta[:3]), dev(full.fdot[:5])
+    out = []
+    for opts in (dict(templates_per_launch=1, skies_per_batch=1), dict()):
+        plan = make_plan([seg], **opts)
+        plan.search_batch(0, al, de, fd)
+        out.append(plan.candidates())
+        plan.destroy()
+    (r1, k1, n1), (r2, k2, n2) = out
+    assert n1 == n2 and n1 > 0
+    np.testing.assert_array_equal(k1, k2)
+    np.testing.assert_array_equal(r1, r2)
+
+
+def test_candidate_overflow_reports_true_count(torch, tiny):
+    seg = tiny.segments[0]
+    from tests.gpu_util import dev
+    from paper_1410_3677_amd import fstat as F
+    al, de, fd = dev(tiny.alpha), dev(tiny.delta), dev(tiny.fdot)
+    big = make_plan([seg], precision=0)
+    big.search_batch(0, al, de, fd)
+    _, _, n_all = big.candidates()
+    small = make_plan([seg], precision=0, candidate_capacity=7)
+    small.search_batch(0, al, de, fd)
+    with pytest.raises(F.FstatError) as ei:
+        small.candidates()
+    assert ei.value.status == F.E_OVERFLOW
+    small.search_batch(0, al, de, fd)
+    recs, keys, n = small.candidates(allow_overflow=True)
+    assert n == n_all > 7 and len(recs) == 7
