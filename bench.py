@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Benchmark of the F-statistic search on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+One step is one pass of the whole hot path over the mixed-precision batched
+workload: a two-sidereal-day segment (N = 86164 samples at 2 s, nfft = 2^18)
+searched over 4096 sky positions x 256 spindowns = 1 048 576 templates
+(per-sky demodulation and resampling, then per template the spindown chirp,
+two FFTs, 2F and the threshold crossings).  Inputs are synthetic (Gaussian
+noise plus five injected signals), resident in HBM before timing starts.
+
+Printed: one JSON line with templates/s, the per-kernel HIP-event timings,
+the roofline of the dominant kernel, the plain one-template-per-launch path
+(256 x 64 templates) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "F-stat templates/s at N=86164 (mixed vs plain FP64-phase); F rel err vs FP64"
+HBM_PEAK_GBS = 8000.0
+CAND_BYTES = 32          # device candidate entry
+CX32 = 8                 # complex FP32
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1410_3677_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, templates_per_launch: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it is current."""
+    path = os.path.join(ROOT, "profiles", "template_kernels_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_sha256") != source_digest() or kernel not in t.get("kernels", {}):
+        return None
+    k = t["kernels"][kernel]
+    if k.get("templates_per_launch") != templates_per_launch:
+        return None
+    return k["bytes_per_launch"]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nsky", type=int, default=4096)
+    ap.add_argument("--nfdot", type=int, default=256)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-skies", type=int, default=2)
+    ap.add_argument("--no-events", action="store_true", help="time without per-launch HIP events")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the search shards by sky "
+              "position across GPUs with no exchange in the hot loop, but only the one-GPU path is built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1410_3677_amd import fstat as F
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+    # ---------------- mixed-precision batched workload
+    w = synth.workload(3, args.nsky, args.nfdot)
+    seg = w.segments[0]
+    nfft = synth.nfft_for(seg.n)
+    al, de, fd = dev(w.alpha), dev(w.delta), dev(w.fdot)
+    templates = args.nsky * args.nfdot
+    cap = int(max(1 << 20, 3.0 * 5.0e-4 * (nfft // 2) * templates * max(args.steps, 1)))
+    plan = F.Plan([F.segment_to_device(seg)], candidate_capacity=cap)
+    info = plan.info(0)
+    log(f"plan {info}, capacity {cap}")
+    for i in range(args.warmup):
+        plan.search_batch(0, al, de, fd)
+        torch.cuda.synchronize()
+        log(f"warmup {i} done, {plan.candidate_count(allow_overflow=True)} candidates")
+    plan.profile_enable(not args.no_events)
+    for c in range(4):
+        plan.profile_read(c, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.search_batch(0, al, de, fd)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n_cand = plan.candidate_count(allow_overflow=True)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = templates / ((t1 - t0) / args.steps)
+    log(f"mixed: {ms_step:.1f} ms/step, {value:.4g} templates/s, {n_cand / args.steps:.4g} candidates/step")
+
+    kernels = {}
+    for c, name in enumerate(F.KERNEL_NAMES):
+        n, ms = plan.profile_read(c, reset=True)
+        kernels[name] = {"launches": n, "total_ms": ms, "avg_ms": ms / n if n else None}
+    B = info["templates_per_launch"]
+    L, N = nfft, seg.n
+    cand_per_template = n_cand / max(templates * args.steps, 1)
+    # algorithmic bytes per launch of the two template kernels:
+    #  pass A writes the 2 x nfft complex FP32 intermediate of each template and reads the
+    #  resampled series (2 x N complex FP32) once per launch (one sky per launch);
+    #  pass B reads the intermediate back and writes the crossings.
+    algo = {"template_a": B * 2 * L * CX32 + 2 * N * CX32,
+            "template_b": B * 2 * L * CX32 + B * cand_per_template * CAND_BYTES}
+    roofline = None
+    if not args.no_events:
+        dom = max(("template_a", "template_b"), key=lambda k: kernels[k]["total_ms"] or 0.0)
+        avg_s = kernels[dom]["avg_ms"] / 1e3
+        achieved = algo[dom] / avg_s / 1e9
+        roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, B),
+                    "algorithmic_bytes_per_launch": algo[dom], "templates_per_launch": B,
+                    "avg_launch_ms": kernels[dom]["avg_ms"]}
+        for k in ("template_a", "template_b"):
+            kernels[k]["achieved_GBs"] = algo[k] / (kernels[k]["avg_ms"] / 1e3) / 1e9
+    plan.destroy()
+
+    # ---------------- plain path: one template per launch, 256 x 64
+    plain = None
+    if not args.no_plain:
+        w2 = synth.workload(2)
+        seg2 = w2.segments[0]
+        p2 = F.Plan([F.segment_to_device(seg2)], templates_per_launch=1, skies_per_batch=1,
+                    candidate_capacity=1 << 22)
+        a2, d2, f2 = dev(w2.alpha), dev(w2.delta), dev(w2.fdot)
+        p2.search_batch(0, a2[:2], d2[:2], f2)
+        torch.cuda.synchronize()
+        p2.candidate_count(allow_overflow=True)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        p2.search_batch(0, a2, d2, f2)
+        torch.cuda.synchronize()
+        s1 = time.perf_counter()
+        n2 = p2.candidate_count(allow_overflow=True)
+        t2 = len(w2.alpha) * len(w2.fdot)
+        plain = {"value": t2 / (s1 - s0), "unit": "templates/s", "ms_per_step": (s1 - s0) * 1e3,
+                 "workload": f"plain FP64-phase path, one template per launch, N=86164, {len(w2.alpha)} sky x "
+                             f"{len(w2.fdot)} spindown", "candidates": n2}
+        log(f"plain: {plain['value']:.4g} templates/s")
+        p2.destroy()
+
+    # ---------------- CPU oracle baseline on a bounded sample (+ F error vs FP64 there)
+    cpu = None
+    f_err = None
+    if not args.no_cpu:
+        from oracle import fstat_oracle as ora
+        sk = list(range(args.cpu_skies))
+        p3 = F.Plan([F.segment_to_device(seg)])
+        nb = nfft // 2
+        spec = torch.empty(len(sk) * args.nfdot * nb, dtype=torch.float32, device="cuda")
+        p3.twoF_spectrum(0, dev(w.alpha[sk]), dev(w.delta[sk]), fd, spec)
+        torch.cuda.synchronize()
+        g = spec.view(len(sk), args.nfdot, nb).cpu().numpy()
+        p3.destroy()
+        errs = []
+        c0 = time.perf_counter()
+        for i in sk:
+            sky = ora.sky_stage(seg, float(w.alpha[i]), float(w.delta[i]), nfft)
+            for s in range(args.nfdot):
+                tf = ora.template_two_f(seg, sky, float(w.fdot[s]), nfft)
+                np.nonzero(tf > w.threshold)
+                errs.append(float(np.max(np.abs(g[i, s] - tf) / np.maximum(tf, 4.0))))
+        c1 = time.perf_counter()
+        ntpl = len(sk) * args.nfdot
+        cpu = {"value": ntpl / (c1 - c0), "unit": "templates/s", "cores": 1, "kind": "oracle",
+               "sample": f"{len(sk)} sky x {args.nfdot} spindown templates of the same workload "
+                         f"(numpy FP64, single thread), {c1 - c0:.1f} s"}
+        f_err = max(errs)
+        log(f"cpu oracle: {cpu['value']:.3g} templates/s, max F rel err vs FP64 {f_err:.3e}")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "templates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"mixed-precision batched search, N={N}, nfft=2^{int(math.log2(nfft))}, "
+                               f"{args.nsky} sky x {args.nfdot} spindown, 5 injections, 2F>20",
+                   "n": N, "nfft": nfft, "nsky": args.nsky, "nfdot": args.nfdot, "templates": templates,
+                   "templates_per_launch": B, "skies_per_batch": info["skies_per_batch"]},
+        "roofline": roofline, "cpu_baseline": cpu, "plain": plain,
+        "f_rel_err_vs_fp64": f_err, "candidates_per_step": n_cand / args.steps, "kernels": kernels,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -57,7 +57,7 @@ typedef enum { FSTAT_FORM_SIMPLIFIED = 0, FSTAT_FORM_FULL = 1 } fstat_form;
 
 /* One data segment: one (frame, band) pair of the paper (Sect. 2, Eq. 1). */
 typedef struct {
-  int64_t n;            /* samples, >= 2048 */
+  int64_t n;            /* samples, 1024 <= n <= 2^19 */
   double dt;            /* sampling interval, s, > 0 */
   double f_off;         /* lower band edge, Hz (Eq. 1); the series is heterodyned by it */
   double sigma2;        /* noise variance of x, > 0 */
@@ -128,7 +128,10 @@ fstat_status fstat_search_batch(fstat_plan_t plan, int32_t segment,
  * NULL).  *n_found receives the true number of crossings, also when it
  * exceeds the device buffer or `capacity`; then FSTAT_E_OVERFLOW is
  * returned and the first min(capacity, stored) entries in key order are
- * written. */
+ * written.  With out and keys both NULL the call only reports the count and
+ * drains the buffer (FSTAT_E_OVERFLOW only if the device buffer overflowed).
+ * When the device buffer overflowed, which crossings were kept is
+ * unspecified. */
 fstat_status fstat_candidates(fstat_plan_t plan, fstat_candidate* out, fstat_candidate_key* keys,
                               int64_t capacity, int64_t* n_found);
 

@@ -706,6 +706,16 @@ fstat_status fstat_candidates(fstat_plan_t plan, fstat_candidate* out, fstat_can
   unsigned long long count = 0;
   HIP_TRY(plan, hipMemcpy(&count, plan->d_count, sizeof count, hipMemcpyDeviceToHost), "count copy");
   const long long stored = std::min<long long>((long long)count, plan->opt.candidate_capacity);
+  if (!out && !keys) {
+    // count-only drain: nothing is copied or sorted
+    HIP_TRY(plan, hipMemset(plan->d_count, 0, sizeof(unsigned long long)), "count reset");
+    for (auto& sr : plan->searches) (void)hipHostFree(sr.host);
+    plan->searches.clear();
+    *n_found = (int64_t)count;
+    if ((long long)count > plan->opt.candidate_capacity)
+      return fail(plan, FSTAT_E_OVERFLOW, "more candidates than the device buffer holds");
+    return FSTAT_OK;
+  }
   std::vector<CandEntry> ent((size_t)stored);
   if (stored > 0)
     HIP_TRY(plan, hipMemcpy(ent.data(), plan->d_cand, (size_t)stored * sizeof(CandEntry), hipMemcpyDeviceToHost),

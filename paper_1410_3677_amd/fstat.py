@@ -186,6 +186,14 @@ class Plan:
         _check(st, self.handle)
         return recs[: n.value], keys[: n.value], n.value
 
+    def candidate_count(self, allow_overflow: bool = False) -> int:
+        """Drain the candidates, returning only how many were found (nothing is copied)."""
+        n = ctypes.c_int64()
+        st = self.lib.fstat_candidates(self.handle, None, None, 0, ctypes.byref(n))
+        if not (st == E_OVERFLOW and allow_overflow):
+            _check(st, self.handle)
+        return n.value
+
     def twoF_spectrum(self, segment: int, alpha, delta, fdot, out, stream=None):
         _check(self.lib.fstat_twoF_spectrum(self.handle, segment, _ptr(alpha), _ptr(delta), int(alpha.numel()),
                                             _ptr(fdot), int(fdot.numel()), _ptr(out), _stream_handle(stream)),
