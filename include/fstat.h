@@ -57,7 +57,7 @@ typedef enum { FSTAT_FORM_SIMPLIFIED = 0, FSTAT_FORM_FULL = 1 } fstat_form;
 
 /* One data segment: one (frame, band) pair of the paper (Sect. 2, Eq. 1). */
 typedef struct {
-  int64_t n;            /* samples, 1024 <= n <= 2^19 */
+  int64_t n;            /* samples, 2048 <= n <= 2^19 */
   double dt;            /* sampling interval, s, > 0 */
   double f_off;         /* lower band edge, Hz (Eq. 1); the series is heterodyned by it */
   double sigma2;        /* noise variance of x, > 0 */

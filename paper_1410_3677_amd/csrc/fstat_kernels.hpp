@@ -542,6 +542,30 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* total) {
   return before + x - v;
 }
 
+// Same for a workgroup of NTH threads.
+template <int NTH>
+__device__ __forceinline__ int block_exclusive_scan_n(int v, int* total) {
+  __shared__ int wsum[NTH / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  int before = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < NTH / 64; ++k) {
+    const int ws = wsum[k];
+    if (k < w) before += ws;
+    all += ws;
+  }
+  *total = all;
+  return before + x - v;
+}
+
 // Pass B of a template: row DFTs for both series, then for every bin k = Q k1 + k2 in
 // [k_min, k_max): 2F = cfa |Fa|^2 + cfb |Fb|^2 + cfab Re(Fa Fb*).
 // MODE 0: bins with 2F > threshold are appended to the candidate buffer with one

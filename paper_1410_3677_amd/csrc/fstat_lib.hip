@@ -13,6 +13,7 @@
 
 #include "../../include/fstat.h"
 #include "fstat_kernels.hpp"
+#include "fstat_tmpl.hpp"
 
 using namespace fstat;
 
@@ -350,10 +351,14 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
       ProfScope ps(p, FSTAT_KERNEL_TEMPLATE_A, st);
       with_len(si.Q, [&](auto c) {
         constexpr int QQ = decltype(c)::value;
-        const int ntiles = si.P / tile_width<T, QQ>();
-        hipLaunchKernelGGL((k_tmpl_pass_a<T, QQ>), dim3(ntiles * nt), dim3(NT), 0, st, ta, d.zt(), tbuf, d.tw1024,
-                           d.lo(si.logL), d.hi(si.logL));
-        err = hipGetLastError();
+        if constexpr (QQ >= 64) {
+          const int ntiles = si.P / tw_a<T, QQ>();
+          hipLaunchKernelGGL((k_tmpl_a<T, QQ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T>()), 0, st, ta, d.zt(), tbuf,
+                             d.tw1024, d.lo(si.logL), d.hi(si.logL));
+          err = hipGetLastError();
+        } else {
+          err = hipErrorInvalidValue;
+        }
       });
     }
     HIP_TRY(p, err, "template pass A launch");
@@ -361,14 +366,18 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
       ProfScope ps(p, FSTAT_KERNEL_TEMPLATE_B, st);
       with_len(si.P, [&](auto c) {
         constexpr int PP = decltype(c)::value;
-        const int ntiles = si.Q / tile_width<T, PP>();
-        if (mode == 0)
-          hipLaunchKernelGGL((k_tmpl_pass_b<T, PP, 0>), dim3(ntiles * nt), dim3(NT), 0, st, ta, d.sp(), tbuf, oa,
-                             d.tw1024);
-        else
-          hipLaunchKernelGGL((k_tmpl_pass_b<T, PP, 1>), dim3(ntiles * nt), dim3(NT), 0, st, ta, d.sp(), tbuf, oa,
-                             d.tw1024);
-        err = hipGetLastError();
+        if constexpr (PP >= 64) {
+          const int ntiles = si.Q / tw_b<T, PP>();
+          if (mode == 0)
+            hipLaunchKernelGGL((k_tmpl_b<T, PP, 0>), dim3(ntiles * nt), dim3(tmpl_nt_b<T>()), 0, st, ta, d.sp(),
+                               tbuf, oa, d.tw1024);
+          else
+            hipLaunchKernelGGL((k_tmpl_b<T, PP, 1>), dim3(ntiles * nt), dim3(tmpl_nt_b<T>()), 0, st, ta, d.sp(),
+                               tbuf, oa, d.tw1024);
+          err = hipGetLastError();
+        } else {
+          err = hipErrorInvalidValue;
+        }
       });
     }
     HIP_TRY(p, err, "template pass B launch");
@@ -480,8 +489,8 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_opt
   for (int i = 0; i < nseg; ++i) {
     const fstat_segment& s = segs[i];
     char msg[160];
-    if (s.n < 1024 || s.n > (1L << (LOG_MAX - 1))) {
-      std::snprintf(msg, sizeof msg, "segment %d: n=%lld outside [1024, %ld]", i, (long long)s.n, 1L << (LOG_MAX - 1));
+    if (s.n < 2048 || s.n > (1L << (LOG_MAX - 1))) {
+      std::snprintf(msg, sizeof msg, "segment %d: n=%lld outside [2048, %ld]", i, (long long)s.n, 1L << (LOG_MAX - 1));
       delete p;
       return fail(nullptr, FSTAT_E_INVAL, msg);
     }
@@ -500,7 +509,7 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_opt
     si.s = s;
     const long nf = opt.nfft ? opt.nfft : next_pow2(2 * s.n);
     const int e = ilog2_exact(nf);
-    if (e < 0 || nf < 2 * s.n || e < LOG_MIN + 1 || e > LOG_MAX) {
+    if (e < 0 || nf < 2 * s.n || e < 12 || e > LOG_MAX) {
       std::snprintf(msg, sizeof msg, "segment %d: nfft=%ld must be a power of two in [2n, 2^%d]", i, nf, LOG_MAX);
       delete p;
       return fail(nullptr, FSTAT_E_INVAL, msg);

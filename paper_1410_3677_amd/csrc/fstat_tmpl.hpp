@@ -1,0 +1,305 @@
+// Per-template kernels of the hot loop (spindown chirp, two-pass FFT, 2F, threshold).
+//
+// An nfft = P*Q FFT of both amplitude series of a template, j = j1 + P j2, k = Q k1 + k2:
+//   pass A  for each column j1: Q-point DFT over j2 of y[j1 + P j2] (the resampled
+//           series times the spindown chirp, zero beyond n), times W_nfft^(j1 k2),
+//           stored to the intermediate T[k2][j1];
+//   pass B  for each row k2: P-point DFT over j1 of T[k2][.], giving Fa, Fb at
+//           k = Q k1 + k2, then 2F, threshold and candidate compaction.
+//
+// Both passes run radix-8 Stockham stages with one butterfly group per thread.
+// The first stage reads its eight inputs straight from global memory and the
+// last stage hands its outputs straight to global memory (pass A) or to the
+// F-statistic (pass B), so only the exchanges between stages go through LDS.
+// LDS index i of a column is stored at i + i/8 and columns are spaced so that
+// the 16 lanes served per LDS cycle hit distinct banks:
+//   pass A lanes run fastest over columns (coalesced rows of the input and of T),
+//   pass B lanes run fastest along a row.
+#pragma once
+
+#include "fstat_kernels.hpp"
+
+namespace fstat {
+
+__host__ __device__ constexpr int phys(int i) { return i + (i >> 3); }
+
+// radix of the stage that starts at stride NS for a LEN-point transform
+template <int LEN, int NS>
+__host__ __device__ constexpr int stage_radix() {
+  return (LEN / NS) >= 8 ? 8 : (LEN / NS);
+}
+
+// threads per template-pass workgroup and butterfly groups per column
+template <typename T>
+__host__ __device__ constexpr int tmpl_nt_a() { return sizeof(T) == 4 ? 512 : 256; }
+template <typename T>
+__host__ __device__ constexpr int tmpl_nt_b() { return 256; }
+template <int LEN>
+__host__ __device__ constexpr int groups_per_col() { return LEN / 8; }
+template <typename T, int LEN>
+__host__ __device__ constexpr int tw_a() { return tmpl_nt_a<T>() / groups_per_col<LEN>(); }
+template <typename T, int LEN>
+__host__ __device__ constexpr int tw_b() { return tmpl_nt_b<T>() / groups_per_col<LEN>(); }
+
+// column stride: phys(LEN) rounded so that stride % 32 == want (in complex elements)
+template <int LEN>
+__host__ __device__ constexpr int col_stride(int want) {
+  return phys(LEN) + ((want - (phys(LEN) % 32)) % 32 + 32) % 32;
+}
+template <int TW>
+__host__ __device__ constexpr int want_a() { return TW >= 16 ? 1 : 16 / TW; }
+
+// twiddle of a Stockham stage: exp(-+2 pi i k r / (NS R)) from the 1024-entry table
+template <typename T, int NS, int R, bool INV>
+__device__ __forceinline__ cx<T> stage_tw(const cx<T>* __restrict__ tw1024, int k, int r) {
+  cx<T> w = tw1024[k * r * (1024 / (NS * R))];
+  if (INV) w.im = -w.im;
+  return w;
+}
+
+// Loads of one stage for butterflies j = g + G*b (b < PB) from an LDS column, twiddled, DFT'd.
+// R is the stage radix, PB = (LEN / R) / G the butterflies per thread.
+template <typename T, int LEN, int G, int NS, int R, int PB, bool INV>
+__device__ __forceinline__ void stage_from_lds(cx<T> (&v)[PB][R], const cx<T>* col, int g,
+                                               const cx<T>* __restrict__ tw1024) {
+  constexpr int NB = LEN / R;
+#pragma unroll
+  for (int b = 0; b < PB; ++b) {
+    const int j = g + G * b;
+    const int k = j % NS;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      cx<T> x = col[phys(j + r * NB)];
+      if (NS > 1 && r > 0) x = cmul(x, stage_tw<T, NS, R, INV>(tw1024, k, r));
+      v[b][r] = x;
+    }
+    dftr<T, R, INV>(v[b]);
+  }
+}
+
+template <typename T, int LEN, int G, int NS, int R, int PB>
+__device__ __forceinline__ void stage_to_lds(const cx<T> (&v)[PB][R], cx<T>* col, int g) {
+#pragma unroll
+  for (int b = 0; b < PB; ++b) {
+    const int j = g + G * b;
+    const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+    for (int r = 0; r < R; ++r) col[phys(base + r * NS)] = v[b][r];
+  }
+}
+
+// Middle stages (stride NS up to, not including, the last stage) for two series.
+template <typename T, int LEN, int G, int NS, bool INV>
+__device__ __forceinline__ void middle_stages(cx<T>* cola, cx<T>* colb, int g, const cx<T>* __restrict__ tw1024) {
+  constexpr int R = stage_radix<LEN, NS>();
+  if constexpr (NS * R < LEN) {
+    constexpr int PB = (LEN / R) / G;
+    cx<T> va[PB][R], vb[PB][R];
+    stage_from_lds<T, LEN, G, NS, R, PB, INV>(va, cola, g, tw1024);
+    stage_from_lds<T, LEN, G, NS, R, PB, INV>(vb, colb, g, tw1024);
+    __syncthreads();
+    stage_to_lds<T, LEN, G, NS, R, PB>(va, cola, g);
+    stage_to_lds<T, LEN, G, NS, R, PB>(vb, colb, g);
+    __syncthreads();
+    middle_stages<T, LEN, G, NS * R, INV>(cola, colb, g, tw1024);
+  }
+}
+
+template <int LEN, int NS>
+__host__ __device__ constexpr int last_ns() {
+  if constexpr (NS * stage_radix<LEN, NS>() >= LEN) return NS;
+  else return last_ns<LEN, NS * stage_radix<LEN, NS>()>();
+}
+
+// ---------------------------------------------------------------- pass A
+// Workgroup: TW adjacent columns j1 of one template; thread (c = t % TW, g = t / TW).
+template <typename T, int Q>
+__global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a(TmplArgs ta, const cx<T>* __restrict__ zt,
+                                                           cx<T>* __restrict__ tbuf,
+                                                           const cx<T>* __restrict__ tw1024,
+                                                           const cx<T>* __restrict__ twlo,
+                                                           const cx<T>* __restrict__ twhi) {
+  constexpr int NTA = tmpl_nt_a<T>();
+  constexpr int G = groups_per_col<Q>();
+  constexpr int TW = tw_a<T, Q>();
+  constexpr int ST = col_stride<Q>(want_a<TW>());
+  constexpr int R1 = stage_radix<Q, 1>();
+  constexpr int NB1 = Q / R1, PB1 = NB1 / G;
+  static_assert(PB1 >= 1 && NB1 % G == 0, "first stage must give each thread whole butterflies");
+  __shared__ cx<T> lds[2 * TW * ST];
+  int tile, item;
+  xcd_tile_item(ta.P / TW, tile, item);
+  const int c = threadIdx.x % TW, g = threadIdx.x / TW;
+  const int t = ta.t0 + item;
+  const int skyl = t / ta.nfdot, sidx = t % ta.nfdot;
+  const double half_fdot_dt2 = 0.5 * ta.fdot[sidx] * ta.dt * ta.dt;
+  const cx<T>* za = zt + (long)(2 * skyl) * ta.ldzt;
+  const cx<T>* zb = za + ta.ldzt;
+  const int j1 = tile * TW + c;
+  cx<T>* cola = lds + c * ST;
+  cx<T>* colb = lds + (TW + c) * ST;
+  // first stage: y[j1 + P j2], j2 = j + NB1 r, chirp exp(-i pi fdot (j dt)^2) in FP64 cycles
+  {
+    cx<T> va[PB1][R1], vb[PB1][R1];
+#pragma unroll
+    for (int b = 0; b < PB1; ++b) {
+      const int j = g + G * b;
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        const int jj = j1 + ta.P * (j + NB1 * r);
+        cx<T> a = mk<T>(0, 0), bb = mk<T>(0, 0);
+        if (jj < ta.n) {
+          const double x = (double)jj;
+          double cyc = half_fdot_dt2 * x * x;
+          cyc -= floor(cyc);
+          T s, co;
+          if constexpr (sizeof(T) == 8) sincospi(2.0 * cyc, &s, &co);
+          else sincospif((float)(2.0 * cyc), &s, &co);
+          const cx<T> w = mk<T>(co, -s);
+          a = cmul(za[jj], w);
+          bb = cmul(zb[jj], w);
+        }
+        va[b][r] = a;
+        vb[b][r] = bb;
+      }
+      dftr<T, R1, false>(va[b]);
+      dftr<T, R1, false>(vb[b]);
+    }
+    if constexpr (R1 < Q) {
+      stage_to_lds<T, Q, G, 1, R1, PB1>(va, cola, g);
+      stage_to_lds<T, Q, G, 1, R1, PB1>(vb, colb, g);
+    }
+    __syncthreads();
+  }
+  middle_stages<T, Q, G, R1, false>(cola, colb, g, tw1024);
+  // last stage: outputs k2 = j + NSL r go to T[k2][j1] times W_nfft^(j1 k2)
+  constexpr int NSL = last_ns<Q, 1>();
+  constexpr int RL = stage_radix<Q, NSL>();
+  constexpr int PBL = (Q / RL) / G;
+  cx<T> va[PBL][RL], vb[PBL][RL];
+  stage_from_lds<T, Q, G, NSL, RL, PBL, false>(va, cola, g, tw1024);
+  stage_from_lds<T, Q, G, NSL, RL, PBL, false>(vb, colb, g, tw1024);
+  cx<T>* outa = tbuf + (long)(2 * item) * ta.L;
+  cx<T>* outb = outa + ta.L;
+#pragma unroll
+  for (int b = 0; b < PBL; ++b) {
+    const int j = g + G * b;
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int k2 = j + NSL * r;
+      const cx<T> w = twiddle_L<T, false>(twlo, twhi, j1 * k2);
+      const long o = (long)k2 * ta.P + j1;
+      outa[o] = cmul(va[b][r], w);
+      outb[o] = cmul(vb[b][r], w);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- pass B
+// Workgroup: TW adjacent rows k2 of one template; thread (c = t / G, g = t % G).
+template <typename T, int P, int MODE>
+__global__ void __launch_bounds__(tmpl_nt_b<T>()) k_tmpl_b(TmplArgs ta, const SkyParams* __restrict__ sp,
+                                                           const cx<T>* __restrict__ tbuf, OutArgs oa,
+                                                           const cx<T>* __restrict__ tw1024) {
+  constexpr int NTB = tmpl_nt_b<T>();
+  constexpr int G = groups_per_col<P>();
+  constexpr int TW = tw_b<T, P>();
+  constexpr int ST = col_stride<P>(16);
+  constexpr int R1 = stage_radix<P, 1>();
+  constexpr int NB1 = P / R1, PB1 = NB1 / G;
+  static_assert(TW * G == NTB, "one butterfly group per thread");
+  __shared__ cx<T> lds[2 * TW * ST];
+  __shared__ unsigned long long sbase;
+  int tile, item;
+  xcd_tile_item(ta.Q / TW, tile, item);
+  const int c = threadIdx.x / G, g = threadIdx.x % G;
+  const int t = ta.t0 + item;
+  const int skyl = t / ta.nfdot, sidx = t % ta.nfdot;
+  const int k2 = tile * TW + c;
+  const cx<T>* ina = tbuf + (long)(2 * item) * ta.L + (long)k2 * ta.P;
+  const cx<T>* inb = ina + ta.L;
+  cx<T>* cola = lds + c * ST;
+  cx<T>* colb = lds + (TW + c) * ST;
+  {
+    cx<T> va[PB1][R1], vb[PB1][R1];
+#pragma unroll
+    for (int b = 0; b < PB1; ++b) {
+      const int j = g + G * b;
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        va[b][r] = ina[j + NB1 * r];
+        vb[b][r] = inb[j + NB1 * r];
+      }
+      dftr<T, R1, false>(va[b]);
+      dftr<T, R1, false>(vb[b]);
+    }
+    stage_to_lds<T, P, G, 1, R1, PB1>(va, cola, g);
+    stage_to_lds<T, P, G, 1, R1, PB1>(vb, colb, g);
+    __syncthreads();
+  }
+  middle_stages<T, P, G, R1, false>(cola, colb, g, tw1024);
+  constexpr int NSL = last_ns<P, 1>();
+  constexpr int RL = stage_radix<P, NSL>();
+  constexpr int PBL = (P / RL) / G;
+  constexpr int NOUT = PBL * RL;
+  static_assert(NOUT <= 32, "output mask");
+  cx<T> va[PBL][RL], vb[PBL][RL];
+  stage_from_lds<T, P, G, NSL, RL, PBL, false>(va, cola, g, tw1024);
+  stage_from_lds<T, P, G, NSL, RL, PBL, false>(vb, colb, g, tw1024);
+  const SkyParams& pr = sp[skyl];
+  const T cfa = (T)pr.cfa, cfb = (T)pr.cfb, cfab = (T)pr.cfab;
+  if constexpr (MODE == 1) {
+    T* out = (T*)oa.spectrum + ((long)(ta.sky0 + skyl) * ta.nfdot + sidx) * (long)(oa.k_max - oa.k_min);
+#pragma unroll
+    for (int b = 0; b < PBL; ++b) {
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int k = ta.Q * (g + G * b + NSL * r) + k2;
+        if (k >= oa.k_min && k < oa.k_max) {
+          const cx<T> fa = va[b][r], fb = vb[b][r];
+          out[k - oa.k_min] = cfa * cnorm2(fa) + cfb * cnorm2(fb) + cfab * (fa.re * fb.re + fa.im * fb.im);
+        }
+      }
+    }
+  } else {
+    uint32_t mask = 0;
+    T val[NOUT];
+#pragma unroll
+    for (int b = 0; b < PBL; ++b) {
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int k = ta.Q * (g + G * b + NSL * r) + k2;
+        const cx<T> fa = va[b][r], fb = vb[b][r];
+        const T v = cfa * cnorm2(fa) + cfb * cnorm2(fb) + cfab * (fa.re * fb.re + fa.im * fb.im);
+        val[b * RL + r] = v;
+        if (k >= oa.k_min && k < oa.k_max && v > (T)oa.threshold) mask |= 1u << (b * RL + r);
+      }
+    }
+    int total;
+    const int off = block_exclusive_scan_n<NTB>(__popc(mask), &total);
+    if (total == 0) return;
+    if (threadIdx.x == 0) sbase = atomicAdd(oa.count, (unsigned long long)total);
+    __syncthreads();
+    unsigned long long slot = sbase + (unsigned long long)off;
+#pragma unroll
+    for (int i = 0; i < NOUT; ++i) {
+      if (mask & (1u << i)) {
+        if (slot < (unsigned long long)oa.capacity) {
+          const int b = i / RL, r = i % RL;
+          CandEntry ce;
+          ce.search = oa.search;
+          ce.segment = oa.segment;
+          ce.sky = ta.sky0 + skyl;
+          ce.fdot_idx = sidx;
+          ce.bin = ta.Q * (g + G * b + NSL * r) + k2;
+          ce.pad = 0;
+          ce.twoF = (double)val[i];
+          oa.cand[slot] = ce;
+        }
+        ++slot;
+      }
+    }
+  }
+}
+
+}  // namespace fstat
