@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-skies", type=int, default=2)
     ap.add_argument("--no-events", action="store_true", help="time without per-launch HIP events")
+    ap.add_argument("--templates-per-launch", type=int, default=0)
+    ap.add_argument("--skies-per-batch", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the search shards by sky "
@@ -94,7 +96,8 @@ def main():
     al, de, fd = dev(w.alpha), dev(w.delta), dev(w.fdot)
     templates = args.nsky * args.nfdot
     cap = int(max(1 << 20, 3.0 * 5.0e-4 * (nfft // 2) * templates * max(args.steps, 1)))
-    plan = F.Plan([F.segment_to_device(seg)], candidate_capacity=cap)
+    plan = F.Plan([F.segment_to_device(seg)], candidate_capacity=cap,
+                  templates_per_launch=args.templates_per_launch, skies_per_batch=args.skies_per_batch)
     info = plan.info(0)
     log(f"plan {info}, capacity {cap}")
     for i in range(args.warmup):

@@ -47,6 +47,7 @@ struct Tables {
   size_t off_lo[2][LOG_MAX + 1] = {};
   size_t off_hi[2][LOG_MAX + 1] = {};
   size_t off_g[2] = {0, 0};
+  size_t off_stage[2] = {0, 0};
   size_t bytes = 0;
 };
 
@@ -186,6 +187,15 @@ static void fill_tables(std::vector<unsigned char>& buf, Tables& tb, int which, 
     tb.off_hi[which][e] = hi;
     for (long m = 0; m < nh; ++m) reinterpret_cast<cx<T>*>(buf.data() + hi)[m] = wexp((1024 * m) % L, L);
   }
+  // per-stage twiddles [k][r-1] of the template kernels (layout of stage_tw_offset)
+  size_t os = put(STAGE_TW_ENTRIES);
+  tb.off_stage[which] = os;
+  for (int ns = 8; ns <= 512; ns *= 8)
+    for (int rr = 2; rr <= 8; rr *= 2)
+      for (int k = 0; k < ns; ++k)
+        for (int r = 1; r < rr; ++r)
+          reinterpret_cast<cx<T>*>(buf.data() + os)[stage_tw_offset(ns, rr) + k * (rr - 1) + (r - 1)] =
+              wexp((long)k * r, (long)ns * rr);
   size_t og = align256(buf.size());
   buf.resize(og + (kt + 1) * sizeof(T));
   tb.off_g[which] = og;
@@ -252,6 +262,7 @@ template <typename T>
 struct Dev {
   fstat_plan_t p;
   const cx<T>* tw1024;
+  const cx<T>* twst;
   const T* g;
   const cx<T>* lo(int e) const {
     return (const cx<T>*)((const char*)p->tab.dev + p->tab.off_lo[sizeof(T) == 8][e]);
@@ -263,6 +274,7 @@ struct Dev {
     const int w = sizeof(T) == 8;
     tw1024 = (const cx<T>*)((const char*)p->tab.dev + p->tab.off_tw1024[w]);
     g = (const T*)((const char*)p->tab.dev + p->tab.off_g[w]);
+    twst = (const cx<T>*)((const char*)p->tab.dev + p->tab.off_stage[w]);
   }
   SkyParams* sp() const { return (SkyParams*)((char*)p->ws + p->off_sp); }
   double* part() const { return (double*)((char*)p->ws + p->off_part); }
@@ -354,7 +366,7 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
         if constexpr (QQ >= 64) {
           const int ntiles = si.P / tw_a<T, QQ>();
           hipLaunchKernelGGL((k_tmpl_a<T, QQ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T>()), 0, st, ta, d.zt(), tbuf,
-                             d.tw1024, d.lo(si.logL), d.hi(si.logL));
+                             d.twst, d.lo(si.logL), d.hi(si.logL));
           err = hipGetLastError();
         } else {
           err = hipErrorInvalidValue;
@@ -370,10 +382,10 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
           const int ntiles = si.Q / tw_b<T, PP>();
           if (mode == 0)
             hipLaunchKernelGGL((k_tmpl_b<T, PP, 0>), dim3(ntiles * nt), dim3(tmpl_nt_b<T>()), 0, st, ta, d.sp(),
-                               tbuf, oa, d.tw1024);
+                               tbuf, oa, d.twst);
           else
             hipLaunchKernelGGL((k_tmpl_b<T, PP, 1>), dim3(ntiles * nt), dim3(tmpl_nt_b<T>()), 0, st, ta, d.sp(),
-                               tbuf, oa, d.tw1024);
+                               tbuf, oa, d.twst);
           err = hipGetLastError();
         } else {
           err = hipErrorInvalidValue;

@@ -49,10 +49,25 @@ __host__ __device__ constexpr int col_stride(int want) {
 template <int TW>
 __host__ __device__ constexpr int want_a() { return TW >= 16 ? 1 : 16 / TW; }
 
-// twiddle of a Stockham stage: exp(-+2 pi i k r / (NS R)) from the 1024-entry table
+// Stage twiddles exp(-2 pi i k r / (NS R)), k < NS, 1 <= r < R, stored per (NS, R) as
+// [k][r - 1] so that one butterfly's R - 1 twiddles are adjacent.  Tables exist for
+// NS in {8, 64, 512} and R in {2, 4, 8}; stage_tw_offset gives each table's start.
+__host__ __device__ constexpr int stage_tw_offset(int NS, int R) {
+  int off = 0;
+  for (int ns = 8; ns <= 512; ns *= 8)
+    for (int rr = 2; rr <= 8; rr *= 2) {
+      if (ns == NS && rr == R) return off;
+      off += ns * (rr - 1);
+    }
+  return -1;
+}
+constexpr int STAGE_TW_ENTRIES = 8 * 11 + 64 * 11 + 512 * 11;
+
 template <typename T, int NS, int R, bool INV>
-__device__ __forceinline__ cx<T> stage_tw(const cx<T>* __restrict__ tw1024, int k, int r) {
-  cx<T> w = tw1024[k * r * (1024 / (NS * R))];
+__device__ __forceinline__ cx<T> stage_tw(const cx<T>* __restrict__ twst, int k, int r) {
+  constexpr int OFF = stage_tw_offset(NS, R);
+  static_assert(OFF >= 0, "no twiddle table for this stage");
+  cx<T> w = twst[OFF + k * (R - 1) + (r - 1)];
   if (INV) w.im = -w.im;
   return w;
 }
@@ -61,7 +76,7 @@ __device__ __forceinline__ cx<T> stage_tw(const cx<T>* __restrict__ tw1024, int 
 // R is the stage radix, PB = (LEN / R) / G the butterflies per thread.
 template <typename T, int LEN, int G, int NS, int R, int PB, bool INV>
 __device__ __forceinline__ void stage_from_lds(cx<T> (&v)[PB][R], const cx<T>* col, int g,
-                                               const cx<T>* __restrict__ tw1024) {
+                                               const cx<T>* __restrict__ twst) {
   constexpr int NB = LEN / R;
 #pragma unroll
   for (int b = 0; b < PB; ++b) {
@@ -70,7 +85,9 @@ __device__ __forceinline__ void stage_from_lds(cx<T> (&v)[PB][R], const cx<T>* c
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       cx<T> x = col[phys(j + r * NB)];
-      if (NS > 1 && r > 0) x = cmul(x, stage_tw<T, NS, R, INV>(tw1024, k, r));
+      if constexpr (NS > 1) {
+        if (r > 0) x = cmul(x, stage_tw<T, NS, R, INV>(twst, k, r));
+      }
       v[b][r] = x;
     }
     dftr<T, R, INV>(v[b]);
@@ -90,18 +107,18 @@ __device__ __forceinline__ void stage_to_lds(const cx<T> (&v)[PB][R], cx<T>* col
 
 // Middle stages (stride NS up to, not including, the last stage) for two series.
 template <typename T, int LEN, int G, int NS, bool INV>
-__device__ __forceinline__ void middle_stages(cx<T>* cola, cx<T>* colb, int g, const cx<T>* __restrict__ tw1024) {
+__device__ __forceinline__ void middle_stages(cx<T>* cola, cx<T>* colb, int g, const cx<T>* __restrict__ twst) {
   constexpr int R = stage_radix<LEN, NS>();
   if constexpr (NS * R < LEN) {
     constexpr int PB = (LEN / R) / G;
     cx<T> va[PB][R], vb[PB][R];
-    stage_from_lds<T, LEN, G, NS, R, PB, INV>(va, cola, g, tw1024);
-    stage_from_lds<T, LEN, G, NS, R, PB, INV>(vb, colb, g, tw1024);
+    stage_from_lds<T, LEN, G, NS, R, PB, INV>(va, cola, g, twst);
+    stage_from_lds<T, LEN, G, NS, R, PB, INV>(vb, colb, g, twst);
     __syncthreads();
     stage_to_lds<T, LEN, G, NS, R, PB>(va, cola, g);
     stage_to_lds<T, LEN, G, NS, R, PB>(vb, colb, g);
     __syncthreads();
-    middle_stages<T, LEN, G, NS * R, INV>(cola, colb, g, tw1024);
+    middle_stages<T, LEN, G, NS * R, INV>(cola, colb, g, twst);
   }
 }
 
@@ -116,7 +133,7 @@ __host__ __device__ constexpr int last_ns() {
 template <typename T, int Q>
 __global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a(TmplArgs ta, const cx<T>* __restrict__ zt,
                                                            cx<T>* __restrict__ tbuf,
-                                                           const cx<T>* __restrict__ tw1024,
+                                                           const cx<T>* __restrict__ twst,
                                                            const cx<T>* __restrict__ twlo,
                                                            const cx<T>* __restrict__ twhi) {
   constexpr int NTA = tmpl_nt_a<T>();
@@ -153,8 +170,15 @@ __global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a(TmplArgs ta, const cx
           double cyc = half_fdot_dt2 * x * x;
           cyc -= floor(cyc);
           T s, co;
-          if constexpr (sizeof(T) == 8) sincospi(2.0 * cyc, &s, &co);
-          else sincospif((float)(2.0 * cyc), &s, &co);
+          if constexpr (sizeof(T) == 8) {
+            sincospi(2.0 * cyc, &s, &co);
+          } else {
+            // the phase is already reduced to [0, 1) cycles in FP64: the hardware
+            // sine and cosine take their argument in cycles
+            const float cf = (float)cyc;
+            s = __builtin_amdgcn_sinf(cf);
+            co = __builtin_amdgcn_cosf(cf);
+          }
           const cx<T> w = mk<T>(co, -s);
           a = cmul(za[jj], w);
           bb = cmul(zb[jj], w);
@@ -171,26 +195,29 @@ __global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a(TmplArgs ta, const cx
     }
     __syncthreads();
   }
-  middle_stages<T, Q, G, R1, false>(cola, colb, g, tw1024);
+  middle_stages<T, Q, G, R1, false>(cola, colb, g, twst);
   // last stage: outputs k2 = j + NSL r go to T[k2][j1] times W_nfft^(j1 k2)
   constexpr int NSL = last_ns<Q, 1>();
   constexpr int RL = stage_radix<Q, NSL>();
   constexpr int PBL = (Q / RL) / G;
   cx<T> va[PBL][RL], vb[PBL][RL];
-  stage_from_lds<T, Q, G, NSL, RL, PBL, false>(va, cola, g, tw1024);
-  stage_from_lds<T, Q, G, NSL, RL, PBL, false>(vb, colb, g, tw1024);
+  stage_from_lds<T, Q, G, NSL, RL, PBL, false>(va, cola, g, twst);
+  stage_from_lds<T, Q, G, NSL, RL, PBL, false>(vb, colb, g, twst);
   cx<T>* outa = tbuf + (long)(2 * item) * ta.L;
   cx<T>* outb = outa + ta.L;
+  // W^(j1 k2) for k2 = j + NSL r: W^(j1 j) times powers of W^(j1 NSL)
+  const cx<T> step = twiddle_L<T, false>(twlo, twhi, j1 * NSL);
 #pragma unroll
   for (int b = 0; b < PBL; ++b) {
     const int j = g + G * b;
+    cx<T> w = twiddle_L<T, false>(twlo, twhi, j1 * j);
 #pragma unroll
     for (int r = 0; r < RL; ++r) {
       const int k2 = j + NSL * r;
-      const cx<T> w = twiddle_L<T, false>(twlo, twhi, j1 * k2);
       const long o = (long)k2 * ta.P + j1;
       outa[o] = cmul(va[b][r], w);
       outb[o] = cmul(vb[b][r], w);
+      if (r + 1 < RL) w = cmul(w, step);
     }
   }
 }
@@ -200,7 +227,7 @@ __global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a(TmplArgs ta, const cx
 template <typename T, int P, int MODE>
 __global__ void __launch_bounds__(tmpl_nt_b<T>()) k_tmpl_b(TmplArgs ta, const SkyParams* __restrict__ sp,
                                                            const cx<T>* __restrict__ tbuf, OutArgs oa,
-                                                           const cx<T>* __restrict__ tw1024) {
+                                                           const cx<T>* __restrict__ twst) {
   constexpr int NTB = tmpl_nt_b<T>();
   constexpr int G = groups_per_col<P>();
   constexpr int TW = tw_b<T, P>();
@@ -237,15 +264,15 @@ __global__ void __launch_bounds__(tmpl_nt_b<T>()) k_tmpl_b(TmplArgs ta, const Sk
     stage_to_lds<T, P, G, 1, R1, PB1>(vb, colb, g);
     __syncthreads();
   }
-  middle_stages<T, P, G, R1, false>(cola, colb, g, tw1024);
+  middle_stages<T, P, G, R1, false>(cola, colb, g, twst);
   constexpr int NSL = last_ns<P, 1>();
   constexpr int RL = stage_radix<P, NSL>();
   constexpr int PBL = (P / RL) / G;
   constexpr int NOUT = PBL * RL;
   static_assert(NOUT <= 32, "output mask");
   cx<T> va[PBL][RL], vb[PBL][RL];
-  stage_from_lds<T, P, G, NSL, RL, PBL, false>(va, cola, g, tw1024);
-  stage_from_lds<T, P, G, NSL, RL, PBL, false>(vb, colb, g, tw1024);
+  stage_from_lds<T, P, G, NSL, RL, PBL, false>(va, cola, g, twst);
+  stage_from_lds<T, P, G, NSL, RL, PBL, false>(vb, colb, g, twst);
   const SkyParams& pr = sp[skyl];
   const T cfa = (T)pr.cfa, cfb = (T)pr.cfb, cfab = (T)pr.cfab;
   if constexpr (MODE == 1) {
@@ -268,11 +295,16 @@ __global__ void __launch_bounds__(tmpl_nt_b<T>()) k_tmpl_b(TmplArgs ta, const Sk
     for (int b = 0; b < PBL; ++b) {
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
-        const int k = ta.Q * (g + G * b + NSL * r) + k2;
-        const cx<T> fa = va[b][r], fb = vb[b][r];
-        const T v = cfa * cnorm2(fa) + cfb * cnorm2(fb) + cfab * (fa.re * fb.re + fa.im * fb.im);
-        val[b * RL + r] = v;
-        if (k >= oa.k_min && k < oa.k_max && v > (T)oa.threshold) mask |= 1u << (b * RL + r);
+        val[b * RL + r] = (T)0;
+        // bins of this output group: k = Q (G b + NSL r + g') + k2 over the G lanes g'
+        const int klo = ta.Q * (G * b + NSL * r) + k2;
+        if (klo < oa.k_max && klo + ta.Q * (G - 1) >= oa.k_min) {
+          const int k = ta.Q * (g + G * b + NSL * r) + k2;
+          const cx<T> fa = va[b][r], fb = vb[b][r];
+          const T v = cfa * cnorm2(fa) + cfb * cnorm2(fb) + cfab * (fa.re * fb.re + fa.im * fb.im);
+          val[b * RL + r] = v;
+          if (k >= oa.k_min && k < oa.k_max && v > (T)oa.threshold) mask |= 1u << (b * RL + r);
+        }
       }
     }
     int total;
