@@ -381,10 +381,10 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
         if constexpr (PP >= 64) {
           const int ntiles = si.Q / tw_b<T, PP>();
           if (mode == 0)
-            hipLaunchKernelGGL((k_tmpl_b<T, PP, 0>), dim3(ntiles * nt), dim3(tmpl_nt_b<T>()), 0, st, ta, d.sp(),
+            hipLaunchKernelGGL((k_tmpl_b<T, PP, 0>), dim3(ntiles * nt), dim3(tmpl_nt_b<T, PP>()), 0, st, ta, d.sp(),
                                tbuf, oa, d.twst);
           else
-            hipLaunchKernelGGL((k_tmpl_b<T, PP, 1>), dim3(ntiles * nt), dim3(tmpl_nt_b<T>()), 0, st, ta, d.sp(),
+            hipLaunchKernelGGL((k_tmpl_b<T, PP, 1>), dim3(ntiles * nt), dim3(tmpl_nt_b<T, PP>()), 0, st, ta, d.sp(),
                                tbuf, oa, d.twst);
           err = hipGetLastError();
         } else {

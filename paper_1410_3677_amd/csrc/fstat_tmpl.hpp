@@ -32,14 +32,31 @@ __host__ __device__ constexpr int stage_radix() {
 // threads per template-pass workgroup and butterfly groups per column
 template <typename T>
 __host__ __device__ constexpr int tmpl_nt_a() { return sizeof(T) == 4 ? 512 : 256; }
-template <typename T>
-__host__ __device__ constexpr int tmpl_nt_b() { return 256; }
 template <int LEN>
 __host__ __device__ constexpr int groups_per_col() { return LEN / 8; }
+// pass B: 256 threads, each row owned by one wavefront (or a fraction of one) when
+// its butterfly groups fit in 64 lanes
+template <typename T, int LEN>
+__host__ __device__ constexpr int tmpl_nt_b() { return 256; }
+template <int LEN>
+__host__ __device__ constexpr bool rows_in_wave() { return groups_per_col<LEN>() <= 64; }
+
+// LDS ordering between the stages of columns that one wavefront owns: a wavefront's
+// LDS operations complete in order, so only compiler reordering must be prevented.
+template <bool WAVE_ONLY>
+__device__ __forceinline__ void stage_sync() {
+  if constexpr (WAVE_ONLY) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
 template <typename T, int LEN>
 __host__ __device__ constexpr int tw_a() { return tmpl_nt_a<T>() / groups_per_col<LEN>(); }
 template <typename T, int LEN>
-__host__ __device__ constexpr int tw_b() { return tmpl_nt_b<T>() / groups_per_col<LEN>(); }
+__host__ __device__ constexpr int tw_b() { return tmpl_nt_b<T, LEN>() / groups_per_col<LEN>(); }
 
 // column stride: phys(LEN) rounded so that stride % 32 == want (in complex elements)
 template <int LEN>
@@ -106,7 +123,7 @@ __device__ __forceinline__ void stage_to_lds(const cx<T> (&v)[PB][R], cx<T>* col
 }
 
 // Middle stages (stride NS up to, not including, the last stage) for two series.
-template <typename T, int LEN, int G, int NS, bool INV>
+template <typename T, int LEN, int G, int NS, bool INV, bool WAVE_ONLY = false>
 __device__ __forceinline__ void middle_stages(cx<T>* cola, cx<T>* colb, int g, const cx<T>* __restrict__ twst) {
   constexpr int R = stage_radix<LEN, NS>();
   if constexpr (NS * R < LEN) {
@@ -114,11 +131,26 @@ __device__ __forceinline__ void middle_stages(cx<T>* cola, cx<T>* colb, int g, c
     cx<T> va[PB][R], vb[PB][R];
     stage_from_lds<T, LEN, G, NS, R, PB, INV>(va, cola, g, twst);
     stage_from_lds<T, LEN, G, NS, R, PB, INV>(vb, colb, g, twst);
-    __syncthreads();
+    stage_sync<WAVE_ONLY>();
     stage_to_lds<T, LEN, G, NS, R, PB>(va, cola, g);
     stage_to_lds<T, LEN, G, NS, R, PB>(vb, colb, g);
+    stage_sync<WAVE_ONLY>();
+    middle_stages<T, LEN, G, NS * R, INV, WAVE_ONLY>(cola, colb, g, twst);
+  }
+}
+
+// Middle stages for one series.
+template <typename T, int LEN, int G, int NS, bool INV>
+__device__ __forceinline__ void middle_stages1(cx<T>* col, int g, const cx<T>* __restrict__ twst) {
+  constexpr int R = stage_radix<LEN, NS>();
+  if constexpr (NS * R < LEN) {
+    constexpr int PB = (LEN / R) / G;
+    cx<T> v[PB][R];
+    stage_from_lds<T, LEN, G, NS, R, PB, INV>(v, col, g, twst);
     __syncthreads();
-    middle_stages<T, LEN, G, NS * R, INV>(cola, colb, g, twst);
+    stage_to_lds<T, LEN, G, NS, R, PB>(v, col, g);
+    __syncthreads();
+    middle_stages1<T, LEN, G, NS * R, INV>(col, g, twst);
   }
 }
 
@@ -130,20 +162,22 @@ __host__ __device__ constexpr int last_ns() {
 
 // ---------------------------------------------------------------- pass A
 // Workgroup: TW adjacent columns j1 of one template; thread (c = t % TW, g = t / TW).
+// The two series share the chirp; they pass through one LDS tile one after the
+// other, the second series' first-stage outputs waiting in registers.
 template <typename T, int Q>
 __global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a(TmplArgs ta, const cx<T>* __restrict__ zt,
                                                            cx<T>* __restrict__ tbuf,
                                                            const cx<T>* __restrict__ twst,
                                                            const cx<T>* __restrict__ twlo,
                                                            const cx<T>* __restrict__ twhi) {
-  constexpr int NTA = tmpl_nt_a<T>();
   constexpr int G = groups_per_col<Q>();
   constexpr int TW = tw_a<T, Q>();
   constexpr int ST = col_stride<Q>(want_a<TW>());
   constexpr int R1 = stage_radix<Q, 1>();
   constexpr int NB1 = Q / R1, PB1 = NB1 / G;
   static_assert(PB1 >= 1 && NB1 % G == 0, "first stage must give each thread whole butterflies");
-  __shared__ cx<T> lds[2 * TW * ST];
+  static_assert(R1 < Q, "at least two stages");
+  __shared__ cx<T> lds[TW * ST];
   int tile, item;
   xcd_tile_item(ta.P / TW, tile, item);
   const int c = threadIdx.x % TW, g = threadIdx.x / TW;
@@ -153,71 +187,82 @@ __global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a(TmplArgs ta, const cx
   const cx<T>* za = zt + (long)(2 * skyl) * ta.ldzt;
   const cx<T>* zb = za + ta.ldzt;
   const int j1 = tile * TW + c;
-  cx<T>* cola = lds + c * ST;
-  cx<T>* colb = lds + (TW + c) * ST;
-  // first stage: y[j1 + P j2], j2 = j + NB1 r, chirp exp(-i pi fdot (j dt)^2) in FP64 cycles
-  {
-    cx<T> va[PB1][R1], vb[PB1][R1];
+  cx<T>* col = lds + c * ST;
+  // first stage: y[j1 + P j2], j2 = j + NB1 r, chirp exp(-i pi fdot (j dt)^2) in FP64 cycles.
+  // All loads are issued before any chirp is computed so that they overlap.
+  cx<T> va[PB1][R1], vb[PB1][R1];
 #pragma unroll
-    for (int b = 0; b < PB1; ++b) {
-      const int j = g + G * b;
+  for (int b = 0; b < PB1; ++b) {
+    const unsigned j = (unsigned)(g + G * b);
 #pragma unroll
-      for (int r = 0; r < R1; ++r) {
-        const int jj = j1 + ta.P * (j + NB1 * r);
-        cx<T> a = mk<T>(0, 0), bb = mk<T>(0, 0);
-        if (jj < ta.n) {
-          const double x = (double)jj;
-          double cyc = half_fdot_dt2 * x * x;
-          cyc -= floor(cyc);
-          T s, co;
-          if constexpr (sizeof(T) == 8) {
-            sincospi(2.0 * cyc, &s, &co);
-          } else {
-            // the phase is already reduced to [0, 1) cycles in FP64: the hardware
-            // sine and cosine take their argument in cycles
-            const float cf = (float)cyc;
-            s = __builtin_amdgcn_sinf(cf);
-            co = __builtin_amdgcn_cosf(cf);
-          }
-          const cx<T> w = mk<T>(co, -s);
-          a = cmul(za[jj], w);
-          bb = cmul(zb[jj], w);
-        }
-        va[b][r] = a;
-        vb[b][r] = bb;
+    for (int r = 0; r < R1; ++r) {
+      const unsigned jj = (unsigned)j1 + (unsigned)ta.P * (j + (unsigned)(NB1 * r));
+      va[b][r] = mk<T>(0, 0);
+      vb[b][r] = mk<T>(0, 0);
+      if (jj < (unsigned)ta.n) {
+        va[b][r] = za[jj];
+        vb[b][r] = zb[jj];
       }
-      dftr<T, R1, false>(va[b]);
-      dftr<T, R1, false>(vb[b]);
     }
-    if constexpr (R1 < Q) {
-      stage_to_lds<T, Q, G, 1, R1, PB1>(va, cola, g);
-      stage_to_lds<T, Q, G, 1, R1, PB1>(vb, colb, g);
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const unsigned jj = (unsigned)j1 + (unsigned)ta.P * (j + (unsigned)(NB1 * r));
+      if (jj < (unsigned)ta.n) {
+        const double x = (double)jj;
+        double cyc = half_fdot_dt2 * x * x;
+        cyc -= floor(cyc);
+        T s, co;
+        if constexpr (sizeof(T) == 8) {
+          sincospi(2.0 * cyc, &s, &co);
+        } else {
+          // the phase is already reduced to [0, 1) cycles in FP64: the hardware
+          // sine and cosine take their argument in cycles
+          const float cf = (float)cyc;
+          s = __builtin_amdgcn_sinf(cf);
+          co = __builtin_amdgcn_cosf(cf);
+        }
+        const cx<T> w = mk<T>(co, -s);
+        va[b][r] = cmul(va[b][r], w);
+        vb[b][r] = cmul(vb[b][r], w);
+      }
     }
-    __syncthreads();
+    dftr<T, R1, false>(va[b]);
+    dftr<T, R1, false>(vb[b]);
   }
-  middle_stages<T, Q, G, R1, false>(cola, colb, g, twst);
-  // last stage: outputs k2 = j + NSL r go to T[k2][j1] times W_nfft^(j1 k2)
+  // twiddles W^(j1 k2) of the last-stage outputs k2 = j + NSL r: W^(j1 j) times powers of W^(j1 NSL)
   constexpr int NSL = last_ns<Q, 1>();
   constexpr int RL = stage_radix<Q, NSL>();
   constexpr int PBL = (Q / RL) / G;
-  cx<T> va[PBL][RL], vb[PBL][RL];
-  stage_from_lds<T, Q, G, NSL, RL, PBL, false>(va, cola, g, twst);
-  stage_from_lds<T, Q, G, NSL, RL, PBL, false>(vb, colb, g, twst);
-  cx<T>* outa = tbuf + (long)(2 * item) * ta.L;
-  cx<T>* outb = outa + ta.L;
-  // W^(j1 k2) for k2 = j + NSL r: W^(j1 j) times powers of W^(j1 NSL)
-  const cx<T> step = twiddle_L<T, false>(twlo, twhi, j1 * NSL);
+  cx<T> tw[PBL][RL];
+  {
+    const cx<T> step = twiddle_L<T, false>(twlo, twhi, j1 * NSL);
 #pragma unroll
-  for (int b = 0; b < PBL; ++b) {
-    const int j = g + G * b;
-    cx<T> w = twiddle_L<T, false>(twlo, twhi, j1 * j);
+    for (int b = 0; b < PBL; ++b) {
+      cx<T> w = twiddle_L<T, false>(twlo, twhi, j1 * (g + G * b));
 #pragma unroll
-    for (int r = 0; r < RL; ++r) {
-      const int k2 = j + NSL * r;
-      const long o = (long)k2 * ta.P + j1;
-      outa[o] = cmul(va[b][r], w);
-      outb[o] = cmul(vb[b][r], w);
-      if (r + 1 < RL) w = cmul(w, step);
+      for (int r = 0; r < RL; ++r) {
+        tw[b][r] = w;
+        if (r + 1 < RL) w = cmul(w, step);
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    if (s == 1) __syncthreads();  // series a's last stage has read the tile
+    stage_to_lds<T, Q, G, 1, R1, PB1>(s == 0 ? va : vb, col, g);
+    __syncthreads();
+    middle_stages1<T, Q, G, R1, false>(col, g, twst);
+    cx<T> v[PBL][RL];
+    stage_from_lds<T, Q, G, NSL, RL, PBL, false>(v, col, g, twst);
+    cx<T>* out = tbuf + (long)(2 * item + s) * ta.L;
+#pragma unroll
+    for (int b = 0; b < PBL; ++b) {
+      const int j = g + G * b;
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const unsigned o = (unsigned)(j + NSL * r) * (unsigned)ta.P + (unsigned)j1;
+        out[o] = cmul(v[b][r], tw[b][r]);
+      }
     }
   }
 }
@@ -225,10 +270,10 @@ __global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a(TmplArgs ta, const cx
 // ---------------------------------------------------------------- pass B
 // Workgroup: TW adjacent rows k2 of one template; thread (c = t / G, g = t % G).
 template <typename T, int P, int MODE>
-__global__ void __launch_bounds__(tmpl_nt_b<T>()) k_tmpl_b(TmplArgs ta, const SkyParams* __restrict__ sp,
+__global__ void __launch_bounds__((tmpl_nt_b<T, P>())) k_tmpl_b(TmplArgs ta, const SkyParams* __restrict__ sp,
                                                            const cx<T>* __restrict__ tbuf, OutArgs oa,
                                                            const cx<T>* __restrict__ twst) {
-  constexpr int NTB = tmpl_nt_b<T>();
+  constexpr int NTB = tmpl_nt_b<T, P>();
   constexpr int G = groups_per_col<P>();
   constexpr int TW = tw_b<T, P>();
   constexpr int ST = col_stride<P>(16);
@@ -262,9 +307,9 @@ __global__ void __launch_bounds__(tmpl_nt_b<T>()) k_tmpl_b(TmplArgs ta, const Sk
     }
     stage_to_lds<T, P, G, 1, R1, PB1>(va, cola, g);
     stage_to_lds<T, P, G, 1, R1, PB1>(vb, colb, g);
-    __syncthreads();
+    stage_sync<rows_in_wave<P>()>();
   }
-  middle_stages<T, P, G, R1, false>(cola, colb, g, twst);
+  middle_stages<T, P, G, R1, false, rows_in_wave<P>()>(cola, colb, g, twst);
   constexpr int NSL = last_ns<P, 1>();
   constexpr int RL = stage_radix<P, NSL>();
   constexpr int PBL = (P / RL) / G;
