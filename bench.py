@@ -70,6 +70,7 @@ def main():
     ap.add_argument("--no-events", action="store_true", help="time without per-launch HIP events")
     ap.add_argument("--templates-per-launch", type=int, default=0)
     ap.add_argument("--skies-per-batch", type=int, default=0)
+    ap.add_argument("--no-graph", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the search shards by sky "
@@ -97,7 +98,8 @@ def main():
     templates = args.nsky * args.nfdot
     cap = int(max(1 << 20, 3.0 * 5.0e-4 * (nfft // 2) * templates * max(args.steps, 1)))
     plan = F.Plan([F.segment_to_device(seg)], candidate_capacity=cap,
-                  templates_per_launch=args.templates_per_launch, skies_per_batch=args.skies_per_batch)
+                  templates_per_launch=args.templates_per_launch, skies_per_batch=args.skies_per_batch,
+                  use_graph=0 if args.no_graph else 1)
     info = plan.info(0)
     log(f"plan {info}, capacity {cap}")
     for i in range(args.warmup):
@@ -150,7 +152,7 @@ def main():
         w2 = synth.workload(2)
         seg2 = w2.segments[0]
         p2 = F.Plan([F.segment_to_device(seg2)], templates_per_launch=1, skies_per_batch=1,
-                    candidate_capacity=1 << 22)
+                    candidate_capacity=1 << 22, use_graph=0)
         a2, d2, f2 = dev(w2.alpha), dev(w2.delta), dev(w2.fdot)
         p2.search_batch(0, a2[:2], d2[:2], f2)
         torch.cuda.synchronize()

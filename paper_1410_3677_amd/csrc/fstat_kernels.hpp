@@ -455,94 +455,25 @@ struct TmplArgs {
   long ldzt;            // stride between series in zt
 };
 
-// Pass A of a template: y_s[j] = zt_s[j] exp(-i pi fdot (j dt)^2) for j < n (chirp phase
-// in FP64, reduced mod 1 cycle), column DFTs over j2, twiddle, store T[k2][j1].
-// Template t = t0 + item belongs to batch sky t / nfdot and spindown t % nfdot.
-template <typename T, int Q>
-__global__ void __launch_bounds__(NT) k_tmpl_pass_a(TmplArgs ta, const cx<T>* __restrict__ zt,
-                                                    cx<T>* __restrict__ tbuf,
-                                                    const cx<T>* __restrict__ tw1024,
-                                                    const cx<T>* __restrict__ twlo, const cx<T>* __restrict__ twhi) {
-  constexpr int TW = tile_width<T, Q>();
-  constexpr int ST = lds_stride<Q>();
-  __shared__ cx<T> lds[2 * TW * ST];
-  int tile, item;
-  xcd_tile_item(ta.P / TW, tile, item);
-  const int t = ta.t0 + item;
-  const int skyl = t / ta.nfdot, sidx = t % ta.nfdot;
-  const double half_fdot_dt2 = 0.5 * ta.fdot[sidx] * ta.dt * ta.dt;
-  const cx<T>* za = zt + (long)(2 * skyl) * ta.ldzt;
-  const cx<T>* zb = za + ta.ldzt;
-  const int j10 = tile * TW;
-  for (int e = threadIdx.x; e < TW * Q; e += NT) {
-    const int j2 = e / TW, c = e % TW;
-    const int j = j10 + c + ta.P * j2;
-    cx<T> va = mk<T>(0, 0), vb = mk<T>(0, 0);
-    if (j < ta.n) {
-      const double jj = (double)j;
-      double cyc = half_fdot_dt2 * jj * jj;
-      cyc -= floor(cyc);
-      T s, co;
-      if constexpr (sizeof(T) == 8) {
-        sincospi(2.0 * cyc, &s, &co);
-      } else {
-        sincospif((float)(2.0 * cyc), &s, &co);
-      }
-      const cx<T> w = mk<T>(co, -s);
-      va = cmul(za[j], w);
-      vb = cmul(zb[j], w);
-    }
-    lds[c * ST + j2] = va;
-    lds[(TW + c) * ST + j2] = vb;
-  }
-  __syncthreads();
-  lds_fft<T, Q, 2 * TW, NT, ST, false>(lds, tw1024);
-  cx<T>* out = tbuf + (long)(2 * item) * ta.L;
-  for (int e = threadIdx.x; e < 2 * TW * Q; e += NT) {
-    const int s = e / (TW * Q), rem = e % (TW * Q);
-    const int k2 = rem / TW, c = rem % TW;
-    const int j1 = j10 + c;
-    out[(long)s * ta.L + (long)k2 * ta.P + j1] =
-        cmul(lds[(s * TW + c) * ST + k2], twiddle_L<T, false>(twlo, twhi, j1 * k2));
-  }
-}
-
 // Where pass B puts its results.
 struct OutArgs {
   int k_min, k_max;
   double threshold;
-  int search, segment;
+  const int* search_next;        // device: searches begun so far (this one included)
+  int segment;
   CandEntry* cand;               // candidate buffer
   unsigned long long* count;     // crossings found so far (may exceed capacity)
   long long capacity;
   void* spectrum;                // [sky][fdot][k - k_min], T
 };
 
-// Exclusive prefix sum of one int per thread over the workgroup; returns the
-// thread's offset and writes the total to *total (all threads).
-__device__ __forceinline__ int block_exclusive_scan(int v, int* total) {
-  __shared__ int wsum[NT / 64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) wsum[w] = x;
-  __syncthreads();
-  int before = 0, all = 0;
-#pragma unroll
-  for (int k = 0; k < NT / 64; ++k) {
-    const int ws = wsum[k];
-    if (k < w) before += ws;
-    all += ws;
-  }
-  *total = all;
-  return before + x - v;
+// Start of a search: advance the device-side search index.
+__global__ void k_begin_search(int* search_next) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) search_next[0] += 1;
 }
 
-// Same for a workgroup of NTH threads.
+// Exclusive prefix sum of one int per thread over a workgroup of NTH threads;
+// returns the thread's offset and writes the total to *total (all threads).
 template <int NTH>
 __device__ __forceinline__ int block_exclusive_scan_n(int v, int* total) {
   __shared__ int wsum[NTH / 64];
@@ -564,87 +495,6 @@ __device__ __forceinline__ int block_exclusive_scan_n(int v, int* total) {
   }
   *total = all;
   return before + x - v;
-}
-
-// Pass B of a template: row DFTs for both series, then for every bin k = Q k1 + k2 in
-// [k_min, k_max): 2F = cfa |Fa|^2 + cfb |Fb|^2 + cfab Re(Fa Fb*).
-// MODE 0: bins with 2F > threshold are appended to the candidate buffer with one
-// atomic per workgroup (wavefront prefix sums give each crossing its slot).
-// MODE 1: 2F is stored to the spectrum array.
-template <typename T, int P, int MODE>
-__global__ void __launch_bounds__(NT) k_tmpl_pass_b(TmplArgs ta, const SkyParams* __restrict__ sp,
-                                                    const cx<T>* __restrict__ tbuf, OutArgs oa,
-                                                    const cx<T>* __restrict__ tw1024) {
-  constexpr int TW = tile_width<T, P>();
-  constexpr int ST = lds_stride<P>();
-  constexpr int PER = (TW * P) / NT;
-  static_assert((TW * P) % NT == 0 && PER <= 32, "tile does not split evenly");
-  __shared__ cx<T> lds[2 * TW * ST];
-  __shared__ unsigned long long sbase;
-  int tile, item;
-  xcd_tile_item(ta.Q / TW, tile, item);
-  const int t = ta.t0 + item;
-  const int skyl = t / ta.nfdot, sidx = t % ta.nfdot;
-  const int k20 = tile * TW;
-  const cx<T>* in = tbuf + (long)(2 * item) * ta.L;
-  for (int e = threadIdx.x; e < 2 * TW * P; e += NT) {
-    const int s = e / (TW * P), rem = e % (TW * P);
-    const int c = rem / P, j1 = rem % P;
-    lds[(s * TW + c) * ST + j1] = in[(long)s * ta.L + (long)(k20 + c) * ta.P + j1];
-  }
-  __syncthreads();
-  lds_fft<T, P, 2 * TW, NT, ST, false>(lds, tw1024);
-  const SkyParams& pr = sp[skyl];
-  const T cfa = (T)pr.cfa, cfb = (T)pr.cfb, cfab = (T)pr.cfab;
-  if constexpr (MODE == 1) {
-    T* out = (T*)oa.spectrum + ((long)(ta.sky0 + skyl) * ta.nfdot + sidx) * (long)(oa.k_max - oa.k_min);
-    for (int e = threadIdx.x; e < TW * P; e += NT) {
-      const int k1 = e / TW, c = e % TW;
-      const int k = ta.Q * k1 + k20 + c;
-      if (k >= oa.k_min && k < oa.k_max) {
-        const cx<T> fa = lds[c * ST + k1], fb = lds[(TW + c) * ST + k1];
-        out[k - oa.k_min] = cfa * cnorm2(fa) + cfb * cnorm2(fb) + cfab * (fa.re * fb.re + fa.im * fb.im);
-      }
-    }
-  } else {
-    uint32_t mask = 0;
-    T val[PER];
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = threadIdx.x + i * NT;
-      const int k1 = e / TW, c = e % TW;
-      const int k = ta.Q * k1 + k20 + c;
-      const cx<T> fa = lds[c * ST + k1], fb = lds[(TW + c) * ST + k1];
-      const T v = cfa * cnorm2(fa) + cfb * cnorm2(fb) + cfab * (fa.re * fb.re + fa.im * fb.im);
-      val[i] = v;
-      if (k >= oa.k_min && k < oa.k_max && v > (T)oa.threshold) mask |= 1u << i;
-    }
-    int total;
-    const int off = block_exclusive_scan(__popc(mask), &total);
-    if (total == 0) return;
-    if (threadIdx.x == 0) sbase = atomicAdd(oa.count, (unsigned long long)total);
-    __syncthreads();
-    unsigned long long slot = sbase + (unsigned long long)off;
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      if (mask & (1u << i)) {
-        if (slot < (unsigned long long)oa.capacity) {
-          const int e = threadIdx.x + i * NT;
-          const int k1 = e / TW, c = e % TW;
-          CandEntry ce;
-          ce.search = oa.search;
-          ce.segment = oa.segment;
-          ce.sky = ta.sky0 + skyl;
-          ce.fdot_idx = sidx;
-          ce.bin = ta.Q * k1 + k20 + c;
-          ce.pad = 0;
-          ce.twoF = (double)val[i];
-          oa.cand[slot] = ce;
-        }
-        ++slot;
-      }
-    }
-  }
 }
 
 }  // namespace fstat

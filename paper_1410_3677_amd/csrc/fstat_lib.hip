@@ -39,6 +39,19 @@ struct SearchRecord {
 struct ProfRec {
   int cls;
   hipEvent_t a, b;
+  bool borrowed = false;   // owned by a graph entry, not by the event pool
+};
+
+// A captured search call, replayed while the call's arguments stay the same.
+struct GraphEntry {
+  int segment = 0, nsky = 0, nfdot = 0, mode = 0;
+  const double *alpha = nullptr, *delta = nullptr, *fdot = nullptr;
+  void* spectrum = nullptr;
+  void* ws = nullptr;
+  bool profiled = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<ProfRec> events;   // event pairs recorded by the graph's own nodes
 };
 
 struct Tables {
@@ -71,7 +84,12 @@ struct fstat_plan_s {
   Tables tab;
   CandEntry* d_cand = nullptr;
   unsigned long long* d_count = nullptr;
+  int* d_search_next = nullptr;   // device copy of the search index (advanced by the search itself)
   int search_count = 0;
+  // graph replay: a plan-owned stream joined to the caller's stream by events
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::vector<GraphEntry> graphs;
   std::vector<SearchRecord> searches;
   hipStream_t last_stream = nullptr;
   bool used_stream = false;
@@ -249,7 +267,7 @@ struct ProfScope {
       hipEvent_t b = take_event(p);
       if (b) {
         (void)hipEventRecord(b, st);
-        p->prof.push_back({cls, a, b});
+        p->prof.push_back({cls, a, b, false});
       } else {
         p->ev_pool.push_back(a);
       }
@@ -414,7 +432,7 @@ static fstat_status search_impl(fstat_plan_t p, int segment, const double* alpha
   Dev<T> d(p);
   OutArgs oa;
   oa.threshold = p->opt.threshold_2F;
-  oa.search = p->search_count;
+  oa.search_next = p->d_search_next;
   oa.cand = p->d_cand;
   oa.count = p->d_count;
   oa.capacity = p->opt.candidate_capacity;
@@ -434,6 +452,91 @@ static fstat_status search_impl(fstat_plan_t p, int segment, const double* alpha
       if (r != FSTAT_OK) return r;
     }
   }
+  return FSTAT_OK;
+}
+
+// All launches of one search call (begin-search marker first).
+static fstat_status enqueue_search(fstat_plan_t p, int segment, const double* alpha, const double* delta, int nsky,
+                                   const double* fdot, int nfdot, int mode, void* spectrum, hipStream_t st) {
+  if (mode == 0) {
+    hipLaunchKernelGGL(k_begin_search, dim3(1), dim3(1), 0, st, p->d_search_next);
+    HIP_TRY(p, hipGetLastError(), "search marker launch");
+  }
+  return p->fp64 ? search_impl<double>(p, segment, alpha, delta, nsky, fdot, nfdot, mode, spectrum, st)
+                 : search_impl<float>(p, segment, alpha, delta, nsky, fdot, nfdot, mode, spectrum, st);
+}
+
+// Eagerly, or as a captured HIP graph that is replayed while the call's arguments are
+// unchanged.  Graphs run on a plan-owned stream (default priority) that waits for the
+// caller's stream and that the caller's stream then waits for, so the call stays
+// asynchronous and ordered on the caller's stream.
+static fstat_status run_search(fstat_plan_t p, int segment, const double* alpha, const double* delta, int nsky,
+                               const double* fdot, int nfdot, int mode, void* spectrum, hipStream_t st) {
+  // per-launch event timing needs eager launches (events recorded by graph nodes do not
+  // report elapsed times)
+  if (!p->opt.use_graph || p->profiling)
+    return enqueue_search(p, segment, alpha, delta, nsky, fdot, nfdot, mode, spectrum, st);
+  if (!p->gstream) {
+    HIP_TRY(p, hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking), "graph stream");
+    HIP_TRY(p, hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming), "graph event");
+    HIP_TRY(p, hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming), "graph event");
+  }
+  GraphEntry* ge = nullptr;
+  for (auto& g : p->graphs)
+    if (g.segment == segment && g.alpha == alpha && g.delta == delta && g.nsky == nsky && g.fdot == fdot &&
+        g.nfdot == nfdot && g.mode == mode && g.spectrum == spectrum && g.ws == p->ws && g.profiled == p->profiling)
+      ge = &g;
+  HIP_TRY(p, hipEventRecord(p->ev_in, st), "graph join");
+  HIP_TRY(p, hipStreamWaitEvent(p->gstream, p->ev_in, 0), "graph join");
+  if (!ge) {
+    GraphEntry g;
+    g.segment = segment;
+    g.alpha = alpha;
+    g.delta = delta;
+    g.nsky = nsky;
+    g.fdot = fdot;
+    g.nfdot = nfdot;
+    g.mode = mode;
+    g.spectrum = spectrum;
+    g.ws = p->ws;
+    g.profiled = p->profiling;
+    const size_t nprof = p->prof.size();
+    HIP_TRY(p, hipStreamBeginCapture(p->gstream, hipStreamCaptureModeThreadLocal), "graph capture");
+    fstat_status r = enqueue_search(p, segment, alpha, delta, nsky, fdot, nfdot, mode, spectrum, p->gstream);
+    hipError_t ec = hipStreamEndCapture(p->gstream, &g.graph);
+    // the event pairs recorded during capture belong to the graph's nodes
+    g.events.assign(p->prof.begin() + nprof, p->prof.end());
+    p->prof.resize(nprof);
+    if (r != FSTAT_OK) {
+      if (g.graph) (void)hipGraphDestroy(g.graph);
+      return r;
+    }
+    if (ec != hipSuccess) return hip_fail(p, ec, "graph capture");
+    hipError_t ei = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      (void)hipGraphDestroy(g.graph);
+      return hip_fail(p, ei, "graph instantiate");
+    }
+    if (p->graphs.size() >= 4) {
+      GraphEntry& old = p->graphs.front();
+      (void)hipStreamSynchronize(p->gstream);
+      (void)hipGraphExecDestroy(old.exec);
+      (void)hipGraphDestroy(old.graph);
+      for (auto& pr : old.events) {
+        (void)hipEventDestroy(pr.a);
+        (void)hipEventDestroy(pr.b);
+      }
+      p->graphs.erase(p->graphs.begin());
+    }
+    p->graphs.push_back(std::move(g));
+    ge = &p->graphs.back();
+  }
+  HIP_TRY(p, hipGraphLaunch(ge->exec, p->gstream), "graph launch");
+  // the graph re-records its own event pairs on every replay: report this replay's
+  // durations (copies of the handles, which the graph entry owns)
+  for (const auto& pr : ge->events) p->prof.push_back({pr.cls, pr.a, pr.b, true});
+  HIP_TRY(p, hipEventRecord(p->ev_out, p->gstream), "graph join");
+  HIP_TRY(p, hipStreamWaitEvent(st, p->ev_out, 0), "graph join");
   return FSTAT_OK;
 }
 
@@ -584,7 +687,9 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_opt
       (e = hipMemcpy(p->tab.dev, tb.data(), tb.size(), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMalloc((void**)&p->d_cand, (size_t)opt.candidate_capacity * sizeof(CandEntry))) != hipSuccess ||
       (e = hipMalloc((void**)&p->d_count, sizeof(unsigned long long))) != hipSuccess ||
-      (e = hipMemset(p->d_count, 0, sizeof(unsigned long long))) != hipSuccess) {
+      (e = hipMemset(p->d_count, 0, sizeof(unsigned long long))) != hipSuccess ||
+      (e = hipMalloc((void**)&p->d_search_next, sizeof(int))) != hipSuccess ||
+      (e = hipMemset(p->d_search_next, 0, sizeof(int))) != hipSuccess) {
     std::string msg = std::string("plan device allocation: ") + hipGetErrorString(e);
     fstat_destroy(p);
     return fail(nullptr, e == hipErrorOutOfMemory ? FSTAT_E_NOMEM : FSTAT_E_DEVICE, msg);
@@ -644,8 +749,7 @@ fstat_status fstat_search_batch(fstat_plan_t plan, int32_t segment, const double
           "list copy");
   plan->last_stream = st;
   plan->used_stream = true;
-  r = plan->fp64 ? search_impl<double>(plan, segment, alpha, delta, nsky, fdot, nfdot, 0, nullptr, st)
-                 : search_impl<float>(plan, segment, alpha, delta, nsky, fdot, nfdot, 0, nullptr, st);
+  r = run_search(plan, segment, alpha, delta, nsky, fdot, nfdot, 0, nullptr, st);
   plan->search_count++;
   return r;
 }
@@ -661,8 +765,7 @@ fstat_status fstat_twoF_spectrum(fstat_plan_t plan, int32_t segment, const doubl
   hipStream_t st = (hipStream_t)stream;
   plan->last_stream = st;
   plan->used_stream = true;
-  return plan->fp64 ? search_impl<double>(plan, segment, alpha, delta, nsky, fdot, nfdot, 1, out, st)
-                    : search_impl<float>(plan, segment, alpha, delta, nsky, fdot, nfdot, 1, out, st);
+  return run_search(plan, segment, alpha, delta, nsky, fdot, nfdot, 1, out, st);
 }
 
 template <typename T>
@@ -804,8 +907,10 @@ fstat_status fstat_profile_read(fstat_plan_t plan, int32_t kernel_class, int64_t
     std::vector<ProfRec> keep;
     for (auto& pr : plan->prof) {
       if (pr.cls == kernel_class) {
-        plan->ev_pool.push_back(pr.a);
-        plan->ev_pool.push_back(pr.b);
+        if (!pr.borrowed) {
+          plan->ev_pool.push_back(pr.a);
+          plan->ev_pool.push_back(pr.b);
+        }
       } else {
         keep.push_back(pr);
       }
@@ -832,6 +937,7 @@ fstat_status fstat_destroy(fstat_plan_t plan) {
   if (!plan) return FSTAT_OK;
   if (plan->tab.dev || plan->ws || plan->d_cand) (void)hipDeviceSynchronize();
   for (auto& pr : plan->prof) {
+    if (pr.borrowed) continue;
     (void)hipEventDestroy(pr.a);
     (void)hipEventDestroy(pr.b);
   }
@@ -841,6 +947,18 @@ fstat_status fstat_destroy(fstat_plan_t plan) {
   if (plan->tab.dev) (void)hipFree(plan->tab.dev);
   if (plan->d_cand) (void)hipFree(plan->d_cand);
   if (plan->d_count) (void)hipFree(plan->d_count);
+  if (plan->d_search_next) (void)hipFree(plan->d_search_next);
+  for (auto& ge : plan->graphs) {
+    if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
+    if (ge.graph) (void)hipGraphDestroy(ge.graph);
+    for (auto& pr : ge.events) {
+      (void)hipEventDestroy(pr.a);
+      (void)hipEventDestroy(pr.b);
+    }
+  }
+  if (plan->ev_in) (void)hipEventDestroy(plan->ev_in);
+  if (plan->ev_out) (void)hipEventDestroy(plan->ev_out);
+  if (plan->gstream) (void)hipStreamDestroy(plan->gstream);
   delete plan;
   return FSTAT_OK;
 }

@@ -357,6 +357,7 @@ __global__ void __launch_bounds__((tmpl_nt_b<T, P>())) k_tmpl_b(TmplArgs ta, con
     if (total == 0) return;
     if (threadIdx.x == 0) sbase = atomicAdd(oa.count, (unsigned long long)total);
     __syncthreads();
+    const int search = oa.search_next[0] - 1;
     unsigned long long slot = sbase + (unsigned long long)off;
 #pragma unroll
     for (int i = 0; i < NOUT; ++i) {
@@ -364,7 +365,7 @@ __global__ void __launch_bounds__((tmpl_nt_b<T, P>())) k_tmpl_b(TmplArgs ta, con
         if (slot < (unsigned long long)oa.capacity) {
           const int b = i / RL, r = i % RL;
           CandEntry ce;
-          ce.search = oa.search;
+          ce.search = search;
           ce.segment = oa.segment;
           ce.sky = ta.sky0 + skyl;
           ce.fdot_idx = sidx;

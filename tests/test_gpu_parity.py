@@ -242,3 +242,26 @@ def test_candidate_overflow_reports_true_count(torch, tiny):
     small.search_batch(0, al, de, fd)
     recs, keys, n = small.candidates(allow_overflow=True)
     assert n == n_all > 7 and len(recs) == 7
+
+
+def test_graph_replays_match_eager_launches(torch, full):
+    note("graph replays vs eager launches")
+    seg = full.segments[0]
+    from tests.gpu_util import dev
+    al, de, fd = dev(full.alpha[:9]), dev(full.delta[:9]), dev(full.fdot[:7])
+    eager = make_plan([seg], use_graph=0, skies_per_batch=4, templates_per_launch=16)
+    eager.search_batch(0, al, de, fd)
+    r0, k0, n0 = eager.candidates()
+    assert n0 > 0
+    graph = make_plan([seg], use_graph=1, skies_per_batch=4, templates_per_launch=16)
+    for rep in range(3):
+        graph.search_batch(0, al, de, fd)
+        # the program's own eager work and a synchronisation between replays
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2.0).sum().item()
+        torch.cuda.synchronize()
+        r, k, n = graph.candidates()
+        assert n == n0, rep
+        np.testing.assert_array_equal(k[["segment", "sky", "fdot_idx", "bin"]], k0[["segment", "sky", "fdot_idx", "bin"]])
+        assert np.all(k["search"] == rep)
+        np.testing.assert_array_equal(r, r0)
