@@ -81,7 +81,10 @@ typedef struct {
   int32_t templates_per_launch;   /* spindown templates per FFT launch; 1 = one template per
                                      launch; 0 = the library's choice */
   int32_t skies_per_batch;        /* sky positions prepared together; 0 = the library's choice */
-  int32_t use_graph;              /* 1: replay each sky batch's launches as a captured HIP graph */
+  int32_t use_graph;              /* 1: capture each search call as a HIP graph and replay it while
+                                     the call's arguments are unchanged */
+  const char* tuning_cache_path;  /* autotuner results file (read by fstat_plan when both batch
+                                     sizes are 0, written by fstat_autotune); NULL = none */
 } fstat_options;
 
 /* The paper's five numbers of a candidate (Sect. 2). */
@@ -170,10 +173,23 @@ fstat_status fstat_profile_enable(fstat_plan_t plan, int32_t on);
 fstat_status fstat_profile_read(fstat_plan_t plan, int32_t kernel_class, int64_t* launches,
                                 double* total_ms, int32_t reset);
 
-/* Plan facts: FFT length and factors P x Q used for a segment, and the
- * batch sizes in force.  Any output pointer may be NULL. */
+/* Plan facts: FFT length and factors P x Q used for a segment, the batch
+ * sizes in force and the first-pass kernel variant (0: series one after the
+ * other through one LDS tile, 1: both series in LDS at once).  Any output
+ * pointer may be NULL. */
 fstat_status fstat_plan_info(fstat_plan_t plan, int32_t segment, int32_t* nfft, int32_t* p,
-                             int32_t* q, int32_t* templates_per_launch, int32_t* skies_per_batch);
+                             int32_t* q, int32_t* templates_per_launch, int32_t* skies_per_batch,
+                             int32_t* pass_a_variant);
+
+/* Autotuner: time the search of `segment` (its own data, a synthetic sky and
+ * spindown grid) for candidate templates-per-launch, skies-per-batch and
+ * first-pass kernel variants that fit the workspace budget, keep the fastest,
+ * and append it to options.tuning_cache_path if set (one line per device,
+ * FFT length and precision).  Runs synchronously on `stream` for roughly
+ * budget_ms.  Must be called before fstat_plan_set_workspace: the workspace
+ * size changes with the batch sizes (query it again afterwards).  Candidates
+ * found by the trial searches are discarded. */
+fstat_status fstat_autotune(fstat_plan_t plan, int32_t segment, double budget_ms, void* stream);
 
 /* Release the plan and everything it owns (waits for its work first).
  * NULL is accepted; a second destroy of the same handle is undefined, as

@@ -72,6 +72,7 @@ struct fstat_plan_s {
   bool fp64 = false;
   int device = 0;
   int Sb = 1, B = 1;           // skies per batch, templates per launch
+  int variant_a = 0;           // pass A kernel variant (0 sequential series, 1 paired)
   size_t cx_bytes = 8;
   // workspace
   void* ws = nullptr;
@@ -383,8 +384,12 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
         constexpr int QQ = decltype(c)::value;
         if constexpr (QQ >= 64) {
           const int ntiles = si.P / tw_a<T, QQ>();
-          hipLaunchKernelGGL((k_tmpl_a<T, QQ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T>()), 0, st, ta, d.zt(), tbuf,
-                             d.twst, d.lo(si.logL), d.hi(si.logL));
+          if (p->variant_a == 1)
+            hipLaunchKernelGGL((k_tmpl_a_pair<T, QQ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T>()), 0, st, ta, d.zt(),
+                               tbuf, d.twst, d.lo(si.logL), d.hi(si.logL));
+          else
+            hipLaunchKernelGGL((k_tmpl_a<T, QQ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T>()), 0, st, ta, d.zt(), tbuf,
+                               d.twst, d.lo(si.logL), d.hi(si.logL));
           err = hipGetLastError();
         } else {
           err = hipErrorInvalidValue;
@@ -540,6 +545,37 @@ static fstat_status run_search(fstat_plan_t p, int segment, const double* alpha,
   return FSTAT_OK;
 }
 
+static std::string device_tag() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string arch = prop.gcnArchName;
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch = arch.substr(0, colon);
+  return arch + "-cu" + std::to_string(prop.multiProcessorCount);
+}
+
+// Tuned (B, Sb, variant) for this device, largest FFT length and precision from the cache file.
+static bool cache_lookup(const char* path, const std::string& tag, long nfft, int prec, int* B, int* Sb, int* var) {
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char dtag[128];
+  long nf;
+  int pr, b, sb, v;
+  bool found = false;
+  while (std::fscanf(f, "%127s %ld %d %d %d %d", dtag, &nf, &pr, &b, &sb, &v) == 6) {
+    if (tag == dtag && nf == nfft && pr == prec && b > 0 && sb > 0 && (v == 0 || v == 1)) {
+      *B = b;
+      *Sb = sb;
+      *var = v;
+      found = true;  // the last matching line wins
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
 // ------------------------------------------------------------------ C ABI
 // (C linkage comes from the declarations in fstat.h)
 
@@ -557,6 +593,7 @@ void fstat_options_default(fstat_options* opt) {
   opt->templates_per_launch = 0;
   opt->skies_per_batch = 0;
   opt->use_graph = 1;
+  opt->tuning_cache_path = nullptr;
 }
 
 const char* fstat_strerror(fstat_status st) {
@@ -652,7 +689,20 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_opt
 
   // batch sizes: requested or defaults, shrunk to the budget (admission)
   int Sb = opt.skies_per_batch ? opt.skies_per_batch : (p->fp64 ? 4 : 8);
-  int B = opt.templates_per_launch ? opt.templates_per_launch : (p->fp64 ? 16 : 64);
+  int B = opt.templates_per_launch ? opt.templates_per_launch : (p->fp64 ? 16 : 256);
+  bool tuned = false;
+  if (!opt.skies_per_batch && !opt.templates_per_launch && opt.tuning_cache_path) {
+    int tb = 0, ts = 0, tv = 0;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0 &&
+        cache_lookup(opt.tuning_cache_path, device_tag(), p->L_max, opt.precision, &tb, &ts, &tv)) {
+      B = tb;
+      Sb = ts;
+      p->variant_a = tv;
+      tuned = true;
+    }
+  }
+  (void)tuned;
   const size_t budget = opt.workspace_budget_bytes;
   if (budget) {
     if (layout(p, 1, 1, false) > budget) {
@@ -921,7 +971,7 @@ fstat_status fstat_profile_read(fstat_plan_t plan, int32_t kernel_class, int64_t
 }
 
 fstat_status fstat_plan_info(fstat_plan_t plan, int32_t segment, int32_t* nfft, int32_t* p, int32_t* q,
-                             int32_t* templates_per_launch, int32_t* skies_per_batch) {
+                             int32_t* templates_per_launch, int32_t* skies_per_batch, int32_t* pass_a_variant) {
   if (!plan || segment < 0 || segment >= (int32_t)plan->segs.size())
     return fail(plan, FSTAT_E_INVAL, "bad arguments");
   const SegInfo& si = plan->segs[segment];
@@ -930,6 +980,116 @@ fstat_status fstat_plan_info(fstat_plan_t plan, int32_t segment, int32_t* nfft, 
   if (q) *q = si.Q;
   if (templates_per_launch) *templates_per_launch = plan->B;
   if (skies_per_batch) *skies_per_batch = plan->Sb;
+  if (pass_a_variant) *pass_a_variant = plan->variant_a;
+  return FSTAT_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+fstat_status fstat_autotune(fstat_plan_t plan, int32_t segment, double budget_ms, void* stream) {
+  if (!plan || segment < 0 || segment >= (int32_t)plan->segs.size() || !(budget_ms > 0))
+    return fail(plan, FSTAT_E_INVAL, "bad arguments");
+  if (plan->ws && !plan->ws_owned) return fail(plan, FSTAT_E_STATE, "autotune must precede fstat_plan_set_workspace");
+  hipStream_t st = (hipStream_t)stream;
+  const SegInfo& si = plan->segs[segment];
+  // trial template lists: 32 sky positions spread over the sphere, 256 spindowns
+  const int nsky = 32, nfdot = 256;
+  std::vector<double> h(2 * nsky + nfdot);
+  for (int i = 0; i < nsky; ++i) {
+    h[i] = std::fmod(2.0 * M_PI * i * 0.6180339887498949, 2.0 * M_PI);
+    h[nsky + i] = std::asin(1.0 - (2.0 * i + 1.0) / nsky);
+  }
+  for (int i = 0; i < nfdot; ++i) h[2 * nsky + i] = -1e-9 * i / (nfdot - 1);
+  double* dl = nullptr;
+  HIP_TRY(plan, hipMalloc(&dl, h.size() * sizeof(double)), "autotune lists");
+  struct Cand { int B, Sb, v; };
+  std::vector<Cand> cands;
+  for (int v = 0; v < 2; ++v)
+    for (int b : {64, 128, 256, 512})
+      for (int sb : {8, 16})
+        if (!plan->opt.workspace_budget_bytes || layout(plan, sb, b, false) <= plan->opt.workspace_budget_bytes)
+          cands.push_back({b, sb, v});
+  const int B0 = plan->B, Sb0 = plan->Sb, V0 = plan->variant_a;
+  const int graph0 = plan->opt.use_graph;
+  const bool prof0 = plan->profiling;
+  plan->opt.use_graph = 0;
+  plan->profiling = false;
+  double best = 1e300;
+  Cand bestc{B0, Sb0, V0};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  fstat_status r = FSTAT_OK;
+  hipError_t e = hipMemcpy(dl, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) r = hip_fail(plan, e, "autotune setup");
+  const double per_cand_ms = budget_ms / std::max<size_t>(1, cands.size());
+  for (size_t ci = 0; r == FSTAT_OK && ci < cands.size(); ++ci) {
+    const Cand c = cands[ci];
+    plan->B = c.B;
+    plan->Sb = c.Sb;
+    plan->variant_a = c.v;
+    if (plan->ws_owned && plan->ws) {
+      (void)hipStreamSynchronize(st);
+      (void)hipFree(plan->ws);
+      plan->ws = nullptr;
+    }
+    if ((r = ensure_workspace(plan)) != FSTAT_OK) break;
+    // warm-up on one sky batch, then time whole batches until the share of the budget is used
+    const int ns = std::min(nsky, c.Sb);
+    if ((r = run_search(plan, segment, dl, dl + nsky, ns, dl + 2 * nsky, nfdot, 0, nullptr, st)) != FSTAT_OK) break;
+    double ms_sum = 0.0;
+    long tmpl = 0;
+    int reps = 0;
+    while (reps < 8 && (reps < 1 || ms_sum < per_cand_ms)) {
+      (void)hipEventRecord(e0, st);
+      if ((r = run_search(plan, segment, dl, dl + nsky, nsky, dl + 2 * nsky, nfdot, 0, nullptr, st)) != FSTAT_OK) break;
+      (void)hipEventRecord(e1, st);
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+        r = hip_fail(plan, e, "autotune timing");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms_sum += ms;
+      tmpl += (long)nsky * nfdot;
+      ++reps;
+    }
+    if (r != FSTAT_OK) break;
+    const double per_tmpl = ms_sum / (double)tmpl;
+    if (per_tmpl < best) {
+      best = per_tmpl;
+      bestc = c;
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  // discard the trial candidates and searches
+  (void)hipMemset(plan->d_count, 0, sizeof(unsigned long long));
+  (void)hipMemset(plan->d_search_next, 0, sizeof(int));
+  plan->search_count = 0;
+  for (auto& sr : plan->searches) (void)hipHostFree(sr.host);
+  plan->searches.clear();
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(dl);
+  plan->opt.use_graph = graph0;
+  plan->profiling = prof0;
+  plan->B = bestc.B;
+  plan->Sb = bestc.Sb;
+  plan->variant_a = bestc.v;
+  if (plan->ws_owned && plan->ws) {
+    (void)hipFree(plan->ws);
+    plan->ws = nullptr;
+    plan->ws_owned = false;
+  }
+  layout(plan, plan->Sb, plan->B, true);
+  if (r != FSTAT_OK) return r;
+  if (plan->opt.tuning_cache_path) {
+    FILE* f = std::fopen(plan->opt.tuning_cache_path, "a");
+    if (f) {
+      std::fprintf(f, "%s %ld %d %d %d %d\n", device_tag().c_str(), plan->L_max, plan->opt.precision, plan->B,
+                   plan->Sb, plan->variant_a);
+      std::fclose(f);
+    }
+  }
   return FSTAT_OK;
 }
 

@@ -160,6 +160,53 @@ __host__ __device__ constexpr int last_ns() {
   else return last_ns<LEN, NS * stage_radix<LEN, NS>()>();
 }
 
+// First stage of pass A for both series: y[j1 + P j2], j2 = j + NB1 r (zero for
+// j1 + P j2 >= n), times the spindown chirp exp(-i pi fdot (j dt)^2) whose phase is
+// evaluated in FP64 and reduced to [0, 1) cycles, then a radix-R1 DFT in registers.
+// All loads are issued before any chirp is computed so that they overlap.
+template <typename T, int Q, int G, int R1, int NB1, int PB1>
+__device__ __forceinline__ void chirped_first_stage(cx<T> (&va)[PB1][R1], cx<T> (&vb)[PB1][R1],
+                                                    const cx<T>* __restrict__ za, const cx<T>* __restrict__ zb,
+                                                    int j1, int g, int P, int n, double half_fdot_dt2) {
+#pragma unroll
+  for (int b = 0; b < PB1; ++b) {
+    const unsigned j = (unsigned)(g + G * b);
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const unsigned jj = (unsigned)j1 + (unsigned)P * (j + (unsigned)(NB1 * r));
+      va[b][r] = mk<T>(0, 0);
+      vb[b][r] = mk<T>(0, 0);
+      if (jj < (unsigned)n) {
+        va[b][r] = za[jj];
+        vb[b][r] = zb[jj];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const unsigned jj = (unsigned)j1 + (unsigned)P * (j + (unsigned)(NB1 * r));
+      if (jj < (unsigned)n) {
+        const double x = (double)jj;
+        double cyc = half_fdot_dt2 * x * x;
+        cyc -= floor(cyc);
+        T s, co;
+        if constexpr (sizeof(T) == 8) {
+          sincospi(2.0 * cyc, &s, &co);
+        } else {
+          // the hardware sine and cosine take their argument in cycles
+          const float cf = (float)cyc;
+          s = __builtin_amdgcn_sinf(cf);
+          co = __builtin_amdgcn_cosf(cf);
+        }
+        const cx<T> w = mk<T>(co, -s);
+        va[b][r] = cmul(va[b][r], w);
+        vb[b][r] = cmul(vb[b][r], w);
+      }
+    }
+    dftr<T, R1, false>(va[b]);
+    dftr<T, R1, false>(vb[b]);
+  }
+}
+
 // ---------------------------------------------------------------- pass A
 // Workgroup: TW adjacent columns j1 of one template; thread (c = t % TW, g = t / TW).
 // The two series share the chirp; they pass through one LDS tile one after the
@@ -188,47 +235,9 @@ __global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a(TmplArgs ta, const cx
   const cx<T>* zb = za + ta.ldzt;
   const int j1 = tile * TW + c;
   cx<T>* col = lds + c * ST;
-  // first stage: y[j1 + P j2], j2 = j + NB1 r, chirp exp(-i pi fdot (j dt)^2) in FP64 cycles.
-  // All loads are issued before any chirp is computed so that they overlap.
+  // first stage: y[j1 + P j2] with the spindown chirp, radix-R1 butterflies in registers
   cx<T> va[PB1][R1], vb[PB1][R1];
-#pragma unroll
-  for (int b = 0; b < PB1; ++b) {
-    const unsigned j = (unsigned)(g + G * b);
-#pragma unroll
-    for (int r = 0; r < R1; ++r) {
-      const unsigned jj = (unsigned)j1 + (unsigned)ta.P * (j + (unsigned)(NB1 * r));
-      va[b][r] = mk<T>(0, 0);
-      vb[b][r] = mk<T>(0, 0);
-      if (jj < (unsigned)ta.n) {
-        va[b][r] = za[jj];
-        vb[b][r] = zb[jj];
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < R1; ++r) {
-      const unsigned jj = (unsigned)j1 + (unsigned)ta.P * (j + (unsigned)(NB1 * r));
-      if (jj < (unsigned)ta.n) {
-        const double x = (double)jj;
-        double cyc = half_fdot_dt2 * x * x;
-        cyc -= floor(cyc);
-        T s, co;
-        if constexpr (sizeof(T) == 8) {
-          sincospi(2.0 * cyc, &s, &co);
-        } else {
-          // the phase is already reduced to [0, 1) cycles in FP64: the hardware
-          // sine and cosine take their argument in cycles
-          const float cf = (float)cyc;
-          s = __builtin_amdgcn_sinf(cf);
-          co = __builtin_amdgcn_cosf(cf);
-        }
-        const cx<T> w = mk<T>(co, -s);
-        va[b][r] = cmul(va[b][r], w);
-        vb[b][r] = cmul(vb[b][r], w);
-      }
-    }
-    dftr<T, R1, false>(va[b]);
-    dftr<T, R1, false>(vb[b]);
-  }
+  chirped_first_stage<T, Q, G, R1, NB1, PB1>(va, vb, za, zb, j1, g, ta.P, ta.n, half_fdot_dt2);
   // twiddles W^(j1 k2) of the last-stage outputs k2 = j + NSL r: W^(j1 j) times powers of W^(j1 NSL)
   constexpr int NSL = last_ns<Q, 1>();
   constexpr int RL = stage_radix<Q, NSL>();
@@ -263,6 +272,65 @@ __global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a(TmplArgs ta, const cx
         const unsigned o = (unsigned)(j + NSL * r) * (unsigned)ta.P + (unsigned)j1;
         out[o] = cmul(v[b][r], tw[b][r]);
       }
+    }
+  }
+}
+
+// Pass A, paired variant: both series in LDS at once (twice the tile, half the
+// barriers).  The same operations as k_tmpl_a (the compiler may contract
+// multiply-adds differently, so results can differ in the last bit).
+template <typename T, int Q>
+__global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a_pair(TmplArgs ta, const cx<T>* __restrict__ zt,
+                                                                cx<T>* __restrict__ tbuf,
+                                                                const cx<T>* __restrict__ twst,
+                                                                const cx<T>* __restrict__ twlo,
+                                                                const cx<T>* __restrict__ twhi) {
+  constexpr int G = groups_per_col<Q>();
+  constexpr int TW = tw_a<T, Q>();
+  constexpr int ST = col_stride<Q>(want_a<TW>());
+  constexpr int R1 = stage_radix<Q, 1>();
+  constexpr int NB1 = Q / R1, PB1 = NB1 / G;
+  static_assert(PB1 >= 1 && NB1 % G == 0, "first stage must give each thread whole butterflies");
+  static_assert(R1 < Q, "at least two stages");
+  __shared__ cx<T> lds[2 * TW * ST];
+  int tile, item;
+  xcd_tile_item(ta.P / TW, tile, item);
+  const int c = threadIdx.x % TW, g = threadIdx.x / TW;
+  const int t = ta.t0 + item;
+  const int skyl = t / ta.nfdot, sidx = t % ta.nfdot;
+  const double half_fdot_dt2 = 0.5 * ta.fdot[sidx] * ta.dt * ta.dt;
+  const cx<T>* za = zt + (long)(2 * skyl) * ta.ldzt;
+  const cx<T>* zb = za + ta.ldzt;
+  const int j1 = tile * TW + c;
+  cx<T>* cola = lds + c * ST;
+  cx<T>* colb = lds + (TW + c) * ST;
+  {
+    cx<T> va[PB1][R1], vb[PB1][R1];
+    chirped_first_stage<T, Q, G, R1, NB1, PB1>(va, vb, za, zb, j1, g, ta.P, ta.n, half_fdot_dt2);
+    stage_to_lds<T, Q, G, 1, R1, PB1>(va, cola, g);
+    stage_to_lds<T, Q, G, 1, R1, PB1>(vb, colb, g);
+    __syncthreads();
+  }
+  middle_stages<T, Q, G, R1, false>(cola, colb, g, twst);
+  constexpr int NSL = last_ns<Q, 1>();
+  constexpr int RL = stage_radix<Q, NSL>();
+  constexpr int PBL = (Q / RL) / G;
+  cx<T> va[PBL][RL], vb[PBL][RL];
+  stage_from_lds<T, Q, G, NSL, RL, PBL, false>(va, cola, g, twst);
+  stage_from_lds<T, Q, G, NSL, RL, PBL, false>(vb, colb, g, twst);
+  cx<T>* outa = tbuf + (long)(2 * item) * ta.L;
+  cx<T>* outb = outa + ta.L;
+  const cx<T> step = twiddle_L<T, false>(twlo, twhi, j1 * NSL);
+#pragma unroll
+  for (int b = 0; b < PBL; ++b) {
+    const int j = g + G * b;
+    cx<T> w = twiddle_L<T, false>(twlo, twhi, j1 * j);
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const unsigned o = (unsigned)(j + NSL * r) * (unsigned)ta.P + (unsigned)j1;
+      outa[o] = cmul(va[b][r], w);
+      outb[o] = cmul(vb[b][r], w);
+      if (r + 1 < RL) w = cmul(w, step);
     }
   }
 }

@@ -25,7 +25,7 @@ KERNEL_NAMES = ("sky_prep", "resample", "template_a", "template_b")
 
 EXPORTED = ("fstat_options_default", "fstat_plan", "fstat_plan_workspace_size", "fstat_plan_set_workspace",
             "fstat_search_batch", "fstat_candidates", "fstat_twoF_spectrum", "fstat_sky_stages",
-            "fstat_profile_enable", "fstat_profile_read", "fstat_plan_info", "fstat_destroy",
+            "fstat_profile_enable", "fstat_profile_read", "fstat_plan_info", "fstat_autotune", "fstat_destroy",
             "fstat_strerror", "fstat_last_error")
 
 
@@ -40,7 +40,7 @@ class fstat_options(ctypes.Structure):
                 ("threshold_2F", ctypes.c_double), ("precision", ctypes.c_int32), ("form", ctypes.c_int32),
                 ("candidate_capacity", ctypes.c_int64), ("workspace_budget_bytes", ctypes.c_size_t),
                 ("templates_per_launch", ctypes.c_int32), ("skies_per_batch", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("tuning_cache_path", ctypes.c_char_p)]
 
 
 class fstat_candidate(ctypes.Structure):
@@ -81,7 +81,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "fstat_sky_stages": (i32, [P, i32, dbl, dbl, P, P, P, P, P, P, P, P]),
         "fstat_profile_enable": (i32, [P, i32]),
         "fstat_profile_read": (i32, [P, i32, ctypes.POINTER(i64), ctypes.POINTER(dbl), i32]),
-        "fstat_plan_info": (i32, [P, i32] + [ctypes.POINTER(i32)] * 5),
+        "fstat_plan_info": (i32, [P, i32] + [ctypes.POINTER(i32)] * 6),
+        "fstat_autotune": (i32, [P, i32, dbl, P]),
         "fstat_destroy": (i32, [P]),
         "fstat_strerror": (ctypes.c_char_p, [i32]),
         "fstat_last_error": (ctypes.c_char_p, [P]),
@@ -137,6 +138,9 @@ class Plan:
         self.lib = load()
         o = options if options is not None else options_default()
         for k, v in opts.items():
+            if k == "tuning_cache_path" and isinstance(v, str):
+                self._cache_path = v.encode()   # keep the bytes alive for the plan
+                v = self._cache_path
             setattr(o, k, v)
         self.options = o
         self._keep = []
@@ -155,17 +159,31 @@ class Plan:
         self.fp64 = o.precision == PREC_FP64
         self.workspace = None
         if workspace_from_torch:
-            nbytes = ctypes.c_size_t()
-            _check(self.lib.fstat_plan_workspace_size(h, ctypes.byref(nbytes)), h)
-            self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device="cuda")
-            base = _ptr(self.workspace)
-            aligned = (base + 255) & ~255
-            _check(self.lib.fstat_plan_set_workspace(h, aligned, int(nbytes.value)), h)
+            self._set_torch_workspace()
 
     def info(self, segment: int = 0) -> dict:
-        v = [ctypes.c_int32() for _ in range(5)]
+        v = [ctypes.c_int32() for _ in range(6)]
         _check(self.lib.fstat_plan_info(self.handle, segment, *[ctypes.byref(x) for x in v]), self.handle)
-        return dict(zip(("nfft", "p", "q", "templates_per_launch", "skies_per_batch"), [x.value for x in v]))
+        return dict(zip(("nfft", "p", "q", "templates_per_launch", "skies_per_batch", "pass_a_variant"),
+                        [x.value for x in v]))
+
+    def autotune(self, segment: int = 0, budget_ms: float = 2000.0, stream=None) -> dict:
+        """Run the autotuner, then give the plan a torch workspace of the new size."""
+        import torch
+        if self.workspace is not None:
+            raise RuntimeError("autotune must run before a workspace is set: create the Plan with "
+                               "workspace_from_torch=False")
+        _check(self.lib.fstat_autotune(self.handle, segment, float(budget_ms), _stream_handle(stream)), self.handle)
+        self._set_torch_workspace()
+        return self.info(segment)
+
+    def _set_torch_workspace(self):
+        import torch
+        nbytes = ctypes.c_size_t()
+        _check(self.lib.fstat_plan_workspace_size(self.handle, ctypes.byref(nbytes)), self.handle)
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device="cuda")
+        aligned = (_ptr(self.workspace) + 255) & ~255
+        _check(self.lib.fstat_plan_set_workspace(self.handle, aligned, int(nbytes.value)), self.handle)
 
     def search_batch(self, segment: int, alpha, delta, fdot, stream=None):
         self._keep_lists = (alpha, delta, fdot)

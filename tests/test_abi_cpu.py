@@ -48,6 +48,7 @@ def test_option_defaults():
     assert o.precision == F.PREC_MIXED and o.form == F.FORM_SIMPLIFIED
     assert o.candidate_capacity == 1 << 24
     assert o.workspace_budget_bytes == 0
+    assert o.use_graph == 1 and o.tuning_cache_path is None
 
 
 def _seg(n=86164, **kw):

@@ -265,3 +265,45 @@ def test_graph_replays_match_eager_launches(torch, full):
         np.testing.assert_array_equal(k[["segment", "sky", "fdot_idx", "bin"]], k0[["segment", "sky", "fdot_idx", "bin"]])
         assert np.all(k["search"] == rep)
         np.testing.assert_array_equal(r, r0)
+
+
+def test_autotune_writes_cache_and_plans_pick_it_up(torch, full, tmp_path):
+    note("autotuner")
+    from paper_1410_3677_amd import fstat as F
+    seg = full.segments[0]
+    cache = str(tmp_path / "tuning.txt")
+    plan = F.Plan([F.segment_to_device(seg)], workspace_from_torch=False, tuning_cache_path=cache)
+    info = plan.autotune(0, budget_ms=600.0)
+    note(f"tuned {info}")
+    assert info["templates_per_launch"] in (64, 128, 256, 512)
+    assert info["skies_per_batch"] in (8, 16) and info["pass_a_variant"] in (0, 1)
+    line = open(cache).read().split()
+    assert len(line) == 6 and int(line[1]) == synth.nfft_for(seg.n)
+    again = F.Plan([F.segment_to_device(seg)], tuning_cache_path=cache)
+    assert again.info(0) == info
+
+
+def test_pass_a_variants_give_identical_candidates(torch, full, tmp_path):
+    note("pass A variants")
+    from paper_1410_3677_amd import fstat as F
+    from tests.gpu_util import dev
+    seg = full.segments[0]
+    nfft = synth.nfft_for(seg.n)
+    # the device tag the library writes is learned from a one-line tuning run
+    probe = str(tmp_path / "probe.txt")
+    p0 = F.Plan([F.segment_to_device(seg)], workspace_from_torch=False, tuning_cache_path=probe)
+    p0.autotune(0, budget_ms=50.0)
+    tag = open(probe).read().split()[0]
+    out = []
+    for v in (0, 1):
+        cache = tmp_path / f"v{v}.txt"
+        cache.write_text(f"{tag} {nfft} 1 64 8 {v}\n")
+        plan = F.Plan([F.segment_to_device(seg)], tuning_cache_path=str(cache), use_graph=0)
+        assert plan.info(0)["pass_a_variant"] == v
+        plan.search_batch(0, dev(full.alpha[:3]), dev(full.delta[:3]), dev(full.fdot[:70]))
+        out.append(plan.candidates())
+    (r0, k0, n0), (r1, k1, n1) = out
+    assert n0 == n1 and n0 > 0
+    np.testing.assert_array_equal(k0, k1)
+    # the same operations; the compiler may contract multiply-adds differently
+    np.testing.assert_allclose(r0["twoF"], r1["twoF"], rtol=1e-6, atol=0)
