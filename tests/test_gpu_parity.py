@@ -307,3 +307,57 @@ def test_pass_a_variants_give_identical_candidates(torch, full, tmp_path):
     np.testing.assert_array_equal(k0, k1)
     # the same operations; the compiler may contract multiply-adds differently
     np.testing.assert_allclose(r0["twoF"], r1["twoF"], rtol=1e-6, atol=0)
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    return synth.workload(4, nsky=3, nfdot=4)
+
+
+def test_ragged_segments_in_one_search(torch, ragged):
+    note("ragged: 32 segments in one search call")
+    from tests.gpu_util import dev
+    segs = ragged.segments
+    plan = make_plan(segs)
+    for i in range(len(segs)):
+        assert plan.info(i)["nfft"] == synth.nfft_for(segs[i].n)
+    plan.search_batch(-1, dev(ragged.alpha), dev(ragged.delta), dev(ragged.fdot))
+    recs, keys, n = plan.candidates()
+    assert n > 0 and set(np.unique(keys["segment"])) <= set(range(len(segs)))
+    order = np.argsort([s.n for s in segs])
+    for si in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        seg = segs[si]
+        nfft = synth.nfft_for(seg.n)
+        m = keys["segment"] == si
+        ref = oracle_spectrum(seg, ragged.alpha, ragged.delta, ragged.fdot, nfft)
+        ng, no, flips, mism, err = compare_candidates(
+            np.stack([keys["sky"][m], keys["fdot_idx"][m], keys["bin"][m]], 1), recs["twoF"][m], ref,
+            ragged.threshold, GUARD_MIXED)
+        note(f"segment {si} n={seg.n} nfft={nfft}: gpu {ng} oracle {no} flips {flips} err {err:.2e}")
+        assert not mism and err < TOL_MIXED
+        np.testing.assert_allclose(recs["f_hz"][m], seg.f_off + keys["bin"][m] / (nfft * seg.dt), rtol=0, atol=1e-9)
+
+
+def test_ragged_admission_with_small_budget_gives_same_candidates(torch, ragged):
+    note("ragged: memory-bounded admission")
+    from tests.gpu_util import dev
+    from paper_1410_3677_amd import fstat as F
+    segs = ragged.segments[:8]
+    args = (dev(ragged.alpha), dev(ragged.delta), dev(ragged.fdot))
+    big = make_plan(segs)
+    big.search_batch(-1, *args)
+    r0, k0, n0 = big.candidates()
+    # a budget that only fits one sky and a handful of templates of the largest segment
+    budget = 80 << 20
+    small = make_plan(segs, workspace_budget_bytes=budget)
+    inf = small.info(0)
+    assert inf["templates_per_launch"] < big.info(0)["templates_per_launch"]
+    assert small.workspace.numel() <= budget + 256
+    small.search_batch(-1, *args)
+    r1, k1, n1 = small.candidates()
+    assert n1 == n0
+    np.testing.assert_array_equal(k0, k1)
+    np.testing.assert_allclose(r0["twoF"], r1["twoF"], rtol=1e-6, atol=0)
+    with pytest.raises(F.FstatError) as ei:
+        make_plan(segs, workspace_budget_bytes=4 << 20)
+    assert ei.value.status == F.E_ADMISSION
