@@ -42,9 +42,9 @@ def source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, templates_per_launch: int):
+def measured_traffic(kernel: str, templates_per_launch: int, variant: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it is current."""
-    path = os.path.join(ROOT, "profiles", "template_kernels_traffic.json")
+    path = os.path.join(ROOT, "profiles", "template_kernels_traffic.txt")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -52,7 +52,7 @@ def measured_traffic(kernel: str, templates_per_launch: int):
     if t.get("source_sha256") != source_digest() or kernel not in t.get("kernels", {}):
         return None
     k = t["kernels"][kernel]
-    if k.get("templates_per_launch") != templates_per_launch:
+    if k.get("templates_per_launch") != templates_per_launch or t.get("pass_a_variant") != variant:
         return None
     return k["bytes_per_launch"]
 
@@ -71,6 +71,12 @@ def main():
     ap.add_argument("--templates-per-launch", type=int, default=0)
     ap.add_argument("--skies-per-batch", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune-ms", type=float, default=3000.0)
+    ap.add_argument("--tuning-cache", default="",
+                    help="tuning cache file: reused if it exists, else written by the autotuner")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the search shards by sky "
@@ -89,6 +95,15 @@ def main():
 
     torch.cuda.set_device(0)
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    if args.copy_calibration_mb:
+        # a plain copy kernel moving a known number of bytes: out = x * 1 (reads and writes N*4 B)
+        nel = args.copy_calibration_mb * (1 << 20) // 4
+        xc = torch.ones(nel, dtype=torch.float32, device="cuda")
+        yc = torch.empty_like(xc)
+        torch.mul(xc, 1.0, out=yc)
+        torch.cuda.synchronize()
+        del xc, yc
+        log(f"copy calibration: {args.copy_calibration_mb} MiB read and written")
 
     # ---------------- mixed-precision batched workload
     w = synth.workload(3, args.nsky, args.nfdot)
@@ -97,9 +112,19 @@ def main():
     al, de, fd = dev(w.alpha), dev(w.delta), dev(w.fdot)
     templates = args.nsky * args.nfdot
     cap = int(max(1 << 20, 3.0 * 5.0e-4 * (nfft // 2) * templates * max(args.steps, 1)))
-    plan = F.Plan([F.segment_to_device(seg)], candidate_capacity=cap,
+    fixed = bool(args.templates_per_launch or args.skies_per_batch or args.no_autotune)
+    cache = args.tuning_cache or None
+    have_cache = bool(cache) and os.path.exists(cache)
+    plan = F.Plan([F.segment_to_device(seg)], candidate_capacity=cap, workspace_from_torch=False,
                   templates_per_launch=args.templates_per_launch, skies_per_batch=args.skies_per_batch,
-                  use_graph=0 if args.no_graph else 1)
+                  use_graph=0 if args.no_graph else 1, tuning_cache_path=cache)
+    tuned = "fixed" if fixed else ("cache" if have_cache else "autotune")
+    if tuned == "autotune":
+        t_tune = time.perf_counter()
+        plan.autotune(0, budget_ms=args.autotune_ms)
+        log(f"autotune {time.perf_counter() - t_tune:.1f} s -> {plan.info(0)}")
+    else:
+        plan._set_torch_workspace()
     info = plan.info(0)
     log(f"plan {info}, capacity {cap}")
     for i in range(args.warmup):
@@ -139,7 +164,7 @@ def main():
         avg_s = kernels[dom]["avg_ms"] / 1e3
         achieved = algo[dom] / avg_s / 1e9
         roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, B),
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, B, info["pass_a_variant"]),
                     "algorithmic_bytes_per_launch": algo[dom], "templates_per_launch": B,
                     "avg_launch_ms": kernels[dom]["avg_ms"]}
         for k in ("template_a", "template_b"):
@@ -206,9 +231,11 @@ def main():
         "config": {"workload": f"mixed-precision batched search, N={N}, nfft=2^{int(math.log2(nfft))}, "
                                f"{args.nsky} sky x {args.nfdot} spindown, 5 injections, 2F>20",
                    "n": N, "nfft": nfft, "nsky": args.nsky, "nfdot": args.nfdot, "templates": templates,
-                   "templates_per_launch": B, "skies_per_batch": info["skies_per_batch"]},
+                   "templates_per_launch": B, "skies_per_batch": info["skies_per_batch"],
+                   "pass_a_variant": info["pass_a_variant"], "tuning": tuned},
         "roofline": roofline, "cpu_baseline": cpu, "plain": plain,
         "f_rel_err_vs_fp64": f_err, "candidates_per_step": n_cand / args.steps, "kernels": kernels,
+        "source_sha256": source_digest(),
     }
     print(json.dumps(out), flush=True)
 

@@ -1,0 +1,106 @@
+"""Summaries of rocprofv3 result databases (SQLite, as written by rocprofv3 on ROCm 7).
+
+    python -m paper_1410_3677_amd.rocprof_summary trace RESULTS.db [--match k_tmpl]
+        per-kernel dispatch statistics (calls, total, average, min, max duration) as markdown
+
+    python -m paper_1410_3677_amd.rocprof_summary traffic FETCH.db WRITE.db --copy-bytes B \
+            --copy-match MulFunctor --templates-per-launch T [--json OUT]
+        average FETCH_SIZE / WRITE_SIZE per dispatch of each kernel, scaled by what the
+        same counters read for a plain copy kernel that moves a known number of bytes
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import json
+import sqlite3
+import sys
+
+
+def _short(name: str) -> str:
+    n = name.split("(")[0]
+    return n.replace("void ", "").replace("fstat::", "")
+
+
+def trace(db: str, match: str = ""):
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, count(*), sum(duration), avg(duration), min(duration), max(duration) "
+                     "from kernels group by name order by sum(duration) desc").fetchall()
+    out = ["| kernel | calls | total (us) | avg (us) | min (us) | max (us) |", "|---|---|---|---|---|---|"]
+    for name, n, tot, avg, mn, mx in rows:
+        if match and match not in name:
+            continue
+        out.append(f"| `{_short(name)}` | {n} | {tot / 1e3:.1f} | {avg / 1e3:.2f} | {mn / 1e3:.2f} | {mx / 1e3:.2f} |")
+    return "\n".join(out)
+
+
+def counter_means(db: str, counter: str):
+    """Average value of `counter` per dispatch, by kernel name (summed over hardware instances)."""
+    c = sqlite3.connect(db)
+    rows = c.execute("select dispatch_id, kernel_name, sum(value) from counters_collection "
+                     "where counter_name = ? group by dispatch_id", (counter,)).fetchall()
+    acc = collections.defaultdict(list)
+    for _, k, v in rows:
+        acc[k].append(v)
+    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+
+def traffic(fetch_db: str, write_db: str, copy_bytes: int, copy_match: str, tpl: int):
+    fetch = counter_means(fetch_db, "FETCH_SIZE")
+    write = counter_means(write_db, "WRITE_SIZE")
+    copy_f = [v for k, (v, n) in fetch.items() if copy_match in k]
+    copy_w = [v for k, (v, n) in write.items() if copy_match in k]
+    if not copy_f or not copy_w:
+        raise SystemExit(f"no dispatch matching {copy_match!r} for the copy calibration")
+    # counters are in KiB; scale = true bytes / (counter KiB * 1024)
+    sf = copy_bytes / (max(copy_f) * 1024.0)
+    sw = copy_bytes / (max(copy_w) * 1024.0)
+    res = {"copy_bytes": copy_bytes, "fetch_scale": sf, "write_scale": sw, "kernels": {}}
+    for k in sorted(set(fetch) | set(write)):
+        if "k_tmpl" not in k and "k_spline" not in k and "k_fft" not in k and "k_sky" not in k:
+            continue
+        f_kib = fetch.get(k, (0.0, 0))[0]
+        w_kib = write.get(k, (0.0, 0))[0]
+        short = _short(k)
+        key = ("template_a" if short.startswith("k_tmpl_a") else
+               "template_b" if short.startswith("k_tmpl_b") else short)
+        res["kernels"][key] = {"kernel": short, "fetch_kib_raw": f_kib, "write_kib_raw": w_kib,
+                               "fetch_bytes": f_kib * 1024 * sf, "write_bytes": w_kib * 1024 * sw,
+                               "bytes_per_launch": f_kib * 1024 * sf + w_kib * 1024 * sw,
+                               "templates_per_launch": tpl if key.startswith("template") else None}
+    return res
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("db")
+    t.add_argument("--match", default="")
+    f = sub.add_parser("traffic")
+    f.add_argument("fetch_db")
+    f.add_argument("write_db")
+    f.add_argument("--copy-bytes", type=int, required=True)
+    f.add_argument("--copy-match", default="MulFunctor")
+    f.add_argument("--templates-per-launch", type=int, required=True)
+    f.add_argument("--json", default="")
+    f.add_argument("--source-sha256", default="")
+    f.add_argument("--pass-a-variant", type=int, default=-1)
+    a = ap.parse_args(argv)
+    if a.cmd == "trace":
+        print(trace(a.db, a.match))
+    else:
+        res = traffic(a.fetch_db, a.write_db, a.copy_bytes, a.copy_match, a.templates_per_launch)
+        if a.source_sha256:
+            res["source_sha256"] = a.source_sha256
+        if a.pass_a_variant >= 0:
+            res["pass_a_variant"] = a.pass_a_variant
+        text = json.dumps(res, indent=1)
+        if a.json:
+            with open(a.json, "w") as fh:
+                fh.write(text + "\n")
+        print(text)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
