@@ -181,6 +181,26 @@ def cw_signal(inj: Injection, n: int, dt: float, f_off: float, r: np.ndarray,
     return fp * hp + fx * hx
 
 
+def cw_basis(inj: Injection, n: int, dt: float, f_off: float, r: np.ndarray,
+             lat: float = DET_LAT, gamma: float = DET_GAMMA, phi_r: float = DET_PHI_R) -> np.ndarray:
+    """The four waveforms whose combination is any signal of this sky position,
+    frequency and spindown: F+(psi=0) cos(phase), Fx(psi=0) cos(phase),
+    F+(psi=0) sin(phase), Fx(psi=0) sin(phase), with the heterodyned phase of
+    cw_signal without phi0.  A signal with amplitudes (A1, A2, A3, A4) is
+    sum_mu A_mu basis[mu]; shape (4, n)."""
+    t = np.arange(n, dtype=np.float64) * dt
+    k = np.array([math.cos(inj.delta) * math.cos(inj.alpha),
+                  math.cos(inj.delta) * math.sin(inj.alpha), math.sin(inj.delta)])
+    delay = k @ r - k @ r[:, 0]
+    tau = t + delay
+    cyc = f_off * delay + inj.f * tau + 0.5 * inj.fdot * tau * tau
+    cyc = cyc - np.floor(cyc)
+    phase = 2.0 * math.pi * cyc
+    fp, fx = antenna_response(t, inj.alpha, inj.delta, 0.0, lat, gamma, phi_r)
+    c, s = np.cos(phase), np.sin(phase)
+    return np.stack([fp * c, fx * c, fp * s, fx * s])
+
+
 # --- segments ---------------------------------------------------------------------
 @dataclasses.dataclass
 class Segment:
