@@ -91,8 +91,10 @@ typedef struct {
 typedef struct { double f_hz, fdot, alpha, delta, twoF; } fstat_candidate;
 
 /* Integer key of a candidate: which search call, segment, sky index, spindown
- * index and frequency bin produced it; bins are f_hz = f_off + bin/(nfft dt). */
-typedef struct { int32_t search, segment, sky, fdot_idx, bin, reserved; } fstat_candidate_key;
+ * index and frequency bin produced it; bins are f_hz = f_off + bin/(nfft dt).
+ * vet_score is the vetting network's score in (0, 1) after
+ * fstat_plan_vet_candidates, NaN otherwise. */
+typedef struct { int32_t search, segment, sky, fdot_idx, bin; float vet_score; } fstat_candidate_key;
 
 /* Fill *opt with defaults: nfft 0, all bins, threshold 20, MIXED, SIMPLIFIED,
  * capacity 1<<24, no budget, library-chosen batching, graphs on. */
@@ -187,14 +189,64 @@ fstat_status fstat_plan_info(fstat_plan_t plan, int32_t segment, int32_t* nfft, 
  * and append it to options.tuning_cache_path if set (one line per device,
  * FFT length and precision).  Runs synchronously on `stream` for roughly
  * budget_ms.  Must be called before fstat_plan_set_workspace: the workspace
- * size changes with the batch sizes (query it again afterwards).  Candidates
- * found by the trial searches are discarded. */
+ * size changes with the batch sizes (query it again afterwards), and before
+ * fstat_plan_attach_vetter.  Candidates found by the trial searches are
+ * discarded. */
 fstat_status fstat_autotune(fstat_plan_t plan, int32_t segment, double budget_ms, void* stream);
 
 /* Release the plan and everything it owns (waits for its work first).
  * NULL is accepted; a second destroy of the same handle is undefined, as
  * for free(). */
 fstat_status fstat_destroy(fstat_plan_t plan);
+
+/* ---- Candidate vetting (a learned score for threshold crossings; not part of
+ * the paper's method, whose threshold stays the fallback) -------------------
+ * The network scores the 256-bin 2F window centred on a crossing:
+ *   u = log(1 + 2F) - log 5; three "same" convolutions of width 7 with 32
+ *   channels and ReLU (1 -> 32 -> 32 -> 32); flattened position-major
+ *   (x[p*32 + c]); dense 8192 -> 128 -> 128 -> 1 with ReLU; logit.
+ * Parameters are one FP32 vector (the master copy), in the order w1[32][1][7],
+ * b1[32], w2[32][32][7], b2, w3[32][32][7], b3, w4[128][8192], b4[128],
+ * w5[128][128], b5, w6[1][128], b6[1]; the matrix products use BF16 copies of
+ * weights and activations with FP32 accumulation. */
+typedef struct fstat_vet_s* fstat_vet_t;
+
+/* Number of parameters (1 080 001). */
+int64_t fstat_vet_param_count(void);
+
+/* A network for batches of up to max_batch patches, parameters zero until set. */
+fstat_status fstat_vet_create(int32_t max_batch, fstat_vet_t* out);
+
+/* Host FP32 parameter vector in and out (n = fstat_vet_param_count()); setting
+ * resets the optimiser state. */
+fstat_status fstat_vet_set_params(fstat_vet_t vet, const float* params, int64_t n);
+fstat_status fstat_vet_get_params(fstat_vet_t vet, float* params, int64_t n);
+
+/* Logits of n patches (device [n][256] 2F values) into device logits[n]; any n
+ * (processed in batches of max_batch).  Asynchronous on `stream`. */
+fstat_status fstat_vet_forward(fstat_vet_t vet, const float* patches, int64_t n, float* logits, void* stream);
+
+/* Mean binary cross-entropy of n <= max_batch patches with device labels[n]
+ * (0 or 1) and its gradient.  loss (device, 1 float) and grad (device, param
+ * count floats) may be NULL; the gradient is kept for fstat_vet_adam_step. */
+fstat_status fstat_vet_gradient(fstat_vet_t vet, const float* patches, const float* labels, int64_t n,
+                                float* loss, float* grad, void* stream);
+
+/* One Adam step with the last gradient (bias-corrected). */
+fstat_status fstat_vet_adam_step(fstat_vet_t vet, float lr, float beta1, float beta2, float eps, void* stream);
+
+fstat_status fstat_vet_destroy(fstat_vet_t vet);
+
+/* Attach a network to a plan: from now on every search also stores, right after
+ * each F kernel launch, the 256-bin 2F window of each new crossing (up to
+ * patch_capacity <= candidate_capacity crossings per drain).  NULL detaches.
+ * The plan keeps using the network until it is detached or the plan destroyed. */
+fstat_status fstat_plan_attach_vetter(fstat_plan_t plan, fstat_vet_t vet, int64_t patch_capacity);
+
+/* Score the stored windows of the crossings found since the last drain with the
+ * attached network (asynchronous on `stream`); fstat_candidates then reports the
+ * scores in the keys (NaN for crossings beyond patch_capacity). */
+fstat_status fstat_plan_vet_candidates(fstat_plan_t plan, void* stream);
 
 /* Static text for a status code. */
 const char* fstat_strerror(fstat_status status);

@@ -14,6 +14,7 @@
 #include "../../include/fstat.h"
 #include "fstat_kernels.hpp"
 #include "fstat_tmpl.hpp"
+#include "fstat_vet.hpp"
 
 using namespace fstat;
 
@@ -66,6 +67,17 @@ struct Tables {
 
 }  // namespace
 
+struct fstat_vet_s {
+  int max_batch = 0;
+  int steps = 0;                 // Adam steps taken
+  void* mem = nullptr;           // one allocation for everything below
+  float *theta = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
+  uint16_t *wf2, *wt2, *wf3, *wt3, *w4b, *w5b;
+  float *u, *z1, *z2, *z3, *z4, *z5, *a5, *logit, *dlogit, *lterm, *dz5, *dh4, *dx, *da, *dwm, *loss;
+  uint16_t *a1b, *a2b, *a3b, *a4b, *colA, *colB, *colC, *dz5b, *dz4b, *dzb;
+  std::string last_error;
+};
+
 struct fstat_plan_s {
   std::vector<SegInfo> segs;
   fstat_options opt;
@@ -91,6 +103,13 @@ struct fstat_plan_s {
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::vector<GraphEntry> graphs;
+  // candidate vetting: patch capture after the F kernel
+  fstat_vet_t vet = nullptr;
+  long long patch_capacity = 0;
+  float* d_patches = nullptr;    // [patch_capacity][256]
+  float* d_spec = nullptr;       // the current launch's 2F rows [B][k_max - k_min]
+  unsigned long long* d_first = nullptr;
+  bool scored = false;
   std::vector<SearchRecord> searches;
   hipStream_t last_stream = nullptr;
   bool used_stream = false;
@@ -397,13 +416,21 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
       });
     }
     HIP_TRY(p, err, "template pass A launch");
+    const bool capture = (mode == 0 && p->vet != nullptr);
+    if (capture) {
+      hipLaunchKernelGGL(k_record_count, dim3(1), dim3(1), 0, st, p->d_count, p->d_first);
+      oa.spectrum = p->d_spec;
+    }
     {
       ProfScope ps(p, FSTAT_KERNEL_TEMPLATE_B, st);
       with_len(si.P, [&](auto c) {
         constexpr int PP = decltype(c)::value;
         if constexpr (PP >= 64) {
           const int ntiles = si.Q / tw_b<T, PP>();
-          if (mode == 0)
+          if (capture)
+            hipLaunchKernelGGL((k_tmpl_b<T, PP, 2>), dim3(ntiles * nt), dim3(tmpl_nt_b<T, PP>()), 0, st, ta, d.sp(),
+                               tbuf, oa, d.twst);
+          else if (mode == 0)
             hipLaunchKernelGGL((k_tmpl_b<T, PP, 0>), dim3(ntiles * nt), dim3(tmpl_nt_b<T, PP>()), 0, st, ta, d.sp(),
                                tbuf, oa, d.twst);
           else
@@ -416,6 +443,12 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
       });
     }
     HIP_TRY(p, err, "template pass B launch");
+    if (capture) {
+      hipLaunchKernelGGL(k_capture_patches, dim3(2048), dim3(256), 0, st, p->d_cand, p->d_spec, p->d_patches,
+                         (unsigned long long)p->patch_capacity, p->d_count, p->d_first, oa.k_min, oa.k_max, t0,
+                         nfdot, sky0);
+      HIP_TRY(p, hipGetLastError(), "patch capture launch");
+    }
   }
   return FSTAT_OK;
 }
@@ -574,6 +607,271 @@ static bool cache_lookup(const char* path, const std::string& tag, long nfft, in
   }
   std::fclose(f);
   return found;
+}
+
+// ------------------------------------------------------------------ vetting network
+namespace {
+inline dim3 blocks_for(long count, int per = 256) { return dim3((unsigned)((count + per - 1) / per)); }
+
+fstat_status vet_fail(fstat_vet_t v, fstat_status st, const std::string& msg) {
+  if (v) v->last_error = msg;
+  else g_last_error = msg;
+  return st;
+}
+
+#define VET_TRY(v, expr, what)                                                        \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return vet_fail(v, e_ == hipErrorOutOfMemory ? FSTAT_E_NOMEM : FSTAT_E_DEVICE,  \
+                      std::string(what) + ": " + hipGetErrorString(e_));              \
+  } while (0)
+
+// C[m][n] = sum_k A(m, k) B(k, n) on the matrix cores
+void gemm(hipStream_t st, int M, int N, int K, const uint16_t* A, long sam, long sak, const uint16_t* B, long sbk,
+          long sbn, float* Cm, long ldc) {
+  dim3 grid((N + 63) / 64, (M + 63) / 64);
+  hipLaunchKernelGGL(vet::k_gemm_bf16, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, Cm, ldc, 1.0f,
+                     0.0f);
+}
+
+__global__ void k_vet_store_scores(CandEntry* cand, const float* logit, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float s = 1.f / (1.f + expf(-logit[i]));
+  cand[i].pad = __float_as_int(s);
+}
+
+void vet_prepare(fstat_vet_t v, hipStream_t st) {
+  hipLaunchKernelGGL(vet::k_vet_prepare, blocks_for((long)vet::H * vet::X), dim3(256), 0, st, v->theta, v->wf2,
+                     v->wt2, v->wf3, v->wt3, v->w4b, v->w5b);
+}
+
+// forward of n <= max_batch patches; logits to `out`
+void vet_forward_batch(fstat_vet_t v, const float* patches, int n, float* out, hipStream_t st) {
+  using namespace vet;
+  const long NL = (long)n * L;
+  hipLaunchKernelGGL(k_vet_conv1, blocks_for(NL * C), dim3(256), 0, st, patches, n, v->theta, v->u, v->z1, v->a1b);
+  hipLaunchKernelGGL(k_vet_im2col, blocks_for(NL * KC), dim3(256), 0, st, v->a1b, n, 1, v->colA);
+  gemm(st, (int)NL, C, KC, v->colA, KC, 1, v->wf2, C, 1, v->z2, C);
+  hipLaunchKernelGGL(k_vet_bias_relu, blocks_for(NL * C), dim3(256), 0, st, v->z2, NL, C, v->theta + O_B2, v->a2b,
+                     (float*)nullptr);
+  hipLaunchKernelGGL(k_vet_im2col, blocks_for(NL * KC), dim3(256), 0, st, v->a2b, n, 1, v->colB);
+  gemm(st, (int)NL, C, KC, v->colB, KC, 1, v->wf3, C, 1, v->z3, C);
+  hipLaunchKernelGGL(k_vet_bias_relu, blocks_for(NL * C), dim3(256), 0, st, v->z3, NL, C, v->theta + O_B3, v->a3b,
+                     (float*)nullptr);
+  gemm(st, n, H, X, v->a3b, X, 1, v->w4b, 1, X, v->z4, H);
+  hipLaunchKernelGGL(k_vet_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->z4, (long)n, H, v->theta + O_B4,
+                     v->a4b, (float*)nullptr);
+  gemm(st, n, H, H, v->a4b, H, 1, v->w5b, 1, H, v->z5, H);
+  hipLaunchKernelGGL(k_vet_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->z5, (long)n, H, v->theta + O_B5,
+                     (uint16_t*)nullptr, v->a5);
+  hipLaunchKernelGGL(k_vet_fc3, blocks_for(n), dim3(256), 0, st, v->a5, n, v->theta, out);
+}
+
+void vet_backward(fstat_vet_t v, const float* labels, int n, hipStream_t st) {
+  using namespace vet;
+  const long NL = (long)n * L;
+  float* g = v->grad;
+  hipLaunchKernelGGL(k_vet_head_backward, blocks_for(n), dim3(256), 0, st, v->logit, labels, n, v->theta, v->z5,
+                     v->a5, v->dz5, v->dz5b, v->dlogit, v->lterm);
+  hipLaunchKernelGGL(k_vet_head_reduce, dim3(1), dim3(H + 1), 0, st, v->dlogit, v->a5, v->lterm, n, g, v->loss);
+  gemm(st, H, H, n, v->dz5b, 1, H, v->a4b, H, 1, g + O_W5, H);                 // dW5 = dz5^T a4
+  hipLaunchKernelGGL(k_vet_colsum, dim3(1), dim3(H), 0, st, v->dz5, (long)n, H, g + O_B5);
+  gemm(st, n, H, H, v->dz5b, H, 1, v->w5b, H, 1, v->dh4, H);                   // dh4 = dz5 W5
+  hipLaunchKernelGGL(k_vet_relu_mask, blocks_for((long)n * H), dim3(256), 0, st, v->dh4, v->z4, (long)n * H, v->dz4b);
+  gemm(st, H, X, n, v->dz4b, 1, H, v->a3b, X, 1, g + O_W4, X);                 // dW4 = dz4^T x
+  hipLaunchKernelGGL(k_vet_colsum, dim3(1), dim3(H), 0, st, v->dh4, (long)n, H, g + O_B4);
+  gemm(st, n, X, H, v->dz4b, H, 1, v->w4b, X, 1, v->dx, X);                    // dx = dz4 W4
+  hipLaunchKernelGGL(k_vet_relu_mask, blocks_for(NL * C), dim3(256), 0, st, v->dx, v->z3, NL * C, v->dzb);
+  gemm(st, KC, C, (int)NL, v->colB, 1, KC, v->dzb, C, 1, v->dwm, C);            // dW3 (im2col layout)
+  hipLaunchKernelGGL(k_vet_scatter_conv_grad, blocks_for(C * C * KW), dim3(256), 0, st, v->dwm, g + O_W3);
+  hipLaunchKernelGGL(k_vet_colsum, dim3(1), dim3(C), 0, st, v->dx, NL, C, g + O_B3);
+  hipLaunchKernelGGL(k_vet_im2col, blocks_for(NL * KC), dim3(256), 0, st, v->dzb, n, -1, v->colC);
+  gemm(st, (int)NL, C, KC, v->colC, KC, 1, v->wt3, C, 1, v->da, C);             // da2
+  hipLaunchKernelGGL(k_vet_relu_mask, blocks_for(NL * C), dim3(256), 0, st, v->da, v->z2, NL * C, v->dzb);
+  gemm(st, KC, C, (int)NL, v->colA, 1, KC, v->dzb, C, 1, v->dwm, C);            // dW2
+  hipLaunchKernelGGL(k_vet_scatter_conv_grad, blocks_for(C * C * KW), dim3(256), 0, st, v->dwm, g + O_W2);
+  hipLaunchKernelGGL(k_vet_colsum, dim3(1), dim3(C), 0, st, v->da, NL, C, g + O_B2);
+  hipLaunchKernelGGL(k_vet_im2col, blocks_for(NL * KC), dim3(256), 0, st, v->dzb, n, -1, v->colC);
+  gemm(st, (int)NL, C, KC, v->colC, KC, 1, v->wt2, C, 1, v->da, C);             // da1
+  hipLaunchKernelGGL(k_vet_relu_mask, blocks_for(NL * C), dim3(256), 0, st, v->da, v->z1, NL * C, v->dzb);
+  hipLaunchKernelGGL(k_vet_conv1_backward, dim3(C), dim3(KW + 1), 0, st, v->da, v->u, n, g);
+}
+}  // namespace
+
+int64_t fstat_vet_param_count(void) { return vet::N_PARAMS; }
+
+fstat_status fstat_vet_create(int32_t max_batch, fstat_vet_t* out) {
+  using namespace vet;
+  if (!out) return vet_fail(nullptr, FSTAT_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (max_batch < 1 || max_batch > 8192) return vet_fail(nullptr, FSTAT_E_INVAL, "max_batch outside [1, 8192]");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return vet_fail(nullptr, FSTAT_E_DEVICE, "no HIP device");
+  auto v = new (std::nothrow) fstat_vet_s();
+  if (!v) return vet_fail(nullptr, FSTAT_E_NOMEM, "vetter allocation");
+  v->max_batch = max_batch;
+  const size_t nb = (size_t)max_batch, NL = nb * L;
+  struct Part { void** p; size_t bytes; };
+  std::vector<Part> parts = {
+      {(void**)&v->theta, N_PARAMS * 4}, {(void**)&v->grad, N_PARAMS * 4}, {(void**)&v->m1, N_PARAMS * 4},
+      {(void**)&v->m2, N_PARAMS * 4}, {(void**)&v->wf2, KC * C * 2}, {(void**)&v->wt2, KC * C * 2},
+      {(void**)&v->wf3, KC * C * 2}, {(void**)&v->wt3, KC * C * 2}, {(void**)&v->w4b, (size_t)H * X * 2},
+      {(void**)&v->w5b, H * H * 2}, {(void**)&v->u, NL * 4}, {(void**)&v->z1, NL * C * 4},
+      {(void**)&v->z2, NL * C * 4}, {(void**)&v->z3, NL * C * 4}, {(void**)&v->z4, nb * H * 4},
+      {(void**)&v->z5, nb * H * 4}, {(void**)&v->a5, nb * H * 4}, {(void**)&v->logit, nb * 4},
+      {(void**)&v->dlogit, nb * 4}, {(void**)&v->lterm, nb * 4}, {(void**)&v->dz5, nb * H * 4},
+      {(void**)&v->dh4, nb * H * 4}, {(void**)&v->dx, NL * C * 4}, {(void**)&v->da, NL * C * 4},
+      {(void**)&v->dwm, KC * C * 4}, {(void**)&v->loss, 4}, {(void**)&v->a1b, NL * C * 2},
+      {(void**)&v->a2b, NL * C * 2}, {(void**)&v->a3b, NL * C * 2}, {(void**)&v->a4b, nb * H * 2},
+      {(void**)&v->colA, NL * KC * 2}, {(void**)&v->colB, NL * KC * 2}, {(void**)&v->colC, NL * KC * 2},
+      {(void**)&v->dz5b, nb * H * 2}, {(void**)&v->dz4b, nb * H * 2}, {(void**)&v->dzb, NL * C * 2}};
+  size_t total = 0;
+  for (auto& pt : parts) total = align256(total + pt.bytes);
+  hipError_t e = hipMalloc(&v->mem, total);
+  if (e != hipSuccess) {
+    delete v;
+    return vet_fail(nullptr, e == hipErrorOutOfMemory ? FSTAT_E_NOMEM : FSTAT_E_DEVICE, "vetter device memory");
+  }
+  size_t off = 0;
+  for (auto& pt : parts) {
+    *pt.p = (char*)v->mem + off;
+    off = align256(off + pt.bytes);
+  }
+  if ((e = hipMemset(v->mem, 0, total)) != hipSuccess) {
+    (void)hipFree(v->mem);
+    delete v;
+    return vet_fail(nullptr, FSTAT_E_DEVICE, "vetter memset");
+  }
+  *out = v;
+  return FSTAT_OK;
+}
+
+fstat_status fstat_vet_set_params(fstat_vet_t v, const float* params, int64_t n) {
+  if (!v || !params || n != vet::N_PARAMS) return vet_fail(v, FSTAT_E_INVAL, "bad arguments");
+  VET_TRY(v, hipMemcpy(v->theta, params, n * 4, hipMemcpyHostToDevice), "parameter copy");
+  VET_TRY(v, hipMemset(v->m1, 0, n * 4), "optimiser reset");
+  VET_TRY(v, hipMemset(v->m2, 0, n * 4), "optimiser reset");
+  v->steps = 0;
+  vet_prepare(v, nullptr);
+  VET_TRY(v, hipGetLastError(), "weight preparation");
+  VET_TRY(v, hipDeviceSynchronize(), "weight preparation");
+  return FSTAT_OK;
+}
+
+fstat_status fstat_vet_get_params(fstat_vet_t v, float* params, int64_t n) {
+  if (!v || !params || n != vet::N_PARAMS) return vet_fail(v, FSTAT_E_INVAL, "bad arguments");
+  VET_TRY(v, hipDeviceSynchronize(), "synchronize");
+  VET_TRY(v, hipMemcpy(params, v->theta, n * 4, hipMemcpyDeviceToHost), "parameter copy");
+  return FSTAT_OK;
+}
+
+fstat_status fstat_vet_forward(fstat_vet_t v, const float* patches, int64_t n, float* logits, void* stream) {
+  if (!v || n < 0 || (n > 0 && (!patches || !logits))) return vet_fail(v, FSTAT_E_INVAL, "bad arguments");
+  hipStream_t st = (hipStream_t)stream;
+  for (int64_t i = 0; i < n; i += v->max_batch) {
+    const int b = (int)std::min<int64_t>(v->max_batch, n - i);
+    vet_forward_batch(v, patches + i * vet::L, b, logits + i, st);
+    VET_TRY(v, hipGetLastError(), "forward launch");
+  }
+  return FSTAT_OK;
+}
+
+fstat_status fstat_vet_gradient(fstat_vet_t v, const float* patches, const float* labels, int64_t n, float* loss,
+                                float* grad, void* stream) {
+  if (!v || !patches || !labels || n < 1 || n > v->max_batch) return vet_fail(v, FSTAT_E_INVAL, "bad arguments");
+  hipStream_t st = (hipStream_t)stream;
+  vet_forward_batch(v, patches, (int)n, v->logit, st);
+  vet_backward(v, labels, (int)n, st);
+  VET_TRY(v, hipGetLastError(), "gradient launch");
+  if (loss) VET_TRY(v, hipMemcpyAsync(loss, v->loss, 4, hipMemcpyDeviceToDevice, st), "loss copy");
+  if (grad) VET_TRY(v, hipMemcpyAsync(grad, v->grad, vet::N_PARAMS * 4, hipMemcpyDeviceToDevice, st), "grad copy");
+  return FSTAT_OK;
+}
+
+fstat_status fstat_vet_adam_step(fstat_vet_t v, float lr, float beta1, float beta2, float eps, void* stream) {
+  if (!v || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return vet_fail(v, FSTAT_E_INVAL, "bad arguments");
+  hipStream_t st = (hipStream_t)stream;
+  v->steps += 1;
+  const double step = lr * std::sqrt(1.0 - std::pow((double)beta2, v->steps)) / (1.0 - std::pow((double)beta1, v->steps));
+  hipLaunchKernelGGL(vet::k_vet_adam, blocks_for(vet::N_PARAMS), dim3(256), 0, st, v->theta, v->grad, v->m1, v->m2,
+                     (long)vet::N_PARAMS, (float)step, beta1, beta2, eps);
+  vet_prepare(v, st);
+  VET_TRY(v, hipGetLastError(), "optimiser launch");
+  return FSTAT_OK;
+}
+
+fstat_status fstat_vet_destroy(fstat_vet_t v) {
+  if (!v) return FSTAT_OK;
+  (void)hipDeviceSynchronize();
+  if (v->mem) (void)hipFree(v->mem);
+  delete v;
+  return FSTAT_OK;
+}
+
+static void drop_graphs(fstat_plan_t plan) {
+  if (plan->gstream) (void)hipStreamSynchronize(plan->gstream);
+  for (auto& ge : plan->graphs) {
+    if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
+    if (ge.graph) (void)hipGraphDestroy(ge.graph);
+  }
+  plan->graphs.clear();
+}
+
+fstat_status fstat_plan_attach_vetter(fstat_plan_t plan, fstat_vet_t vet, int64_t patch_capacity) {
+  if (!plan) return fail(plan, FSTAT_E_INVAL, "NULL plan");
+  drop_graphs(plan);  // captured searches do not contain the patch capture
+  (void)hipDeviceSynchronize();
+  if (plan->d_patches) (void)hipFree(plan->d_patches);
+  if (plan->d_spec) (void)hipFree(plan->d_spec);
+  if (plan->d_first) (void)hipFree(plan->d_first);
+  plan->d_patches = nullptr;
+  plan->d_spec = nullptr;
+  plan->d_first = nullptr;
+  plan->vet = nullptr;
+  plan->patch_capacity = 0;
+  if (!vet) return FSTAT_OK;
+  if (patch_capacity < 1 || patch_capacity > plan->opt.candidate_capacity)
+    return fail(plan, FSTAT_E_INVAL, "patch_capacity outside [1, candidate_capacity]");
+  long nbins = 0;
+  for (auto& si : plan->segs) nbins = std::max(nbins, (long)(si.kmax - si.kmin));
+  HIP_TRY(plan, hipMalloc((void**)&plan->d_patches, (size_t)patch_capacity * 256 * sizeof(float)), "patch store");
+  HIP_TRY(plan, hipMalloc((void**)&plan->d_spec, (size_t)plan->B * nbins * sizeof(float)), "launch spectrum buffer");
+  HIP_TRY(plan, hipMalloc((void**)&plan->d_first, sizeof(unsigned long long)), "count copy");
+  plan->vet = vet;
+  plan->patch_capacity = patch_capacity;
+  return FSTAT_OK;
+}
+
+fstat_status fstat_plan_vet_candidates(fstat_plan_t plan, void* stream) {
+  if (!plan) return fail(plan, FSTAT_E_INVAL, "NULL plan");
+  if (!plan->vet) return fail(plan, FSTAT_E_STATE, "no vetting network attached");
+  hipStream_t st = (hipStream_t)stream;
+  if (plan->used_stream) HIP_TRY(plan, hipStreamSynchronize(plan->last_stream), "stream synchronize");
+  HIP_TRY(plan, hipDeviceSynchronize(), "device synchronize");
+  unsigned long long count = 0;
+  HIP_TRY(plan, hipMemcpy(&count, plan->d_count, sizeof count, hipMemcpyDeviceToHost), "count copy");
+  const long long n = std::min<long long>({(long long)count, plan->opt.candidate_capacity, plan->patch_capacity});
+  if (n > 0) {
+    float* logits = nullptr;
+    HIP_TRY(plan, hipMalloc(&logits, (size_t)n * sizeof(float)), "logits");
+    fstat_status r = fstat_vet_forward(plan->vet, plan->d_patches, n, logits, st);
+    if (r == FSTAT_OK) {
+      hipLaunchKernelGGL(k_vet_store_scores, blocks_for(n), dim3(256), 0, st, plan->d_cand, logits, (long)n);
+      hipError_t e = hipStreamSynchronize(st);
+      if (e != hipSuccess) r = hip_fail(plan, e, "scoring");
+    } else {
+      r = fail(plan, r, std::string("vetting forward: ") + plan->vet->last_error);
+    }
+    (void)hipFree(logits);
+    if (r != FSTAT_OK) return r;
+  }
+  plan->scored = true;
+  plan->last_stream = st;
+  plan->used_stream = true;
+  return FSTAT_OK;
 }
 
 // ------------------------------------------------------------------ C ABI
@@ -882,6 +1180,7 @@ fstat_status fstat_candidates(fstat_plan_t plan, fstat_candidate* out, fstat_can
   const long long stored = std::min<long long>((long long)count, plan->opt.candidate_capacity);
   if (!out && !keys) {
     // count-only drain: nothing is copied or sorted
+    plan->scored = false;
     HIP_TRY(plan, hipMemset(plan->d_count, 0, sizeof(unsigned long long)), "count reset");
     for (auto& sr : plan->searches) (void)hipHostFree(sr.host);
     plan->searches.clear();
@@ -911,7 +1210,9 @@ fstat_status fstat_candidates(fstat_plan_t plan, fstat_candidate* out, fstat_can
       keys[i].sky = c.sky;
       keys[i].fdot_idx = c.fdot_idx;
       keys[i].bin = c.bin;
-      keys[i].reserved = 0;
+      float score = std::nanf("");
+      if (plan->scored) std::memcpy(&score, &c.pad, sizeof score);
+      keys[i].vet_score = score;
     }
     if (out) {
       const SegInfo& si = plan->segs[c.segment];
@@ -925,6 +1226,7 @@ fstat_status fstat_candidates(fstat_plan_t plan, fstat_candidate* out, fstat_can
   }
   for (auto& sr : plan->searches) (void)hipHostFree(sr.host);
   plan->searches.clear();
+  plan->scored = false;
   *n_found = (int64_t)count;
   if ((long long)count > plan->opt.candidate_capacity || (long long)count > capacity)
     return fail(plan, FSTAT_E_OVERFLOW, "more candidates than buffer capacity");
@@ -989,6 +1291,7 @@ fstat_status fstat_autotune(fstat_plan_t plan, int32_t segment, double budget_ms
   if (!plan || segment < 0 || segment >= (int32_t)plan->segs.size() || !(budget_ms > 0))
     return fail(plan, FSTAT_E_INVAL, "bad arguments");
   if (plan->ws && !plan->ws_owned) return fail(plan, FSTAT_E_STATE, "autotune must precede fstat_plan_set_workspace");
+  if (plan->vet) return fail(plan, FSTAT_E_STATE, "autotune must precede fstat_plan_attach_vetter");
   hipStream_t st = (hipStream_t)stream;
   const SegInfo& si = plan->segs[segment];
   // trial template lists: 32 sky positions spread over the sphere, 256 spindowns
@@ -1108,6 +1411,9 @@ fstat_status fstat_destroy(fstat_plan_t plan) {
   if (plan->d_cand) (void)hipFree(plan->d_cand);
   if (plan->d_count) (void)hipFree(plan->d_count);
   if (plan->d_search_next) (void)hipFree(plan->d_search_next);
+  if (plan->d_patches) (void)hipFree(plan->d_patches);
+  if (plan->d_spec) (void)hipFree(plan->d_spec);
+  if (plan->d_first) (void)hipFree(plan->d_first);
   for (auto& ge : plan->graphs) {
     if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
     if (ge.graph) (void)hipGraphDestroy(ge.graph);

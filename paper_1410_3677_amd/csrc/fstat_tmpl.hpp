@@ -335,6 +335,21 @@ __global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a_pair(TmplArgs ta, con
   }
 }
 
+// 2F = cfa |Fa|^2 + cfb |Fb|^2 + cfab Re(Fa Fb*) with every rounding spelled out, so that
+// the threshold, the spectrum store and the patch capture see bitwise the same value.
+__device__ __forceinline__ float two_f_value(cx<float> fa, cx<float> fb, float cfa, float cfb, float cfab) {
+  const float na = __fmaf_rn(fa.re, fa.re, __fmul_rn(fa.im, fa.im));
+  const float nb = __fmaf_rn(fb.re, fb.re, __fmul_rn(fb.im, fb.im));
+  const float xr = __fmaf_rn(fa.re, fb.re, __fmul_rn(fa.im, fb.im));
+  return __fmaf_rn(cfa, na, __fmaf_rn(cfb, nb, __fmul_rn(cfab, xr)));
+}
+__device__ __forceinline__ double two_f_value(cx<double> fa, cx<double> fb, double cfa, double cfb, double cfab) {
+  const double na = __fma_rn(fa.re, fa.re, __dmul_rn(fa.im, fa.im));
+  const double nb = __fma_rn(fb.re, fb.re, __dmul_rn(fb.im, fb.im));
+  const double xr = __fma_rn(fa.re, fb.re, __dmul_rn(fa.im, fb.im));
+  return __fma_rn(cfa, na, __fma_rn(cfb, nb, __dmul_rn(cfab, xr)));
+}
+
 // ---------------------------------------------------------------- pass B
 // Workgroup: TW adjacent rows k2 of one template; thread (c = t / G, g = t % G).
 template <typename T, int P, int MODE>
@@ -388,6 +403,24 @@ __global__ void __launch_bounds__((tmpl_nt_b<T, P>())) k_tmpl_b(TmplArgs ta, con
   stage_from_lds<T, P, G, NSL, RL, PBL, false>(vb, colb, g, twst);
   const SkyParams& pr = sp[skyl];
   const T cfa = (T)pr.cfa, cfb = (T)pr.cfb, cfab = (T)pr.cfab;
+  if constexpr (MODE == 2) {
+    // the launch's 2F rows for the patch capture that follows (template-major, FP32)
+    float* out = (float*)oa.spectrum + (long)item * (long)(oa.k_max - oa.k_min);
+#pragma unroll
+    for (int b = 0; b < PBL; ++b) {
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int klo = ta.Q * (G * b + NSL * r) + k2;
+        if (klo < oa.k_max && klo + ta.Q * (G - 1) >= oa.k_min) {
+          const int k = ta.Q * (g + G * b + NSL * r) + k2;
+          if (k >= oa.k_min && k < oa.k_max) {
+            const cx<T> fa = va[b][r], fb = vb[b][r];
+            out[k - oa.k_min] = (float)two_f_value(fa, fb, cfa, cfb, cfab);
+          }
+        }
+      }
+    }
+  }
   if constexpr (MODE == 1) {
     T* out = (T*)oa.spectrum + ((long)(ta.sky0 + skyl) * ta.nfdot + sidx) * (long)(oa.k_max - oa.k_min);
 #pragma unroll
@@ -397,11 +430,11 @@ __global__ void __launch_bounds__((tmpl_nt_b<T, P>())) k_tmpl_b(TmplArgs ta, con
         const int k = ta.Q * (g + G * b + NSL * r) + k2;
         if (k >= oa.k_min && k < oa.k_max) {
           const cx<T> fa = va[b][r], fb = vb[b][r];
-          out[k - oa.k_min] = cfa * cnorm2(fa) + cfb * cnorm2(fb) + cfab * (fa.re * fb.re + fa.im * fb.im);
+          out[k - oa.k_min] = two_f_value(fa, fb, cfa, cfb, cfab);
         }
       }
     }
-  } else {
+  } else {  // MODE 0 and 2: threshold and compaction
     uint32_t mask = 0;
     T val[NOUT];
 #pragma unroll
@@ -414,7 +447,7 @@ __global__ void __launch_bounds__((tmpl_nt_b<T, P>())) k_tmpl_b(TmplArgs ta, con
         if (klo < oa.k_max && klo + ta.Q * (G - 1) >= oa.k_min) {
           const int k = ta.Q * (g + G * b + NSL * r) + k2;
           const cx<T> fa = va[b][r], fb = vb[b][r];
-          const T v = cfa * cnorm2(fa) + cfb * cnorm2(fb) + cfab * (fa.re * fb.re + fa.im * fb.im);
+          const T v = two_f_value(fa, fb, cfa, cfb, cfab);
           val[b * RL + r] = v;
           if (k >= oa.k_min && k < oa.k_max && v > (T)oa.threshold) mask |= 1u << (b * RL + r);
         }
@@ -445,6 +478,34 @@ __global__ void __launch_bounds__((tmpl_nt_b<T, P>())) k_tmpl_b(TmplArgs ta, con
         ++slot;
       }
     }
+  }
+}
+
+// Count of candidates before a launch (read by the patch capture after it).
+__global__ void k_record_count(const unsigned long long* __restrict__ count, unsigned long long* __restrict__ first) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) first[0] = count[0];
+}
+
+// For each candidate slot written by the launch ([first, min(count, capacity))), copy
+// the 2F window [bin - 128, bin + 128) of its template from the launch's spectrum rows
+// into patches[slot]; bins outside [k_min, k_max) read 0.  One workgroup (256 threads)
+// per patch, grid-stride over the slots.
+__global__ void __launch_bounds__(256) k_capture_patches(const CandEntry* __restrict__ cand,
+                                                         const float* __restrict__ spec, float* __restrict__ patches,
+                                                         unsigned long long patch_capacity,
+                                                         const unsigned long long* __restrict__ count,
+                                                         const unsigned long long* __restrict__ first, int k_min,
+                                                         int k_max, int t0, int nfdot, int sky0) {
+  unsigned long long end = count[0];
+  if (end > patch_capacity) end = patch_capacity;
+  const long nb = k_max - k_min;
+  for (unsigned long long slot = first[0] + blockIdx.x; slot < end; slot += gridDim.x) {
+    const CandEntry ce = cand[slot];
+    const long t_local = (long)(ce.sky - sky0) * nfdot + ce.fdot_idx - t0;
+    const int k = ce.bin - 128 + (int)threadIdx.x;
+    float v = 0.f;
+    if (k >= k_min && k < k_max) v = spec[t_local * nb + (k - k_min)];
+    patches[slot * 256 + threadIdx.x] = v;
   }
 }
 

@@ -1,0 +1,285 @@
+// Kernels of the candidate-vetting network (forward, backward, Adam) and of the
+// patch capture that follows the F-statistic kernel.
+//
+// Network: u = log(1 + 2F) - log 5 over a 256-bin patch; three "same" convolutions
+// of width 7 (1 -> 32 -> 32 -> 32 channels, ReLU); flatten position-major
+// (x[p*32 + c]); dense 8192 -> 128 -> 128 -> 1 (ReLU, ReLU, logit).  Activations
+// are stored position-major [n][256][32].  Convolutions 2 and 3, the dense layers
+// and all their gradients are products of BF16 matrices with FP32 accumulation on
+// the matrix cores (v_mfma_f32_16x16x16_bf16); the first convolution (one input
+// channel) and the last dense layer are plain FP32 loops.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fstat {
+namespace vet {
+
+constexpr int L = 256;        // patch length
+constexpr int C = 32;         // channels
+constexpr int KW = 7;         // kernel width
+constexpr int KC = KW * C;    // im2col width (224)
+constexpr int H = 128;        // hidden units
+constexpr int X = L * C;      // flattened conv output (8192)
+
+// flat parameter vector offsets (order w1 b1 w2 b2 w3 b3 w4 b4 w5 b5 w6 b6)
+constexpr long O_W1 = 0, O_B1 = O_W1 + C * KW, O_W2 = O_B1 + C, O_B2 = O_W2 + C * C * KW, O_W3 = O_B2 + C,
+               O_B3 = O_W3 + C * C * KW, O_W4 = O_B3 + C, O_B4 = O_W4 + (long)H * X, O_W5 = O_B4 + H,
+               O_B5 = O_W5 + H * H, O_W6 = O_B5 + H, O_B6 = O_W6 + H, N_PARAMS = O_B6 + 1;
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest even (finite inputs)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// C[m][n] = alpha * sum_k A(m, k) B(k, n) + beta * C[m][n]
+// A(m, k) = A[m*sam + k*sak], B(k, n) = B[k*sbk + n*sbn] (BF16), C row-major with ldc (FP32).
+// Workgroup: 4 wavefronts, a 64 x 64 tile of C; each wavefront a 32 x 32 block made of
+// 2 x 2 matrix-core tiles of 16 x 16, stepping K by 16.  Out-of-range elements are zero.
+// Matrix-core operand layout (16x16x16): lane l holds A[l%16][4(l/16)+i], B[4(l/16)+i][l%16]
+// and receives D[4(l/16)+i][l%16], i = 0..3.
+__global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const uint16_t* __restrict__ A, long sam,
+                                                   long sak, const uint16_t* __restrict__ B, long sbk, long sbn,
+                                                   float* __restrict__ Cm, long ldc, float alpha, float beta) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
+  const int n0 = blockIdx.x * 64 + (w & 1) * 32;
+  const int r16 = lane & 15, kq = (lane >> 4) * 4;
+  v4f acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    v4s fa[2], fb[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int m = m0 + t * 16 + r16;
+      const int n = n0 + t * 16 + r16;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = k0 + kq + i;
+        fa[t][i] = (m < M && k < K) ? (short)A[(long)m * sam + (long)k * sak] : (short)0;
+        fb[t][i] = (n < N && k < K) ? (short)B[(long)k * sbk + (long)n * sbn] : (short)0;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa[a], fb[b], acc[a][b], 0, 0, 0);
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = m0 + a * 16 + kq + i;
+        const int n = n0 + b * 16 + r16;
+        if (m < M && n < N) {
+          float* c = Cm + (long)m * ldc + n;
+          *c = alpha * acc[a][b][i] + (beta != 0.f ? beta * *c : 0.f);
+        }
+      }
+}
+
+// u = log(1 + 2F) - log 5 per patch bin; conv1 (one input channel):
+// z1[n][p][c] = b1[c] + sum_t w1[c][t] u[n][p+t-3]; a1 = relu(z1) as BF16.
+__global__ void k_vet_conv1(const float* __restrict__ patches, int n, const float* __restrict__ theta,
+                            float* __restrict__ u, float* __restrict__ z1, uint16_t* __restrict__ a1b) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;  // over n * L * C
+  if (idx >= (long)n * L * C) return;
+  const int c = idx % C;
+  const int p = (idx / C) % L;
+  const long s = idx / (C * L);
+  const float* pp = patches + s * L;
+  float z = theta[O_B1 + c];
+#pragma unroll
+  for (int t = 0; t < KW; ++t) {
+    const int q = p + t - 3;
+    if (q >= 0 && q < L) z += theta[O_W1 + c * KW + t] * (log1pf(pp[q]) - 1.6094379124341003f);
+  }
+  z1[idx] = z;
+  a1b[idx] = f2bf(z > 0.f ? z : 0.f);
+  if (c == 0) u[s * L + p] = log1pf(pp[p]) - 1.6094379124341003f;
+}
+
+// im2col of a position-major BF16 activation [n][L][C]:
+//   col[(s*L + p)][t*C + c] = act[s][p + dir*(t-3)][c]   (zero outside [0, L))
+// dir = +1 for a convolution, -1 for the transposed convolution of its input gradient.
+__global__ void k_vet_im2col(const uint16_t* __restrict__ act, int n, int dir, uint16_t* __restrict__ col) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;  // over n * L * KC
+  if (idx >= (long)n * L * KC) return;
+  const int kk = idx % KC;
+  const long row = idx / KC;
+  const int p = row % L;
+  const long s = row / L;
+  const int t = kk / C, c = kk % C;
+  const int q = p + dir * (t - 3);
+  col[idx] = (q >= 0 && q < L) ? act[(s * L + q) * C + c] : (uint16_t)0;
+}
+
+// z[r][j] += bias[j]; optional relu output as BF16; z kept for the backward masks.
+__global__ void k_vet_bias_relu(float* __restrict__ z, long rows, int cols, const float* __restrict__ bias,
+                                uint16_t* __restrict__ outb, float* __restrict__ outf) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const float v = z[idx] + bias[idx % cols];
+  z[idx] = v;
+  const float a = v > 0.f ? v : 0.f;
+  if (outb) outb[idx] = f2bf(a);
+  if (outf) outf[idx] = a;
+}
+
+// logit[s] = b6 + sum_j w6[j] a5[s][j]   (a5 = relu(z5), FP32)
+__global__ void k_vet_fc3(const float* __restrict__ a5, int n, const float* __restrict__ theta,
+                          float* __restrict__ logit) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  float v = theta[O_B6];
+  for (int j = 0; j < H; ++j) v += theta[O_W6 + j] * a5[(long)s * H + j];
+  logit[s] = v;
+}
+
+// Loss and the first backward step: dlogit = (sigmoid(logit) - y) / n; loss = mean BCE.
+// dz5[s][j] = dlogit[s] w6[j] (z5 > 0); also dW6, db6 partial sums per block.
+__global__ void k_vet_head_backward(const float* __restrict__ logit, const float* __restrict__ y, int n,
+                                    const float* __restrict__ theta, const float* __restrict__ z5,
+                                    const float* __restrict__ a5, float* __restrict__ dz5,
+                                    uint16_t* __restrict__ dz5b, float* __restrict__ dlogit,
+                                    float* __restrict__ loss_terms) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const float l = logit[s];
+  const float sig = 1.f / (1.f + expf(-l));
+  const float d = (sig - y[s]) / (float)n;
+  dlogit[s] = d;
+  loss_terms[s] = fmaxf(l, 0.f) - l * y[s] + log1pf(expf(-fabsf(l)));
+  for (int j = 0; j < H; ++j) {
+    const float g = z5[(long)s * H + j] > 0.f ? d * theta[O_W6 + j] : 0.f;
+    dz5[(long)s * H + j] = g;
+    dz5b[(long)s * H + j] = f2bf(g);
+  }
+}
+
+// dz = dh * (z > 0) in place, BF16 copy.
+__global__ void k_vet_relu_mask(float* __restrict__ dh, const float* __restrict__ z, long count,
+                                uint16_t* __restrict__ outb) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= count) return;
+  const float g = z[idx] > 0.f ? dh[idx] : 0.f;
+  dh[idx] = g;
+  outb[idx] = f2bf(g);
+}
+
+// out[j] = sum_r m[r][j] (fixed order over r; one thread per column)
+__global__ void k_vet_colsum(const float* __restrict__ m, long rows, int cols, float* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  float acc = 0.f;
+  for (long r = 0; r < rows; ++r) acc += m[r * cols + j];
+  out[j] = acc;
+}
+
+// dW6[j] = sum_s dlogit[s] a5[s][j]; db6 = sum_s dlogit[s]; loss = mean of the terms.
+__global__ void k_vet_head_reduce(const float* __restrict__ dlogit, const float* __restrict__ a5,
+                                  const float* __restrict__ loss_terms, int n, float* __restrict__ grad,
+                                  float* __restrict__ loss) {
+  const int j = threadIdx.x;  // H + 1 threads
+  if (j < H) {
+    float acc = 0.f;
+    for (int s = 0; s < n; ++s) acc += dlogit[s] * a5[(long)s * H + j];
+    grad[O_W6 + j] = acc;
+  } else if (j == H) {
+    float acc = 0.f, ls = 0.f;
+    for (int s = 0; s < n; ++s) {
+      acc += dlogit[s];
+      ls += loss_terms[s];
+    }
+    grad[O_B6] = acc;
+    if (loss) *loss = ls / (float)n;
+  }
+}
+
+// conv1 weight and bias gradients: dW1[c][t] = sum_{s,p} dz1[s][p][c] u[s][p+t-3]; db1[c].
+__global__ void k_vet_conv1_backward(const float* __restrict__ dz1, const float* __restrict__ u, int n,
+                                     float* __restrict__ grad) {
+  const int c = blockIdx.x;      // C blocks
+  const int t = threadIdx.x;     // KW + 1 threads (t == KW: bias)
+  float acc = 0.f;
+  for (long r = 0; r < (long)n * L; ++r) {
+    const int p = r % L;
+    const long s = r / L;
+    const float g = dz1[r * C + c];
+    if (t == KW) {
+      acc += g;
+    } else {
+      const int q = p + t - 3;
+      if (q >= 0 && q < L) acc += g * u[s * L + q];
+    }
+  }
+  if (t == KW) grad[O_B1 + c] = acc;
+  else grad[O_W1 + c * KW + t] = acc;
+}
+
+// BF16 weight layouts for the matrix products, from the FP32 master vector:
+//   wf[l][t*C + ci][co] = w_l[co][ci][t]   (forward convolution, [KC][C])
+//   wt[l][t*C + co][ci] = w_l[co][ci][t]   (input-gradient convolution, [KC][C])
+//   w4b[j][k] = w4[j][k], w5b[j][k] = w5[j][k]
+__global__ void k_vet_prepare(const float* __restrict__ theta, uint16_t* __restrict__ wf2,
+                              uint16_t* __restrict__ wt2, uint16_t* __restrict__ wf3, uint16_t* __restrict__ wt3,
+                              uint16_t* __restrict__ w4b, uint16_t* __restrict__ w5b) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < (long)H * X) w4b[idx] = f2bf(theta[O_W4 + idx]);
+  if (idx < H * H) w5b[idx] = f2bf(theta[O_W5 + idx]);
+  if (idx < C * C * KW) {
+    const int co = idx / (C * KW), ci = (idx / KW) % C, t = idx % KW;
+    wf2[(t * C + ci) * C + co] = f2bf(theta[O_W2 + idx]);
+    wt2[(t * C + co) * C + ci] = f2bf(theta[O_W2 + idx]);
+    wf3[(t * C + ci) * C + co] = f2bf(theta[O_W3 + idx]);
+    wt3[(t * C + co) * C + ci] = f2bf(theta[O_W3 + idx]);
+  }
+}
+
+// Gradient of a convolution weight from its matrix-product form dWm[t*C + ci][co]
+// back to the flat layout w[co][ci][t].
+__global__ void k_vet_scatter_conv_grad(const float* __restrict__ dwm, float* __restrict__ gw) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= C * C * KW) return;
+  const int co = idx / (C * KW), ci = (idx / KW) % C, t = idx % KW;
+  gw[idx] = dwm[(t * C + ci) * C + co];
+}
+
+// Adam on the FP32 master vector (bias-corrected step size precomputed on the host).
+__global__ void k_vet_adam(float* __restrict__ theta, const float* __restrict__ g, float* __restrict__ m1,
+                           float* __restrict__ m2, long count, float step, float b1, float b2, float eps) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float gi = g[i];
+  const float a = b1 * m1[i] + (1.f - b1) * gi;
+  const float b = b2 * m2[i] + (1.f - b2) * gi * gi;
+  m1[i] = a;
+  m2[i] = b;
+  theta[i] -= step * a / (sqrtf(b) + eps);
+}
+
+// Patch capture after the F kernel: for candidate slots [first, last) of the current
+// launch, copy the 256-bin 2F window centred on the candidate's bin from the launch's
+// spectrum buffer (template-major, bins [k_min, k_max)); bins outside that range read 0.
+struct PatchArgs {
+  const unsigned long long* count;   // candidates found so far (after this launch)
+  const unsigned long long* first;   // value of the count before this launch
+  long long capacity;                // candidate buffer entries (= patch store rows)
+  int k_min, k_max;
+  int t0, nfdot, sky0;               // launch: templates t0.., sky index base
+};
+
+}  // namespace vet
+}  // namespace fstat

@@ -26,7 +26,9 @@ KERNEL_NAMES = ("sky_prep", "resample", "template_a", "template_b")
 EXPORTED = ("fstat_options_default", "fstat_plan", "fstat_plan_workspace_size", "fstat_plan_set_workspace",
             "fstat_search_batch", "fstat_candidates", "fstat_twoF_spectrum", "fstat_sky_stages",
             "fstat_profile_enable", "fstat_profile_read", "fstat_plan_info", "fstat_autotune", "fstat_destroy",
-            "fstat_strerror", "fstat_last_error")
+            "fstat_strerror", "fstat_last_error", "fstat_vet_param_count", "fstat_vet_create",
+            "fstat_vet_set_params", "fstat_vet_get_params", "fstat_vet_forward", "fstat_vet_gradient",
+            "fstat_vet_adam_step", "fstat_vet_destroy", "fstat_plan_attach_vetter", "fstat_plan_vet_candidates")
 
 
 class fstat_segment(ctypes.Structure):
@@ -50,12 +52,12 @@ class fstat_candidate(ctypes.Structure):
 
 class fstat_candidate_key(ctypes.Structure):
     _fields_ = [("search", ctypes.c_int32), ("segment", ctypes.c_int32), ("sky", ctypes.c_int32),
-                ("fdot_idx", ctypes.c_int32), ("bin", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fdot_idx", ctypes.c_int32), ("bin", ctypes.c_int32), ("vet_score", ctypes.c_float)]
 
 
 CANDIDATE_NP = np.dtype([("f_hz", "<f8"), ("fdot", "<f8"), ("alpha", "<f8"), ("delta", "<f8"), ("twoF", "<f8")])
 KEY_NP = np.dtype([("search", "<i4"), ("segment", "<i4"), ("sky", "<i4"), ("fdot_idx", "<i4"), ("bin", "<i4"),
-                   ("reserved", "<i4")])
+                   ("vet_score", "<f4")])
 
 _lib = None
 
@@ -85,6 +87,16 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "fstat_autotune": (i32, [P, i32, dbl, P]),
         "fstat_destroy": (i32, [P]),
         "fstat_strerror": (ctypes.c_char_p, [i32]),
+        "fstat_vet_param_count": (i64, []),
+        "fstat_vet_create": (i32, [i32, ctypes.POINTER(P)]),
+        "fstat_vet_set_params": (i32, [P, P, i64]),
+        "fstat_vet_get_params": (i32, [P, P, i64]),
+        "fstat_vet_forward": (i32, [P, P, i64, P, P]),
+        "fstat_vet_gradient": (i32, [P, P, P, i64, P, P, P]),
+        "fstat_vet_adam_step": (i32, [P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P]),
+        "fstat_vet_destroy": (i32, [P]),
+        "fstat_plan_attach_vetter": (i32, [P, P, i64]),
+        "fstat_plan_vet_candidates": (i32, [P, P]),
         "fstat_last_error": (ctypes.c_char_p, [P]),
     }
     for name, (res, args) in sig.items():
@@ -232,6 +244,14 @@ class Plan:
                                            1 if reset else 0), self.handle)
         return n.value, ms.value
 
+    def attach_vetter(self, vetter, patch_capacity: int):
+        self._vetter = vetter
+        _check(self.lib.fstat_plan_attach_vetter(self.handle, vetter.handle if vetter else None, int(patch_capacity)),
+               self.handle)
+
+    def vet_candidates(self, stream=None):
+        _check(self.lib.fstat_plan_vet_candidates(self.handle, _stream_handle(stream)), self.handle)
+
     def destroy(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             self.lib.fstat_destroy(self.handle)
@@ -251,3 +271,51 @@ def segment_to_device(seg) -> dict:
                 x=torch.as_tensor(np.ascontiguousarray(seg.x), dtype=torch.float64, device="cuda"),
                 r=torch.as_tensor(np.ascontiguousarray(seg.r), dtype=torch.float64, device="cuda"),
                 lat=seg.lat, gamma=seg.gamma, phi_r=seg.phi_r)
+
+
+class Vetter:
+    """The candidate-vetting network on the GPU (parameters FP32, products BF16/FP32)."""
+
+    def __init__(self, max_batch: int = 512):
+        self.lib = load()
+        h = ctypes.c_void_p()
+        _check(self.lib.fstat_vet_create(int(max_batch), ctypes.byref(h)))
+        self.handle = h
+        self.max_batch = max_batch
+        self.n_params = int(self.lib.fstat_vet_param_count())
+
+    def _chk(self, st):
+        if st != OK:
+            raise FstatError(st, self.lib.fstat_strerror(st).decode())
+
+    def set_params(self, theta: np.ndarray):
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        assert t.size == self.n_params
+        self._chk(self.lib.fstat_vet_set_params(self.handle, t.ctypes.data, t.size))
+
+    def get_params(self) -> np.ndarray:
+        t = np.empty(self.n_params, dtype=np.float32)
+        self._chk(self.lib.fstat_vet_get_params(self.handle, t.ctypes.data, t.size))
+        return t
+
+    def forward(self, patches, logits, stream=None):
+        self._chk(self.lib.fstat_vet_forward(self.handle, _ptr(patches), int(patches.shape[0]), _ptr(logits),
+                                             _stream_handle(stream)))
+
+    def gradient(self, patches, labels, loss=None, grad=None, stream=None):
+        self._chk(self.lib.fstat_vet_gradient(self.handle, _ptr(patches), _ptr(labels), int(patches.shape[0]),
+                                              _ptr(loss), _ptr(grad), _stream_handle(stream)))
+
+    def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None):
+        self._chk(self.lib.fstat_vet_adam_step(self.handle, lr, beta1, beta2, eps, _stream_handle(stream)))
+
+    def destroy(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.fstat_vet_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

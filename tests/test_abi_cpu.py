@@ -125,3 +125,17 @@ def test_valid_plan_without_gpu_reports_device_error():
     st, h, msg = _plan([_seg()])
     assert st == F.E_DEVICE
     assert h.value is None
+
+
+def test_vetting_entry_points_validate_arguments():
+    lib = F.load()
+    assert lib.fstat_vet_param_count() == 1080001
+    h = ctypes.c_void_p()
+    assert lib.fstat_vet_create(0, ctypes.byref(h)) == F.E_INVAL
+    assert lib.fstat_vet_create(1 << 20, ctypes.byref(h)) == F.E_INVAL
+    assert lib.fstat_vet_create(64, None) == F.E_INVAL
+    assert lib.fstat_vet_forward(None, FAKE_PTR, 1, FAKE_PTR, None) == F.E_INVAL
+    assert lib.fstat_vet_adam_step(None, 1e-3, 0.9, 0.999, 1e-8, None) == F.E_INVAL
+    assert lib.fstat_plan_attach_vetter(None, None, 1) == F.E_INVAL
+    assert lib.fstat_plan_vet_candidates(None, None) == F.E_INVAL
+    assert lib.fstat_vet_destroy(None) == F.OK
