@@ -57,6 +57,78 @@ def measured_traffic(kernel: str, templates_per_launch: int, variant: int):
     return k["bytes_per_launch"]
 
 
+def vetting_leg(args, F, torch, np, dev, log):
+    """Train the vetting network on oracle-generated patches (N = 86164), report false-alarm and
+    false-dismissal rates against the threshold alone on held-out shapes, then run the plain
+    workload (256 sky x 64 spindown) with the network attached: patch capture right after each
+    F kernel launch and scoring of every crossing on the device."""
+    import synth
+    from oracle import vet_data, vet_oracle
+    t0 = time.perf_counter()
+    x, y, st = vet_data.make_dataset(5000, 32, 1600, 24)
+    xe, ye, ste = vet_data.make_dataset(5001, 8, 1300, 20)
+    t_gen = time.perf_counter() - t0
+    log(f"vetting data: train {len(y)}, held out {len(ye)} ({t_gen:.1f} s)")
+    batch = 256
+    v = F.Vetter(8192)
+    v.set_params(vet_oracle.init_params(np.random.default_rng(21)).astype(np.float32))
+    xg, yg = torch.as_tensor(x, device="cuda"), torch.as_tensor(y, device="cuda")
+    rng = np.random.default_rng(22)
+    loss = torch.empty(1, device="cuda")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    steps = 0
+    for ep in range(args.vet_epochs):
+        perm = torch.as_tensor(rng.permutation(len(y)), device="cuda")
+        for i in range(0, len(y) - batch + 1, batch):
+            idx = perm[i:i + batch]
+            v.gradient(xg[idx].contiguous(), yg[idx].contiguous(), loss)
+            v.adam_step(1e-3)
+            steps += 1
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    le = torch.empty(len(ye), device="cuda")
+    v.forward(torch.as_tensor(xe, device="cuda"), le)
+    le = le.cpu().numpy()
+    cut = float(np.quantile(le[ye == 1], 0.01))
+    far = float(np.mean(le[ye == 0] >= cut))
+    fdr_added = float(np.mean(le[ye == 1] < cut))
+    log(f"vetting: trained {steps} steps in {t_train:.1f} s, loss {loss.item():.4f}; held out: network keeps "
+        f"{far:.4f} of noise crossings at {fdr_added:.4f} added false dismissal")
+    # fused: the plain workload with patch capture and device scoring
+    w2 = synth.workload(2)
+    seg2 = w2.segments[0]
+    cap = 1 << 21
+    p = F.Plan([F.segment_to_device(seg2)], candidate_capacity=cap, use_graph=0)
+    p.attach_vetter(v, cap)
+    a2, d2, f2 = dev(w2.alpha), dev(w2.delta), dev(w2.fdot)
+    p.search_batch(0, a2[:2], d2[:2], f2)
+    p.vet_candidates()
+    p.candidate_count(allow_overflow=True)
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    p.search_batch(0, a2, d2, f2)
+    torch.cuda.synchronize()
+    s1 = time.perf_counter()
+    p.vet_candidates()
+    torch.cuda.synchronize()
+    s2 = time.perf_counter()
+    recs, keys, n = p.candidates(capacity=cap)
+    kept = int(np.sum(keys["vet_score"] >= 1.0 / (1.0 + np.exp(-cut))))
+    inj = seg2.injections[0]
+    near = np.abs(recs["f_hz"] - (seg2.f_off + inj.f)) < 2e-4
+    p.destroy()
+    v.destroy()
+    return {"train_patches": int(len(y)), "heldout_patches": int(len(ye)), "epochs": args.vet_epochs,
+            "train_s": t_train, "data_s": t_gen, "threshold_false_dismissal": st["threshold_false_dismissal"],
+            "heldout_noise_kept_by_network": far, "heldout_added_false_dismissal": fdr_added,
+            "heldout_noise_kept_by_threshold": 1.0,
+            "plain_search_with_capture_ms": (s1 - s0) * 1e3, "scoring_ms": (s2 - s1) * 1e3,
+            "plain_crossings": int(n), "plain_crossings_kept_by_network": kept,
+            "plain_crossings_near_injection": int(near.sum()),
+            "plain_crossings_near_injection_kept": int(np.sum(near & (keys["vet_score"] >= 1.0 / (1.0 + np.exp(-cut)))))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +147,8 @@ def main():
     ap.add_argument("--autotune-ms", type=float, default=3000.0)
     ap.add_argument("--tuning-cache", default="",
                     help="tuning cache file: reused if it exists, else written by the autotuner")
+    ap.add_argument("--no-vetting", action="store_true")
+    ap.add_argument("--vet-epochs", type=int, default=3)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -224,6 +298,11 @@ def main():
         f_err = max(errs)
         log(f"cpu oracle: {cpu['value']:.3g} templates/s, max F rel err vs FP64 {f_err:.3e}")
 
+    # ---------------- learned vetting: train on oracle patches, then score the plain search's crossings
+    vetting = None
+    if not args.no_vetting:
+        vetting = vetting_leg(args, F, torch, np, dev, log)
+
     out = {
         "metric": METRIC, "value": value, "unit": "templates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -235,6 +314,7 @@ def main():
                    "pass_a_variant": info["pass_a_variant"], "tuning": tuned},
         "roofline": roofline, "cpu_baseline": cpu, "plain": plain,
         "f_rel_err_vs_fp64": f_err, "candidates_per_step": n_cand / args.steps, "kernels": kernels,
+        "vetting": vetting,
         "source_sha256": source_digest(),
     }
     print(json.dumps(out), flush=True)

@@ -74,6 +74,7 @@ struct fstat_vet_s {
   float *theta = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
   uint16_t *wf2, *wt2, *wf3, *wt3, *w4b, *w5b;
   float *u, *z1, *z2, *z3, *z4, *z5, *a5, *logit, *dlogit, *lterm, *dz5, *dh4, *dx, *da, *dwm, *loss;
+  float* scratch = nullptr;      // split-K partial tiles and reduction partials
   uint16_t *a1b, *a2b, *a3b, *a4b, *colA, *colB, *colC, *dz5b, *dz4b, *dzb;
   std::string last_error;
 };
@@ -627,12 +628,38 @@ fstat_status vet_fail(fstat_vet_t v, fstat_status st, const std::string& msg) {
                       std::string(what) + ": " + hipGetErrorString(e_));              \
   } while (0)
 
-// C[m][n] = sum_k A(m, k) B(k, n) on the matrix cores
+// C[m][n] = sum_k A(m, k) B(k, n) on the matrix cores.  Products with a long K and a small
+// output split K over workgroups into partial tiles (in `scratch`) summed in a fixed order.
+constexpr long VET_SCRATCH = 8L << 20;  // floats of split-K and reduction scratch
 void gemm(hipStream_t st, int M, int N, int K, const uint16_t* A, long sam, long sak, const uint16_t* B, long sbk,
-          long sbn, float* Cm, long ldc) {
-  dim3 grid((N + 63) / 64, (M + 63) / 64);
-  hipLaunchKernelGGL(vet::k_gemm_bf16, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, Cm, ldc, 1.0f,
-                     0.0f);
+          long sbn, float* Cm, long ldc, float* scratch = nullptr) {
+  const int tiles = ((N + 63) / 64) * ((M + 63) / 64);
+  int splits = 1;
+  if (scratch && tiles < 256 && K >= 4096) {
+    splits = std::min(K / 1024, 1024 / tiles);
+    while (splits > 1 && (long)splits * M * N > VET_SCRATCH) --splits;
+    splits = std::max(splits, 1);
+  }
+  const int kchunk = ((K + splits - 1) / splits + 15) / 16 * 16;
+  dim3 grid((N + 63) / 64, (M + 63) / 64, splits);
+  if (splits == 1) {
+    hipLaunchKernelGGL(vet::k_gemm_bf16, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, Cm, ldc, 0L,
+                       kchunk);
+  } else {
+    const long count = (long)M * N;
+    hipLaunchKernelGGL(vet::k_gemm_bf16, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, scratch, (long)N,
+                       count, kchunk);
+    hipLaunchKernelGGL(vet::k_vet_sum_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, scratch, splits,
+                       count, N, ldc, Cm);
+  }
+}
+
+// out[j] = sum_r m[r][j] (rows x cols, FP32), two fixed-order stages
+void colsum(hipStream_t st, const float* m, long rows, int cols, float* out, float* scratch) {
+  const long per = 4096;
+  const int chunks = (int)((rows + per - 1) / per);
+  hipLaunchKernelGGL(vet::k_vet_colsum_part, dim3(cols, chunks), dim3(256), 0, st, m, rows, cols, per, scratch);
+  hipLaunchKernelGGL(vet::k_vet_colsum_final, dim3((cols + 255) / 256), dim3(256), 0, st, scratch, chunks, cols, out);
 }
 
 __global__ void k_vet_store_scores(CandEntry* cand, const float* logit, long n) {
@@ -673,30 +700,39 @@ void vet_backward(fstat_vet_t v, const float* labels, int n, hipStream_t st) {
   using namespace vet;
   const long NL = (long)n * L;
   float* g = v->grad;
+  float* sc = v->scratch;
   hipLaunchKernelGGL(k_vet_head_backward, blocks_for(n), dim3(256), 0, st, v->logit, labels, n, v->theta, v->z5,
                      v->a5, v->dz5, v->dz5b, v->dlogit, v->lterm);
   hipLaunchKernelGGL(k_vet_head_reduce, dim3(1), dim3(H + 1), 0, st, v->dlogit, v->a5, v->lterm, n, g, v->loss);
-  gemm(st, H, H, n, v->dz5b, 1, H, v->a4b, H, 1, g + O_W5, H);                 // dW5 = dz5^T a4
-  hipLaunchKernelGGL(k_vet_colsum, dim3(1), dim3(H), 0, st, v->dz5, (long)n, H, g + O_B5);
+  gemm(st, H, H, n, v->dz5b, 1, H, v->a4b, H, 1, g + O_W5, H, sc);             // dW5 = dz5^T a4
+  colsum(st, v->dz5, (long)n, H, g + O_B5, sc);
   gemm(st, n, H, H, v->dz5b, H, 1, v->w5b, H, 1, v->dh4, H);                   // dh4 = dz5 W5
   hipLaunchKernelGGL(k_vet_relu_mask, blocks_for((long)n * H), dim3(256), 0, st, v->dh4, v->z4, (long)n * H, v->dz4b);
-  gemm(st, H, X, n, v->dz4b, 1, H, v->a3b, X, 1, g + O_W4, X);                 // dW4 = dz4^T x
-  hipLaunchKernelGGL(k_vet_colsum, dim3(1), dim3(H), 0, st, v->dh4, (long)n, H, g + O_B4);
+  gemm(st, H, X, n, v->dz4b, 1, H, v->a3b, X, 1, g + O_W4, X, sc);             // dW4 = dz4^T x
+  colsum(st, v->dh4, (long)n, H, g + O_B4, sc);
   gemm(st, n, X, H, v->dz4b, H, 1, v->w4b, X, 1, v->dx, X);                    // dx = dz4 W4
   hipLaunchKernelGGL(k_vet_relu_mask, blocks_for(NL * C), dim3(256), 0, st, v->dx, v->z3, NL * C, v->dzb);
-  gemm(st, KC, C, (int)NL, v->colB, 1, KC, v->dzb, C, 1, v->dwm, C);            // dW3 (im2col layout)
+  gemm(st, KC, C, (int)NL, v->colB, 1, KC, v->dzb, C, 1, v->dwm, C, sc);        // dW3 (im2col layout)
   hipLaunchKernelGGL(k_vet_scatter_conv_grad, blocks_for(C * C * KW), dim3(256), 0, st, v->dwm, g + O_W3);
-  hipLaunchKernelGGL(k_vet_colsum, dim3(1), dim3(C), 0, st, v->dx, NL, C, g + O_B3);
+  colsum(st, v->dx, NL, C, g + O_B3, sc);
   hipLaunchKernelGGL(k_vet_im2col, blocks_for(NL * KC), dim3(256), 0, st, v->dzb, n, -1, v->colC);
   gemm(st, (int)NL, C, KC, v->colC, KC, 1, v->wt3, C, 1, v->da, C);             // da2
   hipLaunchKernelGGL(k_vet_relu_mask, blocks_for(NL * C), dim3(256), 0, st, v->da, v->z2, NL * C, v->dzb);
-  gemm(st, KC, C, (int)NL, v->colA, 1, KC, v->dzb, C, 1, v->dwm, C);            // dW2
+  gemm(st, KC, C, (int)NL, v->colA, 1, KC, v->dzb, C, 1, v->dwm, C, sc);        // dW2
   hipLaunchKernelGGL(k_vet_scatter_conv_grad, blocks_for(C * C * KW), dim3(256), 0, st, v->dwm, g + O_W2);
-  hipLaunchKernelGGL(k_vet_colsum, dim3(1), dim3(C), 0, st, v->da, NL, C, g + O_B2);
+  colsum(st, v->da, NL, C, g + O_B2, sc);
   hipLaunchKernelGGL(k_vet_im2col, blocks_for(NL * KC), dim3(256), 0, st, v->dzb, n, -1, v->colC);
   gemm(st, (int)NL, C, KC, v->colC, KC, 1, v->wt2, C, 1, v->da, C);             // da1
   hipLaunchKernelGGL(k_vet_relu_mask, blocks_for(NL * C), dim3(256), 0, st, v->da, v->z1, NL * C, v->dzb);
-  hipLaunchKernelGGL(k_vet_conv1_backward, dim3(C), dim3(KW + 1), 0, st, v->da, v->u, n, g);
+  {
+    const long per = 4096;
+    const int chunks = (int)((NL + per - 1) / per);
+    const int ncols = C * (KW + 1);
+    hipLaunchKernelGGL(k_vet_conv1_backward_part, dim3(ncols, chunks), dim3(256), 0, st, v->da, v->u, NL, per, sc);
+    hipLaunchKernelGGL(k_vet_colsum_final, dim3((ncols + 255) / 256), dim3(256), 0, st, sc, chunks, ncols,
+                       sc + (long)chunks * ncols);
+    hipLaunchKernelGGL(k_vet_conv1_scatter, dim3(1), dim3(256), 0, st, sc + (long)chunks * ncols, g);
+  }
 }
 }  // namespace
 
@@ -723,7 +759,8 @@ fstat_status fstat_vet_create(int32_t max_batch, fstat_vet_t* out) {
       {(void**)&v->z5, nb * H * 4}, {(void**)&v->a5, nb * H * 4}, {(void**)&v->logit, nb * 4},
       {(void**)&v->dlogit, nb * 4}, {(void**)&v->lterm, nb * 4}, {(void**)&v->dz5, nb * H * 4},
       {(void**)&v->dh4, nb * H * 4}, {(void**)&v->dx, NL * C * 4}, {(void**)&v->da, NL * C * 4},
-      {(void**)&v->dwm, KC * C * 4}, {(void**)&v->loss, 4}, {(void**)&v->a1b, NL * C * 2},
+      {(void**)&v->dwm, KC * C * 4}, {(void**)&v->loss, 4}, {(void**)&v->scratch, (size_t)VET_SCRATCH * 4},
+      {(void**)&v->a1b, NL * C * 2},
       {(void**)&v->a2b, NL * C * 2}, {(void**)&v->a3b, NL * C * 2}, {(void**)&v->a4b, nb * H * 2},
       {(void**)&v->colA, NL * KC * 2}, {(void**)&v->colB, NL * KC * 2}, {(void**)&v->colC, NL * KC * 2},
       {(void**)&v->dz5b, nb * H * 2}, {(void**)&v->dz4b, nb * H * 2}, {(void**)&v->dzb, NL * C * 2}};

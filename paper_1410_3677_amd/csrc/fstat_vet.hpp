@@ -39,42 +39,59 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
-// C[m][n] = alpha * sum_k A(m, k) B(k, n) + beta * C[m][n]
+// C[m][n] = sum_k A(m, k) B(k, n) over k in this workgroup's K range
 // A(m, k) = A[m*sam + k*sak], B(k, n) = B[k*sbk + n*sbn] (BF16), C row-major with ldc (FP32).
 // Workgroup: 4 wavefronts, a 64 x 64 tile of C; each wavefront a 32 x 32 block made of
 // 2 x 2 matrix-core tiles of 16 x 16, stepping K by 16.  Out-of-range elements are zero.
 // Matrix-core operand layout (16x16x16): lane l holds A[l%16][4(l/16)+i], B[4(l/16)+i][l%16]
-// and receives D[4(l/16)+i][l%16], i = 0..3.
+// and receives D[4(l/16)+i][l%16], i = 0..3.  With gridDim.z > 1 the K range is split and
+// each split writes its partial tile to C + z * split_stride (summed by k_vet_sum_splits).
+// Operands contiguous along K (stride 1) are read four elements per 8-byte load.
+__device__ __forceinline__ v4s load4(const uint16_t* __restrict__ p, long base, long stride, int k, int K, bool vec) {
+  v4s r;
+  if (vec && k + 3 < K && (reinterpret_cast<uintptr_t>(p + base + k) & 7) == 0) {
+    const ushort4 q = *reinterpret_cast<const ushort4*>(p + base + k);
+    r[0] = (short)q.x;
+    r[1] = (short)q.y;
+    r[2] = (short)q.z;
+    r[3] = (short)q.w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r[i] = (k + i < K) ? (short)p[base + (long)(k + i) * stride] : (short)0;
+  }
+  return r;
+}
+
 __global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const uint16_t* __restrict__ A, long sam,
                                                    long sak, const uint16_t* __restrict__ B, long sbk, long sbn,
-                                                   float* __restrict__ Cm, long ldc, float alpha, float beta) {
+                                                   float* __restrict__ Cm, long ldc, long split_stride, int kchunk) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
   const int n0 = blockIdx.x * 64 + (w & 1) * 32;
   const int r16 = lane & 15, kq = (lane >> 4) * 4;
+  const int kbeg = blockIdx.z * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  const bool va = (sak == 1), vb = (sbk == 1);
   v4f acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  for (int k0 = kbeg; k0 < kend; k0 += 16) {
     v4s fa[2], fb[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       const int m = m0 + t * 16 + r16;
       const int n = n0 + t * 16 + r16;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = k0 + kq + i;
-        fa[t][i] = (m < M && k < K) ? (short)A[(long)m * sam + (long)k * sak] : (short)0;
-        fb[t][i] = (n < N && k < K) ? (short)B[(long)k * sbk + (long)n * sbn] : (short)0;
-      }
+      fa[t] = m < M ? load4(A, (long)m * sam, sak, k0 + kq, kend, va) : v4s{0, 0, 0, 0};
+      fb[t] = n < N ? load4(B, (long)n * sbn, sbk, k0 + kq, kend, vb) : v4s{0, 0, 0, 0};
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa[a], fb[b], acc[a][b], 0, 0, 0);
   }
+  float* Cz = Cm + (long)blockIdx.z * split_stride;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -83,11 +100,37 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const ui
       for (int i = 0; i < 4; ++i) {
         const int m = m0 + a * 16 + kq + i;
         const int n = n0 + b * 16 + r16;
-        if (m < M && n < N) {
-          float* c = Cm + (long)m * ldc + n;
-          *c = alpha * acc[a][b][i] + (beta != 0.f ? beta * *c : 0.f);
-        }
+        if (m < M && n < N) Cz[(long)m * ldc + n] = acc[a][b][i];
       }
+}
+
+// out[m][n] = sum over splits z (in order) of part[z][m][n]
+__global__ void k_vet_sum_splits(const float* __restrict__ part, int splits, long count, int N, long ldc,
+                                 float* __restrict__ out) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= count) return;
+  const long m = idx / N, n = idx % N;
+  float acc = 0.f;
+  for (int z = 0; z < splits; ++z) acc += part[(long)z * count + idx];
+  out[m * ldc + n] = acc;
+}
+
+// Column sums in two fixed-order stages: block (j, chunk) sums its rows of column j.
+__global__ void __launch_bounds__(256) k_vet_colsum_part(const float* __restrict__ m, long rows, int cols,
+                                                         long rows_per_chunk, float* __restrict__ part) {
+  const int j = blockIdx.x, chunk = blockIdx.y;
+  const long r0 = (long)chunk * rows_per_chunk;
+  const long r1 = min(rows, r0 + rows_per_chunk);
+  float acc = 0.f;
+  for (long r = r0 + threadIdx.x; r < r1; r += 256) acc += m[r * cols + j];
+  __shared__ float red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(long)chunk * cols + j] = red[0];
 }
 
 // u = log(1 + 2F) - log 5 per patch bin; conv1 (one input channel):
@@ -179,12 +222,12 @@ __global__ void k_vet_relu_mask(float* __restrict__ dh, const float* __restrict_
   outb[idx] = f2bf(g);
 }
 
-// out[j] = sum_r m[r][j] (fixed order over r; one thread per column)
-__global__ void k_vet_colsum(const float* __restrict__ m, long rows, int cols, float* __restrict__ out) {
+// out[j] = sum over chunks (in order) of part[chunk][j]
+__global__ void k_vet_colsum_final(const float* __restrict__ part, int chunks, int cols, float* __restrict__ out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= cols) return;
   float acc = 0.f;
-  for (long r = 0; r < rows; ++r) acc += m[r * cols + j];
+  for (int c = 0; c < chunks; ++c) acc += part[(long)c * cols + j];
   out[j] = acc;
 }
 
@@ -209,24 +252,45 @@ __global__ void k_vet_head_reduce(const float* __restrict__ dlogit, const float*
 }
 
 // conv1 weight and bias gradients: dW1[c][t] = sum_{s,p} dz1[s][p][c] u[s][p+t-3]; db1[c].
-__global__ void k_vet_conv1_backward(const float* __restrict__ dz1, const float* __restrict__ u, int n,
-                                     float* __restrict__ grad) {
-  const int c = blockIdx.x;      // C blocks
-  const int t = threadIdx.x;     // KW + 1 threads (t == KW: bias)
+// Block (c * (KW + 1) + t, chunk) sums a chunk of the n * L rows; k_vet_colsum_final adds
+// the chunks in order into grad[O_W1 ...] (layout c * KW + t, bias c).
+__global__ void __launch_bounds__(256) k_vet_conv1_backward_part(const float* __restrict__ dz1,
+                                                                 const float* __restrict__ u, long rows,
+                                                                 long rows_per_chunk, float* __restrict__ part) {
+  const int ct = blockIdx.x;  // C * (KW + 1)
+  const int c = ct / (KW + 1), t = ct % (KW + 1);
+  const int chunk = blockIdx.y;
+  const long r0 = (long)chunk * rows_per_chunk;
+  const long r1 = min(rows, r0 + rows_per_chunk);
   float acc = 0.f;
-  for (long r = 0; r < (long)n * L; ++r) {
-    const int p = r % L;
-    const long s = r / L;
+  for (long r = r0 + threadIdx.x; r < r1; r += 256) {
     const float g = dz1[r * C + c];
     if (t == KW) {
       acc += g;
     } else {
+      const int p = r % L;
+      const long s = r / L;
       const int q = p + t - 3;
       if (q >= 0 && q < L) acc += g * u[s * L + q];
     }
   }
-  if (t == KW) grad[O_B1 + c] = acc;
-  else grad[O_W1 + c * KW + t] = acc;
+  __shared__ float red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(long)chunk * (C * (KW + 1)) + ct] = red[0];
+}
+
+// Move the conv1 sums (c * (KW + 1) + t order) into the flat gradient (weights c * KW + t, biases c).
+__global__ void k_vet_conv1_scatter(const float* __restrict__ sums, float* __restrict__ grad) {
+  const int ct = threadIdx.x;
+  if (ct >= C * (KW + 1)) return;
+  const int c = ct / (KW + 1), t = ct % (KW + 1);
+  if (t == KW) grad[O_B1 + c] = sums[ct];
+  else grad[O_W1 + c * KW + t] = sums[ct];
 }
 
 // BF16 weight layouts for the matrix products, from the FP32 master vector:
