@@ -42,7 +42,7 @@ def source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, templates_per_launch: int, variant: int):
+def measured_traffic(kernel: str, templates_per_launch: int, variants: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it is current."""
     path = os.path.join(ROOT, "profiles", "template_kernels_traffic.txt")
     if not os.path.exists(path):
@@ -52,7 +52,7 @@ def measured_traffic(kernel: str, templates_per_launch: int, variant: int):
     if t.get("source_sha256") != source_digest() or kernel not in t.get("kernels", {}):
         return None
     k = t["kernels"][kernel]
-    if k.get("templates_per_launch") != templates_per_launch or t.get("pass_a_variant") != variant:
+    if k.get("templates_per_launch") != templates_per_launch or t.get("variants") != variants:
         return None
     return k["bytes_per_launch"]
 
@@ -96,7 +96,7 @@ def vetting_leg(args, F, torch, np, dev, log):
     log(f"vetting: trained {steps} steps in {t_train:.1f} s, loss {loss.item():.4f}; held out: network keeps "
         f"{far:.4f} of noise crossings at {fdr_added:.4f} added false dismissal")
     # fused: the plain workload with patch capture and device scoring
-    w2 = synth.workload(2)
+    w2 = synth.workload("full")
     seg2 = w2.segments[0]
     cap = 1 << 21
     p = F.Plan([F.segment_to_device(seg2)], candidate_capacity=cap, use_graph=0)
@@ -180,7 +180,7 @@ def main():
         log(f"copy calibration: {args.copy_calibration_mb} MiB read and written")
 
     # ---------------- mixed-precision batched workload
-    w = synth.workload(3, args.nsky, args.nfdot)
+    w = synth.workload("batched", args.nsky, args.nfdot)
     seg = w.segments[0]
     nfft = synth.nfft_for(seg.n)
     al, de, fd = dev(w.alpha), dev(w.delta), dev(w.fdot)
@@ -237,8 +237,9 @@ def main():
         dom = max(("template_a", "template_b"), key=lambda k: kernels[k]["total_ms"] or 0.0)
         avg_s = kernels[dom]["avg_ms"] / 1e3
         achieved = algo[dom] / avg_s / 1e9
+        variants = info["pass_a_variant"] + 2 * info["pass_b_variant"]
         roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, B, info["pass_a_variant"]),
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, B, variants),
                     "algorithmic_bytes_per_launch": algo[dom], "templates_per_launch": B,
                     "avg_launch_ms": kernels[dom]["avg_ms"]}
         for k in ("template_a", "template_b"):
@@ -248,7 +249,7 @@ def main():
     # ---------------- plain path: one template per launch, 256 x 64
     plain = None
     if not args.no_plain:
-        w2 = synth.workload(2)
+        w2 = synth.workload("full")
         seg2 = w2.segments[0]
         p2 = F.Plan([F.segment_to_device(seg2)], templates_per_launch=1, skies_per_batch=1,
                     candidate_capacity=1 << 22, use_graph=0)
@@ -311,7 +312,8 @@ def main():
                                f"{args.nsky} sky x {args.nfdot} spindown, 5 injections, 2F>20",
                    "n": N, "nfft": nfft, "nsky": args.nsky, "nfdot": args.nfdot, "templates": templates,
                    "templates_per_launch": B, "skies_per_batch": info["skies_per_batch"],
-                   "pass_a_variant": info["pass_a_variant"], "tuning": tuned},
+                   "pass_a_variant": info["pass_a_variant"], "pass_b_variant": info["pass_b_variant"],
+                   "tuning": tuned},
         "roofline": roofline, "cpu_baseline": cpu, "plain": plain,
         "f_rel_err_vs_fp64": f_err, "candidates_per_step": n_cand / args.steps, "kernels": kernels,
         "vetting": vetting,

@@ -176,18 +176,24 @@ fstat_status fstat_profile_read(fstat_plan_t plan, int32_t kernel_class, int64_t
                                 double* total_ms, int32_t reset);
 
 /* Plan facts: FFT length and factors P x Q used for a segment, the batch
- * sizes in force and the first-pass kernel variant (0: series one after the
- * other through one LDS tile, 1: both series in LDS at once).  Any output
+ * sizes in force, the first-pass kernel variant (0: series one after the
+ * other through one LDS tile, 1: both series in LDS at once) and the
+ * second-pass variant (0: one launch-wide grid of row tiles; 1: about one
+ * resident round of wavefronts that walk the launch's rows, prefetching the
+ * next row and staging candidates in LDS; variant 1 applies to the mixed
+ * precision path with P <= 512, other segments use row tiles).  Any output
  * pointer may be NULL. */
 fstat_status fstat_plan_info(fstat_plan_t plan, int32_t segment, int32_t* nfft, int32_t* p,
                              int32_t* q, int32_t* templates_per_launch, int32_t* skies_per_batch,
-                             int32_t* pass_a_variant);
+                             int32_t* pass_a_variant, int32_t* pass_b_variant);
 
 /* Autotuner: time the search of `segment` (its own data, a synthetic sky and
  * spindown grid) for candidate templates-per-launch, skies-per-batch and
  * first-pass kernel variants that fit the workspace budget, keep the fastest,
  * and append it to options.tuning_cache_path if set (one line per device,
- * FFT length and precision).  Runs synchronously on `stream` for roughly
+ * FFT length and precision: "<device> <nfft> <precision> <templates per
+ * launch> <skies per batch> <pass_a_variant + 2 pass_b_variant>"; the last
+ * matching line wins).  Runs synchronously on `stream` for roughly
  * budget_ms.  Must be called before fstat_plan_set_workspace: the workspace
  * size changes with the batch sizes (query it again afterwards), and before
  * fstat_plan_attach_vetter.  Candidates found by the trial searches are

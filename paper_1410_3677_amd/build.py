@@ -30,7 +30,7 @@ def build(verbose: bool = False) -> str:
     src = os.path.join(CSRC, "fstat_lib.hip")
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           # packed FP32 instructions are disabled ("Build")
+           # packed FP32 instructions are disabled: the compiler emits no v_pk_*_f32
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wno-unused-command-line-argument",
            "-I", os.path.join(ROOT, "include"), src, "-o", tmp]

@@ -73,6 +73,7 @@ struct fstat_vet_s {
   void* mem = nullptr;           // one allocation for everything below
   float *theta = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
   uint16_t *wf2, *wt2, *wf3, *wt3, *w4b, *w5b;
+  uint16_t *wq2, *wq3;           // convolution weights in matrix-core fragment order (inference)
   float *u, *z1, *z2, *z3, *z4, *z5, *a5, *logit, *dlogit, *lterm, *dz5, *dh4, *dx, *da, *dwm, *loss;
   float* scratch = nullptr;      // split-K partial tiles and reduction partials
   uint16_t *a1b, *a2b, *a3b, *a4b, *colA, *colB, *colC, *dz5b, *dz4b, *dzb;
@@ -86,6 +87,8 @@ struct fstat_plan_s {
   int device = 0;
   int Sb = 1, B = 1;           // skies per batch, templates per launch
   int variant_a = 0;           // pass A kernel variant (0 sequential series, 1 paired)
+  int variant_b = 1;           // pass B kernel variant (0 row tiles, 1 streaming wavefronts)
+  int n_cu = 256;              // compute units of the device
   size_t cx_bytes = 8;
   // workspace
   void* ws = nullptr;
@@ -379,6 +382,10 @@ static fstat_status run_sky_batch(fstat_plan_t p, const Dev<T>& d, const SegInfo
 }
 
 // Template stage for the nb skies of the current batch: nb * nfdot templates in launches of B.
+// workgroups per compute unit resident at once in the streaming second pass (its LDS and
+// registers allow four)
+constexpr int STREAM_WG_PER_CU = 4;
+
 template <typename T>
 static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo& si, int sky0, int nb,
                                   const double* fdot, int nfdot, int mode, OutArgs oa, hipStream_t st) {
@@ -404,12 +411,20 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
         constexpr int QQ = decltype(c)::value;
         if constexpr (QQ >= 64) {
           const int ntiles = si.P / tw_a<T, QQ>();
-          if (p->variant_a == 1)
-            hipLaunchKernelGGL((k_tmpl_a_pair<T, QQ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T>()), 0, st, ta, d.zt(),
-                               tbuf, d.twst, d.lo(si.logL), d.hi(si.logL));
-          else
-            hipLaunchKernelGGL((k_tmpl_a<T, QQ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T>()), 0, st, ta, d.zt(), tbuf,
-                               d.twst, d.lo(si.logL), d.hi(si.logL));
+          // first-stage inputs r >= rnz are zero for every column when n <= rnz nfft / 8
+          const int rnz = (8L * si.s.n <= 3L * si.nfft) ? 3 : (8L * si.s.n <= 4L * si.nfft) ? 4 : 8;
+          auto go = [&](auto rnz_c) {
+            constexpr int RZ = decltype(rnz_c)::value;
+            if (p->variant_a == 1)
+              hipLaunchKernelGGL((k_tmpl_a_pair<T, QQ, RZ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T>()), 0, st, ta,
+                                 d.zt(), tbuf, d.twst, d.lo(si.logL), d.hi(si.logL));
+            else
+              hipLaunchKernelGGL((k_tmpl_a<T, QQ, RZ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T>()), 0, st, ta, d.zt(),
+                                 tbuf, d.twst, d.lo(si.logL), d.hi(si.logL));
+          };
+          if (rnz == 3) go(std::integral_constant<int, 3>{});
+          else if (rnz == 4) go(std::integral_constant<int, 4>{});
+          else go(std::integral_constant<int, 8>{});
           err = hipGetLastError();
         } else {
           err = hipErrorInvalidValue;
@@ -426,6 +441,31 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
       ProfScope ps(p, FSTAT_KERNEL_TEMPLATE_B, st);
       with_len(si.P, [&](auto c) {
         constexpr int PP = decltype(c)::value;
+        if constexpr (sizeof(T) == 4 && PP >= 64 && PP <= 512) {
+          if (p->variant_b == 1) {
+          // streaming kernel: about one resident round of wavefronts walks the launch's row units
+          const long waves = (long)nt * (si.Q / stream_rpw<PP>());
+          const long wgs = std::min((waves + 3) / 4, (long)p->n_cu * STREAM_WG_PER_CU);
+          const dim3 grid((unsigned)wgs);
+          const bool half = (oa.k_min == 0 && oa.k_max == si.nfft / 2);
+          auto go = [&](auto mode_c, auto half_c) {
+            constexpr int MD = decltype(mode_c)::value;
+            constexpr bool HF = decltype(half_c)::value;
+            hipLaunchKernelGGL((k_tmpl_b_stream<T, PP, MD, HF>), grid, dim3(256), 0, st, ta, nt, d.sp(), tbuf, oa,
+                               d.twst);
+          };
+          using I0 = std::integral_constant<int, 0>;
+          using I1 = std::integral_constant<int, 1>;
+          using I2 = std::integral_constant<int, 2>;
+          using BT = std::true_type;
+          using BF = std::false_type;
+          if (capture) half ? go(I2{}, BT{}) : go(I2{}, BF{});
+          else if (mode == 0) half ? go(I0{}, BT{}) : go(I0{}, BF{});
+          else half ? go(I1{}, BT{}) : go(I1{}, BF{});
+          err = hipGetLastError();
+          return;
+          }
+        }
         if constexpr (PP >= 64) {
           const int ntiles = si.Q / tw_b<T, PP>();
           if (capture)
@@ -599,7 +639,7 @@ static bool cache_lookup(const char* path, const std::string& tag, long nfft, in
   int pr, b, sb, v;
   bool found = false;
   while (std::fscanf(f, "%127s %ld %d %d %d %d", dtag, &nf, &pr, &b, &sb, &v) == 6) {
-    if (tag == dtag && nf == nfft && pr == prec && b > 0 && sb > 0 && (v == 0 || v == 1)) {
+    if (tag == dtag && nf == nfft && pr == prec && b > 0 && sb > 0 && v >= 0 && v <= 3) {
       *B = b;
       *Sb = sb;
       *var = v;
@@ -672,6 +712,28 @@ __global__ void k_vet_store_scores(CandEntry* cand, const float* logit, long n) 
 void vet_prepare(fstat_vet_t v, hipStream_t st) {
   hipLaunchKernelGGL(vet::k_vet_prepare, blocks_for((long)vet::H * vet::X), dim3(256), 0, st, v->theta, v->wf2,
                      v->wt2, v->wf3, v->wt3, v->w4b, v->w5b);
+  hipLaunchKernelGGL(vet::k_vet_prepare_frag, blocks_for(vet::WQ_ELEMS), dim3(256), 0, st, v->theta, v->wq2, v->wq3);
+}
+
+// inference of n <= max_batch patches (logits to `out`): fused LDS convolutions, the
+// 8192 -> 128 layer as an LDS-tiled product split four ways along K, then the small layers
+constexpr int INFER_SPLITS = 4;
+void vet_infer_batch(fstat_vet_t v, const float* patches, int n, float* out, hipStream_t st) {
+  using namespace vet;
+  const int nbp = (n + GT - 1) / GT * GT;
+  hipLaunchKernelGGL(k_vet_conv_infer, dim3((n + CV_NP - 1) / CV_NP), dim3(256), 0, st, patches, n, v->theta, v->wq2,
+                     v->wq3, v->a3b);
+  hipLaunchKernelGGL(k_gemm_nt_lds, dim3(H / GT, nbp / GT, INFER_SPLITS), dim3(256), 0, st, nbp, H, X, v->a3b, v->w4b,
+                     v->scratch, X / INFER_SPLITS);
+  const long count = (long)nbp * H;
+  hipLaunchKernelGGL(k_vet_sum_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, v->scratch,
+                     INFER_SPLITS, count, H, (long)H, v->z4);
+  hipLaunchKernelGGL(k_vet_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->z4, (long)n, H, v->theta + O_B4,
+                     v->a4b, (float*)nullptr);
+  gemm(st, n, H, H, v->a4b, H, 1, v->w5b, 1, H, v->z5, H);
+  hipLaunchKernelGGL(k_vet_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->z5, (long)n, H, v->theta + O_B5,
+                     (uint16_t*)nullptr, v->a5);
+  hipLaunchKernelGGL(k_vet_fc3, blocks_for(n), dim3(256), 0, st, v->a5, n, v->theta, out);
 }
 
 // forward of n <= max_batch patches; logits to `out`
@@ -749,19 +811,20 @@ fstat_status fstat_vet_create(int32_t max_batch, fstat_vet_t* out) {
   if (!v) return vet_fail(nullptr, FSTAT_E_NOMEM, "vetter allocation");
   v->max_batch = max_batch;
   const size_t nb = (size_t)max_batch, NL = nb * L;
+  const size_t nbp = (nb + GT - 1) / GT * GT;  // rows of the 8192 -> 128 product
   struct Part { void** p; size_t bytes; };
   std::vector<Part> parts = {
       {(void**)&v->theta, N_PARAMS * 4}, {(void**)&v->grad, N_PARAMS * 4}, {(void**)&v->m1, N_PARAMS * 4},
       {(void**)&v->m2, N_PARAMS * 4}, {(void**)&v->wf2, KC * C * 2}, {(void**)&v->wt2, KC * C * 2},
       {(void**)&v->wf3, KC * C * 2}, {(void**)&v->wt3, KC * C * 2}, {(void**)&v->w4b, (size_t)H * X * 2},
-      {(void**)&v->w5b, H * H * 2}, {(void**)&v->u, NL * 4}, {(void**)&v->z1, NL * C * 4},
-      {(void**)&v->z2, NL * C * 4}, {(void**)&v->z3, NL * C * 4}, {(void**)&v->z4, nb * H * 4},
+      {(void**)&v->w5b, H * H * 2}, {(void**)&v->wq2, WQ_ELEMS * 2}, {(void**)&v->wq3, WQ_ELEMS * 2}, {(void**)&v->u, NL * 4}, {(void**)&v->z1, NL * C * 4},
+      {(void**)&v->z2, NL * C * 4}, {(void**)&v->z3, NL * C * 4}, {(void**)&v->z4, nbp * H * 4},
       {(void**)&v->z5, nb * H * 4}, {(void**)&v->a5, nb * H * 4}, {(void**)&v->logit, nb * 4},
       {(void**)&v->dlogit, nb * 4}, {(void**)&v->lterm, nb * 4}, {(void**)&v->dz5, nb * H * 4},
       {(void**)&v->dh4, nb * H * 4}, {(void**)&v->dx, NL * C * 4}, {(void**)&v->da, NL * C * 4},
       {(void**)&v->dwm, KC * C * 4}, {(void**)&v->loss, 4}, {(void**)&v->scratch, (size_t)VET_SCRATCH * 4},
       {(void**)&v->a1b, NL * C * 2},
-      {(void**)&v->a2b, NL * C * 2}, {(void**)&v->a3b, NL * C * 2}, {(void**)&v->a4b, nb * H * 2},
+      {(void**)&v->a2b, NL * C * 2}, {(void**)&v->a3b, nbp * X * 2}, {(void**)&v->a4b, nb * H * 2},
       {(void**)&v->colA, NL * KC * 2}, {(void**)&v->colB, NL * KC * 2}, {(void**)&v->colC, NL * KC * 2},
       {(void**)&v->dz5b, nb * H * 2}, {(void**)&v->dz4b, nb * H * 2}, {(void**)&v->dzb, NL * C * 2}};
   size_t total = 0;
@@ -809,7 +872,7 @@ fstat_status fstat_vet_forward(fstat_vet_t v, const float* patches, int64_t n, f
   hipStream_t st = (hipStream_t)stream;
   for (int64_t i = 0; i < n; i += v->max_batch) {
     const int b = (int)std::min<int64_t>(v->max_batch, n - i);
-    vet_forward_batch(v, patches + i * vet::L, b, logits + i, st);
+    vet_infer_batch(v, patches + i * vet::L, b, logits + i, st);
     VET_TRY(v, hipGetLastError(), "forward launch");
   }
   return FSTAT_OK;
@@ -1033,7 +1096,8 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_opt
         cache_lookup(opt.tuning_cache_path, device_tag(), p->L_max, opt.precision, &tb, &ts, &tv)) {
       B = tb;
       Sb = ts;
-      p->variant_a = tv;
+      p->variant_a = tv & 1;
+      p->variant_b = tv >> 1;
       tuned = true;
     }
   }
@@ -1064,6 +1128,11 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_opt
     return fail(nullptr, FSTAT_E_DEVICE, "no HIP device available");
   }
   (void)hipGetDevice(&p->device);
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && ncu > 0)
+      p->n_cu = ncu;
+  }
   std::vector<unsigned char> tb;
   fill_tables<float>(tb, p->tab, 0, KT_F32);
   fill_tables<double>(tb, p->tab, 1, KT_F64);
@@ -1310,7 +1379,8 @@ fstat_status fstat_profile_read(fstat_plan_t plan, int32_t kernel_class, int64_t
 }
 
 fstat_status fstat_plan_info(fstat_plan_t plan, int32_t segment, int32_t* nfft, int32_t* p, int32_t* q,
-                             int32_t* templates_per_launch, int32_t* skies_per_batch, int32_t* pass_a_variant) {
+                             int32_t* templates_per_launch, int32_t* skies_per_batch, int32_t* pass_a_variant,
+                             int32_t* pass_b_variant) {
   if (!plan || segment < 0 || segment >= (int32_t)plan->segs.size())
     return fail(plan, FSTAT_E_INVAL, "bad arguments");
   const SegInfo& si = plan->segs[segment];
@@ -1320,6 +1390,7 @@ fstat_status fstat_plan_info(fstat_plan_t plan, int32_t segment, int32_t* nfft, 
   if (templates_per_launch) *templates_per_launch = plan->B;
   if (skies_per_batch) *skies_per_batch = plan->Sb;
   if (pass_a_variant) *pass_a_variant = plan->variant_a;
+  if (pass_b_variant) *pass_b_variant = plan->variant_b;
   return FSTAT_OK;
 }
 
@@ -1426,7 +1497,7 @@ fstat_status fstat_autotune(fstat_plan_t plan, int32_t segment, double budget_ms
     FILE* f = std::fopen(plan->opt.tuning_cache_path, "a");
     if (f) {
       std::fprintf(f, "%s %ld %d %d %d %d\n", device_tag().c_str(), plan->L_max, plan->opt.precision, plan->B,
-                   plan->Sb, plan->variant_a);
+                   plan->Sb, plan->variant_a | (plan->variant_b << 1));
       std::fclose(f);
     }
   }

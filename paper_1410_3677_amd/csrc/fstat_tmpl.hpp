@@ -160,11 +160,49 @@ __host__ __device__ constexpr int last_ns() {
   else return last_ns<LEN, NS * stage_radix<LEN, NS>()>();
 }
 
+// Forward 8-point DFT of x[0 .. RNZ-1] with x[RNZ ..] = 0 (RNZ = 3 or 4), in place.
+// With at most four nonzero inputs the first radix-2 layer is a copy:
+// X[k] = E[k mod 4] + W8^k O[k mod 4], E and O the 4-point DFTs of the even and odd
+// inputs (x3 = 0 when RNZ = 3).
+template <typename T, int RNZ>
+__device__ __forceinline__ void dft8_pruned(cx<T>* v) {
+  static_assert(RNZ == 3 || RNZ == 4, "pruned first stage");
+  const T h = (T)0.70710678118654752440084436210485;
+  const cx<T> x0 = v[0], x1 = v[1], x2 = v[2];
+  // E = DFT4(x0, x2, 0, 0): x0 + x2, x0 - i x2, x0 - x2, x0 + i x2
+  const cx<T> e0 = x0 + x2, e2 = x0 - x2;
+  const cx<T> e1 = mk<T>(x0.re + x2.im, x0.im - x2.re), e3 = mk<T>(x0.re - x2.im, x0.im + x2.re);
+  cx<T> o0, o1, o2, o3;
+  if constexpr (RNZ == 4) {
+    const cx<T> x3 = v[3];
+    o0 = x1 + x3;
+    o2 = x1 - x3;
+    o1 = mk<T>(x1.re + x3.im, x1.im - x3.re);
+    o3 = mk<T>(x1.re - x3.im, x1.im + x3.re);
+  } else {
+    o0 = o1 = o2 = o3 = x1;
+  }
+  // W8^k O[k]: k = 1: h (1 - i), k = 2: -i, k = 3: h (-1 - i)
+  const cx<T> w1 = mk<T>(h * (o1.re + o1.im), h * (o1.im - o1.re));
+  const cx<T> w2 = mul_mi<T, false>(o2);
+  const cx<T> w3 = mk<T>(h * (o3.im - o3.re), -h * (o3.re + o3.im));
+  v[0] = e0 + o0;
+  v[4] = e0 - o0;
+  v[1] = e1 + w1;
+  v[5] = e1 - w1;
+  v[2] = e2 + w2;
+  v[6] = e2 - w2;
+  v[3] = e3 + w3;
+  v[7] = e3 - w3;
+}
+
 // First stage of pass A for both series: y[j1 + P j2], j2 = j + NB1 r (zero for
 // j1 + P j2 >= n), times the spindown chirp exp(-i pi fdot (j dt)^2) whose phase is
 // evaluated in FP64 and reduced to [0, 1) cycles, then a radix-R1 DFT in registers.
-// All loads are issued before any chirp is computed so that they overlap.
-template <typename T, int Q, int G, int R1, int NB1, int PB1>
+// All loads are issued before any chirp is computed so that they overlap.  RNZ < R1
+// states that inputs r >= RNZ are zero for every column (n <= RNZ nfft / 8), so they
+// are neither loaded nor transformed.
+template <typename T, int Q, int G, int R1, int NB1, int PB1, int RNZ = R1>
 __device__ __forceinline__ void chirped_first_stage(cx<T> (&va)[PB1][R1], cx<T> (&vb)[PB1][R1],
                                                     const cx<T>* __restrict__ za, const cx<T>* __restrict__ zb,
                                                     int j1, int g, int P, int n, double half_fdot_dt2) {
@@ -172,7 +210,7 @@ __device__ __forceinline__ void chirped_first_stage(cx<T> (&va)[PB1][R1], cx<T> 
   for (int b = 0; b < PB1; ++b) {
     const unsigned j = (unsigned)(g + G * b);
 #pragma unroll
-    for (int r = 0; r < R1; ++r) {
+    for (int r = 0; r < RNZ; ++r) {
       const unsigned jj = (unsigned)j1 + (unsigned)P * (j + (unsigned)(NB1 * r));
       va[b][r] = mk<T>(0, 0);
       vb[b][r] = mk<T>(0, 0);
@@ -182,7 +220,7 @@ __device__ __forceinline__ void chirped_first_stage(cx<T> (&va)[PB1][R1], cx<T> 
       }
     }
 #pragma unroll
-    for (int r = 0; r < R1; ++r) {
+    for (int r = 0; r < RNZ; ++r) {
       const unsigned jj = (unsigned)j1 + (unsigned)P * (j + (unsigned)(NB1 * r));
       if (jj < (unsigned)n) {
         const double x = (double)jj;
@@ -202,8 +240,14 @@ __device__ __forceinline__ void chirped_first_stage(cx<T> (&va)[PB1][R1], cx<T> 
         vb[b][r] = cmul(vb[b][r], w);
       }
     }
-    dftr<T, R1, false>(va[b]);
-    dftr<T, R1, false>(vb[b]);
+    if constexpr (RNZ < R1) {
+      static_assert(R1 == 8, "pruning is for radix-8 first stages");
+      dft8_pruned<T, RNZ>(va[b]);
+      dft8_pruned<T, RNZ>(vb[b]);
+    } else {
+      dftr<T, R1, false>(va[b]);
+      dftr<T, R1, false>(vb[b]);
+    }
   }
 }
 
@@ -211,7 +255,7 @@ __device__ __forceinline__ void chirped_first_stage(cx<T> (&va)[PB1][R1], cx<T> 
 // Workgroup: TW adjacent columns j1 of one template; thread (c = t % TW, g = t / TW).
 // The two series share the chirp; they pass through one LDS tile one after the
 // other, the second series' first-stage outputs waiting in registers.
-template <typename T, int Q>
+template <typename T, int Q, int RNZ = stage_radix<Q, 1>()>
 __global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a(TmplArgs ta, const cx<T>* __restrict__ zt,
                                                            cx<T>* __restrict__ tbuf,
                                                            const cx<T>* __restrict__ twst,
@@ -237,7 +281,7 @@ __global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a(TmplArgs ta, const cx
   cx<T>* col = lds + c * ST;
   // first stage: y[j1 + P j2] with the spindown chirp, radix-R1 butterflies in registers
   cx<T> va[PB1][R1], vb[PB1][R1];
-  chirped_first_stage<T, Q, G, R1, NB1, PB1>(va, vb, za, zb, j1, g, ta.P, ta.n, half_fdot_dt2);
+  chirped_first_stage<T, Q, G, R1, NB1, PB1, RNZ>(va, vb, za, zb, j1, g, ta.P, ta.n, half_fdot_dt2);
   // twiddles W^(j1 k2) of the last-stage outputs k2 = j + NSL r: W^(j1 j) times powers of W^(j1 NSL)
   constexpr int NSL = last_ns<Q, 1>();
   constexpr int RL = stage_radix<Q, NSL>();
@@ -279,7 +323,7 @@ __global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a(TmplArgs ta, const cx
 // Pass A, paired variant: both series in LDS at once (twice the tile, half the
 // barriers).  The same operations as k_tmpl_a (the compiler may contract
 // multiply-adds differently, so results can differ in the last bit).
-template <typename T, int Q>
+template <typename T, int Q, int RNZ = stage_radix<Q, 1>()>
 __global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a_pair(TmplArgs ta, const cx<T>* __restrict__ zt,
                                                                 cx<T>* __restrict__ tbuf,
                                                                 const cx<T>* __restrict__ twst,
@@ -306,7 +350,7 @@ __global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a_pair(TmplArgs ta, con
   cx<T>* colb = lds + (TW + c) * ST;
   {
     cx<T> va[PB1][R1], vb[PB1][R1];
-    chirped_first_stage<T, Q, G, R1, NB1, PB1>(va, vb, za, zb, j1, g, ta.P, ta.n, half_fdot_dt2);
+    chirped_first_stage<T, Q, G, R1, NB1, PB1, RNZ>(va, vb, za, zb, j1, g, ta.P, ta.n, half_fdot_dt2);
     stage_to_lds<T, Q, G, 1, R1, PB1>(va, cola, g);
     stage_to_lds<T, Q, G, 1, R1, PB1>(vb, colb, g);
     __syncthreads();
@@ -479,6 +523,298 @@ __global__ void __launch_bounds__((tmpl_nt_b<T, P>())) k_tmpl_b(TmplArgs ta, con
       }
     }
   }
+}
+
+// ---------------------------------------------------------------- pass B, streaming (FP32, P <= 512)
+// Each wavefront owns RPW = 64 / G whole rows and walks NR row units of one template.  The eight loads per series of the next unit are issued before the current
+// unit is transformed, so HBM reads overlap the butterflies; twiddles of the stages
+// after the first stay in registers for the whole walk; all LDS exchanges are local to
+// the wavefront; candidates are compacted with ballots and one atomic per wavefront
+// and unit that has any.  When the searched bins are exactly [0, nfft/2) (HALF), the
+// last stage computes only the outputs k1 < P/2 and no bin needs a range check.
+
+// Twiddles of the stage at stride NS and of all later stages, for butterflies j = g + G b.
+template <typename T, int LEN, int G, int NS, bool MORE = (NS < LEN)>
+struct StageTw {
+  static constexpr int R = stage_radix<LEN, NS>();
+  static constexpr int PB = (LEN / R) / G;
+  cx<T> w[PB][R - 1];
+  StageTw<T, LEN, G, NS * R> next;
+  __device__ __forceinline__ void load(const cx<T>* __restrict__ twst, int g) {
+#pragma unroll
+    for (int b = 0; b < PB; ++b)
+#pragma unroll
+      for (int r = 1; r < R; ++r) w[b][r - 1] = stage_tw<T, NS, R, false>(twst, (g + G * b) % NS, r);
+    next.load(twst, g);
+  }
+};
+template <typename T, int LEN, int G, int NS>
+struct StageTw<T, LEN, G, NS, false> {
+  __device__ __forceinline__ void load(const cx<T>* __restrict__, int) {}
+};
+
+// The first R/2 outputs of a forward R-point DFT (v[0 .. R/2 - 1]; the rest is garbage).
+// Even outputs are the R/2-point DFT of x[n] + x[n + R/2], odd ones that of
+// (x[n] - x[n + R/2]) W_R^n, of which only the first halves are formed.
+template <typename T, int R>
+__device__ __forceinline__ void dft_first_half(cx<T>* v) {
+  if constexpr (R == 2) {
+    v[0] = v[0] + v[1];
+  } else if constexpr (R == 4) {
+    const cx<T> s02 = v[0] + v[2], d02 = v[0] - v[2];
+    const cx<T> s13 = v[1] + v[3], d13 = mul_mi<T, false>(v[1] - v[3]);
+    v[0] = s02 + s13;
+    v[1] = d02 + d13;
+  } else {
+    const T h = (T)0.70710678118654752440084436210485;
+    const cx<T> a0 = v[0] + v[4], a1 = v[1] + v[5], a2 = v[2] + v[6], a3 = v[3] + v[7];
+    const cx<T> d0 = v[0] - v[4], e1 = v[1] - v[5], e2 = v[2] - v[6], e3 = v[3] - v[7];
+    const cx<T> d1 = mk<T>(h * (e1.re + e1.im), h * (e1.im - e1.re));
+    const cx<T> d2 = mul_mi<T, false>(e2);
+    const cx<T> d3 = mk<T>(h * (e3.im - e3.re), -h * (e3.re + e3.im));
+    v[0] = (a0 + a2) + (a1 + a3);
+    v[2] = (a0 - a2) + mul_mi<T, false>(a1 - a3);
+    v[1] = (d0 + d2) + (d1 + d3);
+    v[3] = (d0 - d2) + mul_mi<T, false>(d1 - d3);
+  }
+}
+
+// Stage loads and stores addressed as one base plus compile-time offsets: for the strides
+// used here phys(a + c) = phys(a) + c + c/8 (c a multiple of 8, or a % 8 + c < 8).
+template <typename T, int LEN, int G, int NS, int R, int PB, bool HALFOUT>
+__device__ __forceinline__ void stage_from_lds_reg(cx<T> (&v)[PB][R], const cx<T>* col, int g,
+                                                   const cx<T> (&w)[PB][R - 1]) {
+  constexpr int NB = LEN / R;
+  static_assert(NB % 8 == 0, "constant offsets need NB a multiple of 8");
+  const cx<T>* p = col + phys(g);
+#pragma unroll
+  for (int b = 0; b < PB; ++b) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int c = G * b + r * NB;  // G * b is a multiple of 8 when PB > 1
+      cx<T> x = p[c + c / 8];
+      if (r > 0) x = cmul(x, w[b][r - 1]);
+      v[b][r] = x;
+    }
+    if constexpr (HALFOUT) dft_first_half<T, R>(v[b]);
+    else dftr<T, R, false>(v[b]);
+  }
+}
+
+template <typename T, int LEN, int G, int NS, int R, int PB>
+__device__ __forceinline__ void stage_to_lds_off(const cx<T> (&v)[PB][R], cx<T>* col, int g) {
+#pragma unroll
+  for (int b = 0; b < PB; ++b) {
+    const int j = g + G * b;
+    const int base = (j / NS) * NS * R + (j % NS);
+    cx<T>* p = col + phys(base);
+#pragma unroll
+    for (int r = 0; r < R; ++r) p[r * NS + (r * NS) / 8] = v[b][r];
+  }
+}
+
+template <typename T, int LEN, int G, int NS>
+__device__ __forceinline__ void middle_stages_reg(cx<T>* cola, cx<T>* colb, int g, const StageTw<T, LEN, G, NS>& tw) {
+  constexpr int R = stage_radix<LEN, NS>();
+  if constexpr (NS * R < LEN) {
+    constexpr int PB = (LEN / R) / G;
+    cx<T> va[PB][R], vb[PB][R];
+    stage_from_lds_reg<T, LEN, G, NS, R, PB, false>(va, cola, g, tw.w);
+    stage_from_lds_reg<T, LEN, G, NS, R, PB, false>(vb, colb, g, tw.w);
+    stage_sync<true>();
+    stage_to_lds_off<T, LEN, G, NS, R, PB>(va, cola, g);
+    stage_to_lds_off<T, LEN, G, NS, R, PB>(vb, colb, g);
+    stage_sync<true>();
+    middle_stages_reg<T, LEN, G, NS * R>(cola, colb, g, tw.next);
+  }
+}
+
+template <typename T, int LEN, int G, int NS>
+__device__ __forceinline__ const auto& last_stage_tw(const StageTw<T, LEN, G, NS>& tw) {
+  if constexpr (NS * stage_radix<LEN, NS>() >= LEN) return tw;
+  else return last_stage_tw<T, LEN, G, NS * stage_radix<LEN, NS>()>(tw.next);
+}
+
+// Candidates a wavefront stages in LDS before it reserves their slots with one atomic.
+constexpr int STAGE_CAP = 32;
+
+// Row units per wavefront step: RPW rows of P points.
+template <int P>
+__host__ __device__ constexpr int stream_rpw() { return 64 / groups_per_col<P>(); }
+
+template <typename T, int P, int MODE, bool HALF>
+__global__ void __launch_bounds__(256) k_tmpl_b_stream(TmplArgs ta, int ntmpl, const SkyParams* __restrict__ sp,
+                                                       const cx<T>* __restrict__ tbuf, OutArgs oa,
+                                                       const cx<T>* __restrict__ twst) {
+  constexpr int G = groups_per_col<P>();
+  static_assert(G <= 64 && 64 % G == 0, "rows must tile a wavefront");
+  constexpr int RPW = stream_rpw<P>();
+  constexpr int ST = col_stride<P>(16);
+  constexpr int R1 = stage_radix<P, 1>();
+  constexpr int NB1 = P / R1, PB1 = NB1 / G;
+  static_assert(PB1 >= 1 && NB1 % G == 0, "first stage must give each lane whole butterflies");
+  constexpr int NSL = last_ns<P, 1>();
+  constexpr int RL = stage_radix<P, NSL>();
+  constexpr int PBL = (P / RL) / G;
+  constexpr int ROUT = HALF ? RL / 2 : RL;
+  constexpr int NOUT = PBL * ROUT;
+  static_assert(NOUT <= 32, "output mask");
+  __shared__ cx<T> lds[4 * 2 * RPW * ST];
+  // per-wavefront candidate staging: (template of the launch, bin, 2F)
+  __shared__ int st_item[4][STAGE_CAP];
+  __shared__ int st_bin[4][STAGE_CAP];
+  __shared__ float st_val[4][STAGE_CAP];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int units = ta.Q / RPW;        // row units of one template
+  const int total = ntmpl * units;     // row units of the launch
+  const int nw = gridDim.x * 4;        // wavefronts of the grid
+  const int sub = lane / G, g = lane % G;
+  cx<T>* cola = lds + (wave * 2 * RPW + sub) * ST;
+  cx<T>* colb = cola + RPW * ST;
+  const T thr = (T)oa.threshold;
+  const int search = oa.search_next[0] - 1;
+  StageTw<T, P, G, R1> tw;
+  tw.load(twst, g);
+  const auto& twl = last_stage_tw<T, P, G, R1>(tw);
+  const int lofs = sub * P + g;
+
+  // unit U of the launch: template U / units, rows (U % units) RPW + sub
+  auto load_unit = [&](cx<T> (&ca)[PB1][R1], cx<T> (&cb)[PB1][R1], int U) {
+    const int item = U / units, u = U - item * units;
+    const cx<T>* pa = tbuf + (long)(2 * item) * ta.L + (long)u * (RPW * P);
+    const cx<T>* pb = pa + ta.L;
+#pragma unroll
+    for (int b = 0; b < PB1; ++b)
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        ca[b][r] = pa[lofs + G * b + NB1 * r];
+        cb[b][r] = pb[lofs + G * b + NB1 * r];
+      }
+  };
+
+  auto emit = [&](unsigned long long slot, int item, int bin, T v) {
+    if (slot < (unsigned long long)oa.capacity) {
+      const int t = ta.t0 + item;
+      const int skyl = t / ta.nfdot;
+      CandEntry ce;
+      ce.search = search;
+      ce.segment = oa.segment;
+      ce.sky = ta.sky0 + skyl;
+      ce.fdot_idx = t - skyl * ta.nfdot;
+      ce.bin = bin;
+      ce.pad = 0;
+      ce.twoF = (double)v;
+      oa.cand[slot] = ce;
+    }
+  };
+  // one atomic reserves the slots of all staged candidates
+  int nstaged = 0;
+  auto flush = [&]() {
+    if (nstaged == 0) return;
+    stage_sync<true>();
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(oa.count, (unsigned long long)nstaged);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)base);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(base >> 32));
+    base = ((unsigned long long)hi << 32) | lo;
+    if (lane < nstaged) emit(base + lane, st_item[wave][lane], st_bin[wave][lane], (T)st_val[wave][lane]);
+    stage_sync<true>();
+    nstaged = 0;
+  };
+
+  // Wavefront w takes units w, w + nw, w + 2 nw, ...: the grid is about one resident
+  // round of wavefronts, so the rows being read at any time form one contiguous window.
+  int U = blockIdx.x * 4 + wave;
+  if (U >= total) return;
+  cx<T> xa[PB1][R1], xb[PB1][R1];
+  load_unit(xa, xb, U);
+  for (; U < total; U += nw) {
+    const int item = U / units;
+    const int u = U - item * units;
+    const int t = ta.t0 + item;
+    const int skyl = t / ta.nfdot, sidx = t - skyl * ta.nfdot;
+    const SkyParams& pr = sp[skyl];
+    const T cfa = (T)pr.cfa, cfb = (T)pr.cfb, cfab = (T)pr.cfab;
+#pragma unroll
+    for (int b = 0; b < PB1; ++b) {
+      dftr<T, R1, false>(xa[b]);
+      dftr<T, R1, false>(xb[b]);
+    }
+    stage_sync<true>();  // the previous unit's last stage has read the slab
+    stage_to_lds_off<T, P, G, 1, R1, PB1>(xa, cola, g);
+    stage_to_lds_off<T, P, G, 1, R1, PB1>(xb, colb, g);
+    stage_sync<true>();
+    // the next unit's loads go into the registers just freed and overlap the rest
+    if (U + nw < total) load_unit(xa, xb, U + nw);
+    middle_stages_reg<T, P, G, R1>(cola, colb, g, tw);
+    cx<T> fa[PBL][RL], fb[PBL][RL];
+    stage_from_lds_reg<T, P, G, NSL, RL, PBL, HALF>(fa, cola, g, twl.w);
+    stage_from_lds_reg<T, P, G, NSL, RL, PBL, HALF>(fb, colb, g, twl.w);
+    const int k2 = u * RPW + sub;
+    if constexpr (MODE == 1) {
+      T* out = (T*)oa.spectrum + ((long)(ta.sky0 + skyl) * ta.nfdot + sidx) * (long)(oa.k_max - oa.k_min);
+#pragma unroll
+      for (int b = 0; b < PBL; ++b)
+#pragma unroll
+        for (int r = 0; r < ROUT; ++r) {
+          const int k = ta.Q * (g + G * b + NSL * r) + k2;
+          if (HALF || (k >= oa.k_min && k < oa.k_max))
+            out[k - oa.k_min] = two_f_value(fa[b][r], fb[b][r], cfa, cfb, cfab);
+        }
+    } else {
+      float* srow = (float*)oa.spectrum + (long)item * (long)(oa.k_max - oa.k_min);
+      uint32_t mask = 0;
+      T val[NOUT];
+#pragma unroll
+      for (int b = 0; b < PBL; ++b)
+#pragma unroll
+        for (int r = 0; r < ROUT; ++r) {
+          const int k = ta.Q * (g + G * b + NSL * r) + k2;
+          const T v = two_f_value(fa[b][r], fb[b][r], cfa, cfb, cfab);
+          val[b * ROUT + r] = v;
+          const bool inr = HALF || (k >= oa.k_min && k < oa.k_max);
+          if (MODE == 2 && inr) srow[k - oa.k_min] = (float)v;
+          if (inr && v > thr) mask |= 1u << (b * ROUT + r);
+        }
+      if (__ballot(mask != 0)) {
+        int off[NOUT];
+        int total = 0;
+#pragma unroll
+        for (int q = 0; q < NOUT; ++q) {
+          const unsigned long long bi = __ballot((mask >> q) & 1u);
+          off[q] = total + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bi >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((unsigned)bi, 0u));
+          total += __popcll(bi);
+        }
+        if (nstaged + total > STAGE_CAP) flush();
+        if (total > STAGE_CAP) {
+          // a burst larger than the staging buffer goes straight out
+          unsigned long long base = 0;
+          if (lane == 0) base = atomicAdd(oa.count, (unsigned long long)total);
+          const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)base);
+          const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(base >> 32));
+          base = ((unsigned long long)hi << 32) | lo;
+#pragma unroll
+          for (int q = 0; q < NOUT; ++q)
+            if ((mask >> q) & 1u)
+              emit(base + (unsigned long long)off[q], item, ta.Q * (g + G * (q / ROUT) + NSL * (q % ROUT)) + k2,
+                   val[q]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < NOUT; ++q)
+            if ((mask >> q) & 1u) {
+              const int e = nstaged + off[q];
+              st_item[wave][e] = item;
+              st_bin[wave][e] = ta.Q * (g + G * (q / ROUT) + NSL * (q % ROUT)) + k2;
+              st_val[wave][e] = (float)val[q];
+            }
+          nstaged += total;
+        }
+      }
+    }
+  }
+  if constexpr (MODE != 1) flush();
 }
 
 // Count of candidates before a launch (read by the patch capture after it).

@@ -83,7 +83,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "fstat_sky_stages": (i32, [P, i32, dbl, dbl, P, P, P, P, P, P, P, P]),
         "fstat_profile_enable": (i32, [P, i32]),
         "fstat_profile_read": (i32, [P, i32, ctypes.POINTER(i64), ctypes.POINTER(dbl), i32]),
-        "fstat_plan_info": (i32, [P, i32] + [ctypes.POINTER(i32)] * 6),
+        "fstat_plan_info": (i32, [P, i32] + [ctypes.POINTER(i32)] * 7),
         "fstat_autotune": (i32, [P, i32, dbl, P]),
         "fstat_destroy": (i32, [P]),
         "fstat_strerror": (ctypes.c_char_p, [i32]),
@@ -174,10 +174,10 @@ class Plan:
             self._set_torch_workspace()
 
     def info(self, segment: int = 0) -> dict:
-        v = [ctypes.c_int32() for _ in range(6)]
+        v = [ctypes.c_int32() for _ in range(7)]
         _check(self.lib.fstat_plan_info(self.handle, segment, *[ctypes.byref(x) for x in v]), self.handle)
-        return dict(zip(("nfft", "p", "q", "templates_per_launch", "skies_per_batch", "pass_a_variant"),
-                        [x.value for x in v]))
+        return dict(zip(("nfft", "p", "q", "templates_per_launch", "skies_per_batch", "pass_a_variant",
+                         "pass_b_variant"), [x.value for x in v]))
 
     def autotune(self, segment: int = 0, budget_ms: float = 2000.0, stream=None) -> dict:
         """Run the autotuner, then give the plan a torch workspace of the new size."""

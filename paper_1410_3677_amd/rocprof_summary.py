@@ -85,7 +85,8 @@ def main(argv=None):
     f.add_argument("--templates-per-launch", type=int, required=True)
     f.add_argument("--json", default="")
     f.add_argument("--source-sha256", default="")
-    f.add_argument("--pass-a-variant", type=int, default=-1)
+    f.add_argument("--variants", type=int, default=-1,
+                   help="kernel variants of the profiled plan: pass_a_variant + 2 pass_b_variant")
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         print(trace(a.db, a.match))
@@ -93,8 +94,8 @@ def main(argv=None):
         res = traffic(a.fetch_db, a.write_db, a.copy_bytes, a.copy_match, a.templates_per_launch)
         if a.source_sha256:
             res["source_sha256"] = a.source_sha256
-        if a.pass_a_variant >= 0:
-            res["pass_a_variant"] = a.pass_a_variant
+        if a.variants >= 0:
+            res["variants"] = a.variants
         text = json.dumps(res, indent=1)
         if a.json:
             with open(a.json, "w") as fh:

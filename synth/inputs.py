@@ -244,7 +244,7 @@ def make_segment(n: int, dt: float = 2.0, f_off: float = 100.0, sigma: float = 1
                    lat=lat, gamma=gamma, phi_r=phi_r, injections=injs)
 
 
-# --- the workload configurations -------------------------------------------------------
+# --- the search workloads ----------------------------------------------------------------
 N_FULL = 86164            # two sidereal days at dt = 2 s
 THRESHOLD_2F = 20.0
 
@@ -260,30 +260,37 @@ class Workload:
     fp64: bool
 
 
-def workload(c: int, nsky: Optional[int] = None, nfdot: Optional[int] = None) -> Workload:
-    """Seeded inputs of the five workloads (noise seed 1000+c, injections 2000+c).
+# name -> seed offset of the workload's noise (1000 + offset) and injections (2000 + offset)
+WORKLOADS = {"tiny": 1, "full": 2, "batched": 3, "ragged": 4}
 
-    1: tiny, N=4096, 8 sky x 4 spindown, one SNR-10 injection, FP64 throughout.
-    2: full segment N=86164, 256 x 64 templates, one SNR-10 injection.
-    3: full segment N=86164, 4096 x 256 templates, five injections at SNR 8-20.
-    4: 32 ragged segments, N ~ U{20000..172328}, band offsets from Eq. 1,
-       0-3 injections each, 1024 x 128 templates per segment.
+
+def workload(name: str, nsky: Optional[int] = None, nfdot: Optional[int] = None) -> Workload:
+    """Seeded inputs of the four search workloads.
+
+    tiny:    N=4096, 8 sky x 4 spindown, one SNR-10 injection, FP64 throughout.
+    full:    one full segment N=86164, 256 x 64 templates, one SNR-10 injection.
+    batched: one full segment N=86164, 4096 x 256 templates, five injections at SNR 8-20.
+    ragged:  32 segments, N ~ U{20000..172328}, band offsets from Eq. 1,
+             0-3 injections each, 1024 x 128 templates per segment.
     nsky / nfdot override the grid size (parity tests use sub-grids).
     """
+    if name not in WORKLOADS:
+        raise ValueError(f"unknown workload {name!r}")
+    c = WORKLOADS[name]
     rng_inj = np.random.default_rng(2000 + c)
-    if c == 1:
+    if name == "tiny":
         injs = draw_injections(rng_inj, 1, 10.0, 10.0)
         segs = [make_segment(4096, 2.0, 100.0, 1.0, 1001, injs)]
         ns, nf, fp64 = 8, 4, True
-    elif c == 2:
+    elif name == "full":
         injs = draw_injections(rng_inj, 1, 10.0, 10.0)
         segs = [make_segment(N_FULL, 2.0, 100.0, 1.0, 1002, injs)]
         ns, nf, fp64 = 256, 64, False
-    elif c == 3:
+    elif name == "batched":
         injs = draw_injections(rng_inj, 5, 8.0, 20.0)
         segs = [make_segment(N_FULL, 2.0, 100.0, 1.0, 1003, injs)]
         ns, nf, fp64 = 4096, 256, False
-    elif c == 4:
+    else:
         segs = []
         for i in range(32):
             n = int(rng_inj.integers(20000, 172328 + 1))
@@ -291,10 +298,8 @@ def workload(c: int, nsky: Optional[int] = None, nfdot: Optional[int] = None) ->
             injs = draw_injections(rng_inj, int(rng_inj.integers(0, 4)), 8.0, 20.0)
             segs.append(make_segment(n, 2.0, f_off, 1.0, 1004 * 1000 + i, injs))
         ns, nf, fp64 = 1024, 128, False
-    else:
-        raise ValueError(f"unknown workload {c}")
     ns = nsky if nsky is not None else ns
     nf = nfdot if nfdot is not None else nf
     alpha, delta = fibonacci_sky(ns)
-    return Workload(name=f"c{c}", segments=segs, alpha=alpha, delta=delta,
+    return Workload(name=name, segments=segs, alpha=alpha, delta=delta,
                     fdot=spindown_grid(nf), threshold=THRESHOLD_2F, fp64=fp64)

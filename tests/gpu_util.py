@@ -18,6 +18,19 @@ def dev(a):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
+KEY_INT_FIELDS = ["search", "segment", "sky", "fdot_idx", "bin"]
+
+
+def assert_keys_equal(a, b):
+    """Candidate keys equal field by field; unscored vet_score values are NaN on both sides."""
+    assert a.shape == b.shape
+    for f in KEY_INT_FIELDS:
+        np.testing.assert_array_equal(a[f], b[f])
+    np.testing.assert_array_equal(np.isnan(a["vet_score"]), np.isnan(b["vet_score"]))
+    m = ~np.isnan(a["vet_score"])
+    np.testing.assert_array_equal(a["vet_score"][m], b["vet_score"][m])
+
+
 def make_plan(segments, **opts):
     from paper_1410_3677_amd import fstat as F
     return F.Plan([F.segment_to_device(s) for s in segments], **opts)

@@ -14,7 +14,8 @@ import torch as _torch  # imported at collection: the first import on a fresh bo
 import synth
 from oracle import fstat_oracle as ora
 from tests import pins
-from tests.gpu_util import (compare_candidates, gpu_spectrum, make_plan, note, oracle_spectrum, rel_err_floor)
+from tests.gpu_util import (assert_keys_equal, compare_candidates, gpu_spectrum, make_plan, note, oracle_spectrum,
+                            rel_err_floor)
 
 pytestmark = pytest.mark.gpu
 
@@ -34,12 +35,12 @@ def torch():
 
 @pytest.fixture(scope="module")
 def tiny():
-    return synth.workload(1)
+    return synth.workload("tiny")
 
 
 @pytest.fixture(scope="module")
 def full():
-    return synth.workload(2)
+    return synth.workload("full")
 
 
 def _stages(torch, plan, seg, al, de, fp64):
@@ -100,7 +101,7 @@ def test_sky_stages_mixed_full(torch, full):
 
 
 def test_spectrum_fp64_tiny(torch, tiny):
-    note("spectrum fp64 config-1 grid 8x4")
+    note("spectrum fp64, N=4096, grid 8x4")
     seg = tiny.segments[0]
     nfft = synth.nfft_for(seg.n)
     plan = make_plan([seg], precision=0)
@@ -112,7 +113,7 @@ def test_spectrum_fp64_tiny(torch, tiny):
 
 
 def test_candidates_fp64_tiny(torch, tiny):
-    note("candidates fp64 config-1 grid 8x4")
+    note("candidates fp64, N=4096, grid 8x4")
     seg = tiny.segments[0]
     nfft = synth.nfft_for(seg.n)
     plan = make_plan([seg], precision=0)
@@ -222,7 +223,7 @@ def test_plain_launches_equal_batched(torch, full):
         plan.destroy()
     (r1, k1, n1), (r2, k2, n2) = out
     assert n1 == n2 and n1 > 0
-    np.testing.assert_array_equal(k1, k2)
+    assert_keys_equal(k1, k2)
     np.testing.assert_array_equal(r1, r2)
 
 
@@ -242,6 +243,48 @@ def test_candidate_overflow_reports_true_count(torch, tiny):
     small.search_batch(0, al, de, fd)
     recs, keys, n = small.candidates(allow_overflow=True)
     assert n == n_all > 7 and len(recs) == 7
+
+
+def test_dense_crossings_match_oracle_mixed(torch, full):
+    """A low threshold (2F > 5: about 29% of bins) gives rows with more crossings than a
+    wavefront stages at once, so staged, flushed and burst emission all run."""
+    note("dense crossings, mixed, threshold 5")
+    seg = full.segments[0]
+    nfft = synth.nfft_for(seg.n)
+    from tests.gpu_util import dev
+    al, de, fd = full.alpha[:1], full.delta[:1], full.fdot[:2]
+    plan = make_plan([seg], threshold_2F=5.0, candidate_capacity=1 << 20)
+    plan.search_batch(0, dev(al), dev(de), dev(fd))
+    recs, keys, n = plan.candidates()
+    ref = oracle_spectrum(seg, al, de, fd, nfft)
+    key3 = np.stack([keys["sky"], keys["fdot_idx"], keys["bin"]], 1)
+    ng, no, flips, mism, err = compare_candidates(key3, recs["twoF"], ref, 5.0, 1e-4)
+    note(f"gpu {ng} oracle {no} flips {flips} mismatches {len(mism)} err {err:.3e}")
+    assert no > 50000 and not mism and err < 1e-4
+    # every key once
+    assert len(np.unique(key3, axis=0)) == len(key3)
+
+
+def test_candidate_overflow_mixed_keeps_a_valid_subset(torch, full):
+    seg = full.segments[0]
+    from tests.gpu_util import dev
+    from paper_1410_3677_amd import fstat as F
+    al, de, fd = dev(full.alpha[:2]), dev(full.delta[:2]), dev(full.fdot[:3])
+    big = make_plan([seg])
+    big.search_batch(0, al, de, fd)
+    r_all, k_all, n_all = big.candidates()
+    small = make_plan([seg], candidate_capacity=50)
+    small.search_batch(0, al, de, fd)
+    with pytest.raises(F.FstatError) as ei:
+        small.candidates()
+    assert ei.value.status == F.E_OVERFLOW
+    small.search_batch(0, al, de, fd)
+    recs, keys, n = small.candidates(allow_overflow=True)
+    assert n == n_all > 50 and len(recs) == 50
+    full_set = {(int(a), int(b), int(c)): float(f) for a, b, c, f in
+                zip(k_all["sky"], k_all["fdot_idx"], k_all["bin"], r_all["twoF"])}
+    for a, b, c, f in zip(keys["sky"], keys["fdot_idx"], keys["bin"], recs["twoF"]):
+        assert full_set[(int(a), int(b), int(c))] == float(f)
 
 
 def test_graph_replays_match_eager_launches(torch, full):
@@ -283,8 +326,11 @@ def test_autotune_writes_cache_and_plans_pick_it_up(torch, full, tmp_path):
     assert again.info(0) == info
 
 
-def test_pass_a_variants_give_identical_candidates(torch, full, tmp_path):
-    note("pass A variants")
+def test_kernel_variants_give_identical_candidates(torch, full, tmp_path):
+    """Both first-pass and both second-pass kernels (selected through the tuning cache)
+    find the same candidates; 2F agrees to rounding (the half-output last stage and
+    multiply-add contraction differ in the last bits)."""
+    note("pass A x pass B kernel variants")
     from paper_1410_3677_amd import fstat as F
     from tests.gpu_util import dev
     seg = full.segments[0]
@@ -295,23 +341,25 @@ def test_pass_a_variants_give_identical_candidates(torch, full, tmp_path):
     p0.autotune(0, budget_ms=50.0)
     tag = open(probe).read().split()[0]
     out = []
-    for v in (0, 1):
+    for v in (0, 1, 2, 3):
         cache = tmp_path / f"v{v}.txt"
         cache.write_text(f"{tag} {nfft} 1 64 8 {v}\n")
         plan = F.Plan([F.segment_to_device(seg)], tuning_cache_path=str(cache), use_graph=0)
-        assert plan.info(0)["pass_a_variant"] == v
+        inf = plan.info(0)
+        assert (inf["pass_a_variant"], inf["pass_b_variant"]) == (v & 1, v >> 1)
         plan.search_batch(0, dev(full.alpha[:3]), dev(full.delta[:3]), dev(full.fdot[:70]))
         out.append(plan.candidates())
-    (r0, k0, n0), (r1, k1, n1) = out
-    assert n0 == n1 and n0 > 0
-    np.testing.assert_array_equal(k0, k1)
-    # the same operations; the compiler may contract multiply-adds differently
-    np.testing.assert_allclose(r0["twoF"], r1["twoF"], rtol=1e-6, atol=0)
+    r0, k0, n0 = out[0]
+    assert n0 > 0
+    for r1, k1, n1 in out[1:]:
+        assert n1 == n0
+        assert_keys_equal(k0, k1)
+        np.testing.assert_allclose(r0["twoF"], r1["twoF"], rtol=2e-6, atol=0)
 
 
 @pytest.fixture(scope="module")
 def ragged():
-    return synth.workload(4, nsky=3, nfdot=4)
+    return synth.workload("ragged", nsky=3, nfdot=4)
 
 
 def test_ragged_segments_in_one_search(torch, ragged):
@@ -356,7 +404,7 @@ def test_ragged_admission_with_small_budget_gives_same_candidates(torch, ragged)
     small.search_batch(-1, *args)
     r1, k1, n1 = small.candidates()
     assert n1 == n0
-    np.testing.assert_array_equal(k0, k1)
+    assert_keys_equal(k0, k1)
     np.testing.assert_allclose(r0["twoF"], r1["twoF"], rtol=1e-6, atol=0)
     with pytest.raises(F.FstatError) as ei:
         make_plan(segs, workspace_budget_bytes=4 << 20)

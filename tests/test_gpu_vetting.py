@@ -128,7 +128,7 @@ def test_training_on_oracle_patches_beats_the_threshold_alone(torch):
 def test_fused_capture_scores_equal_network_on_search_spectra(torch):
     from paper_1410_3677_amd import fstat as F
     note("fused patch capture after the F kernel")
-    w = synth.workload(2)
+    w = synth.workload("full")
     seg = w.segments[0]
     nfft = synth.nfft_for(seg.n)
     nb = nfft // 2

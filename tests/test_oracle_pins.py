@@ -92,7 +92,7 @@ def test_full_form_recovers_rho2_on_tiny_segment():
 
 
 def test_search_candidates_are_sorted_and_above_threshold():
-    w = synth.workload(1)
+    w = synth.workload("tiny")
     seg = w.segments[0]
     c = oracle.search(seg, w.alpha[:2], w.delta[:2], w.fdot[:2], w.threshold)
     assert c.size > 0
