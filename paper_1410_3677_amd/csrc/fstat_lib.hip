@@ -416,10 +416,10 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
           auto go = [&](auto rnz_c) {
             constexpr int RZ = decltype(rnz_c)::value;
             if (p->variant_a == 1)
-              hipLaunchKernelGGL((k_tmpl_a_pair<T, QQ, RZ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T>()), 0, st, ta,
+              hipLaunchKernelGGL((k_tmpl_a_pair<T, QQ, RZ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T, QQ>()), 0, st, ta,
                                  d.zt(), tbuf, d.twst, d.lo(si.logL), d.hi(si.logL));
             else
-              hipLaunchKernelGGL((k_tmpl_a<T, QQ, RZ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T>()), 0, st, ta, d.zt(),
+              hipLaunchKernelGGL((k_tmpl_a<T, QQ, RZ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T, QQ>()), 0, st, ta, d.zt(),
                                  tbuf, d.twst, d.lo(si.logL), d.hi(si.logL));
           };
           if (rnz == 3) go(std::integral_constant<int, 3>{});

@@ -29,9 +29,10 @@ __host__ __device__ constexpr int stage_radix() {
   return (LEN / NS) >= 8 ? 8 : (LEN / NS);
 }
 
-// threads per template-pass workgroup and butterfly groups per column
-template <typename T>
+// threads per first-pass workgroup
+template <typename T, int Q>
 __host__ __device__ constexpr int tmpl_nt_a() { return sizeof(T) == 4 ? 512 : 256; }
+// butterfly groups per column of LEN points (one radix-8 butterfly per thread and stage)
 template <int LEN>
 __host__ __device__ constexpr int groups_per_col() { return LEN / 8; }
 // pass B: 256 threads, each row owned by one wavefront (or a fraction of one) when
@@ -54,7 +55,7 @@ __device__ __forceinline__ void stage_sync() {
   }
 }
 template <typename T, int LEN>
-__host__ __device__ constexpr int tw_a() { return tmpl_nt_a<T>() / groups_per_col<LEN>(); }
+__host__ __device__ constexpr int tw_a() { return tmpl_nt_a<T, LEN>() / groups_per_col<LEN>(); }
 template <typename T, int LEN>
 __host__ __device__ constexpr int tw_b() { return tmpl_nt_b<T, LEN>() / groups_per_col<LEN>(); }
 
@@ -256,7 +257,7 @@ __device__ __forceinline__ void chirped_first_stage(cx<T> (&va)[PB1][R1], cx<T> 
 // The two series share the chirp; they pass through one LDS tile one after the
 // other, the second series' first-stage outputs waiting in registers.
 template <typename T, int Q, int RNZ = stage_radix<Q, 1>()>
-__global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a(TmplArgs ta, const cx<T>* __restrict__ zt,
+__global__ void __launch_bounds__((tmpl_nt_a<T, Q>())) k_tmpl_a(TmplArgs ta, const cx<T>* __restrict__ zt,
                                                            cx<T>* __restrict__ tbuf,
                                                            const cx<T>* __restrict__ twst,
                                                            const cx<T>* __restrict__ twlo,
@@ -324,7 +325,7 @@ __global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a(TmplArgs ta, const cx
 // barriers).  The same operations as k_tmpl_a (the compiler may contract
 // multiply-adds differently, so results can differ in the last bit).
 template <typename T, int Q, int RNZ = stage_radix<Q, 1>()>
-__global__ void __launch_bounds__(tmpl_nt_a<T>()) k_tmpl_a_pair(TmplArgs ta, const cx<T>* __restrict__ zt,
+__global__ void __launch_bounds__((tmpl_nt_a<T, Q>())) k_tmpl_a_pair(TmplArgs ta, const cx<T>* __restrict__ zt,
                                                                 cx<T>* __restrict__ tbuf,
                                                                 const cx<T>* __restrict__ twst,
                                                                 const cx<T>* __restrict__ twlo,
@@ -635,6 +636,15 @@ __device__ __forceinline__ const auto& last_stage_tw(const StageTw<T, LEN, G, NS
   else return last_stage_tw<T, LEN, G, NS * stage_radix<LEN, NS>()>(tw.next);
 }
 
+// A value of the intermediate, read once: a non-temporal load (the row is not kept in
+// the caches for reuse).
+typedef float f2v_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ cx<float> load_stream(const cx<float>* p) {
+  const f2v_t v = __builtin_nontemporal_load(reinterpret_cast<const f2v_t*>(p));
+  return mk<float>(v.x, v.y);
+}
+__device__ __forceinline__ cx<double> load_stream(const cx<double>* p) { return *p; }
+
 // Candidates a wavefront stages in LDS before it reserves their slots with one atomic.
 constexpr int STAGE_CAP = 32;
 
@@ -688,8 +698,8 @@ __global__ void __launch_bounds__(256) k_tmpl_b_stream(TmplArgs ta, int ntmpl, c
     for (int b = 0; b < PB1; ++b)
 #pragma unroll
       for (int r = 0; r < R1; ++r) {
-        ca[b][r] = pa[lofs + G * b + NB1 * r];
-        cb[b][r] = pb[lofs + G * b + NB1 * r];
+        ca[b][r] = load_stream(pa + lofs + G * b + NB1 * r);
+        cb[b][r] = load_stream(pb + lofs + G * b + NB1 * r);
       }
   };
 
