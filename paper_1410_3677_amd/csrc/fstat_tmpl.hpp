@@ -123,6 +123,83 @@ __device__ __forceinline__ void stage_to_lds(const cx<T> (&v)[PB][R], cx<T>* col
   }
 }
 
+// The same stage loads and stores addressed as one LDS base plus compile-time offsets:
+// phys(a + c) = phys(a) + c + c/8 whenever c is a multiple of 8, or a % 8 + c < 8.
+template <typename T, int LEN, int G, int NS, int R, int PB, bool INV>
+__device__ __forceinline__ void stage_from_lds_off(cx<T> (&v)[PB][R], const cx<T>* col, int g,
+                                                   const cx<T>* __restrict__ twst) {
+  constexpr int NB = LEN / R;
+  static_assert(NB % 8 == 0 && (PB == 1 || G % 8 == 0), "constant offsets need multiples of 8");
+  const cx<T>* p = col + phys(g);
+#pragma unroll
+  for (int b = 0; b < PB; ++b) {
+    const int k = (g + G * b) % NS;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int c = G * b + r * NB;
+      cx<T> x = p[c + c / 8];
+      if constexpr (NS > 1) {
+        if (r > 0) x = cmul(x, stage_tw<T, NS, R, INV>(twst, k, r));
+      }
+      v[b][r] = x;
+    }
+    dftr<T, R, INV>(v[b]);
+  }
+}
+
+template <typename T, int LEN, int G, int NS, int R, int PB>
+__device__ __forceinline__ void stage_to_lds_off(const cx<T> (&v)[PB][R], cx<T>* col, int g) {
+#pragma unroll
+  for (int b = 0; b < PB; ++b) {
+    const int j = g + G * b;
+    const int base = (j / NS) * NS * R + (j % NS);
+    cx<T>* p = col + phys(base);
+#pragma unroll
+    for (int r = 0; r < R; ++r) p[r * NS + (r * NS) / 8] = v[b][r];
+  }
+}
+
+template <typename T, int LEN, int G, int NS, bool INV, bool WAVE_ONLY = false>
+__device__ __forceinline__ void middle_stages_off(cx<T>* cola, cx<T>* colb, int g, const cx<T>* __restrict__ twst) {
+  constexpr int R = stage_radix<LEN, NS>();
+  if constexpr (NS * R < LEN) {
+    constexpr int PB = (LEN / R) / G;
+    cx<T> va[PB][R], vb[PB][R];
+    stage_from_lds_off<T, LEN, G, NS, R, PB, INV>(va, cola, g, twst);
+    stage_from_lds_off<T, LEN, G, NS, R, PB, INV>(vb, colb, g, twst);
+    stage_sync<WAVE_ONLY>();
+    stage_to_lds_off<T, LEN, G, NS, R, PB>(va, cola, g);
+    stage_to_lds_off<T, LEN, G, NS, R, PB>(vb, colb, g);
+    stage_sync<WAVE_ONLY>();
+    middle_stages_off<T, LEN, G, NS * R, INV, WAVE_ONLY>(cola, colb, g, twst);
+  }
+}
+
+template <typename T, int LEN, int G, int NS, bool INV>
+__device__ __forceinline__ void middle_stages1_off(cx<T>* col, int g, const cx<T>* __restrict__ twst) {
+  constexpr int R = stage_radix<LEN, NS>();
+  if constexpr (NS * R < LEN) {
+    constexpr int PB = (LEN / R) / G;
+    cx<T> v[PB][R];
+    stage_from_lds_off<T, LEN, G, NS, R, PB, INV>(v, col, g, twst);
+    __syncthreads();
+    stage_to_lds_off<T, LEN, G, NS, R, PB>(v, col, g);
+    __syncthreads();
+    middle_stages1_off<T, LEN, G, NS * R, INV>(col, g, twst);
+  }
+}
+
+// Element o of a series as a 32-bit byte offset from a uniform base (loads and stores
+// then take the scalar-base form instead of 64-bit vector addresses).
+template <typename T>
+__device__ __forceinline__ cx<T>& at32(cx<T>* base, unsigned o) {
+  return *reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(base) + o * (unsigned)sizeof(cx<T>));
+}
+template <typename T>
+__device__ __forceinline__ const cx<T>& at32(const cx<T>* base, unsigned o) {
+  return *reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(base) + o * (unsigned)sizeof(cx<T>));
+}
+
 // Middle stages (stride NS up to, not including, the last stage) for two series.
 template <typename T, int LEN, int G, int NS, bool INV, bool WAVE_ONLY = false>
 __device__ __forceinline__ void middle_stages(cx<T>* cola, cx<T>* colb, int g, const cx<T>* __restrict__ twst) {
@@ -216,8 +293,8 @@ __device__ __forceinline__ void chirped_first_stage(cx<T> (&va)[PB1][R1], cx<T> 
       va[b][r] = mk<T>(0, 0);
       vb[b][r] = mk<T>(0, 0);
       if (jj < (unsigned)n) {
-        va[b][r] = za[jj];
-        vb[b][r] = zb[jj];
+        va[b][r] = at32(za, jj);
+        vb[b][r] = at32(zb, jj);
       }
     }
 #pragma unroll
@@ -303,11 +380,11 @@ __global__ void __launch_bounds__((tmpl_nt_a<T, Q>())) k_tmpl_a(TmplArgs ta, con
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     if (s == 1) __syncthreads();  // series a's last stage has read the tile
-    stage_to_lds<T, Q, G, 1, R1, PB1>(s == 0 ? va : vb, col, g);
+    stage_to_lds_off<T, Q, G, 1, R1, PB1>(s == 0 ? va : vb, col, g);
     __syncthreads();
-    middle_stages1<T, Q, G, R1, false>(col, g, twst);
+    middle_stages1_off<T, Q, G, R1, false>(col, g, twst);
     cx<T> v[PBL][RL];
-    stage_from_lds<T, Q, G, NSL, RL, PBL, false>(v, col, g, twst);
+    stage_from_lds_off<T, Q, G, NSL, RL, PBL, false>(v, col, g, twst);
     cx<T>* out = tbuf + (long)(2 * item + s) * ta.L;
 #pragma unroll
     for (int b = 0; b < PBL; ++b) {
@@ -315,7 +392,7 @@ __global__ void __launch_bounds__((tmpl_nt_a<T, Q>())) k_tmpl_a(TmplArgs ta, con
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
         const unsigned o = (unsigned)(j + NSL * r) * (unsigned)ta.P + (unsigned)j1;
-        out[o] = cmul(v[b][r], tw[b][r]);
+        at32(out, o) = cmul(v[b][r], tw[b][r]);
       }
     }
   }
@@ -352,17 +429,17 @@ __global__ void __launch_bounds__((tmpl_nt_a<T, Q>())) k_tmpl_a_pair(TmplArgs ta
   {
     cx<T> va[PB1][R1], vb[PB1][R1];
     chirped_first_stage<T, Q, G, R1, NB1, PB1, RNZ>(va, vb, za, zb, j1, g, ta.P, ta.n, half_fdot_dt2);
-    stage_to_lds<T, Q, G, 1, R1, PB1>(va, cola, g);
-    stage_to_lds<T, Q, G, 1, R1, PB1>(vb, colb, g);
+    stage_to_lds_off<T, Q, G, 1, R1, PB1>(va, cola, g);
+    stage_to_lds_off<T, Q, G, 1, R1, PB1>(vb, colb, g);
     __syncthreads();
   }
-  middle_stages<T, Q, G, R1, false>(cola, colb, g, twst);
+  middle_stages_off<T, Q, G, R1, false>(cola, colb, g, twst);
   constexpr int NSL = last_ns<Q, 1>();
   constexpr int RL = stage_radix<Q, NSL>();
   constexpr int PBL = (Q / RL) / G;
   cx<T> va[PBL][RL], vb[PBL][RL];
-  stage_from_lds<T, Q, G, NSL, RL, PBL, false>(va, cola, g, twst);
-  stage_from_lds<T, Q, G, NSL, RL, PBL, false>(vb, colb, g, twst);
+  stage_from_lds_off<T, Q, G, NSL, RL, PBL, false>(va, cola, g, twst);
+  stage_from_lds_off<T, Q, G, NSL, RL, PBL, false>(vb, colb, g, twst);
   cx<T>* outa = tbuf + (long)(2 * item) * ta.L;
   cx<T>* outb = outa + ta.L;
   const cx<T> step = twiddle_L<T, false>(twlo, twhi, j1 * NSL);
@@ -373,8 +450,8 @@ __global__ void __launch_bounds__((tmpl_nt_a<T, Q>())) k_tmpl_a_pair(TmplArgs ta
 #pragma unroll
     for (int r = 0; r < RL; ++r) {
       const unsigned o = (unsigned)(j + NSL * r) * (unsigned)ta.P + (unsigned)j1;
-      outa[o] = cmul(va[b][r], w);
-      outb[o] = cmul(vb[b][r], w);
+      at32(outa, o) = cmul(va[b][r], w);
+      at32(outb, o) = cmul(vb[b][r], w);
       if (r + 1 < RL) w = cmul(w, step);
     }
   }
@@ -599,18 +676,6 @@ __device__ __forceinline__ void stage_from_lds_reg(cx<T> (&v)[PB][R], const cx<T
     }
     if constexpr (HALFOUT) dft_first_half<T, R>(v[b]);
     else dftr<T, R, false>(v[b]);
-  }
-}
-
-template <typename T, int LEN, int G, int NS, int R, int PB>
-__device__ __forceinline__ void stage_to_lds_off(const cx<T> (&v)[PB][R], cx<T>* col, int g) {
-#pragma unroll
-  for (int b = 0; b < PB; ++b) {
-    const int j = g + G * b;
-    const int base = (j / NS) * NS * R + (j % NS);
-    cx<T>* p = col + phys(base);
-#pragma unroll
-    for (int r = 0; r < R; ++r) p[r * NS + (r * NS) / 8] = v[b][r];
   }
 }
 
