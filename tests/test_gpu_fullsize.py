@@ -1,0 +1,95 @@
+"""GPU parity at the workloads' full sizes, in the launch configurations the benchmark times.
+
+* full:    256 sky x 64 spindown at N = 86164, one template per launch (the plain path),
+           threshold 2F > 20: every crossing drained; sampled templates checked bin by bin
+           against the FP64 oracle, and the injection's loudest template among them.
+* batched: 4096 sky x 256 spindown (1 048 576 templates), autotuned batch sizes and
+           kernel variants, HIP graph: the threshold is raised to 2F > 40 so that the
+           drained set stays small (the launch configuration is that of the benchmark;
+           only the threshold differs); sampled templates, including the loudest
+           template of every injection, are checked against the oracle.
+Tolerances are those of the other parity tests (1e-4 relative, floor 4; key sets equal
+outside a 1e-4 x threshold guard band).
+"""
+import numpy as np
+import pytest
+import torch as _torch  # noqa: F401  (first import on a fresh box is slow)
+
+import synth
+from tests.gpu_util import compare_candidates, dev, make_plan, note, oracle_spectrum
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _check_templates(seg, w, recs, keys, picks, thr):
+    nfft = synth.nfft_for(seg.n)
+    worst = 0.0
+    for (i, s) in picks:
+        m = (keys["sky"] == i) & (keys["fdot_idx"] == s)
+        key3 = np.stack([np.zeros(int(m.sum()), dtype=np.int64), np.zeros(int(m.sum()), dtype=np.int64),
+                         keys["bin"][m]], 1)
+        ref = oracle_spectrum(seg, w.alpha[i:i + 1], w.delta[i:i + 1], w.fdot[s:s + 1], nfft)
+        ng, no, flips, mism, err = compare_candidates(key3, recs["twoF"][m], ref, thr, 1e-4)
+        note(f"template (sky {i}, fdot {s}): gpu {ng} oracle {no} flips {flips} mismatches {len(mism)} err {err:.2e}")
+        assert not mism and err < 1e-4
+        worst = max(worst, err)
+    return worst
+
+
+def test_full_workload_plain_path_sampled_parity(torch):
+    w = synth.workload("full")
+    seg = w.segments[0]
+    note(f"full workload, plain path: {len(w.alpha)} x {len(w.fdot)} templates, one per launch")
+    plan = make_plan([seg], templates_per_launch=1, skies_per_batch=1, use_graph=0, candidate_capacity=1 << 22)
+    plan.search_batch(0, dev(w.alpha), dev(w.delta), dev(w.fdot))
+    recs, keys, n = plan.candidates()
+    assert n == len(recs) and n > 500000
+    assert np.all(recs["twoF"] > w.threshold)
+    key3 = np.stack([keys["sky"], keys["fdot_idx"], keys["bin"]], 1)
+    assert len(np.unique(key3, axis=0)) == n
+    rng = np.random.default_rng(71)
+    picks = [(int(rng.integers(len(w.alpha))), int(rng.integers(len(w.fdot)))) for _ in range(3)]
+    top = int(np.argmax(recs["twoF"]))
+    picks.append((int(keys["sky"][top]), int(keys["fdot_idx"][top])))
+    _check_templates(seg, w, recs, keys, picks, w.threshold)
+
+
+def test_batched_workload_full_size_sampled_parity(torch):
+    from paper_1410_3677_amd import fstat as F
+    w = synth.workload("batched")
+    seg = w.segments[0]
+    thr = 40.0
+    note(f"batched workload at full size: {len(w.alpha)} x {len(w.fdot)} templates, 2F > {thr}")
+    plan = F.Plan([F.segment_to_device(seg)], workspace_from_torch=False, threshold_2F=thr,
+                  candidate_capacity=1 << 25)
+    plan.autotune(0, budget_ms=3000.0)
+    info = plan.info(0)
+    note(f"launch configuration {info}")
+    plan.search_batch(0, dev(w.alpha), dev(w.delta), dev(w.fdot))
+    recs, keys, n = plan.candidates()
+    note(f"{n} candidates")
+    assert n == len(recs) and n > 10000
+    assert np.all(recs["twoF"] > thr)
+    key3 = np.stack([keys["sky"], keys["fdot_idx"], keys["bin"]], 1)
+    assert len(np.unique(key3, axis=0)) == n
+    picks = []
+    # the loudest template near each injection's frequency, then seeded random templates
+    f_hz = recs["f_hz"]
+    for inj in seg.injections:
+        near = np.abs(f_hz - (seg.f_off + inj.f)) < 1e-3
+        if near.any():
+            j = int(np.flatnonzero(near)[np.argmax(recs["twoF"][near])])
+            picks.append((int(keys["sky"][j]), int(keys["fdot_idx"][j])))
+    rng = np.random.default_rng(72)
+    picks += [(int(rng.integers(len(w.alpha))), int(rng.integers(len(w.fdot)))) for _ in range(2)]
+    assert len(picks) >= 3
+    _check_templates(seg, w, recs, keys, picks, thr)
+    plan.destroy()
