@@ -156,6 +156,15 @@ def vetting_leg(args, F, torch, np, dev, log):
     near = np.abs(recs["f_hz"] - (seg2.f_off + inj.f)) < 2e-4
     p.destroy()
     v.destroy()
+    # matrix-core roofline of inference: FLOPs per patch (multiply-add = 2) of the layers
+    conv1 = 2 * 256 * 32 * 7
+    conv23 = 2 * (2 * 256 * 32 * 224)
+    dense = 2 * (8192 * 128 + 128 * 128 + 128)
+    flop_patch = conv1 + conv23 + dense
+    infer_tflops = flop_patch * n / (s2 - s1) / 1e12 if n else 0.0
+    roof = {"bound": "mfma", "achieved": infer_tflops, "peak": 2500.0, "unit": "TFLOP/s",
+            "frac": infer_tflops / 2500.0, "flop_per_patch": flop_patch, "patches": int(n),
+            "note": "BF16 products with FP32 accumulation; dense BF16 peak"}
     return {"train_patches": int(len(y)), "heldout_patches": int(len(ye)), "epochs": args.vet_epochs,
             "train_s": t_train, "data_s": t_gen, "threshold_false_dismissal": st["threshold_false_dismissal"],
             "heldout_noise_kept_by_network": far, "heldout_added_false_dismissal": fdr_added,
@@ -163,7 +172,8 @@ def vetting_leg(args, F, torch, np, dev, log):
             "plain_search_with_capture_ms": (s1 - s0) * 1e3, "scoring_ms": (s2 - s1) * 1e3,
             "plain_crossings": int(n), "plain_crossings_kept_by_network": kept,
             "plain_crossings_near_injection": int(near.sum()),
-            "plain_crossings_near_injection_kept": int(np.sum(near & (keys["vet_score"] >= 1.0 / (1.0 + np.exp(-cut)))))}
+            "plain_crossings_near_injection_kept": int(np.sum(near & (keys["vet_score"] >= 1.0 / (1.0 + np.exp(-cut))))),
+            "inference_roofline": roof}
 
 
 def main():

@@ -721,7 +721,7 @@ constexpr int INFER_SPLITS = 4;
 void vet_infer_batch(fstat_vet_t v, const float* patches, int n, float* out, hipStream_t st) {
   using namespace vet;
   const int nbp = (n + GT - 1) / GT * GT;
-  hipLaunchKernelGGL(k_vet_conv_infer, dim3((n + CV_NP - 1) / CV_NP), dim3(256), 0, st, patches, n, v->theta, v->wq2,
+  hipLaunchKernelGGL(k_vet_conv_infer, dim3((n + CV_NP - 1) / CV_NP), dim3(CV_NT), 0, st, patches, n, v->theta, v->wq2,
                      v->wq3, v->a3b);
   hipLaunchKernelGGL(k_gemm_nt_lds, dim3(H / GT, nbp / GT, INFER_SPLITS), dim3(256), 0, st, nbp, H, X, v->a3b, v->w4b,
                      v->scratch, X / INFER_SPLITS);

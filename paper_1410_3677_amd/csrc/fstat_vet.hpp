@@ -29,14 +29,24 @@ constexpr long O_W1 = 0, O_B1 = O_W1 + C * KW, O_W2 = O_B1 + C, O_B2 = O_W2 + C 
                O_B5 = O_W5 + H * H, O_W6 = O_B5 + H, O_B6 = O_W6 + H, N_PARAMS = O_B6 + 1;
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// FP32 -> BF16, round to nearest even (finite inputs)
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+// 16 x 16 x 32 BF16 matrix-core step (gfx950): lane l (q = l / 16) holds A[l % 16][8q + j]
+// and B[8q + j][l % 16], j = 0..7, and receives D[4q + i][l % 16], i = 0..3.
+__device__ __forceinline__ v4f mfma32(v8s a, v8s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0,
+                                                 0, 0);
 }
+// eight BF16 from an 8-byte aligned LDS address
+__device__ __forceinline__ v8s lds8(const uint16_t* p) {
+  const v4s lo = *reinterpret_cast<const v4s*>(p), hi = *reinterpret_cast<const v4s*>(p + 4);
+  return v8s{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+
+// FP32 -> BF16, round to nearest even (the hardware conversion of gfx950)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
 // C[m][n] = sum_k A(m, k) B(k, n) over k in this workgroup's K range
@@ -347,56 +357,60 @@ struct PatchArgs {
 
 // ------------------------------------------------------------------ inference
 // Inference runs the three convolutions of CV_NP patches in one workgroup with the
-// activations resident in LDS (position-major rows of 32 BF16 channels, padded to
+// activations resident in one LDS buffer (position-major rows of 32 BF16 channels, padded to
 // CV_LD so that the sixteen rows one matrix-core operand spans hit distinct banks,
 // with three zero rows above and below every patch for the "same" padding), then
 // the 8192 -> 128 layer as an LDS-tiled product.  The matrix-core operands and the
 // order of the K steps are those of the training forward, so scores agree with it.
 constexpr int CV_NP = 2;          // patches per workgroup
+constexpr int CV_NT = 512;        // threads per workgroup (8 wavefronts)
+constexpr int CV_MB = CV_NP * L / 16 / (CV_NT / 64);  // sixteen-position blocks per wavefront (4)
 constexpr int CV_R = L + 6;       // LDS rows per patch
 constexpr int CV_LD = 36;         // BF16 per LDS row
-constexpr int KS = KC / 16;       // matrix-core K steps of a convolution (14)
+constexpr int KS = KC / 32;       // matrix-core K steps of a convolution (7: one tap each)
 
-// Convolution weights in matrix-core fragment order: [step s][column block nb][lane][4],
-// element i of lane l = w[co = 16 nb + l % 16][ci][t] with k = 16 s + 4 (l / 16) + i,
-// t = k / 32, ci = k % 32.
-constexpr int WQ_ELEMS = KS * 2 * 64 * 4;
+// Convolution weights in matrix-core fragment order: [step s][column block nb][lane][8],
+// element j of lane l = w[co = 16 nb + l % 16][ci = 8 (l / 16) + j][t = s].
+constexpr int WQ_ELEMS = KS * 2 * 64 * 8;
 
 __global__ void k_vet_prepare_frag(const float* __restrict__ theta, uint16_t* __restrict__ wq2,
                                    uint16_t* __restrict__ wq3) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= WQ_ELEMS) return;
-  const int i = idx & 3, l = (idx >> 2) & 63, nb = (idx >> 8) & 1, st = idx >> 9;
-  const int k = 16 * st + 4 * (l >> 4) + i;
-  const int t = k / C, ci = k % C, co = 16 * nb + (l & 15);
+  const int j = idx & 7, l = (idx >> 3) & 63, nb = (idx >> 9) & 1, t = idx >> 10;
+  const int ci = 8 * (l >> 4) + j, co = 16 * nb + (l & 15);
   wq2[idx] = f2bf(theta[O_W2 + (co * C + ci) * KW + t]);
   wq3[idx] = f2bf(theta[O_W3 + (co * C + ci) * KW + t]);
 }
 
-// One convolution layer of the workgroup's patches, LDS to LDS; wavefront w computes the
-// sixteen-position blocks 8w .. 8w+7 for all 32 output channels.
-__device__ __forceinline__ void conv_layer_lds(const uint16_t* __restrict__ in, uint16_t* __restrict__ out,
-                                               const uint16_t* __restrict__ wq, const float* __restrict__ bias,
-                                               int w, int lane) {
-  v4f acc[8][2];
+// One convolution layer of the workgroup's patches, in place in LDS (the outputs wait in
+// the matrix-core accumulators until every wavefront has read the input); wavefront w
+// computes the sixteen-position blocks CV_MB w .. CV_MB w + CV_MB - 1 for all 32 output
+// channels.  K step t is tap t over
+// all 32 input channels, so a lane's A operand is eight channels of one LDS row.
+__device__ __forceinline__ void conv_layer_lds(uint16_t* act, const uint16_t* __restrict__ wq,
+                                               const float* __restrict__ bias, int w, int lane) {
+  const uint16_t* in = act;
+  v4f acc[CV_MB][2];
 #pragma unroll
-  for (int m = 0; m < 8; ++m) acc[m][0] = acc[m][1] = v4f{0.f, 0.f, 0.f, 0.f};
-  const v4s* wqv = reinterpret_cast<const v4s*>(wq);
-  for (int st = 0; st < KS; ++st) {
-    const v4s b0 = wqv[(st * 2 + 0) * 64 + lane];
-    const v4s b1 = wqv[(st * 2 + 1) * 64 + lane];
-    const int t = st >> 1, ci0 = (st & 1) * 16 + 4 * (lane >> 4);
+  for (int m = 0; m < CV_MB; ++m) acc[m][0] = acc[m][1] = v4f{0.f, 0.f, 0.f, 0.f};
+  const v8s* wqv = reinterpret_cast<const v8s*>(wq);
+  const int ci0 = 8 * (lane >> 4);
+  for (int t = 0; t < KS; ++t) {
+    const v8s b0 = wqv[(t * 2 + 0) * 64 + lane];
+    const v8s b1 = wqv[(t * 2 + 1) * 64 + lane];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      const int mb = 8 * w + m, pp = mb >> 4, p0 = (mb & 15) * 16;
-      const v4s a = *reinterpret_cast<const v4s*>(in + (pp * CV_R + p0 + (lane & 15) + t) * CV_LD + ci0);
-      acc[m][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b0, acc[m][0], 0, 0, 0);
-      acc[m][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b1, acc[m][1], 0, 0, 0);
+    for (int m = 0; m < CV_MB; ++m) {
+      const int mb = CV_MB * w + m, pp = mb >> 4, p0 = (mb & 15) * 16;
+      const v8s a = lds8(in + (pp * CV_R + p0 + (lane & 15) + t) * CV_LD + ci0);
+      acc[m][0] = mfma32(a, b0, acc[m][0]);
+      acc[m][1] = mfma32(a, b1, acc[m][1]);
     }
   }
+  __syncthreads();  // every wavefront has read the layer's input: overwrite it in place
 #pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    const int mb = 8 * w + m, pp = mb >> 4, p0 = (mb & 15) * 16;
+  for (int m = 0; m < CV_MB; ++m) {
+    const int mb = CV_MB * w + m, pp = mb >> 4, p0 = (mb & 15) * 16;
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
       const int co = 16 * nb + (lane & 15);
@@ -405,49 +419,64 @@ __device__ __forceinline__ void conv_layer_lds(const uint16_t* __restrict__ in, 
       for (int i = 0; i < 4; ++i) {
         const int p = p0 + 4 * (lane >> 4) + i;
         const float v = acc[m][nb][i] + bc;
-        out[(pp * CV_R + p + 3) * CV_LD + co] = f2bf(v > 0.f ? v : 0.f);
+        act[(pp * CV_R + p + 3) * CV_LD + co] = f2bf(v > 0.f ? v : 0.f);
       }
     }
   }
 }
 
 // u -> conv1 -> conv2 -> conv3 for patches [CV_NP b, CV_NP b + CV_NP); x[s][p*32 + c] (BF16).
-__global__ void __launch_bounds__(256) k_vet_conv_infer(const float* __restrict__ patches, int n,
+__global__ void __launch_bounds__(CV_NT) k_vet_conv_infer(const float* __restrict__ patches, int n,
                                                         const float* __restrict__ theta,
                                                         const uint16_t* __restrict__ wq2,
                                                         const uint16_t* __restrict__ wq3, uint16_t* __restrict__ x) {
   __shared__ float su[CV_NP][CV_R];
   __shared__ __align__(16) uint16_t sa[CV_NP * CV_R * CV_LD];
-  __shared__ __align__(16) uint16_t sb[CV_NP * CV_R * CV_LD];
   const int s0 = blockIdx.x * CV_NP;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int i = tid; i < CV_NP * CV_R; i += 256) {
+  for (int i = tid; i < CV_NP * CV_R; i += CV_NT) {
     const int pp = i / CV_R, r = i % CV_R, q = r - 3;
     float v = 0.f;
     if (s0 + pp < n && q >= 0 && q < L) v = log1pf(patches[(long)(s0 + pp) * L + q]) - 1.6094379124341003f;
     su[pp][r] = v;
   }
-  for (int i = tid; i < CV_NP * 6 * CV_LD; i += 256) {
+  for (int i = tid; i < CV_NP * 6 * CV_LD; i += CV_NT) {
     const int pp = i / (6 * CV_LD), rem = i % (6 * CV_LD), hr = rem / CV_LD, c = rem % CV_LD;
     const int row = hr < 3 ? hr : L + hr;
     sa[(pp * CV_R + row) * CV_LD + c] = 0;
-    sb[(pp * CV_R + row) * CV_LD + c] = 0;
   }
   __syncthreads();
-  for (int i = tid; i < CV_NP * L * C; i += 256) {
-    const int c = i % C, p = (i / C) % L, pp = i / (C * L);
-    float z = theta[O_B1 + c];
+  {
+    // conv1: thread (channel c, group grp) slides along 64 positions with its channel's
+    // weights in registers and a seven-sample window, one LDS read per output
+    constexpr int PER = CV_NP * L * C / CV_NT;  // positions per thread (32)
+    static_assert(L % PER == 0, "conv1 work split");
+    const int c = tid & (C - 1), grp = tid >> 5;
+    const int pp = grp / (L / PER), p0 = (grp % (L / PER)) * PER;
+    float wt[KW];
 #pragma unroll
-    for (int t = 0; t < KW; ++t) z += theta[O_W1 + c * KW + t] * su[pp][p + t];
-    sa[(pp * CV_R + p + 3) * CV_LD + c] = f2bf(z > 0.f ? z : 0.f);
+    for (int t = 0; t < KW; ++t) wt[t] = theta[O_W1 + c * KW + t];
+    const float bc = theta[O_B1 + c];
+    float win[KW];
+#pragma unroll
+    for (int t = 0; t < KW - 1; ++t) win[t] = su[pp][p0 + t];
+    for (int p = p0; p < p0 + PER; ++p) {
+      win[KW - 1] = su[pp][p + KW - 1];
+      float z = bc;
+#pragma unroll
+      for (int t = 0; t < KW; ++t) z += wt[t] * win[t];
+      sa[(pp * CV_R + p + 3) * CV_LD + c] = f2bf(z > 0.f ? z : 0.f);
+#pragma unroll
+      for (int t = 0; t < KW - 1; ++t) win[t] = win[t + 1];
+    }
   }
   __syncthreads();
-  conv_layer_lds(sa, sb, wq2, theta + O_B2, w, lane);
+  conv_layer_lds(sa, wq2, theta + O_B2, w, lane);
   __syncthreads();
-  conv_layer_lds(sb, sa, wq3, theta + O_B3, w, lane);
+  conv_layer_lds(sa, wq3, theta + O_B3, w, lane);
   __syncthreads();
   // rows 3 .. L+2 of each patch to x, 16 bytes per item
-  for (int i = tid; i < CV_NP * L * (C / 8); i += 256) {
+  for (int i = tid; i < CV_NP * L * (C / 8); i += CV_NT) {
     const int pp = i / (L * (C / 8)), rem = i % (L * (C / 8)), p = rem / (C / 8), c8 = (rem % (C / 8)) * 8;
     if (s0 + pp < n) {
       const uint2* src = reinterpret_cast<const uint2*>(sa + (pp * CV_R + p + 3) * CV_LD + c8);
@@ -460,9 +489,10 @@ __global__ void __launch_bounds__(256) k_vet_conv_infer(const float* __restrict_
 // C[m][n] (split z of K) = sum_k A[m][k] B[n][k] for row-major BF16 A [M][K] and B [N][K]
 // (both contiguous along K), M a multiple of 64, N a multiple of 64 and K of 64 * splits.
 // Workgroup tile 64 x 64, four wavefronts of 32 x 32; K in stages of 64 through LDS
-// (rows padded to 68 BF16), the next stage loaded into registers while the current one
+// (rows padded to 72 BF16: 16-byte aligned, and the sixteen rows of an operand fall on
+// distinct banks), the next stage loaded into registers while the current one
 // is multiplied.  Partial tiles of split z go to C + z * M * N (ldc = N).
-constexpr int GT = 64, GK = 64, GLD = GK + 4;
+constexpr int GT = 64, GK = 64, GLD = GK + 8;
 __global__ void __launch_bounds__(256) k_gemm_nt_lds(int M, int N, int K, const uint16_t* __restrict__ A,
                                                      const uint16_t* __restrict__ B, float* __restrict__ Cm,
                                                      int kchunk) {
@@ -483,18 +513,18 @@ __global__ void __launch_bounds__(256) k_gemm_nt_lds(int M, int N, int K, const 
     rb1 = *reinterpret_cast<const uint4*>(gb + k0 + 8);
   };
   auto sstore = [&]() {
-    uint2* pa = reinterpret_cast<uint2*>(sA + lr * GLD + lc);
-    uint2* pb = reinterpret_cast<uint2*>(sB + lr * GLD + lc);
-    pa[0] = make_uint2(ra0.x, ra0.y); pa[1] = make_uint2(ra0.z, ra0.w);
-    pa[2] = make_uint2(ra1.x, ra1.y); pa[3] = make_uint2(ra1.z, ra1.w);
-    pb[0] = make_uint2(rb0.x, rb0.y); pb[1] = make_uint2(rb0.z, rb0.w);
-    pb[2] = make_uint2(rb1.x, rb1.y); pb[3] = make_uint2(rb1.z, rb1.w);
+    uint4* pa = reinterpret_cast<uint4*>(sA + lr * GLD + lc);
+    uint4* pb = reinterpret_cast<uint4*>(sB + lr * GLD + lc);
+    pa[0] = ra0;
+    pa[1] = ra1;
+    pb[0] = rb0;
+    pb[1] = rb1;
   };
   v4f acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a) acc[a][0] = acc[a][1] = v4f{0.f, 0.f, 0.f, 0.f};
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
-  const int r16 = lane & 15, kq = 4 * (lane >> 4);
+  const int r16 = lane & 15, kq = 4 * (lane >> 4), k8 = 8 * (lane >> 4);
   gload(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += GK) {
     __syncthreads();  // the previous stage has been read
@@ -502,17 +532,17 @@ __global__ void __launch_bounds__(256) k_gemm_nt_lds(int M, int N, int K, const 
     __syncthreads();
     if (k0 + GK < kend) gload(k0 + GK);
 #pragma unroll
-    for (int kk = 0; kk < GK; kk += 16) {
-      v4s fa[2], fb[2];
+    for (int kk = 0; kk < GK; kk += 32) {
+      v8s fa[2], fb[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        fa[t] = *reinterpret_cast<const v4s*>(sA + (wm + 16 * t + r16) * GLD + kk + kq);
-        fb[t] = *reinterpret_cast<const v4s*>(sB + (wn + 16 * t + r16) * GLD + kk + kq);
+        fa[t] = *reinterpret_cast<const v8s*>(sA + (wm + 16 * t + r16) * GLD + kk + k8);
+        fb[t] = *reinterpret_cast<const v8s*>(sB + (wn + 16 * t + r16) * GLD + kk + k8);
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa[a], fb[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma32(fa[a], fb[b], acc[a][b]);
     }
   }
   float* Cz = Cm + (long)blockIdx.z * M * N;
