@@ -33,10 +33,15 @@ CAND_BYTES = 32          # device candidate entry
 CX32 = 8                 # complex FP32
 
 
+# device sources of the search kernels whose HBM traffic profiles/template_kernels_traffic.txt
+# records (the vetting network and the host code do not change what those kernels move)
+SEARCH_KERNEL_SOURCES = ("fstat_fft.hpp", "fstat_kernels.hpp", "fstat_tmpl.hpp")
+
+
 def source_digest() -> str:
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1410_3677_amd", "csrc")
-    for name in sorted(os.listdir(d)):
+    for name in SEARCH_KERNEL_SOURCES:
         with open(os.path.join(d, name), "rb") as f:
             h.update(name.encode() + f.read())
     return h.hexdigest()

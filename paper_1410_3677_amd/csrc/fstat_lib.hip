@@ -723,13 +723,11 @@ void vet_infer_batch(fstat_vet_t v, const float* patches, int n, float* out, hip
   const int nbp = (n + GT - 1) / GT * GT;
   hipLaunchKernelGGL(k_vet_conv_infer, dim3((n + CV_NP - 1) / CV_NP), dim3(CV_NT), 0, st, patches, n, v->theta, v->wq2,
                      v->wq3, v->a3b);
-  hipLaunchKernelGGL(k_gemm_nt_lds, dim3(H / GT, nbp / GT, INFER_SPLITS), dim3(256), 0, st, nbp, H, X, v->a3b, v->w4b,
-                     v->scratch, X / INFER_SPLITS);
+  hipLaunchKernelGGL(k_gemm_nt_lds, dim3(H / GT, nbp / GT, INFER_SPLITS), dim3(256), 0, st, nbp, H, X, v->a3b,
+                     v->w4b, v->scratch, X / INFER_SPLITS);
   const long count = (long)nbp * H;
-  hipLaunchKernelGGL(k_vet_sum_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, v->scratch,
-                     INFER_SPLITS, count, H, (long)H, v->z4);
-  hipLaunchKernelGGL(k_vet_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->z4, (long)n, H, v->theta + O_B4,
-                     v->a4b, (float*)nullptr);
+  hipLaunchKernelGGL(k_vet_sum_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->scratch, INFER_SPLITS, count,
+                     n, H, v->theta + O_B4, v->a4b);
   gemm(st, n, H, H, v->a4b, H, 1, v->w5b, 1, H, v->z5, H);
   hipLaunchKernelGGL(k_vet_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->z5, (long)n, H, v->theta + O_B5,
                      (uint16_t*)nullptr, v->a5);
@@ -811,7 +809,7 @@ fstat_status fstat_vet_create(int32_t max_batch, fstat_vet_t* out) {
   if (!v) return vet_fail(nullptr, FSTAT_E_NOMEM, "vetter allocation");
   v->max_batch = max_batch;
   const size_t nb = (size_t)max_batch, NL = nb * L;
-  const size_t nbp = (nb + GT - 1) / GT * GT;  // rows of the 8192 -> 128 product
+  const size_t nbp = (nb + vet::GT - 1) / vet::GT * vet::GT;  // rows of the 8192 -> 128 product
   struct Part { void** p; size_t bytes; };
   std::vector<Part> parts = {
       {(void**)&v->theta, N_PARAMS * 4}, {(void**)&v->grad, N_PARAMS * 4}, {(void**)&v->m1, N_PARAMS * 4},
@@ -954,20 +952,15 @@ fstat_status fstat_plan_vet_candidates(fstat_plan_t plan, void* stream) {
   unsigned long long count = 0;
   HIP_TRY(plan, hipMemcpy(&count, plan->d_count, sizeof count, hipMemcpyDeviceToHost), "count copy");
   const long long n = std::min<long long>({(long long)count, plan->opt.candidate_capacity, plan->patch_capacity});
-  if (n > 0) {
-    float* logits = nullptr;
-    HIP_TRY(plan, hipMalloc(&logits, (size_t)n * sizeof(float)), "logits");
-    fstat_status r = fstat_vet_forward(plan->vet, plan->d_patches, n, logits, st);
-    if (r == FSTAT_OK) {
-      hipLaunchKernelGGL(k_vet_store_scores, blocks_for(n), dim3(256), 0, st, plan->d_cand, logits, (long)n);
-      hipError_t e = hipStreamSynchronize(st);
-      if (e != hipSuccess) r = hip_fail(plan, e, "scoring");
-    } else {
-      r = fail(plan, r, std::string("vetting forward: ") + plan->vet->last_error);
-    }
-    (void)hipFree(logits);
-    if (r != FSTAT_OK) return r;
+  // batches of the vetter's size: logits into its own buffer, scores into the entries
+  fstat_vet_t v = plan->vet;
+  for (long long i = 0; i < n; i += v->max_batch) {
+    const int b = (int)std::min<long long>(v->max_batch, n - i);
+    vet_infer_batch(v, plan->d_patches + i * vet::L, b, v->logit, st);
+    hipLaunchKernelGGL(k_vet_store_scores, blocks_for(b), dim3(256), 0, st, plan->d_cand + i, v->logit, (long)b);
+    HIP_TRY(plan, hipGetLastError(), "scoring launch");
   }
+  HIP_TRY(plan, hipStreamSynchronize(st), "scoring");
   plan->scored = true;
   plan->last_stream = st;
   plan->used_stream = true;

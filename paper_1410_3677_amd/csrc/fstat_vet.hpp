@@ -555,5 +555,16 @@ __global__ void __launch_bounds__(256) k_gemm_nt_lds(int M, int N, int K, const 
         Cz[(long)(m0 + wm + 16 * a + kq + i) * N + n0 + wn + 16 * b + r16] = acc[a][b][i];
 }
 
+// out_b[m][n] = bf16(relu(bias[n] + sum over splits z (in order) of part[z][m][n])), rows < rows
+__global__ void k_vet_sum_bias_relu(const float* __restrict__ part, int splits, long count, int rows, int N,
+                                    const float* __restrict__ bias, uint16_t* __restrict__ outb) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)rows * N) return;
+  float acc = 0.f;
+  for (int z = 0; z < splits; ++z) acc += part[(long)z * count + idx];
+  const float v = acc + bias[idx % N];
+  outb[idx] = f2bf(v > 0.f ? v : 0.f);
+}
+
 }  // namespace vet
 }  // namespace fstat

@@ -210,6 +210,30 @@ def test_bin_range_matches_full_spectrum(torch, tiny):
     np.testing.assert_array_equal(a[:, :, 1000:3001], b)
 
 
+def test_bin_range_across_half_spectrum_mixed(torch, full):
+    """Mixed precision with a bin range that is not [0, nfft/2): the second pass forms every
+    output of its last stage and checks bins, here across nfft/2 into the upper half."""
+    note("bin range [100000, 200000), mixed")
+    seg = full.segments[0]
+    nfft = synth.nfft_for(seg.n)
+    k0, k1 = 100000, 200000
+    al, de, fd = full.alpha[:2], full.delta[:2], full.fdot[:2]
+    plan = make_plan([seg], k_min=k0, k_max=k1)
+    got = gpu_spectrum(plan, 0, al, de, fd, k1 - k0, False)
+    ref = oracle_spectrum(seg, al, de, fd, nfft, k0, k1)
+    err = rel_err_floor(got, ref)
+    note(f"spectrum max rel err {err:.3e}")
+    assert err < TOL_MIXED
+    from tests.gpu_util import dev
+    plan.search_batch(0, dev(al), dev(de), dev(fd))
+    recs, keys, n = plan.candidates()
+    assert np.all((keys["bin"] >= k0) & (keys["bin"] < k1))
+    key3 = np.stack([keys["sky"], keys["fdot_idx"], keys["bin"]], 1)
+    ng, no, flips, mism, e2 = compare_candidates(key3, recs["twoF"], ref, full.threshold, GUARD_MIXED, k_min=k0)
+    note(f"gpu {ng} oracle {no} flips {flips} mismatches {len(mism)}")
+    assert no > 0 and not mism
+
+
 def test_plain_launches_equal_batched(torch, full):
     note("one template per launch vs batched")
     seg = full.segments[0]
