@@ -217,21 +217,6 @@ __device__ __forceinline__ void middle_stages(cx<T>* cola, cx<T>* colb, int g, c
   }
 }
 
-// Middle stages for one series.
-template <typename T, int LEN, int G, int NS, bool INV>
-__device__ __forceinline__ void middle_stages1(cx<T>* col, int g, const cx<T>* __restrict__ twst) {
-  constexpr int R = stage_radix<LEN, NS>();
-  if constexpr (NS * R < LEN) {
-    constexpr int PB = (LEN / R) / G;
-    cx<T> v[PB][R];
-    stage_from_lds<T, LEN, G, NS, R, PB, INV>(v, col, g, twst);
-    __syncthreads();
-    stage_to_lds<T, LEN, G, NS, R, PB>(v, col, g);
-    __syncthreads();
-    middle_stages1<T, LEN, G, NS * R, INV>(col, g, twst);
-  }
-}
-
 template <int LEN, int NS>
 __host__ __device__ constexpr int last_ns() {
   if constexpr (NS * stage_radix<LEN, NS>() >= LEN) return NS;
