@@ -250,8 +250,10 @@ fstat_status fstat_vet_destroy(fstat_vet_t vet);
 fstat_status fstat_plan_attach_vetter(fstat_plan_t plan, fstat_vet_t vet, int64_t patch_capacity);
 
 /* Score the stored windows of the crossings found since the last drain with the
- * attached network (asynchronous on `stream`); fstat_candidates then reports the
- * scores in the keys (NaN for crossings beyond patch_capacity). */
+ * attached network, in batches of the network's max_batch on `stream`.  Waits for
+ * the plan's searches before it starts and for the scoring before it returns;
+ * fstat_candidates then reports the scores in the keys (NaN for crossings beyond
+ * patch_capacity). */
 fstat_status fstat_plan_vet_candidates(fstat_plan_t plan, void* stream);
 
 /* Static text for a status code. */
