@@ -738,7 +738,8 @@ void vet_infer_batch(fstat_vet_t v, const float* patches, int n, float* out, hip
 void vet_forward_batch(fstat_vet_t v, const float* patches, int n, float* out, hipStream_t st) {
   using namespace vet;
   const long NL = (long)n * L;
-  hipLaunchKernelGGL(k_vet_conv1, blocks_for(NL * C), dim3(256), 0, st, patches, n, v->theta, v->u, v->z1, v->a1b);
+  hipLaunchKernelGGL(k_vet_input, blocks_for(NL), dim3(256), 0, st, patches, NL, v->u);
+  hipLaunchKernelGGL(k_vet_conv1, blocks_for(NL * C), dim3(256), 0, st, v->u, n, v->theta, v->z1, v->a1b);
   hipLaunchKernelGGL(k_vet_im2col, blocks_for(NL * KC), dim3(256), 0, st, v->a1b, n, 1, v->colA);
   gemm(st, (int)NL, C, KC, v->colA, KC, 1, v->wf2, C, 1, v->z2, C);
   hipLaunchKernelGGL(k_vet_bias_relu, blocks_for(NL * C), dim3(256), 0, st, v->z2, NL, C, v->theta + O_B2, v->a2b,
@@ -747,7 +748,18 @@ void vet_forward_batch(fstat_vet_t v, const float* patches, int n, float* out, h
   gemm(st, (int)NL, C, KC, v->colB, KC, 1, v->wf3, C, 1, v->z3, C);
   hipLaunchKernelGGL(k_vet_bias_relu, blocks_for(NL * C), dim3(256), 0, st, v->z3, NL, C, v->theta + O_B3, v->a3b,
                      (float*)nullptr);
-  gemm(st, n, H, X, v->a3b, X, 1, v->w4b, 1, X, v->z4, H);
+  {
+    // the 8192 -> 128 layer: LDS-tiled product, K split so that the grid fills the chip
+    const int nbp = (n + GT - 1) / GT * GT;
+    const int tiles = (H / GT) * (nbp / GT);
+    int splits = 1;
+    while (splits < 32 && tiles * splits < 256) splits <<= 1;
+    hipLaunchKernelGGL(k_gemm_nt_lds, dim3(H / GT, nbp / GT, splits), dim3(256), 0, st, nbp, H, X, v->a3b, v->w4b,
+                       v->scratch, X / splits);
+    const long count = (long)nbp * H;
+    hipLaunchKernelGGL(k_vet_sum_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, v->scratch, splits,
+                       count, H, (long)H, v->z4);
+  }
   hipLaunchKernelGGL(k_vet_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->z4, (long)n, H, v->theta + O_B4,
                      v->a4b, (float*)nullptr);
   gemm(st, n, H, H, v->a4b, H, 1, v->w5b, 1, H, v->z5, H);
@@ -761,9 +773,9 @@ void vet_backward(fstat_vet_t v, const float* labels, int n, hipStream_t st) {
   const long NL = (long)n * L;
   float* g = v->grad;
   float* sc = v->scratch;
-  hipLaunchKernelGGL(k_vet_head_backward, blocks_for(n), dim3(256), 0, st, v->logit, labels, n, v->theta, v->z5,
-                     v->a5, v->dz5, v->dz5b, v->dlogit, v->lterm);
-  hipLaunchKernelGGL(k_vet_head_reduce, dim3(1), dim3(H + 1), 0, st, v->dlogit, v->a5, v->lterm, n, g, v->loss);
+  hipLaunchKernelGGL(k_vet_head_backward, blocks_for((long)n * H), dim3(256), 0, st, v->logit, labels, n, v->theta,
+                     v->z5, v->dz5, v->dz5b, v->dlogit, v->lterm);
+  hipLaunchKernelGGL(k_vet_head_reduce, dim3(1), dim3(1024), 0, st, v->dlogit, v->a5, v->lterm, n, g, v->loss);
   gemm(st, H, H, n, v->dz5b, 1, H, v->a4b, H, 1, g + O_W5, H, sc);             // dW5 = dz5^T a4
   colsum(st, v->dz5, (long)n, H, g + O_B5, sc);
   gemm(st, n, H, H, v->dz5b, H, 1, v->w5b, H, 1, v->dh4, H);                   // dh4 = dz5 W5
@@ -785,10 +797,10 @@ void vet_backward(fstat_vet_t v, const float* labels, int n, hipStream_t st) {
   gemm(st, (int)NL, C, KC, v->colC, KC, 1, v->wt2, C, 1, v->da, C);             // da1
   hipLaunchKernelGGL(k_vet_relu_mask, blocks_for(NL * C), dim3(256), 0, st, v->da, v->z1, NL * C, v->dzb);
   {
-    const long per = 4096;
+    const long per = 256;
     const int chunks = (int)((NL + per - 1) / per);
     const int ncols = C * (KW + 1);
-    hipLaunchKernelGGL(k_vet_conv1_backward_part, dim3(ncols, chunks), dim3(256), 0, st, v->da, v->u, NL, per, sc);
+    hipLaunchKernelGGL(k_vet_conv1_backward_part, dim3(chunks), dim3(256), 0, st, v->da, v->u, NL, per, sc);
     hipLaunchKernelGGL(k_vet_colsum_final, dim3((ncols + 255) / 256), dim3(256), 0, st, sc, chunks, ncols,
                        sc + (long)chunks * ncols);
     hipLaunchKernelGGL(k_vet_conv1_scatter, dim3(1), dim3(256), 0, st, sc + (long)chunks * ncols, g);

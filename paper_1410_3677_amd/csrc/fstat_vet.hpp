@@ -143,25 +143,30 @@ __global__ void __launch_bounds__(256) k_vet_colsum_part(const float* __restrict
   if (threadIdx.x == 0) part[(long)chunk * cols + j] = red[0];
 }
 
-// u = log(1 + 2F) - log 5 per patch bin; conv1 (one input channel):
-// z1[n][p][c] = b1[c] + sum_t w1[c][t] u[n][p+t-3]; a1 = relu(z1) as BF16.
-__global__ void k_vet_conv1(const float* __restrict__ patches, int n, const float* __restrict__ theta,
-                            float* __restrict__ u, float* __restrict__ z1, uint16_t* __restrict__ a1b) {
+// u = log(1 + 2F) - log 5 per patch bin (n * L threads)
+__global__ void k_vet_input(const float* __restrict__ patches, long count, float* __restrict__ u) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < count) u[idx] = log1pf(patches[idx]) - 1.6094379124341003f;
+}
+
+// conv1 (one input channel): z1[n][p][c] = b1[c] + sum_t w1[c][t] u[n][p+t-3]; a1 = relu(z1)
+// as BF16 (n * L * C threads).
+__global__ void k_vet_conv1(const float* __restrict__ u, int n, const float* __restrict__ theta,
+                            float* __restrict__ z1, uint16_t* __restrict__ a1b) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;  // over n * L * C
   if (idx >= (long)n * L * C) return;
   const int c = idx % C;
   const int p = (idx / C) % L;
   const long s = idx / (C * L);
-  const float* pp = patches + s * L;
+  const float* us = u + s * L;
   float z = theta[O_B1 + c];
 #pragma unroll
   for (int t = 0; t < KW; ++t) {
     const int q = p + t - 3;
-    if (q >= 0 && q < L) z += theta[O_W1 + c * KW + t] * (log1pf(pp[q]) - 1.6094379124341003f);
+    if (q >= 0 && q < L) z += theta[O_W1 + c * KW + t] * us[q];
   }
   z1[idx] = z;
   a1b[idx] = f2bf(z > 0.f ? z : 0.f);
-  if (c == 0) u[s * L + p] = log1pf(pp[p]) - 1.6094379124341003f;
 }
 
 // im2col of a position-major BF16 activation [n][L][C]:
@@ -203,23 +208,25 @@ __global__ void k_vet_fc3(const float* __restrict__ a5, int n, const float* __re
 
 // Loss and the first backward step: dlogit = (sigmoid(logit) - y) / n; loss = mean BCE.
 // dz5[s][j] = dlogit[s] w6[j] (z5 > 0); also dW6, db6 partial sums per block.
+// Head backward over n * H threads: dlogit = (sigmoid(logit) - y) / n, its loss term, and
+// dz5[s][j] = dlogit w6[j] [z5 > 0] (FP32 and BF16).
 __global__ void k_vet_head_backward(const float* __restrict__ logit, const float* __restrict__ y, int n,
                                     const float* __restrict__ theta, const float* __restrict__ z5,
-                                    const float* __restrict__ a5, float* __restrict__ dz5,
-                                    uint16_t* __restrict__ dz5b, float* __restrict__ dlogit,
-                                    float* __restrict__ loss_terms) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
+                                    float* __restrict__ dz5, uint16_t* __restrict__ dz5b,
+                                    float* __restrict__ dlogit, float* __restrict__ loss_terms) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)n * H) return;
+  const int s = (int)(idx / H), j = (int)(idx % H);
   const float l = logit[s];
   const float sig = 1.f / (1.f + expf(-l));
   const float d = (sig - y[s]) / (float)n;
-  dlogit[s] = d;
-  loss_terms[s] = fmaxf(l, 0.f) - l * y[s] + log1pf(expf(-fabsf(l)));
-  for (int j = 0; j < H; ++j) {
-    const float g = z5[(long)s * H + j] > 0.f ? d * theta[O_W6 + j] : 0.f;
-    dz5[(long)s * H + j] = g;
-    dz5b[(long)s * H + j] = f2bf(g);
+  if (j == 0) {
+    dlogit[s] = d;
+    loss_terms[s] = fmaxf(l, 0.f) - l * y[s] + log1pf(expf(-fabsf(l)));
   }
+  const float g = z5[idx] > 0.f ? d * theta[O_W6 + j] : 0.f;
+  dz5[idx] = g;
+  dz5b[idx] = f2bf(g);
 }
 
 // dz = dh * (z > 0) in place, BF16 copy.
@@ -241,57 +248,62 @@ __global__ void k_vet_colsum_final(const float* __restrict__ part, int chunks, i
   out[j] = acc;
 }
 
-// dW6[j] = sum_s dlogit[s] a5[s][j]; db6 = sum_s dlogit[s]; loss = mean of the terms.
-__global__ void k_vet_head_reduce(const float* __restrict__ dlogit, const float* __restrict__ a5,
-                                  const float* __restrict__ loss_terms, int n, float* __restrict__ grad,
-                                  float* __restrict__ loss) {
-  const int j = threadIdx.x;  // H + 1 threads
-  if (j < H) {
-    float acc = 0.f;
-    for (int s = 0; s < n; ++s) acc += dlogit[s] * a5[(long)s * H + j];
-    grad[O_W6 + j] = acc;
-  } else if (j == H) {
-    float acc = 0.f, ls = 0.f;
-    for (int s = 0; s < n; ++s) {
-      acc += dlogit[s];
-      ls += loss_terms[s];
+// dW6[j] = sum_s dlogit[s] a5[s][j], db6 = sum_s dlogit[s], loss = mean of the loss terms:
+// 1024 threads, eight interleaved partial sums per column added in a fixed order.
+__global__ void __launch_bounds__(1024) k_vet_head_reduce(const float* __restrict__ dlogit,
+                                                          const float* __restrict__ a5,
+                                                          const float* __restrict__ loss_terms, int n,
+                                                          float* __restrict__ grad, float* __restrict__ loss) {
+  constexpr int PARTS = 1024 / H;
+  __shared__ float red[PARTS][H + 2];
+  const int j = threadIdx.x % H, part = threadIdx.x / H;
+  float acc = 0.f, accd = 0.f, accl = 0.f;
+  for (int s = part; s < n; s += PARTS) {
+    const float d = dlogit[s];
+    acc += d * a5[(long)s * H + j];
+    if (j == 0) {
+      accd += d;
+      accl += loss_terms[s];
     }
-    grad[O_B6] = acc;
-    if (loss) *loss = ls / (float)n;
+  }
+  red[part][j] = acc;
+  if (j == 0) {
+    red[part][H] = accd;
+    red[part][H + 1] = accl;
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < H + 2) {
+    float sum = 0.f;
+    for (int q = 0; q < PARTS; ++q) sum += red[q][t];
+    if (t < H) grad[O_W6 + t] = sum;
+    else if (t == H) grad[O_B6] = sum;
+    else if (loss) *loss = sum / (float)n;
   }
 }
 
 // conv1 weight and bias gradients: dW1[c][t] = sum_{s,p} dz1[s][p][c] u[s][p+t-3]; db1[c].
-// Block (c * (KW + 1) + t, chunk) sums a chunk of the n * L rows; k_vet_colsum_final adds
-// the chunks in order into grad[O_W1 ...] (layout c * KW + t, bias c).
+// Block b sums rows [b rows_per_chunk, ...) with thread (c = t % 32, k = t / 32): tap k < KW
+// or the bias (k = KW), writing part[b][c (KW + 1) + k]; k_vet_colsum_final adds the chunks
+// in order.
 __global__ void __launch_bounds__(256) k_vet_conv1_backward_part(const float* __restrict__ dz1,
                                                                  const float* __restrict__ u, long rows,
                                                                  long rows_per_chunk, float* __restrict__ part) {
-  const int ct = blockIdx.x;  // C * (KW + 1)
-  const int c = ct / (KW + 1), t = ct % (KW + 1);
-  const int chunk = blockIdx.y;
-  const long r0 = (long)chunk * rows_per_chunk;
+  const int c = threadIdx.x % C, k = threadIdx.x / C;
+  const long r0 = (long)blockIdx.x * rows_per_chunk;
   const long r1 = min(rows, r0 + rows_per_chunk);
   float acc = 0.f;
-  for (long r = r0 + threadIdx.x; r < r1; r += 256) {
+  for (long r = r0; r < r1; ++r) {
     const float g = dz1[r * C + c];
-    if (t == KW) {
+    if (k == KW) {
       acc += g;
     } else {
       const int p = r % L;
-      const long s = r / L;
-      const int q = p + t - 3;
-      if (q >= 0 && q < L) acc += g * u[s * L + q];
+      const int q = p + k - 3;
+      if (q >= 0 && q < L) acc += g * u[(r - p) + q];
     }
   }
-  __shared__ float red[256];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[(long)chunk * (C * (KW + 1)) + ct] = red[0];
+  part[(long)blockIdx.x * (C * (KW + 1)) + c * (KW + 1) + k] = acc;
 }
 
 // Move the conv1 sums (c * (KW + 1) + t order) into the flat gradient (weights c * KW + t, biases c).
