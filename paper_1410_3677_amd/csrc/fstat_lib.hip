@@ -382,9 +382,11 @@ static fstat_status run_sky_batch(fstat_plan_t p, const Dev<T>& d, const SegInfo
 }
 
 // Template stage for the nb skies of the current batch: nb * nfdot templates in launches of B.
-// workgroups per compute unit resident at once in the streaming second pass (its LDS and
-// registers allow four)
-constexpr int STREAM_WG_PER_CU = 4;
+// workgroups per compute unit of the streaming second pass.  Its LDS and registers allow
+// four; three wavefronts per SIMD read the interleaved intermediate faster on MI355X
+// (0.70 against 0.75 us per 2^18-point template), and grids between three and four per
+// CU are slower still (uneven CUs).
+constexpr int STREAM_WG_PER_CU = 3;
 
 template <typename T>
 static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo& si, int sky0, int nb,

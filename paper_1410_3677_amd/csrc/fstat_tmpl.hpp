@@ -200,6 +200,20 @@ __device__ __forceinline__ const cx<T>& at32(const cx<T>* base, unsigned o) {
   return *reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(base) + o * (unsigned)sizeof(cx<T>));
 }
 
+// The intermediate between the two passes holds a template's two series interleaved:
+// value (k2, j1) of series s at 2 (k2 P + j1) + s, so that the pair (a, b) of one
+// position is one 16-byte access in FP32 and eight adjacent columns fill a 128-byte line.
+typedef float f4v_t __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ void store_pair(cx<T>* base, unsigned o, cx<T> a, cx<T> b) {
+  if constexpr (sizeof(T) == 4) {
+    *reinterpret_cast<f4v_t*>(reinterpret_cast<char*>(base) + o * 16u) = f4v_t{a.re, a.im, b.re, b.im};
+  } else {
+    at32(base, 2 * o) = a;
+    at32(base, 2 * o + 1) = b;
+  }
+}
+
 // Middle stages (stride NS up to, not including, the last stage) for two series.
 template <typename T, int LEN, int G, int NS, bool INV, bool WAVE_ONLY = false>
 __device__ __forceinline__ void middle_stages(cx<T>* cola, cx<T>* colb, int g, const cx<T>* __restrict__ twst) {
@@ -370,14 +384,14 @@ __global__ void __launch_bounds__((tmpl_nt_a<T, Q>())) k_tmpl_a(TmplArgs ta, con
     middle_stages1_off<T, Q, G, R1, false>(col, g, twst);
     cx<T> v[PBL][RL];
     stage_from_lds_off<T, Q, G, NSL, RL, PBL, false>(v, col, g, twst);
-    cx<T>* out = tbuf + (long)(2 * item + s) * ta.L;
+    cx<T>* out = tbuf + (long)(2 * item) * ta.L;
 #pragma unroll
     for (int b = 0; b < PBL; ++b) {
       const int j = g + G * b;
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
         const unsigned o = (unsigned)(j + NSL * r) * (unsigned)ta.P + (unsigned)j1;
-        at32(out, o) = cmul(v[b][r], tw[b][r]);
+        at32(out, 2 * o + s) = cmul(v[b][r], tw[b][r]);
       }
     }
   }
@@ -425,8 +439,7 @@ __global__ void __launch_bounds__((tmpl_nt_a<T, Q>())) k_tmpl_a_pair(TmplArgs ta
   cx<T> va[PBL][RL], vb[PBL][RL];
   stage_from_lds_off<T, Q, G, NSL, RL, PBL, false>(va, cola, g, twst);
   stage_from_lds_off<T, Q, G, NSL, RL, PBL, false>(vb, colb, g, twst);
-  cx<T>* outa = tbuf + (long)(2 * item) * ta.L;
-  cx<T>* outb = outa + ta.L;
+  cx<T>* out = tbuf + (long)(2 * item) * ta.L;
   const cx<T> step = twiddle_L<T, false>(twlo, twhi, j1 * NSL);
 #pragma unroll
   for (int b = 0; b < PBL; ++b) {
@@ -435,8 +448,7 @@ __global__ void __launch_bounds__((tmpl_nt_a<T, Q>())) k_tmpl_a_pair(TmplArgs ta
 #pragma unroll
     for (int r = 0; r < RL; ++r) {
       const unsigned o = (unsigned)(j + NSL * r) * (unsigned)ta.P + (unsigned)j1;
-      at32(outa, o) = cmul(va[b][r], w);
-      at32(outb, o) = cmul(vb[b][r], w);
+      store_pair(out, o, cmul(va[b][r], w), cmul(vb[b][r], w));
       if (r + 1 < RL) w = cmul(w, step);
     }
   }
@@ -478,8 +490,7 @@ __global__ void __launch_bounds__((tmpl_nt_b<T, P>())) k_tmpl_b(TmplArgs ta, con
   const int t = ta.t0 + item;
   const int skyl = t / ta.nfdot, sidx = t % ta.nfdot;
   const int k2 = tile * TW + c;
-  const cx<T>* ina = tbuf + (long)(2 * item) * ta.L + (long)k2 * ta.P;
-  const cx<T>* inb = ina + ta.L;
+  const cx<T>* in = tbuf + (long)(2 * item) * ta.L + 2 * (long)k2 * ta.P;
   cx<T>* cola = lds + c * ST;
   cx<T>* colb = lds + (TW + c) * ST;
   {
@@ -489,8 +500,8 @@ __global__ void __launch_bounds__((tmpl_nt_b<T, P>())) k_tmpl_b(TmplArgs ta, con
       const int j = g + G * b;
 #pragma unroll
       for (int r = 0; r < R1; ++r) {
-        va[b][r] = ina[j + NB1 * r];
-        vb[b][r] = inb[j + NB1 * r];
+        va[b][r] = in[2 * (j + NB1 * r)];
+        vb[b][r] = in[2 * (j + NB1 * r) + 1];
       }
       dftr<T, R1, false>(va[b]);
       dftr<T, R1, false>(vb[b]);
@@ -589,7 +600,7 @@ __global__ void __launch_bounds__((tmpl_nt_b<T, P>())) k_tmpl_b(TmplArgs ta, con
 }
 
 // ---------------------------------------------------------------- pass B, streaming (FP32, P <= 512)
-// Each wavefront owns RPW = 64 / G whole rows and walks NR row units of one template.  The eight loads per series of the next unit are issued before the current
+// Each wavefront owns RPW = 64 / G whole rows and walks NR row units of one template.  The eight paired (a, b) loads of the next unit are issued before the current
 // unit is transformed, so HBM reads overlap the butterflies; twiddles of the stages
 // after the first stay in registers for the whole walk; all LDS exchanges are local to
 // the wavefront; candidates are compacted with ballots and one atomic per wavefront
@@ -688,12 +699,15 @@ __device__ __forceinline__ const auto& last_stage_tw(const StageTw<T, LEN, G, NS
 
 // A value of the intermediate, read once: a non-temporal load (the row is not kept in
 // the caches for reuse).
-typedef float f2v_t __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ cx<float> load_stream(const cx<float>* p) {
-  const f2v_t v = __builtin_nontemporal_load(reinterpret_cast<const f2v_t*>(p));
-  return mk<float>(v.x, v.y);
+__device__ __forceinline__ void load_stream(const cx<float>* p, cx<float>& a, cx<float>& b) {
+  const f4v_t v = __builtin_nontemporal_load(reinterpret_cast<const f4v_t*>(p));
+  a = mk<float>(v.x, v.y);
+  b = mk<float>(v.z, v.w);
 }
-__device__ __forceinline__ cx<double> load_stream(const cx<double>* p) { return *p; }
+__device__ __forceinline__ void load_stream(const cx<double>* p, cx<double>& a, cx<double>& b) {
+  a = p[0];
+  b = p[1];
+}
 
 // Candidates a wavefront stages in LDS before it reserves their slots with one atomic.
 constexpr int STAGE_CAP = 32;
@@ -742,15 +756,11 @@ __global__ void __launch_bounds__(256) k_tmpl_b_stream(TmplArgs ta, int ntmpl, c
   // unit U of the launch: template U / units, rows (U % units) RPW + sub
   auto load_unit = [&](cx<T> (&ca)[PB1][R1], cx<T> (&cb)[PB1][R1], int U) {
     const int item = U / units, u = U - item * units;
-    const cx<T>* pa = tbuf + (long)(2 * item) * ta.L + (long)u * (RPW * P);
-    const cx<T>* pb = pa + ta.L;
+    const cx<T>* p = tbuf + (long)(2 * item) * ta.L + 2 * (long)u * (RPW * P);
 #pragma unroll
     for (int b = 0; b < PB1; ++b)
 #pragma unroll
-      for (int r = 0; r < R1; ++r) {
-        ca[b][r] = load_stream(pa + lofs + G * b + NB1 * r);
-        cb[b][r] = load_stream(pb + lofs + G * b + NB1 * r);
-      }
+      for (int r = 0; r < R1; ++r) load_stream(p + 2 * (lofs + G * b + NB1 * r), ca[b][r], cb[b][r]);
   };
 
   auto emit = [&](unsigned long long slot, int item, int bin, T v) {
