@@ -36,6 +36,13 @@ below states the reading it uses:
   provided as well;
 * candidates: every bin with 2F strictly above the threshold.
 
+Interbinning (an alternative to the 2x zero-padding, not the paper's own
+step): the transform is taken over nfft/2 points only; even bins 2k of the
+fine grid are its bins k exactly, odd bins 2k+1 are estimated from the two
+neighbours as c (X_k - X_{k+1}), with c chosen so that a sinusoid midway
+between two bins, over the N nonzero samples, comes out exactly (at N = nfft/2
+this is the classic interbinning weight, about pi/4).
+
 Every floating-point step is FP64.  numpy's FFT and scipy's banded solver are
 used as library primitives.
 """
@@ -227,6 +234,47 @@ def template_two_f(seg, sky, fdot: float, nfft: int, k_min: int = 0, k_max: int 
     return two_f(fa, fb, sky["A"], sky["B"], seg.n, seg.sigma2)
 
 
+def interbin_weight(n: int, length: int) -> float:
+    """Interbinning weight c for a length-`length` transform of n nonzero samples.
+
+    Take the sinusoid y_j = exp(i pi j / length), j < n, midway between bins 0 and
+    1; X_0 and X_1 are its transform values at those bins (summed directly) and its
+    exact value halfway is n, so c = n / |X_0 - X_1|.
+    """
+    j = np.arange(n, dtype=np.float64)
+    y = np.exp(1j * math.pi * j / length)
+    x0 = np.sum(y)
+    x1 = np.sum(y * np.exp(-2j * math.pi * j / length))
+    return float(n / abs(x0 - x1))
+
+
+def interbinned_transform(y: np.ndarray, nfft: int) -> np.ndarray:
+    """All nfft bins of the interpolated transform from a transform of nfft/2 points.
+
+    Even bins 2k: X_k of the nfft/2-point transform (the zero-padded values exactly);
+    odd bins 2k+1: c (X_k - X_{k+1}), the index taken modulo nfft/2.
+    """
+    half = nfft // 2
+    x = fourier_transform(y, half)
+    c = interbin_weight(y.shape[0], half)
+    out = np.empty(nfft, dtype=np.complex128)
+    out[0::2] = x
+    out[1::2] = c * (x - np.roll(x, -1))
+    return out
+
+
+def template_two_f_interbin(seg, sky, fdot: float, nfft: int, k_min: int = 0, k_max: int = -1,
+                            full: bool = False) -> np.ndarray:
+    """2F over bins [k_min, k_max) of the nfft grid, with the interbinned transform."""
+    if k_max < 0:
+        k_max = nfft // 2
+    fa = interbinned_transform(spindown_demodulate(sky["za_t"], fdot, seg.dt), nfft)[k_min:k_max]
+    fb = interbinned_transform(spindown_demodulate(sky["zb_t"], fdot, seg.dt), nfft)[k_min:k_max]
+    if full:
+        return two_f_full(fa, fb, sky["A"], sky["B"], sky["C"], seg.n, seg.sigma2)
+    return two_f(fa, fb, sky["A"], sky["B"], seg.n, seg.sigma2)
+
+
 # ---------------------------------------------------------------- candidates
 CANDIDATE_DTYPE = np.dtype([("segment", np.int32), ("sky", np.int32), ("fdot_idx", np.int32),
                             ("bin", np.int32), ("f_hz", np.float64), ("fdot", np.float64),
@@ -235,13 +283,14 @@ CANDIDATE_DTYPE = np.dtype([("segment", np.int32), ("sky", np.int32), ("fdot_idx
 
 def search(seg, alpha, delta, fdot, threshold: float, nfft: int = 0, k_min: int = 0,
            k_max: int = -1, segment_index: int = 0, full: bool = False,
-           skies=None, fdot_indices=None):
+           skies=None, fdot_indices=None, interbin: bool = False):
     """Threshold crossings of every (sky, spindown) template (Sect. 2, Fig. 3).
 
     Each candidate is the paper's five numbers (frequency, spindown, sky
     position, 2F) plus its integer key (segment, sky, spindown index, bin);
     the result is sorted by key.  `skies` / `fdot_indices` restrict the search
-    to a subset of the lists (same indices as the full search).
+    to a subset of the lists (same indices as the full search).  `interbin`
+    selects the interbinned transform of nfft/2 points.
     """
     if nfft <= 0:
         nfft = default_nfft(seg.n)
@@ -256,7 +305,8 @@ def search(seg, alpha, delta, fdot, threshold: float, nfft: int = 0, k_min: int 
     for i in skies:
         sky = sky_stage(seg, float(alpha[i]), float(delta[i]), nfft)
         for s in fdot_indices:
-            tf = template_two_f(seg, sky, float(fdot[s]), nfft, k_min, k_max, full)
+            tfun = template_two_f_interbin if interbin else template_two_f
+            tf = tfun(seg, sky, float(fdot[s]), nfft, k_min, k_max, full)
             ks = np.nonzero(tf > threshold)[0]
             for k in ks:
                 kk = int(k) + k_min

@@ -218,3 +218,37 @@ def p6_linearity(n: int = 4096, seed: int = 5) -> float:
         sky = oracle.sky_stage(s, al, de, nfft)
         f.append(oracle.fourier_transform(oracle.spindown_demodulate(sky["za_t"], fd, s.dt), nfft))
     return float(np.max(np.abs(f[2] - (f[0] + 0.5 * f[1]))) / np.max(np.abs(f[2])))
+
+
+# ---------------------------------------------------------------- interbinning
+def ib_midway_error(n: int = 3000, nfft: int = 8192, k0: int = 517) -> float:
+    """| |odd bin 2 k0 + 1| - exact | / exact for a sinusoid midway between bins k0, k0 + 1."""
+    half = nfft // 2
+    j = np.arange(n)
+    y = 0.3 * np.exp(1j * 0.7) * np.exp(2j * math.pi * (k0 + 0.5) * j / half)
+    ib = oracle.interbinned_transform(y, nfft)
+    return abs(abs(ib[2 * k0 + 1]) - 0.3 * n) / (0.3 * n)
+
+
+def ib_direct_sum_error(n: int = 500, nfft: int = 2048, seed: int = 12) -> float:
+    """Max relative deviation of odd bins (interior and the wrap-around one) and even bins
+    from direct sums: even 2k = X_k, odd 2k + 1 = c (X_k - X_{k+1 mod nfft/2})."""
+    half = nfft // 2
+    g = np.random.default_rng(seed)
+    y = g.standard_normal(n) + 1j * g.standard_normal(n)
+    j = np.arange(n)
+    c = oracle.interbin_weight(n, half)
+
+    def X(k):
+        return np.sum(y * np.exp(-2j * math.pi * j * (k % half) / half))
+    ib = oracle.interbinned_transform(y, nfft)
+    scale = abs(X(0))
+    err = 0.0
+    for k in (0, 1, 300, half - 2, half - 1):
+        err = max(err, abs(ib[2 * k] - X(k)) / scale, abs(ib[2 * k + 1] - c * (X(k) - X(k + 1))) / scale)
+    return err
+
+
+def ib_weight_error() -> float:
+    """Deviation of the full-length weight from the classic pi/4."""
+    return abs(oracle.interbin_weight(4096, 4096) - math.pi / 4)

@@ -120,3 +120,48 @@ def test_swapped_a_b_averages_are_caught(monkeypatch):
     orig = fo.antenna_averages
     monkeypatch.setattr(fo, "antenna_averages", lambda a, b: (lambda A, B, C: (B, A, C))(*orig(a, b)))
     assert not _p2_ok()
+
+
+def _ib_variant(diff):
+    def wrong(y, nfft):
+        half = nfft // 2
+        x = np.fft.fft(y, half)
+        c = fo.interbin_weight(y.shape[0], half)
+        out = np.empty(nfft, dtype=np.complex128)
+        out[0::2] = x
+        out[1::2] = c * diff(x)
+        return out
+    return wrong
+
+
+def test_interbinning_with_a_sum_is_caught(monkeypatch):
+    monkeypatch.setattr(fo, "interbinned_transform", _ib_variant(lambda x: x + np.roll(x, -1)))
+    assert pins.ib_midway_error() > 0.5
+    assert pins.ib_direct_sum_error() > 1e-3
+
+
+def test_interbinning_with_the_lower_neighbour_is_caught(monkeypatch):
+    monkeypatch.setattr(fo, "interbinned_transform", _ib_variant(lambda x: x - np.roll(x, 1)))
+    assert pins.ib_midway_error() > 0.1
+    assert pins.ib_direct_sum_error() > 1e-3
+
+
+def test_interbinning_without_the_wrap_is_caught(monkeypatch):
+    def no_wrap(x):
+        d = x - np.roll(x, -1)
+        d[-1] = x[-1]
+        return d
+    monkeypatch.setattr(fo, "interbinned_transform", _ib_variant(no_wrap))
+    assert pins.ib_direct_sum_error() > 1e-3
+
+
+def test_interbinning_weight_of_one_is_caught(monkeypatch):
+    monkeypatch.setattr(fo, "interbin_weight", lambda n, length: 1.0)
+    assert pins.ib_midway_error() > 0.1
+    assert pins.ib_weight_error() > 0.1
+
+
+def test_interbinning_weight_for_the_full_length_is_caught(monkeypatch):
+    # the classic pi/4 used although the data fill only part of the transform
+    monkeypatch.setattr(fo, "interbin_weight", lambda n, length: math.pi / 4)
+    assert pins.ib_midway_error() > 0.05
