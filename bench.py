@@ -12,7 +12,9 @@ noise plus five injected signals), resident in HBM before timing starts.
 
 Printed: one JSON line with templates/s, the per-kernel HIP-event timings,
 the roofline of the dominant kernel, the plain one-template-per-launch path
-(256 x 64 templates) and the CPU oracle timed on a bounded sample.
+(256 x 64 templates), the CPU oracle timed on a bounded sample, and the same
+batched workload searched with interbinning (template transforms of nfft/2
+points, odd bins from their neighbours) as a separate entry.
 """
 from __future__ import annotations
 
@@ -62,6 +64,19 @@ def measured_traffic(kernel: str, templates_per_launch: int, variants: int):
     return k["bytes_per_launch"]
 
 
+def cache_has_line(path, nfft: int, precision_key: int) -> bool:
+    """Whether a tuning cache holds a line for this FFT length and precision key (the
+    precision plus 2 with interbinning); the device tag is the library's business."""
+    if not path or not os.path.exists(path):
+        return False
+    with open(path) as f:
+        for line in f:
+            p = line.split()
+            if len(p) == 6 and p[1] == str(nfft) and p[2] == str(precision_key):
+                return True
+    return False
+
+
 def _oracle_sky_worker(job):
     """One sky of the oracle sample: its sky stage and every spindown template (2F + threshold)."""
     import numpy as np
@@ -97,6 +112,95 @@ def cpu_multicore_leg(args, log):
     return {"value": ntpl / dt, "unit": "templates/s", "cores": workers, "kind": "oracle",
             "sample": f"{workers} sky x {args.nfdot} spindown templates of the batched workload, one process "
                       f"per core (numpy FP64, one thread each), {dt:.1f} s wall"}
+
+
+def timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbinning=0):
+    """Plan (autotuned, from the cache or fixed), warm up, time args.steps searches of the
+    whole template list, and read the per-kernel HIP-event timings of the timed steps."""
+    label = "interbinning" if interbinning else "mixed"
+    tlen = nfft // 2 if interbinning else nfft          # template transform length
+    # crossings at 2F > 20: 5e-4 of the bins in noise (more on interbinned odd bins)
+    rate = 2.5e-3 if interbinning else 5.0e-4
+    cap = int(max(1 << 20, 3.0 * rate * (nfft // 2) * templates * max(args.steps, 1)))
+    fixed = bool(args.templates_per_launch or args.skies_per_batch or args.no_autotune)
+    cache = args.tuning_cache or None
+    have_cache = cache_has_line(cache, nfft, 1 + 2 * interbinning)
+    plan = F.Plan([F.segment_to_device(seg)], candidate_capacity=cap, workspace_from_torch=False,
+                  templates_per_launch=args.templates_per_launch, skies_per_batch=args.skies_per_batch,
+                  use_graph=0 if args.no_graph else 1, tuning_cache_path=cache, interbinning=interbinning)
+    tuned = "fixed" if fixed else ("cache" if have_cache else "autotune")
+    if tuned == "autotune":
+        t_tune = time.perf_counter()
+        plan.autotune(0, budget_ms=args.autotune_ms)
+        log(f"{label}: autotune {time.perf_counter() - t_tune:.1f} s -> {plan.info(0)}")
+    else:
+        plan._set_torch_workspace()
+    info = plan.info(0)
+    log(f"{label}: plan {info}, capacity {cap}")
+    for i in range(args.warmup):
+        plan.search_batch(0, al, de, fd)
+        torch.cuda.synchronize()
+        log(f"{label}: warmup {i} done, {plan.candidate_count(allow_overflow=True)} candidates")
+    plan.profile_enable(not args.no_events)
+    for c in range(4):
+        plan.profile_read(c, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.search_batch(0, al, de, fd)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n_cand = plan.candidate_count(allow_overflow=True)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = templates / ((t1 - t0) / args.steps)
+    log(f"{label}: {ms_step:.1f} ms/step, {value:.4g} templates/s, {n_cand / args.steps:.4g} candidates/step")
+
+    kernels = {}
+    for c, name in enumerate(F.KERNEL_NAMES):
+        n, ms = plan.profile_read(c, reset=True)
+        kernels[name] = {"launches": n, "total_ms": ms, "avg_ms": ms / n if n else None}
+    B = info["templates_per_launch"]
+    N = seg.n
+    cand_per_template = n_cand / max(templates * args.steps, 1)
+    # algorithmic bytes per launch of the two template kernels:
+    #  pass A writes the 2 x tlen complex FP32 intermediate of each template and reads the
+    #  resampled series (2 x N complex FP32) once per launch (one sky per launch);
+    #  pass B reads the intermediate back and writes the crossings.
+    algo = {"template_a": B * 2 * tlen * CX32 + 2 * N * CX32,
+            "template_b": B * 2 * tlen * CX32 + B * cand_per_template * CAND_BYTES}
+    roofline = None
+    if not args.no_events:
+        dom = max(("template_a", "template_b"), key=lambda k: kernels[k]["total_ms"] or 0.0)
+        avg_s = kernels[dom]["avg_ms"] / 1e3
+        achieved = algo[dom] / avg_s / 1e9
+        variants = info["pass_a_variant"] + 2 * info["pass_b_variant"]
+        traffic = None if interbinning else measured_traffic(dom, B, variants)
+        roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                    "algorithmic_bytes_per_launch": algo[dom], "templates_per_launch": B,
+                    "avg_launch_ms": kernels[dom]["avg_ms"]}
+        for k in ("template_a", "template_b"):
+            kernels[k]["achieved_GBs"] = algo[k] / (kernels[k]["avg_ms"] / 1e3) / 1e9
+    plan.destroy()
+    return {"value": value, "unit": "templates/s", "ms_per_step": ms_step, "n_cand": n_cand,
+            "candidates_per_step": n_cand / args.steps, "info": info, "kernels": kernels, "roofline": roofline,
+            "tuning": tuned, "template_fft": tlen}
+
+
+def ib_summary(ib, templates, nfft):
+    """The interbinning leg for the JSON line (its own throughput; not the headline value)."""
+    if ib is None:
+        return None
+    keep = ("value", "unit", "ms_per_step", "candidates_per_step", "kernels", "roofline", "tuning",
+            "f_rel_err_vs_fp64_interbinned", "even_bins_rel_dev_vs_zero_padded",
+            "odd_bins_mean_2F_ratio_vs_zero_padded", "accuracy_sample")
+    out = {k: ib[k] for k in keep if k in ib}
+    i = ib["info"]
+    out["config"] = {"workload": f"the same {templates} templates, template transforms of nfft/2 = {nfft // 2} "
+                                 "points, odd bins interbinned", "templates_per_launch": i["templates_per_launch"],
+                     "skies_per_batch": i["skies_per_batch"], "pass_a_variant": i["pass_a_variant"],
+                     "template_fft": ib["template_fft"], "p": i["p"], "q": i["q"]}
+    return out
 
 
 def vetting_leg(args, F, torch, np, dev, log):
@@ -200,6 +304,7 @@ def main():
     ap.add_argument("--tuning-cache", default="",
                     help="tuning cache file: reused if it exists, else written by the autotuner")
     ap.add_argument("--no-vetting", action="store_true")
+    ap.add_argument("--no-interbinning", action="store_true")
     ap.add_argument("--vet-epochs", type=int, default=3)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
@@ -240,66 +345,15 @@ def main():
     nfft = synth.nfft_for(seg.n)
     al, de, fd = dev(w.alpha), dev(w.delta), dev(w.fdot)
     templates = args.nsky * args.nfdot
-    cap = int(max(1 << 20, 3.0 * 5.0e-4 * (nfft // 2) * templates * max(args.steps, 1)))
-    fixed = bool(args.templates_per_launch or args.skies_per_batch or args.no_autotune)
-    cache = args.tuning_cache or None
-    have_cache = bool(cache) and os.path.exists(cache)
-    plan = F.Plan([F.segment_to_device(seg)], candidate_capacity=cap, workspace_from_torch=False,
-                  templates_per_launch=args.templates_per_launch, skies_per_batch=args.skies_per_batch,
-                  use_graph=0 if args.no_graph else 1, tuning_cache_path=cache)
-    tuned = "fixed" if fixed else ("cache" if have_cache else "autotune")
-    if tuned == "autotune":
-        t_tune = time.perf_counter()
-        plan.autotune(0, budget_ms=args.autotune_ms)
-        log(f"autotune {time.perf_counter() - t_tune:.1f} s -> {plan.info(0)}")
-    else:
-        plan._set_torch_workspace()
-    info = plan.info(0)
-    log(f"plan {info}, capacity {cap}")
-    for i in range(args.warmup):
-        plan.search_batch(0, al, de, fd)
-        torch.cuda.synchronize()
-        log(f"warmup {i} done, {plan.candidate_count(allow_overflow=True)} candidates")
-    plan.profile_enable(not args.no_events)
-    for c in range(4):
-        plan.profile_read(c, reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.search_batch(0, al, de, fd)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    n_cand = plan.candidate_count(allow_overflow=True)
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    value = templates / ((t1 - t0) / args.steps)
-    log(f"mixed: {ms_step:.1f} ms/step, {value:.4g} templates/s, {n_cand / args.steps:.4g} candidates/step")
+    main_leg = timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbinning=0)
+    value, ms_step, n_cand = main_leg["value"], main_leg["ms_per_step"], main_leg["n_cand"]
+    info, kernels, roofline, tuned = main_leg["info"], main_leg["kernels"], main_leg["roofline"], main_leg["tuning"]
+    B, N = info["templates_per_launch"], seg.n
 
-    kernels = {}
-    for c, name in enumerate(F.KERNEL_NAMES):
-        n, ms = plan.profile_read(c, reset=True)
-        kernels[name] = {"launches": n, "total_ms": ms, "avg_ms": ms / n if n else None}
-    B = info["templates_per_launch"]
-    L, N = nfft, seg.n
-    cand_per_template = n_cand / max(templates * args.steps, 1)
-    # algorithmic bytes per launch of the two template kernels:
-    #  pass A writes the 2 x nfft complex FP32 intermediate of each template and reads the
-    #  resampled series (2 x N complex FP32) once per launch (one sky per launch);
-    #  pass B reads the intermediate back and writes the crossings.
-    algo = {"template_a": B * 2 * L * CX32 + 2 * N * CX32,
-            "template_b": B * 2 * L * CX32 + B * cand_per_template * CAND_BYTES}
-    roofline = None
-    if not args.no_events:
-        dom = max(("template_a", "template_b"), key=lambda k: kernels[k]["total_ms"] or 0.0)
-        avg_s = kernels[dom]["avg_ms"] / 1e3
-        achieved = algo[dom] / avg_s / 1e9
-        variants = info["pass_a_variant"] + 2 * info["pass_b_variant"]
-        roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, B, variants),
-                    "algorithmic_bytes_per_launch": algo[dom], "templates_per_launch": B,
-                    "avg_launch_ms": kernels[dom]["avg_ms"]}
-        for k in ("template_a", "template_b"):
-            kernels[k]["achieved_GBs"] = algo[k] / (kernels[k]["avg_ms"] / 1e3) / 1e9
-    plan.destroy()
+    # ---------------- the same workload with interbinning (template transforms of nfft/2 points)
+    ib = None
+    if not args.no_interbinning:
+        ib = timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbinning=1)
 
     # ---------------- plain path: one template per launch, 256 x 64
     plain = None
@@ -338,7 +392,16 @@ def main():
         torch.cuda.synchronize()
         g = spec.view(len(sk), args.nfdot, nb).cpu().numpy()
         p3.destroy()
+        gi = None
+        if ib is not None:
+            p4 = F.Plan([F.segment_to_device(seg)], interbinning=1)
+            p4.twoF_spectrum(0, dev(w.alpha[sk]), dev(w.delta[sk]), fd, spec)
+            torch.cuda.synchronize()
+            gi = spec.view(len(sk), args.nfdot, nb).cpu().numpy()
+            p4.destroy()
+        del spec
         errs = []
+        ib_err, ib_even, ib_odd_mean, zp_odd_mean = [], [], 0.0, 0.0
         c0 = time.perf_counter()
         for i in sk:
             sky = ora.sky_stage(seg, float(w.alpha[i]), float(w.delta[i]), nfft)
@@ -346,6 +409,16 @@ def main():
                 tf = ora.template_two_f(seg, sky, float(w.fdot[s]), nfft)
                 np.nonzero(tf > w.threshold)
                 errs.append(float(np.max(np.abs(g[i, s] - tf) / np.maximum(tf, 4.0))))
+                if gi is not None:
+                    # outside the timed oracle sample's cost: parity of the interbinned GPU
+                    # spectrum and the method's deviation from the zero-padded transform
+                    c_ib = time.perf_counter()
+                    ti = ora.template_two_f_interbin(seg, sky, float(w.fdot[s]), nfft)
+                    ib_err.append(float(np.max(np.abs(gi[i, s] - ti) / np.maximum(ti, 4.0))))
+                    ib_even.append(float(np.max(np.abs(ti[0::2] - tf[0::2]) / np.maximum(tf[0::2], 4.0))))
+                    ib_odd_mean += float(np.mean(ti[1::2]))
+                    zp_odd_mean += float(np.mean(tf[1::2]))
+                    c0 += time.perf_counter() - c_ib
         c1 = time.perf_counter()
         ntpl = len(sk) * args.nfdot
         single = {"value": ntpl / (c1 - c0), "unit": "templates/s", "cores": 1,
@@ -355,6 +428,13 @@ def main():
         cpu["single_core"] = single
         f_err = max(errs)
         log(f"cpu oracle, one core: {single['value']:.3g} templates/s, max F rel err vs FP64 {f_err:.3e}")
+        if ib is not None and ib_err:
+            ib["f_rel_err_vs_fp64_interbinned"] = max(ib_err)
+            ib["even_bins_rel_dev_vs_zero_padded"] = max(ib_even)
+            ib["odd_bins_mean_2F_ratio_vs_zero_padded"] = ib_odd_mean / zp_odd_mean
+            ib["accuracy_sample"] = f"{len(sk)} sky x {args.nfdot} spindown templates, all bins, FP64 oracle"
+            log(f"interbinning: max F rel err vs the FP64 interbinned oracle {max(ib_err):.3e}; oracle even bins vs "
+                f"zero-padded {max(ib_even):.2e}; odd-bin mean 2F ratio {ib_odd_mean / zp_odd_mean:.3f}")
 
     # ---------------- learned vetting: train on oracle patches, then score the plain search's crossings
     vetting = None
@@ -374,6 +454,7 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu, "plain": plain,
         "f_rel_err_vs_fp64": f_err, "candidates_per_step": n_cand / args.steps, "kernels": kernels,
         "vetting": vetting,
+        "interbinning": ib_summary(ib, templates, nfft),
         "source_sha256": source_digest(),
     }
     print(json.dumps(out), flush=True)

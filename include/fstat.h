@@ -85,6 +85,18 @@ typedef struct {
                                      the call's arguments are unchanged */
   const char* tuning_cache_path;  /* autotuner results file (read by fstat_plan when both batch
                                      sizes are 0, written by fstat_autotune); NULL = none */
+  int32_t interbinning;           /* 0: the template transforms are nfft points long (the 2x
+                                     interpolation by zero-padding, Sect. 2).  1: they are nfft/2
+                                     points long; bin 2k of the nfft grid is bin k of that transform
+                                     (the same value), bin 2k+1 is estimated from its neighbours as
+                                     c (X_k - X_{k+1 mod nfft/2}) for both series, with c chosen so
+                                     that a sinusoid midway between two bins over the n samples comes
+                                     out exactly (c = n sin h / (2 sin(n h) sin((n-1) h)),
+                                     h = pi/nfft; about pi/4 when n = nfft/2).  Halves the template
+                                     stage's memory traffic; the odd bins are an approximation
+                                     (exact for a sinusoid midway between bins; odd bins of pure
+                                     noise have a larger mean than even ones).  Mixed precision
+                                     only (FSTAT_E_NOT_IMPLEMENTED otherwise); needs nfft >= 2^13. */
 } fstat_options;
 
 /* The paper's five numbers of a candidate (Sect. 2). */
@@ -175,14 +187,17 @@ fstat_status fstat_profile_enable(fstat_plan_t plan, int32_t on);
 fstat_status fstat_profile_read(fstat_plan_t plan, int32_t kernel_class, int64_t* launches,
                                 double* total_ms, int32_t reset);
 
-/* Plan facts: FFT length and factors P x Q used for a segment, the batch
+/* Plan facts: FFT length nfft of the bin grid and factors P x Q of the
+ * template transforms of a segment (P Q = nfft, or nfft/2 with
+ * interbinning), the batch
  * sizes in force, the first-pass kernel variant (0: series one after the
  * other through one LDS tile, 1: both series in LDS at once) and the
  * second-pass variant (0: one launch-wide grid of row tiles; 1: about one
  * resident round of wavefronts that walk the launch's rows, prefetching the
  * next row and staging candidates in LDS; variant 1 applies to the mixed
- * precision path with P <= 512, other segments use row tiles).  Any output
- * pointer may be NULL. */
+ * precision path with P <= 512, other segments use row tiles; with
+ * interbinning the second pass is always a walk of wavefronts, each over an
+ * even share of the launch's rows in order).  Any output pointer may be NULL. */
 fstat_status fstat_plan_info(fstat_plan_t plan, int32_t segment, int32_t* nfft, int32_t* p,
                              int32_t* q, int32_t* templates_per_launch, int32_t* skies_per_batch,
                              int32_t* pass_a_variant, int32_t* pass_b_variant);
@@ -191,8 +206,9 @@ fstat_status fstat_plan_info(fstat_plan_t plan, int32_t segment, int32_t* nfft, 
  * spindown grid) for candidate templates-per-launch, skies-per-batch and
  * first-pass kernel variants that fit the workspace budget, keep the fastest,
  * and append it to options.tuning_cache_path if set (one line per device,
- * FFT length and precision: "<device> <nfft> <precision> <templates per
- * launch> <skies per batch> <pass_a_variant + 2 pass_b_variant>"; the last
+ * FFT length and precision: "<device> <nfft> <precision + 2 interbinning>
+ * <templates per launch> <skies per batch> <pass_a_variant + 2
+ * pass_b_variant>"; the last
  * matching line wins).  Runs synchronously on `stream` for roughly
  * budget_ms.  Must be called before fstat_plan_set_workspace: the workspace
  * size changes with the batch sizes (query it again afterwards), and before

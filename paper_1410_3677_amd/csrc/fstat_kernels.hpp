@@ -446,7 +446,8 @@ __global__ void __launch_bounds__(NT) k_spline(SegConst sc, const SkyParams* __r
 
 // ------------------------------------------------------------- template stage
 struct TmplArgs {
-  int n, P, Q, L;
+  int n, P, Q, L;       // samples; template FFT L = P * Q
+  float ibw;            // interbinning weight (second pass with interbinning only)
   int nfdot;            // spindowns per sky
   int t0;               // first template of this launch (within the sky batch)
   int sky0;             // global index of the batch's first sky

@@ -26,10 +26,13 @@ constexpr int LOG_MIN = 10, LOG_MAX = 20;  // supported FFT lengths 2^10 .. 2^20
 
 struct SegInfo {
   fstat_segment s;
-  int nfft, M;                 // template FFT length and upsampling FFT length nfft/2
+  int nfft, M;                 // interpolated transform length and upsampling FFT length nfft/2
   int logL, P, Q;              // nfft = P * Q
   int PM, QM;                  // M = PM * QM
   int kmin, kmax;
+  // the template FFTs: tL = nfft, or nfft/2 with interbinning; tL = tP * tQ
+  int tlog, tP, tQ, tL;
+  double ibw = 0.0;            // interbinning weight (0 without interbinning)
 };
 
 struct SearchRecord {
@@ -97,6 +100,7 @@ struct fstat_plan_s {
   size_t off_sp = 0, off_part = 0, off_zt = 0, off_shared = 0;
   int nblk_max = 0;
   long n_max = 0, L_max = 0, M_max = 0;
+  long TL_max = 0;             // longest template FFT
   // tables and candidates
   Tables tab;
   CandEntry* d_cand = nullptr;
@@ -188,9 +192,9 @@ static size_t layout(fstat_plan_t p, int Sb, int B, bool commit) {
   off = align256(off + (size_t)Sb * 2 * p->n_max * cx);
   const size_t o_sh = off;
   // per-sky scratch: za [2][M], Z [2][M], tmp [2][L], u [2][L]; aliased by the
-  // template intermediate [B][2][L] (per-sky scratch is dead once zt is built)
+  // template intermediate [B][tL][2] (per-sky scratch is dead once zt is built)
   const size_t sky_scratch = (size_t)Sb * (4 * p->M_max + 4 * p->L_max) * cx;
-  const size_t tmpl = (size_t)B * 2 * p->L_max * cx;
+  const size_t tmpl = (size_t)B * 2 * p->TL_max * cx;
   off = align256(off + std::max(sky_scratch, tmpl));
   if (commit) {
     p->off_sp = o_sp;
@@ -387,15 +391,20 @@ static fstat_status run_sky_batch(fstat_plan_t p, const Dev<T>& d, const SegInfo
 // (0.70 against 0.75 us per 2^18-point template), and grids between three and four per
 // CU are slower still (uneven CUs).
 constexpr int STREAM_WG_PER_CU = 3;
+// the interbinning second pass holds two units' outputs per lane: with the bins [0, nfft/2)
+// (half the outputs) it needs 124-150 VGPRs and three workgroups per CU are resident, with
+// other bin ranges 190-225 and two; every wavefront has an equal share of the rows
+constexpr int IB_WG_PER_CU_HALF = 3, IB_WG_PER_CU_FULL = 2;
 
 template <typename T>
 static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo& si, int sky0, int nb,
                                   const double* fdot, int nfdot, int mode, OutArgs oa, hipStream_t st) {
   TmplArgs ta;
   ta.n = (int)si.s.n;
-  ta.P = si.P;
-  ta.Q = si.Q;
-  ta.L = si.nfft;
+  ta.P = si.tP;
+  ta.Q = si.tQ;
+  ta.L = si.tL;
+  ta.ibw = (float)si.ibw;
   ta.nfdot = nfdot;
   ta.sky0 = sky0;
   ta.dt = si.s.dt;
@@ -409,20 +418,20 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
     hipError_t err = hipSuccess;
     {
       ProfScope ps(p, FSTAT_KERNEL_TEMPLATE_A, st);
-      with_len(si.Q, [&](auto c) {
+      with_len(si.tQ, [&](auto c) {
         constexpr int QQ = decltype(c)::value;
         if constexpr (QQ >= 64) {
-          const int ntiles = si.P / tw_a<T, QQ>();
-          // first-stage inputs r >= rnz are zero for every column when n <= rnz nfft / 8
-          const int rnz = (8L * si.s.n <= 3L * si.nfft) ? 3 : (8L * si.s.n <= 4L * si.nfft) ? 4 : 8;
+          const int ntiles = si.tP / tw_a<T, QQ>();
+          // first-stage inputs r >= rnz are zero for every column when n <= rnz tL / 8
+          const int rnz = (8L * si.s.n <= 3L * si.tL) ? 3 : (8L * si.s.n <= 4L * si.tL) ? 4 : 8;
           auto go = [&](auto rnz_c) {
             constexpr int RZ = decltype(rnz_c)::value;
             if (p->variant_a == 1)
               hipLaunchKernelGGL((k_tmpl_a_pair<T, QQ, RZ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T, QQ>()), 0, st, ta,
-                                 d.zt(), tbuf, d.twst, d.lo(si.logL), d.hi(si.logL));
+                                 d.zt(), tbuf, d.twst, d.lo(si.tlog), d.hi(si.tlog));
             else
               hipLaunchKernelGGL((k_tmpl_a<T, QQ, RZ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T, QQ>()), 0, st, ta, d.zt(),
-                                 tbuf, d.twst, d.lo(si.logL), d.hi(si.logL));
+                                 tbuf, d.twst, d.lo(si.tlog), d.hi(si.tlog));
           };
           if (rnz == 3) go(std::integral_constant<int, 3>{});
           else if (rnz == 4) go(std::integral_constant<int, 4>{});
@@ -441,12 +450,32 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
     }
     {
       ProfScope ps(p, FSTAT_KERNEL_TEMPLATE_B, st);
-      with_len(si.P, [&](auto c) {
+      with_len(si.tP, [&](auto c) {
         constexpr int PP = decltype(c)::value;
         if constexpr (sizeof(T) == 4 && PP >= 64 && PP <= 512) {
+          if (si.ibw != 0.0) {
+            // interbinning: about one resident round of wavefronts, each walking an even share
+            // of the launch's row units in order
+            const long units = (long)nt * (si.tQ / stream_rpw<PP>());
+            const bool half = (oa.k_min == 0 && oa.k_max == si.nfft / 2);
+            const long wgs = std::min((units + 3) / 4, (long)p->n_cu * (half ? IB_WG_PER_CU_HALF : IB_WG_PER_CU_FULL));
+            auto go = [&](auto mode_c, auto half_c) {
+              constexpr int MD = decltype(mode_c)::value;
+              constexpr bool HF = decltype(half_c)::value;
+              hipLaunchKernelGGL((k_tmpl_b_ib<PP, MD, HF>), dim3((unsigned)wgs), dim3(256), 0, st, ta, nt, d.sp(),
+                                 (const cx<float>*)tbuf, oa, (const cx<float>*)d.twst);
+            };
+            using BT = std::true_type;
+            using BF = std::false_type;
+            if (capture) half ? go(std::integral_constant<int, 2>{}, BT{}) : go(std::integral_constant<int, 2>{}, BF{});
+            else if (mode == 0) half ? go(std::integral_constant<int, 0>{}, BT{}) : go(std::integral_constant<int, 0>{}, BF{});
+            else half ? go(std::integral_constant<int, 1>{}, BT{}) : go(std::integral_constant<int, 1>{}, BF{});
+            err = hipGetLastError();
+            return;
+          }
           if (p->variant_b == 1) {
           // streaming kernel: about one resident round of wavefronts walks the launch's row units
-          const long waves = (long)nt * (si.Q / stream_rpw<PP>());
+          const long waves = (long)nt * (si.tQ / stream_rpw<PP>());
           const long wgs = std::min((waves + 3) / 4, (long)p->n_cu * STREAM_WG_PER_CU);
           const dim3 grid((unsigned)wgs);
           const bool half = (oa.k_min == 0 && oa.k_max == si.nfft / 2);
@@ -469,7 +498,7 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
           }
         }
         if constexpr (PP >= 64) {
-          const int ntiles = si.Q / tw_b<T, PP>();
+          const int ntiles = si.tQ / tw_b<T, PP>();
           if (capture)
             hipLaunchKernelGGL((k_tmpl_b<T, PP, 2>), dim3(ntiles * nt), dim3(tmpl_nt_b<T, PP>()), 0, st, ta, d.sp(),
                                tbuf, oa, d.twst);
@@ -632,6 +661,18 @@ static std::string device_tag() {
 }
 
 // Tuned (B, Sb, variant) for this device, largest FFT length and precision from the cache file.
+// precision field of a tuning-cache line: the precision, plus 2 with interbinning
+static int cache_precision(const fstat_options& o) { return o.precision + 2 * (o.interbinning ? 1 : 0); }
+
+// Interbinning weight c for a transform of L points over the n nonzero samples: a
+// sinusoid midway between bins k and k + 1 has transform values whose difference has
+// modulus 2 sin(pi n / 2L) sin(pi (n - 1) / 2L) / sin(pi / 2L), and its exact value
+// midway is n; c makes c |X_k - X_{k+1}| equal to it (about pi/4 when n = L).
+static double interbin_weight(long n, long L) {
+  const double h = M_PI / (2.0 * (double)L);
+  return (double)n * std::sin(h) / (2.0 * std::sin(h * (double)n) * std::sin(h * (double)(n - 1)));
+}
+
 static bool cache_lookup(const char* path, const std::string& tag, long nfft, int prec, int* B, int* Sb, int* var) {
   if (!path) return false;
   FILE* f = std::fopen(path, "r");
@@ -999,6 +1040,7 @@ void fstat_options_default(fstat_options* opt) {
   opt->skies_per_batch = 0;
   opt->use_graph = 1;
   opt->tuning_cache_path = nullptr;
+  opt->interbinning = 0;
 }
 
 const char* fstat_strerror(fstat_status st) {
@@ -1037,6 +1079,9 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_opt
   if (!(std::isfinite(opt.threshold_2F))) return fail(nullptr, FSTAT_E_INVAL, "threshold must be finite");
   if (opt.k_min < 0 || opt.k_max < 0 || (opt.k_max != 0 && opt.k_max <= opt.k_min))
     return fail(nullptr, FSTAT_E_INVAL, "bad bin range");
+  if (opt.interbinning != 0 && opt.interbinning != 1) return fail(nullptr, FSTAT_E_INVAL, "interbinning must be 0 or 1");
+  if (opt.interbinning && opt.precision != FSTAT_PREC_MIXED)
+    return fail(nullptr, FSTAT_E_NOT_IMPLEMENTED, "interbinning is implemented for the mixed precision only");
 
   auto p = new (std::nothrow) fstat_plan_s();
   if (!p) return fail(nullptr, FSTAT_E_NOMEM, "plan allocation");
@@ -1080,6 +1125,22 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_opt
     si.QM = 1 << ((e - 1) / 2);
     si.kmin = opt.k_min;
     si.kmax = opt.k_max ? opt.k_max : si.nfft / 2;
+    si.tlog = e;
+    si.tP = si.P;
+    si.tQ = si.Q;
+    si.tL = si.nfft;
+    if (opt.interbinning) {
+      if (e < 13) {
+        std::snprintf(msg, sizeof msg, "segment %d: interbinning needs nfft >= 2^13 (nfft=%ld)", i, nf);
+        delete p;
+        return fail(nullptr, FSTAT_E_INVAL, msg);
+      }
+      si.tlog = e - 1;
+      si.tP = 1 << (e / 2);
+      si.tQ = 1 << ((e - 1) / 2);
+      si.tL = si.tP * si.tQ;
+      si.ibw = interbin_weight(s.n, si.tL);
+    }
     if (si.kmax > si.nfft) {
       std::snprintf(msg, sizeof msg, "segment %d: k_max=%d beyond nfft=%d", i, si.kmax, si.nfft);
       delete p;
@@ -1088,6 +1149,7 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_opt
     p->segs.push_back(si);
     p->n_max = std::max(p->n_max, (long)s.n);
     p->L_max = std::max(p->L_max, (long)si.nfft);
+    p->TL_max = std::max(p->TL_max, (long)si.tL);
     p->M_max = std::max(p->M_max, (long)si.M);
   }
   p->nblk_max = (int)((p->n_max + NT - 1) / NT);
@@ -1100,7 +1162,7 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_opt
     int tb = 0, ts = 0, tv = 0;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0 &&
-        cache_lookup(opt.tuning_cache_path, device_tag(), p->L_max, opt.precision, &tb, &ts, &tv)) {
+        cache_lookup(opt.tuning_cache_path, device_tag(), p->L_max, cache_precision(opt), &tb, &ts, &tv)) {
       B = tb;
       Sb = ts;
       p->variant_a = tv & 1;
@@ -1392,8 +1454,8 @@ fstat_status fstat_plan_info(fstat_plan_t plan, int32_t segment, int32_t* nfft, 
     return fail(plan, FSTAT_E_INVAL, "bad arguments");
   const SegInfo& si = plan->segs[segment];
   if (nfft) *nfft = si.nfft;
-  if (p) *p = si.P;
-  if (q) *q = si.Q;
+  if (p) *p = si.tP;
+  if (q) *q = si.tQ;
   if (templates_per_launch) *templates_per_launch = plan->B;
   if (skies_per_batch) *skies_per_batch = plan->Sb;
   if (pass_a_variant) *pass_a_variant = plan->variant_a;
@@ -1503,7 +1565,7 @@ fstat_status fstat_autotune(fstat_plan_t plan, int32_t segment, double budget_ms
   if (plan->opt.tuning_cache_path) {
     FILE* f = std::fopen(plan->opt.tuning_cache_path, "a");
     if (f) {
-      std::fprintf(f, "%s %ld %d %d %d %d\n", device_tag().c_str(), plan->L_max, plan->opt.precision, plan->B,
+      std::fprintf(f, "%s %ld %d %d %d %d\n", device_tag().c_str(), plan->L_max, cache_precision(plan->opt), plan->B,
                    plan->Sb, plan->variant_a | (plan->variant_b << 1));
       std::fclose(f);
     }

@@ -887,6 +887,316 @@ __global__ void __launch_bounds__(256) k_tmpl_b_stream(TmplArgs ta, int ntmpl, c
   if constexpr (MODE != 1) flush();
 }
 
+// ---------------------------------------------------------------- pass B with interbinning (FP32)
+// The template transforms have L = nfft/2 points.  Bin 2k of the nfft grid is bin k of the
+// transform; bin 2k + 1 is w (X_k - X_{k+1 mod L}) for each series.  Bin k = Q k1 + k2 lies in
+// row k2 of the intermediate and its neighbour k + 1 in row k2 + 1 at the same k1 (for row
+// Q - 1: row 0 at k1 + 1).  Each wavefront walks an even share [U0, U1) of the launch's row
+// units in order, so the neighbour of a lane's output is one row later: at lane + G in the
+// same unit, or, for the unit's last row, at lane g of the next unit's first row.  A unit's
+// odd bins are formed once the next unit has been transformed.  After a template's last unit
+// the wavefront transforms the template's first unit once more (the neighbours k1 + 1 of row
+// Q - 1), and after its share the first unit of the next share, whose own bins belong to the
+// next wavefront.  Loads, stages and candidate staging are those of k_tmpl_b_stream.  With
+// HALF (bins [0, nfft/2)) only the outputs k1 < P/2 are formed, plus output k1 = P/2 of the
+// first butterfly, the neighbour of row Q - 1 at k1 = P/2 - 1.
+
+// Flat output index o = b RO + r of a lane's outputs (k1 = g + G b + NSL r, r < RO).  For
+// g = G - 1 the output holding k1 + 1 is in lane 0 at ib_next(o): the same r in the next
+// butterfly, r + 1 in the first, or past the last (k1 + 1 = P/2 with HALF: the extra output
+// NO; k1 + 1 = P otherwise: output 0, since the transform is periodic).
+template <int PBL, int RO, int RL>
+__host__ __device__ constexpr int ib_next(int o) {
+  return (o / RO + 1 < PBL) ? o + RO : (o % RO + 1 < RO ? o % RO + 1 : (RO < RL ? PBL * RO : 0));
+}
+
+__device__ __forceinline__ cx<float> shfl_cx(cx<float> v, int src) {
+  return mk<float>(__shfl(v.re, src, 64), __shfl(v.im, src, 64));
+}
+
+// dft_first_half plus output R/2: the alternating sum of the inputs.
+template <typename T, int R>
+__device__ __forceinline__ void dft_first_half_mid(cx<T>* v, cx<T>& mid) {
+  if constexpr (R == 2) {
+    mid = v[0] - v[1];
+  } else if constexpr (R == 4) {
+    mid = (v[0] + v[2]) - (v[1] + v[3]);
+  } else {
+    mid = ((v[0] + v[4]) + (v[2] + v[6])) - ((v[1] + v[5]) + (v[3] + v[7]));
+  }
+  dft_first_half<T, R>(v);
+}
+
+template <int P, int MODE, bool HALF>
+__global__ void __launch_bounds__(256) k_tmpl_b_ib(TmplArgs ta, int ntmpl, const SkyParams* __restrict__ sp,
+                                                   const cx<float>* __restrict__ tbuf, OutArgs oa,
+                                                   const cx<float>* __restrict__ twst) {
+  using T = float;
+  constexpr int G = groups_per_col<P>();
+  static_assert(G <= 64 && 64 % G == 0, "rows must tile a wavefront");
+  constexpr int RPW = stream_rpw<P>();
+  constexpr int ST = col_stride<P>(16);
+  constexpr int R1 = stage_radix<P, 1>();
+  constexpr int NB1 = P / R1, PB1 = NB1 / G;
+  static_assert(PB1 >= 1 && NB1 % G == 0, "first stage must give each lane whole butterflies");
+  constexpr int NSL = last_ns<P, 1>();
+  constexpr int RL = stage_radix<P, NSL>();
+  constexpr int PBL = (P / RL) / G;
+  constexpr int RO = HALF ? RL / 2 : RL;       // outputs kept per last-stage butterfly
+  constexpr int NO = PBL * RO;                 // outputs per lane and series
+  constexpr int NX = HALF ? NO + 1 : NO;       // plus output P/2 of the first butterfly
+  constexpr int NV = 2 * NO;                   // 2F values per lane and unit: even and odd bins
+  static_assert(NV <= 32, "output mask");
+  __shared__ cx<T> lds[4 * 2 * RPW * ST];
+  __shared__ int st_item[4][STAGE_CAP];
+  __shared__ int st_bin[4][STAGE_CAP];
+  __shared__ float st_val[4][STAGE_CAP];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int units = ta.Q / RPW;                 // row units of one template
+  const long total = (long)ntmpl * units;       // row units of the launch
+  const long nw = (long)gridDim.x * 4;          // wavefronts of the grid
+  const long w = (long)blockIdx.x * 4 + wave;
+  const long U0 = w * total / nw, U1 = (w + 1) * total / nw;
+  if (U0 >= U1) return;
+  const int sub = lane / G, g = lane % G;
+  cx<T>* cola = lds + (wave * 2 * RPW + sub) * ST;
+  cx<T>* colb = cola + RPW * ST;
+  const T thr = (T)oa.threshold;
+  const T wib = ta.ibw;
+  const int search = oa.search_next[0] - 1;
+  StageTw<T, P, G, R1> tw;
+  tw.load(twst, g);
+  const auto& twl = last_stage_tw<T, P, G, R1>(tw);
+  const int lofs = sub * P + g;
+
+  auto load_unit = [&](cx<T> (&ca)[PB1][R1], cx<T> (&cb)[PB1][R1], long U) {
+    const long item = U / units;
+    const long u = U - item * units;
+    const cx<T>* p = tbuf + 2 * item * ta.L + 2 * u * (RPW * P);
+#pragma unroll
+    for (int b = 0; b < PB1; ++b)
+#pragma unroll
+      for (int r = 0; r < R1; ++r) load_stream(p + 2 * (lofs + G * b + NB1 * r), ca[b][r], cb[b][r]);
+  };
+
+  // last stage: the kept outputs of every butterfly in flat order (and output P/2 of the first)
+  auto last_stage = [&](cx<T>* col, cx<T> (&f)[NX]) {
+    constexpr int NB = P / RL;
+    static_assert(NB % 8 == 0, "constant offsets need NB a multiple of 8");
+    const cx<T>* p = col + phys(g);
+#pragma unroll
+    for (int b = 0; b < PBL; ++b) {
+      cx<T> v[RL];
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int c = G * b + r * NB;
+        cx<T> x = p[c + c / 8];
+        if (r > 0) x = cmul(x, twl.w[b][r - 1]);
+        v[r] = x;
+      }
+      if constexpr (HALF) {
+        if (b == 0) dft_first_half_mid<T, RL>(v, f[NO]);
+        else dft_first_half<T, RL>(v);
+      } else {
+        dftr<T, RL, false>(v);
+      }
+#pragma unroll
+      for (int r = 0; r < RO; ++r) f[b * RO + r] = v[r];
+    }
+  };
+
+  auto emit = [&](unsigned long long slot, int item, int bin, T v) {
+    if (slot < (unsigned long long)oa.capacity) {
+      const int t = ta.t0 + item;
+      const int skyl = t / ta.nfdot;
+      CandEntry ce;
+      ce.search = search;
+      ce.segment = oa.segment;
+      ce.sky = ta.sky0 + skyl;
+      ce.fdot_idx = t - skyl * ta.nfdot;
+      ce.bin = bin;
+      ce.pad = 0;
+      ce.twoF = (double)v;
+      oa.cand[slot] = ce;
+    }
+  };
+  int nstaged = 0;
+  auto flush = [&]() {
+    if (nstaged == 0) return;
+    stage_sync<true>();
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(oa.count, (unsigned long long)nstaged);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)base);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(base >> 32));
+    base = ((unsigned long long)hi << 32) | lo;
+    if (lane < nstaged) emit(base + lane, st_item[wave][lane], st_bin[wave][lane], (T)st_val[wave][lane]);
+    stage_sync<true>();
+    nstaged = 0;
+  };
+
+  // Even and odd bins of unit V (outputs pa, pb) with the neighbours of its rows in the unit
+  // just transformed (outputs fa, fb); `wrap`: that unit is the template's first unit again.
+  cx<T> pa[NO], pb[NO];
+  auto finish = [&](long V, bool wrap, const cx<T> (&fa)[NX], const cx<T> (&fb)[NX]) {
+    const int item = (int)(V / units);
+    const int u = (int)(V - (long)item * units);
+    const int t = ta.t0 + item;
+    const int skyl = t / ta.nfdot, sidx = t - skyl * ta.nfdot;
+    const SkyParams& pr = sp[skyl];
+    const T cfa = (T)pr.cfa, cfb = (T)pr.cfb, cfab = (T)pr.cfab;
+    const int k2 = u * RPW + sub;
+    // Neighbours by lane shuffles.  The only reader of lane 0's current outputs is lane
+    // (RPW - 1, G - 1) when `wrap` (it needs output ib_next(o) there) and lane (RPW - 1, 0)
+    // otherwise, so lane 0 supplies whichever is wanted.
+    const bool inner = sub < RPW - 1;
+    const int src = inner ? lane + G : (wrap ? (g + 1) % G : g);
+    T val[NV];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+      cx<T> na, nb;
+      if (RPW == 1 && !wrap) {
+        na = fa[o];
+        nb = fb[o];
+      } else {
+        const bool alt = wrap && lane == 0;
+        const int on = ib_next<PBL, RO, RL>(o);   // a constant once the loop is unrolled
+        const cx<T> sa = alt ? fa[on] : fa[o];
+        const cx<T> sb = alt ? fb[on] : fb[o];
+        na = shfl_cx(sa, src);
+        nb = shfl_cx(sb, src);
+        if constexpr (RPW > 1) {
+          const cx<T> qa = shfl_cx(pa[o], src), qb = shfl_cx(pb[o], src);
+          na = inner ? qa : na;
+          nb = inner ? qb : nb;
+        }
+      }
+      val[2 * o] = two_f_value(pa[o], pb[o], cfa, cfb, cfab);
+      const cx<T> da = pa[o] - na, db = pb[o] - nb;
+      val[2 * o + 1] = two_f_value(mk<T>(wib * da.re, wib * da.im), mk<T>(wib * db.re, wib * db.im), cfa, cfb, cfab);
+    }
+    auto bin_of = [&](int v) {
+      const int o = v >> 1;
+      return 2 * (ta.Q * (g + G * (o / RO) + NSL * (o % RO)) + k2) + (v & 1);
+    };
+    if constexpr (MODE == 1) {
+      T* out = (T*)oa.spectrum + ((long)(ta.sky0 + skyl) * ta.nfdot + sidx) * (long)(oa.k_max - oa.k_min);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int k = bin_of(v);
+        if (HALF || (k >= oa.k_min && k < oa.k_max)) out[k - oa.k_min] = val[v];
+      }
+    } else {
+      float* srow = (float*)oa.spectrum + (long)item * (long)(oa.k_max - oa.k_min);
+      uint32_t mask = 0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int k = bin_of(v);
+        const bool inr = HALF || (k >= oa.k_min && k < oa.k_max);
+        if (MODE == 2 && inr) srow[k - oa.k_min] = (float)val[v];
+        if (inr && val[v] > thr) mask |= 1u << v;
+      }
+      if (__ballot(mask != 0)) {
+        // two passes over the ballots (count, then place) keep no per-value offsets
+        int tot = 0;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) tot += __popcll(__ballot((mask >> q) & 1u));
+        if (nstaged + tot > STAGE_CAP) flush();
+        const bool direct = tot > STAGE_CAP;   // a burst larger than the staging area goes straight out
+        unsigned long long base = 0;
+        if (direct) {
+          if (lane == 0) base = atomicAdd(oa.count, (unsigned long long)tot);
+          const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)base);
+          const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(base >> 32));
+          base = ((unsigned long long)hi << 32) | lo;
+        }
+        int run = 0;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          const unsigned long long bi = __ballot((mask >> q) & 1u);
+          const int off = run + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bi >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((unsigned)bi, 0u));
+          if ((mask >> q) & 1u) {
+            if (direct) {
+              emit(base + (unsigned long long)off, item, bin_of(q), val[q]);
+            } else {
+              st_item[wave][nstaged + off] = item;
+              st_bin[wave][nstaged + off] = bin_of(q);
+              st_val[wave][nstaged + off] = (float)val[q];
+            }
+          }
+          run += __popcll(bi);
+        }
+        if (!direct) nstaged += tot;
+      }
+    }
+  };
+
+  // The walk: phase 0 transforms unit U of the share, phase 1 the first unit of U's template
+  // (after its last unit), phase 2 the unit U1 after the share.
+  auto advance = [&](long& U, int& ph) -> bool {
+    if (ph == 0) {
+      if (U % units == units - 1) {
+        ph = 1;
+        return true;
+      }
+      if (U + 1 == U1) {
+        if (U1 >= total) return false;
+        U = U1;
+        ph = 2;
+        return true;
+      }
+      ++U;
+      return true;
+    }
+    if (ph == 1 && U + 1 < U1) {
+      ++U;
+      ph = 0;
+      return true;
+    }
+    return false;
+  };
+  auto read_unit = [&](long U, int ph) { return ph == 1 ? U - (units - 1) : U; };
+
+  long U = U0, last = -1;
+  int ph = 0;
+  cx<T> xa[PB1][R1], xb[PB1][R1];
+  load_unit(xa, xb, read_unit(U, ph));
+  while (true) {
+    const bool fin = ph != 0 || (U != U0 && U % units != 0);
+#pragma unroll
+    for (int b = 0; b < PB1; ++b) {
+      dftr<T, R1, false>(xa[b]);
+      dftr<T, R1, false>(xb[b]);
+    }
+    stage_sync<true>();  // the previous unit's last stage has read the slab
+    stage_to_lds_off<T, P, G, 1, R1, PB1>(xa, cola, g);
+    stage_to_lds_off<T, P, G, 1, R1, PB1>(xb, colb, g);
+    stage_sync<true>();
+    long Un = U;
+    int phn = ph;
+    const bool more = advance(Un, phn);
+    if (more) load_unit(xa, xb, read_unit(Un, phn));
+    middle_stages_reg<T, P, G, R1>(cola, colb, g, tw);
+    cx<T> fa[NX], fb[NX];
+    last_stage(cola, fa);
+    last_stage(colb, fb);
+    if (fin) finish(last, ph == 1, fa, fb);
+    if (ph == 0) {
+#pragma unroll
+      for (int o = 0; o < NO; ++o) {
+        pa[o] = fa[o];
+        pb[o] = fb[o];
+      }
+      last = U;
+    }
+    if (!more) break;
+    U = Un;
+    ph = phn;
+  }
+  if constexpr (MODE != 1) flush();
+}
+
 // Count of candidates before a launch (read by the patch capture after it).
 __global__ void k_record_count(const unsigned long long* __restrict__ count, unsigned long long* __restrict__ first) {
   if (threadIdx.x == 0 && blockIdx.x == 0) first[0] = count[0];

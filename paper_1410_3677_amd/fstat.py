@@ -42,7 +42,8 @@ class fstat_options(ctypes.Structure):
                 ("threshold_2F", ctypes.c_double), ("precision", ctypes.c_int32), ("form", ctypes.c_int32),
                 ("candidate_capacity", ctypes.c_int64), ("workspace_budget_bytes", ctypes.c_size_t),
                 ("templates_per_launch", ctypes.c_int32), ("skies_per_batch", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("tuning_cache_path", ctypes.c_char_p)]
+                ("use_graph", ctypes.c_int32), ("tuning_cache_path", ctypes.c_char_p),
+                ("interbinning", ctypes.c_int32)]
 
 
 class fstat_candidate(ctypes.Structure):

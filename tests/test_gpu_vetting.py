@@ -125,9 +125,10 @@ def test_training_on_oracle_patches_beats_the_threshold_alone(torch):
     assert far < 0.5
 
 
-def test_fused_capture_scores_equal_network_on_search_spectra(torch):
+@pytest.mark.parametrize("ib", [0, 1])
+def test_fused_capture_scores_equal_network_on_search_spectra(torch, ib):
     from paper_1410_3677_amd import fstat as F
-    note("fused patch capture after the F kernel")
+    note(f"fused patch capture after the F kernel, interbinning={ib}")
     w = synth.workload("full")
     seg = w.segments[0]
     nfft = synth.nfft_for(seg.n)
@@ -135,7 +136,7 @@ def test_fused_capture_scores_equal_network_on_search_spectra(torch):
     al, de, fd = w.alpha[:2], w.delta[:2], w.fdot[:3]
     v = F.Vetter(512)
     v.set_params(_theta(5).astype(np.float32))
-    plan = make_plan([seg], use_graph=0)
+    plan = make_plan([seg], use_graph=0, interbinning=ib)
     plan.attach_vetter(v, 1 << 16)
     plan.search_batch(0, dev(al), dev(de), dev(fd))
     plan.vet_candidates()
@@ -143,7 +144,7 @@ def test_fused_capture_scores_equal_network_on_search_spectra(torch):
     assert n > 100 and np.all(np.isfinite(keys["vet_score"]))
     # the same network on windows of the 2F spectrum of the same templates
     spec = torch.empty(len(al) * len(fd) * nb, dtype=torch.float32, device="cuda")
-    plain = make_plan([seg], use_graph=0)
+    plain = make_plan([seg], use_graph=0, interbinning=ib)
     plain.twoF_spectrum(0, dev(al), dev(de), dev(fd), spec)
     s = spec.view(len(al), len(fd), nb).cpu().numpy()
     win = np.zeros((n, 256), np.float32)
