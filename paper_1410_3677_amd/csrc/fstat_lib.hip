@@ -392,8 +392,8 @@ static fstat_status run_sky_batch(fstat_plan_t p, const Dev<T>& d, const SegInfo
 // CU are slower still (uneven CUs).
 constexpr int STREAM_WG_PER_CU = 3;
 // the interbinning second pass holds two units' outputs per lane: with the bins [0, nfft/2)
-// (half the outputs) it needs 124-150 VGPRs and three workgroups per CU are resident, with
-// other bin ranges 190-225 and two; every wavefront has an equal share of the rows
+// (half the outputs) it needs 135-165 VGPRs and three workgroups per CU are resident, with
+// other bin ranges 190-225 and two
 constexpr int IB_WG_PER_CU_HALF = 3, IB_WG_PER_CU_FULL = 2;
 
 template <typename T>
@@ -423,7 +423,9 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
         if constexpr (QQ >= 64) {
           const int ntiles = si.tP / tw_a<T, QQ>();
           // first-stage inputs r >= rnz are zero for every column when n <= rnz tL / 8
-          const int rnz = (8L * si.s.n <= 3L * si.tL) ? 3 : (8L * si.s.n <= 4L * si.tL) ? 4 : 8;
+          int rnz = 8;
+          for (int r = 7; r >= 3; --r)
+            if (8L * si.s.n <= (long)r * si.tL) rnz = r;
           auto go = [&](auto rnz_c) {
             constexpr int RZ = decltype(rnz_c)::value;
             if (p->variant_a == 1)
@@ -433,9 +435,14 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
               hipLaunchKernelGGL((k_tmpl_a<T, QQ, RZ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T, QQ>()), 0, st, ta, d.zt(),
                                  tbuf, d.twst, d.lo(si.tlog), d.hi(si.tlog));
           };
-          if (rnz == 3) go(std::integral_constant<int, 3>{});
-          else if (rnz == 4) go(std::integral_constant<int, 4>{});
-          else go(std::integral_constant<int, 8>{});
+          switch (rnz) {
+            case 3: go(std::integral_constant<int, 3>{}); break;
+            case 4: go(std::integral_constant<int, 4>{}); break;
+            case 5: go(std::integral_constant<int, 5>{}); break;
+            case 6: go(std::integral_constant<int, 6>{}); break;
+            case 7: go(std::integral_constant<int, 7>{}); break;
+            default: go(std::integral_constant<int, 8>{}); break;
+          }
           err = hipGetLastError();
         } else {
           err = hipErrorInvalidValue;
@@ -454,11 +461,11 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
         constexpr int PP = decltype(c)::value;
         if constexpr (sizeof(T) == 4 && PP >= 64 && PP <= 512) {
           if (si.ibw != 0.0) {
-            // interbinning: about one resident round of wavefronts, each walking an even share
-            // of the launch's row units in order
-            const long units = (long)nt * (si.tQ / stream_rpw<PP>());
+            // interbinning: about one resident round of wavefronts walking chunks of row units
+            const long units = si.tQ / stream_rpw<PP>();
+            const long chunks = (long)nt * (units / std::min<long>(units, IB_CHUNK));
             const bool half = (oa.k_min == 0 && oa.k_max == si.nfft / 2);
-            const long wgs = std::min((units + 3) / 4, (long)p->n_cu * (half ? IB_WG_PER_CU_HALF : IB_WG_PER_CU_FULL));
+            const long wgs = std::min((chunks + 3) / 4, (long)p->n_cu * (half ? IB_WG_PER_CU_HALF : IB_WG_PER_CU_FULL));
             auto go = [&](auto mode_c, auto half_c) {
               constexpr int MD = decltype(mode_c)::value;
               constexpr bool HF = decltype(half_c)::value;

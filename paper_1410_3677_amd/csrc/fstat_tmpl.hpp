@@ -237,28 +237,46 @@ __host__ __device__ constexpr int last_ns() {
   else return last_ns<LEN, NS * stage_radix<LEN, NS>()>();
 }
 
-// Forward 8-point DFT of x[0 .. RNZ-1] with x[RNZ ..] = 0 (RNZ = 3 or 4), in place.
-// With at most four nonzero inputs the first radix-2 layer is a copy:
-// X[k] = E[k mod 4] + W8^k O[k mod 4], E and O the 4-point DFTs of the even and odd
-// inputs (x3 = 0 when RNZ = 3).
+// Forward 8-point DFT of x[0 .. RNZ-1] with x[RNZ ..] = 0 (3 <= RNZ <= 7), in place:
+// X[k] = E[k mod 4] + W8^k O[k mod 4], E and O the 4-point DFTs of the even and odd inputs,
+// whose zero inputs are left out.  With at most four nonzero inputs the first radix-2
+// layer of each 4-point DFT is a copy.
+template <typename T, int NZ>
+__device__ __forceinline__ void dft4_nz(cx<T> a, cx<T> b, cx<T> c, cx<T> d, cx<T>& y0, cx<T>& y1, cx<T>& y2,
+                                        cx<T>& y3) {
+  // inputs a, b, c, d with only the first NZ nonzero; y_k = sum x_n (-i)^(nk)
+  if constexpr (NZ == 1) {
+    y0 = y1 = y2 = y3 = a;
+    return;
+  }
+  cx<T> s0, d0, s1, d1;
+  if constexpr (NZ >= 3) {
+    s0 = a + c;
+    d0 = a - c;
+  } else {
+    s0 = d0 = a;
+  }
+  if constexpr (NZ >= 4) {
+    s1 = b + d;
+    d1 = b - d;
+  } else {
+    s1 = d1 = b;
+  }
+  y0 = s0 + s1;
+  y2 = s0 - s1;
+  y1 = mk<T>(d0.re + d1.im, d0.im - d1.re);
+  y3 = mk<T>(d0.re - d1.im, d0.im + d1.re);
+}
+
 template <typename T, int RNZ>
 __device__ __forceinline__ void dft8_pruned(cx<T>* v) {
-  static_assert(RNZ == 3 || RNZ == 4, "pruned first stage");
+  static_assert(RNZ >= 3 && RNZ <= 7, "pruned first stage");
   const T h = (T)0.70710678118654752440084436210485;
-  const cx<T> x0 = v[0], x1 = v[1], x2 = v[2];
-  // E = DFT4(x0, x2, 0, 0): x0 + x2, x0 - i x2, x0 - x2, x0 + i x2
-  const cx<T> e0 = x0 + x2, e2 = x0 - x2;
-  const cx<T> e1 = mk<T>(x0.re + x2.im, x0.im - x2.re), e3 = mk<T>(x0.re - x2.im, x0.im + x2.re);
-  cx<T> o0, o1, o2, o3;
-  if constexpr (RNZ == 4) {
-    const cx<T> x3 = v[3];
-    o0 = x1 + x3;
-    o2 = x1 - x3;
-    o1 = mk<T>(x1.re + x3.im, x1.im - x3.re);
-    o3 = mk<T>(x1.re - x3.im, x1.im + x3.re);
-  } else {
-    o0 = o1 = o2 = o3 = x1;
-  }
+  const cx<T> z = mk<T>(0, 0);
+  // even inputs x0 x2 x4 x6: (RNZ + 1) / 2 nonzero; odd inputs x1 x3 x5 x7: RNZ / 2
+  cx<T> e0, e1, e2, e3, o0, o1, o2, o3;
+  dft4_nz<T, (RNZ + 1) / 2>(v[0], v[2], RNZ > 4 ? v[4] : z, RNZ > 6 ? v[6] : z, e0, e1, e2, e3);
+  dft4_nz<T, RNZ / 2>(v[1], v[3], RNZ > 5 ? v[5] : z, z, o0, o1, o2, o3);
   // W8^k O[k]: k = 1: h (1 - i), k = 2: -i, k = 3: h (-1 - i)
   const cx<T> w1 = mk<T>(h * (o1.re + o1.im), h * (o1.im - o1.re));
   const cx<T> w2 = mul_mi<T, false>(o2);
@@ -277,8 +295,8 @@ __device__ __forceinline__ void dft8_pruned(cx<T>* v) {
 // j1 + P j2 >= n), times the spindown chirp exp(-i pi fdot (j dt)^2) whose phase is
 // evaluated in FP64 and reduced to [0, 1) cycles, then a radix-R1 DFT in registers.
 // All loads are issued before any chirp is computed so that they overlap.  RNZ < R1
-// states that inputs r >= RNZ are zero for every column (n <= RNZ nfft / 8), so they
-// are neither loaded nor transformed.
+// states that inputs r >= RNZ are zero for every column (n <= RNZ L / 8, L the transform
+// length), so they are neither loaded nor transformed.
 template <typename T, int Q, int G, int R1, int NB1, int PB1, int RNZ = R1>
 __device__ __forceinline__ void chirped_first_stage(cx<T> (&va)[PB1][R1], cx<T> (&vb)[PB1][R1],
                                                     const cx<T>* __restrict__ za, const cx<T>* __restrict__ zb,
@@ -461,6 +479,12 @@ __device__ __forceinline__ float two_f_value(cx<float> fa, cx<float> fb, float c
   const float nb = __fmaf_rn(fb.re, fb.re, __fmul_rn(fb.im, fb.im));
   const float xr = __fmaf_rn(fa.re, fb.re, __fmul_rn(fa.im, fb.im));
   return __fmaf_rn(cfa, na, __fmaf_rn(cfb, nb, __fmul_rn(cfab, xr)));
+}
+// The same value when cfab = 0 (the simplified form): fma(cfb, nb, 0 * xr) rounds as cfb * nb.
+__device__ __forceinline__ float two_f_value_nc(cx<float> fa, cx<float> fb, float cfa, float cfb) {
+  const float na = __fmaf_rn(fa.re, fa.re, __fmul_rn(fa.im, fa.im));
+  const float nb = __fmaf_rn(fb.re, fb.re, __fmul_rn(fb.im, fb.im));
+  return __fmaf_rn(cfa, na, __fmul_rn(cfb, nb));
 }
 __device__ __forceinline__ double two_f_value(cx<double> fa, cx<double> fb, double cfa, double cfb, double cfab) {
   const double na = __fma_rn(fa.re, fa.re, __dmul_rn(fa.im, fa.im));
@@ -891,13 +915,15 @@ __global__ void __launch_bounds__(256) k_tmpl_b_stream(TmplArgs ta, int ntmpl, c
 // The template transforms have L = nfft/2 points.  Bin 2k of the nfft grid is bin k of the
 // transform; bin 2k + 1 is w (X_k - X_{k+1 mod L}) for each series.  Bin k = Q k1 + k2 lies in
 // row k2 of the intermediate and its neighbour k + 1 in row k2 + 1 at the same k1 (for row
-// Q - 1: row 0 at k1 + 1).  Each wavefront walks an even share [U0, U1) of the launch's row
-// units in order, so the neighbour of a lane's output is one row later: at lane + G in the
-// same unit, or, for the unit's last row, at lane g of the next unit's first row.  A unit's
-// odd bins are formed once the next unit has been transformed.  After a template's last unit
-// the wavefront transforms the template's first unit once more (the neighbours k1 + 1 of row
-// Q - 1), and after its share the first unit of the next share, whose own bins belong to the
-// next wavefront.  Loads, stages and candidate staging are those of k_tmpl_b_stream.  With
+// Q - 1: row 0 at k1 + 1).  A wavefront walks chunks of IB_CHUNK consecutive row units of
+// one template (chunks w, w + nw, ... of the launch, so that the rows in flight form one
+// window of HBM, as in k_tmpl_b_stream), and within a chunk the units in order: the
+// neighbour of a lane's output is one row later, at lane + G in the same unit or, for the
+// unit's last row, at lane g of the next unit's first row.  A unit's odd bins are formed
+// once the next unit has been transformed; after a chunk's last unit the wavefront
+// transforms one more, the next chunk's first unit or, at the template's end, the
+// template's first unit (the neighbours k1 + 1 of row Q - 1).  Loads, stages and candidate
+// staging are those of k_tmpl_b_stream.  With
 // HALF (bins [0, nfft/2)) only the outputs k1 < P/2 are formed, plus output k1 = P/2 of the
 // first butterfly, the neighbour of row Q - 1 at k1 = P/2 - 1.
 
@@ -927,6 +953,8 @@ __device__ __forceinline__ void dft_first_half_mid(cx<T>* v, cx<T>& mid) {
   dft_first_half<T, R>(v);
 }
 
+constexpr int IB_CHUNK = 16;
+
 template <int P, int MODE, bool HALF>
 __global__ void __launch_bounds__(256) k_tmpl_b_ib(TmplArgs ta, int ntmpl, const SkyParams* __restrict__ sp,
                                                    const cx<float>* __restrict__ tbuf, OutArgs oa,
@@ -953,12 +981,13 @@ __global__ void __launch_bounds__(256) k_tmpl_b_ib(TmplArgs ta, int ntmpl, const
   __shared__ float st_val[4][STAGE_CAP];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int units = ta.Q / RPW;                 // row units of one template
-  const long total = (long)ntmpl * units;       // row units of the launch
-  const long nw = (long)gridDim.x * 4;          // wavefronts of the grid
-  const long w = (long)blockIdx.x * 4 + wave;
-  const long U0 = w * total / nw, U1 = (w + 1) * total / nw;
-  if (U0 >= U1) return;
+  const int units = ta.Q / RPW;                 // row units of one template (a power of two)
+  const int ch = units < IB_CHUNK ? units : IB_CHUNK;
+  const int lg_cpt = __builtin_ctz((unsigned)(units / ch));   // chunks per template, log2
+  const int nchunk = ntmpl << lg_cpt;           // chunks of the launch
+  const int nw = gridDim.x * 4;                 // wavefronts of the grid
+  int c = blockIdx.x * 4 + wave;
+  if (c >= nchunk) return;
   const int sub = lane / G, g = lane % G;
   cx<T>* cola = lds + (wave * 2 * RPW + sub) * ST;
   cx<T>* colb = cola + RPW * ST;
@@ -970,10 +999,8 @@ __global__ void __launch_bounds__(256) k_tmpl_b_ib(TmplArgs ta, int ntmpl, const
   const auto& twl = last_stage_tw<T, P, G, R1>(tw);
   const int lofs = sub * P + g;
 
-  auto load_unit = [&](cx<T> (&ca)[PB1][R1], cx<T> (&cb)[PB1][R1], long U) {
-    const long item = U / units;
-    const long u = U - item * units;
-    const cx<T>* p = tbuf + 2 * item * ta.L + 2 * u * (RPW * P);
+  auto load_unit = [&](cx<T> (&ca)[PB1][R1], cx<T> (&cb)[PB1][R1], int item, int u) {
+    const cx<T>* p = tbuf + 2 * (long)item * ta.L + 2 * (long)u * (RPW * P);
 #pragma unroll
     for (int b = 0; b < PB1; ++b)
 #pragma unroll
@@ -1038,13 +1065,19 @@ __global__ void __launch_bounds__(256) k_tmpl_b_ib(TmplArgs ta, int ntmpl, const
   // Even and odd bins of unit V (outputs pa, pb) with the neighbours of its rows in the unit
   // just transformed (outputs fa, fb); `wrap`: that unit is the template's first unit again.
   cx<T> pa[NO], pb[NO];
-  auto finish = [&](long V, bool wrap, const cx<T> (&fa)[NX], const cx<T> (&fb)[NX]) {
-    const int item = (int)(V / units);
-    const int u = (int)(V - (long)item * units);
-    const int t = ta.t0 + item;
-    const int skyl = t / ta.nfdot, sidx = t - skyl * ta.nfdot;
-    const SkyParams& pr = sp[skyl];
-    const T cfa = (T)pr.cfa, cfb = (T)pr.cfb, cfab = (T)pr.cfab;
+  int c_item = -1, skyl = 0, sidx = 0;   // template of the cached constants
+  T cfa = 0, cfb = 0, cfab = 0;
+  auto finish = [&](int item, int u, bool wrap, const cx<T> (&fa)[NX], const cx<T> (&fb)[NX]) {
+    if (item != c_item) {
+      c_item = item;
+      const int t = ta.t0 + item;
+      skyl = t / ta.nfdot;
+      sidx = t - skyl * ta.nfdot;
+      const SkyParams& pr = sp[skyl];
+      cfa = (T)pr.cfa;
+      cfb = (T)pr.cfb;
+      cfab = (T)pr.cfab;
+    }
     const int k2 = u * RPW + sub;
     // Neighbours by lane shuffles.  The only reader of lane 0's current outputs is lane
     // (RPW - 1, G - 1) when `wrap` (it needs output ib_next(o) there) and lane (RPW - 1, 0)
@@ -1052,6 +1085,11 @@ __global__ void __launch_bounds__(256) k_tmpl_b_ib(TmplArgs ta, int ntmpl, const
     const bool inner = sub < RPW - 1;
     const int src = inner ? lane + G : (wrap ? (g + 1) % G : g);
     T val[NV];
+    auto two_f = [&](cx<T> a, cx<T> b, auto cross_c) {
+      if constexpr (decltype(cross_c)::value) return two_f_value(a, b, cfa, cfb, cfab);
+      else return two_f_value_nc(a, b, cfa, cfb);
+    };
+    auto values = [&](auto cross_c) {
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
       cx<T> na, nb;
@@ -1071,10 +1109,13 @@ __global__ void __launch_bounds__(256) k_tmpl_b_ib(TmplArgs ta, int ntmpl, const
           nb = inner ? qb : nb;
         }
       }
-      val[2 * o] = two_f_value(pa[o], pb[o], cfa, cfb, cfab);
+      val[2 * o] = two_f(pa[o], pb[o], cross_c);
       const cx<T> da = pa[o] - na, db = pb[o] - nb;
-      val[2 * o + 1] = two_f_value(mk<T>(wib * da.re, wib * da.im), mk<T>(wib * db.re, wib * db.im), cfa, cfb, cfab);
+      val[2 * o + 1] = two_f(mk<T>(wib * da.re, wib * da.im), mk<T>(wib * db.re, wib * db.im), cross_c);
     }
+    };
+    if (cfab != (T)0) values(std::true_type{});
+    else values(std::false_type{});
     auto bin_of = [&](int v) {
       const int o = v >> 1;
       return 2 * (ta.Q * (g + G * (o / RO) + NSL * (o % RO)) + k2) + (v & 1);
@@ -1132,38 +1173,14 @@ __global__ void __launch_bounds__(256) k_tmpl_b_ib(TmplArgs ta, int ntmpl, const
     }
   };
 
-  // The walk: phase 0 transforms unit U of the share, phase 1 the first unit of U's template
-  // (after its last unit), phase 2 the unit U1 after the share.
-  auto advance = [&](long& U, int& ph) -> bool {
-    if (ph == 0) {
-      if (U % units == units - 1) {
-        ph = 1;
-        return true;
-      }
-      if (U + 1 == U1) {
-        if (U1 >= total) return false;
-        U = U1;
-        ph = 2;
-        return true;
-      }
-      ++U;
-      return true;
-    }
-    if (ph == 1 && U + 1 < U1) {
-      ++U;
-      ph = 0;
-      return true;
-    }
-    return false;
-  };
-  auto read_unit = [&](long U, int ph) { return ph == 1 ? U - (units - 1) : U; };
-
-  long U = U0, last = -1;
-  int ph = 0;
+  // The walk: step j = 0 .. ch of chunk c transforms unit u0 + j of template item (step ch:
+  // the unit after the chunk, unit 0 at the template's end) and forms the bins of unit
+  // u0 + j - 1.
+  auto unit_of = [&](int u0, int j) { return j < ch ? u0 + j : (u0 + ch == units ? 0 : u0 + ch); };
+  int item = c >> lg_cpt, u0 = (c - (item << lg_cpt)) * ch, j = 0;
   cx<T> xa[PB1][R1], xb[PB1][R1];
-  load_unit(xa, xb, read_unit(U, ph));
+  load_unit(xa, xb, item, u0);
   while (true) {
-    const bool fin = ph != 0 || (U != U0 && U % units != 0);
 #pragma unroll
     for (int b = 0; b < PB1; ++b) {
       dftr<T, R1, false>(xa[b]);
@@ -1173,26 +1190,32 @@ __global__ void __launch_bounds__(256) k_tmpl_b_ib(TmplArgs ta, int ntmpl, const
     stage_to_lds_off<T, P, G, 1, R1, PB1>(xa, cola, g);
     stage_to_lds_off<T, P, G, 1, R1, PB1>(xb, colb, g);
     stage_sync<true>();
-    long Un = U;
-    int phn = ph;
-    const bool more = advance(Un, phn);
-    if (more) load_unit(xa, xb, read_unit(Un, phn));
+    int n_c = c, n_item = item, n_u0 = u0, n_j = j + 1;
+    if (j == ch) {
+      n_c = c + nw;
+      n_item = n_c >> lg_cpt;
+      n_u0 = (n_c - (n_item << lg_cpt)) * ch;
+      n_j = 0;
+    }
+    const bool more = n_c < nchunk;
+    if (more) load_unit(xa, xb, n_item, unit_of(n_u0, n_j));
     middle_stages_reg<T, P, G, R1>(cola, colb, g, tw);
     cx<T> fa[NX], fb[NX];
     last_stage(cola, fa);
     last_stage(colb, fb);
-    if (fin) finish(last, ph == 1, fa, fb);
-    if (ph == 0) {
+    if (j > 0) finish(item, u0 + j - 1, j == ch && u0 + ch == units, fa, fb);
+    if (j < ch) {
 #pragma unroll
       for (int o = 0; o < NO; ++o) {
         pa[o] = fa[o];
         pb[o] = fb[o];
       }
-      last = U;
     }
     if (!more) break;
-    U = Un;
-    ph = phn;
+    c = n_c;
+    item = n_item;
+    u0 = n_u0;
+    j = n_j;
   }
   if constexpr (MODE != 1) flush();
 }

@@ -2,10 +2,11 @@
 from their neighbours) against the oracle's interbinned transform, element by element.
 
 Mixed precision: |2F_gpu - 2F_ora| / max(2F_ora, 4) <= 1e-4; candidate key sets equal
-outside a guard band of 1e-4 * threshold.  The second pass walks each wavefront's share
-of rows in order; the cases cover one row per wavefront unit (nfft/2 = 2^17: P = 512),
-two (2^15, 2^16: P = 256) and eight (2^12: P = 64), bin ranges that end in the wrap-around
-bin nfft - 1, shares that cross templates, and plain against batched launches.
+outside a guard band of 1e-4 * threshold.  The second pass walks chunks of consecutive
+rows; the cases cover one row per wavefront unit (nfft/2 = 2^17: P = 512), two (2^15,
+2^16: P = 256) and eight (2^12: P = 64), templates shorter than a chunk (N = 3000: eight
+units), bin ranges that end in the wrap-around bin nfft - 1, and plain against batched
+launches.
 """
 import numpy as np
 import pytest
@@ -74,8 +75,10 @@ def test_spectrum_full_segment(torch):
     assert err < TOL
 
 
-@pytest.mark.parametrize("n", [3000, 20000, 45000, 120000])
+@pytest.mark.parametrize("n", [3000, 20000, 45000, 110000, 120000])
 def test_spectrum_other_lengths(torch, n):
+    # nfft/2 over n: the first pass prunes inputs r >= 6 (3000, 45000), >= 5 (20000),
+    # >= 7 (110000) or none (120000)
     rng = np.random.default_rng(n + 7)
     injs = synth.draw_injections(rng, 1, 15.0, 15.0)
     seg = synth.make_segment(n, 2.0, 100.0, 1.0, 4100 + n, injs)
@@ -121,7 +124,7 @@ def test_full_form(torch):
 
 
 def test_candidates_full_segment_batched(torch):
-    """Launches of 64 templates: each wavefront's share of rows crosses template ends."""
+    """Launches of 64 templates: many chunks per wavefront, across templates."""
     w = synth.workload("full")
     seg = w.segments[0]
     nfft = synth.nfft_for(seg.n)
