@@ -119,9 +119,11 @@ def timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbin
     whole template list, and read the per-kernel HIP-event timings of the timed steps."""
     label = "interbinning" if interbinning else "mixed"
     tlen = nfft // 2 if interbinning else nfft          # template transform length
-    # crossings at 2F > 20: 5e-4 of the bins in noise (more on interbinned odd bins)
-    rate = 2.5e-3 if interbinning else 5.0e-4
-    cap = int(max(1 << 20, 3.0 * rate * (nfft // 2) * templates * max(args.steps, 1)))
+    # crossings at 2F > 20 on the batched workload: about 1.1e-3 of the bins (2.1e-3 with
+    # interbinning, whose odd bins of noise have a larger mean); capacity for the timed
+    # steps with a margin (entries are 32 bytes)
+    rate = 2.1e-3 if interbinning else 1.1e-3
+    cap = int(max(1 << 20, 2.0 * rate * (nfft // 2) * templates * max(args.steps, 1)))
     fixed = bool(args.templates_per_launch or args.skies_per_batch or args.no_autotune)
     cache = args.tuning_cache or None
     have_cache = cache_has_line(cache, nfft, 1 + 2 * interbinning)
@@ -174,7 +176,7 @@ def timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbin
         avg_s = kernels[dom]["avg_ms"] / 1e3
         achieved = algo[dom] / avg_s / 1e9
         variants = info["pass_a_variant"] + 2 * info["pass_b_variant"]
-        traffic = None if interbinning else measured_traffic(dom, B, variants)
+        traffic = measured_traffic(dom + ("_ib" if interbinning else ""), B, variants)
         roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                     "algorithmic_bytes_per_launch": algo[dom], "templates_per_launch": B,

@@ -4,9 +4,11 @@
         per-kernel dispatch statistics (calls, total, average, min, max duration) as markdown
 
     python -m paper_1410_3677_amd.rocprof_summary traffic FETCH.db WRITE.db --copy-bytes B \
-            --copy-match MulFunctor --templates-per-launch T [--json OUT]
+            --copy-match MulFunctor --templates-per-launch T [--kernel KEY=SUBSTRING ...] [--json OUT]
         average FETCH_SIZE / WRITE_SIZE per dispatch of each kernel, scaled by what the
-        same counters read for a plain copy kernel that moves a known number of bytes
+        same counters read for a plain copy kernel that moves a known number of bytes;
+        --kernel names the template kernels (default: template_a = k_tmpl_a,
+        template_b = k_tmpl_b; the first matching entry wins)
 """
 from __future__ import annotations
 
@@ -45,7 +47,8 @@ def counter_means(db: str, counter: str):
     return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
 
 
-def traffic(fetch_db: str, write_db: str, copy_bytes: int, copy_match: str, tpl: int):
+def traffic(fetch_db: str, write_db: str, copy_bytes: int, copy_match: str, tpl: int, kernel_keys=None):
+    keys = kernel_keys or [("template_a", "k_tmpl_a"), ("template_b", "k_tmpl_b")]
     fetch = counter_means(fetch_db, "FETCH_SIZE")
     write = counter_means(write_db, "WRITE_SIZE")
     copy_f = [v for k, (v, n) in fetch.items() if copy_match in k]
@@ -62,8 +65,7 @@ def traffic(fetch_db: str, write_db: str, copy_bytes: int, copy_match: str, tpl:
         f_kib = fetch.get(k, (0.0, 0))[0]
         w_kib = write.get(k, (0.0, 0))[0]
         short = _short(k)
-        key = ("template_a" if short.startswith("k_tmpl_a") else
-               "template_b" if short.startswith("k_tmpl_b") else short)
+        key = next((name for name, sub in keys if sub in short), short)
         res["kernels"][key] = {"kernel": short, "fetch_kib_raw": f_kib, "write_kib_raw": w_kib,
                                "fetch_bytes": f_kib * 1024 * sf, "write_bytes": w_kib * 1024 * sw,
                                "bytes_per_launch": f_kib * 1024 * sf + w_kib * 1024 * sw,
@@ -83,6 +85,7 @@ def main(argv=None):
     f.add_argument("--copy-bytes", type=int, required=True)
     f.add_argument("--copy-match", default="MulFunctor")
     f.add_argument("--templates-per-launch", type=int, required=True)
+    f.add_argument("--kernel", action="append", default=[], metavar="KEY=SUBSTRING")
     f.add_argument("--json", default="")
     f.add_argument("--source-sha256", default="")
     f.add_argument("--variants", type=int, default=-1,
@@ -91,7 +94,8 @@ def main(argv=None):
     if a.cmd == "trace":
         print(trace(a.db, a.match))
     else:
-        res = traffic(a.fetch_db, a.write_db, a.copy_bytes, a.copy_match, a.templates_per_launch)
+        keys = [tuple(x.split("=", 1)) for x in a.kernel] or None
+        res = traffic(a.fetch_db, a.write_db, a.copy_bytes, a.copy_match, a.templates_per_launch, keys)
         if a.source_sha256:
             res["source_sha256"] = a.source_sha256
         if a.variants >= 0:
