@@ -372,8 +372,10 @@ struct PatchArgs {
 // activations resident in one LDS buffer (position-major rows of 32 BF16 channels, padded to
 // CV_LD so that the sixteen rows one matrix-core operand spans hit distinct banks,
 // with three zero rows above and below every patch for the "same" padding), then
-// the 8192 -> 128 layer as an LDS-tiled product.  The matrix-core operands and the
-// order of the K steps are those of the training forward, so scores agree with it.
+// the 8192 -> 128 layer as an LDS-tiled product.  The convolutions use the training
+// forward's operands and K order (the matrix-core products transposed, so that a lane
+// holds four channels of one position), so scores agree with it.  Both layers' weight
+// fragments are staged in LDS once per workgroup.
 constexpr int CV_NP = 2;          // patches per workgroup
 constexpr int CV_NT = 512;        // threads per workgroup (8 wavefronts)
 constexpr int CV_MB = CV_NP * L / 16 / (CV_NT / 64);  // sixteen-position blocks per wavefront (4)
@@ -395,18 +397,35 @@ __global__ void k_vet_prepare_frag(const float* __restrict__ theta, uint16_t* __
   wq3[idx] = f2bf(theta[O_W3 + (co * C + ci) * KW + t]);
 }
 
+// Bias, ReLU and BF16 rounding of a product tile D[co][p] (lane l: channels
+// 16 nb + 4 (l / 16) + i, i < 4, of position p0 + l % 16) into the LDS rows, four channels
+// (8 bytes) per store.
+__device__ __forceinline__ void store_tile(uint16_t* act, int pp, int p0, int nb, v4f d, const float* __restrict__ bias,
+                                           int lane) {
+  const int co0 = 16 * nb + 4 * (lane >> 4);
+  uint32_t h[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float v = d[i] + bias[co0 + i];
+    h[i] = f2bf(v > 0.f ? v : 0.f);
+  }
+  uint16_t* row = act + (pp * CV_R + p0 + (lane & 15) + 3) * CV_LD + co0;
+  *reinterpret_cast<uint2*>(row) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+}
+
 // One convolution layer of the workgroup's patches, in place in LDS (the outputs wait in
 // the matrix-core accumulators until every wavefront has read the input); wavefront w
 // computes the sixteen-position blocks CV_MB w .. CV_MB w + CV_MB - 1 for all 32 output
-// channels.  K step t is tap t over
-// all 32 input channels, so a lane's A operand is eight channels of one LDS row.
+// channels as D[co][p] = sum_k W[co][k] X[p][k]: K step t is tap t over all 32 input
+// channels, a lane's B operand eight channels of one LDS row, and a lane's result four
+// consecutive channels of one position.
 __device__ __forceinline__ void conv_layer_lds(uint16_t* act, const uint16_t* __restrict__ wq,
                                                const float* __restrict__ bias, int w, int lane) {
   const uint16_t* in = act;
   v4f acc[CV_MB][2];
 #pragma unroll
   for (int m = 0; m < CV_MB; ++m) acc[m][0] = acc[m][1] = v4f{0.f, 0.f, 0.f, 0.f};
-  const v8s* wqv = reinterpret_cast<const v8s*>(wq);
+  const v8s* wqv = reinterpret_cast<const v8s*>(wq);   // fragments in LDS
   const int ci0 = 8 * (lane >> 4);
   for (int t = 0; t < KS; ++t) {
     const v8s b0 = wqv[(t * 2 + 0) * 64 + lane];
@@ -415,25 +434,16 @@ __device__ __forceinline__ void conv_layer_lds(uint16_t* act, const uint16_t* __
     for (int m = 0; m < CV_MB; ++m) {
       const int mb = CV_MB * w + m, pp = mb >> 4, p0 = (mb & 15) * 16;
       const v8s a = lds8(in + (pp * CV_R + p0 + (lane & 15) + t) * CV_LD + ci0);
-      acc[m][0] = mfma32(a, b0, acc[m][0]);
-      acc[m][1] = mfma32(a, b1, acc[m][1]);
+      acc[m][0] = mfma32(b0, a, acc[m][0]);
+      acc[m][1] = mfma32(b1, a, acc[m][1]);
     }
   }
   __syncthreads();  // every wavefront has read the layer's input: overwrite it in place
 #pragma unroll
   for (int m = 0; m < CV_MB; ++m) {
     const int mb = CV_MB * w + m, pp = mb >> 4, p0 = (mb & 15) * 16;
-#pragma unroll
-    for (int nb = 0; nb < 2; ++nb) {
-      const int co = 16 * nb + (lane & 15);
-      const float bc = bias[co];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int p = p0 + 4 * (lane >> 4) + i;
-        const float v = acc[m][nb][i] + bc;
-        act[(pp * CV_R + p + 3) * CV_LD + co] = f2bf(v > 0.f ? v : 0.f);
-      }
-    }
+    store_tile(act, pp, p0, 0, acc[m][0], bias, lane);
+    store_tile(act, pp, p0, 1, acc[m][1], bias, lane);
   }
 }
 
@@ -444,8 +454,13 @@ __global__ void __launch_bounds__(CV_NT) k_vet_conv_infer(const float* __restric
                                                         const uint16_t* __restrict__ wq3, uint16_t* __restrict__ x) {
   __shared__ float su[CV_NP][CV_R];
   __shared__ __align__(16) uint16_t sa[CV_NP * CV_R * CV_LD];
+  __shared__ __align__(16) uint16_t swq[2 * WQ_ELEMS];   // conv2 and conv3 weight fragments
   const int s0 = blockIdx.x * CV_NP;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int i = tid; i < 2 * WQ_ELEMS / 8; i += CV_NT) {
+    const uint4* src = reinterpret_cast<const uint4*>(i < WQ_ELEMS / 8 ? wq2 : wq3);
+    reinterpret_cast<uint4*>(swq)[i] = src[i < WQ_ELEMS / 8 ? i : i - WQ_ELEMS / 8];
+  }
   for (int i = tid; i < CV_NP * CV_R; i += CV_NT) {
     const int pp = i / CV_R, r = i % CV_R, q = r - 3;
     float v = 0.f;
@@ -483,9 +498,9 @@ __global__ void __launch_bounds__(CV_NT) k_vet_conv_infer(const float* __restric
     }
   }
   __syncthreads();
-  conv_layer_lds(sa, wq2, theta + O_B2, w, lane);
+  conv_layer_lds(sa, swq, theta + O_B2, w, lane);
   __syncthreads();
-  conv_layer_lds(sa, wq3, theta + O_B3, w, lane);
+  conv_layer_lds(sa, swq + WQ_ELEMS, theta + O_B3, w, lane);
   __syncthreads();
   // rows 3 .. L+2 of each patch to x, 16 bytes per item
   for (int i = tid; i < CV_NP * L * (C / 8); i += CV_NT) {
