@@ -97,7 +97,9 @@ struct fstat_plan_s {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   bool ws_owned = false;
-  size_t off_sp = 0, off_part = 0, off_zt = 0, off_shared = 0;
+  // per-sky parameters and resampled series twice (the sky batch being prepared and the
+  // one being searched), per-sky scratch, template intermediate
+  size_t off_sp[2] = {0, 0}, off_part = 0, off_zt[2] = {0, 0}, off_sky = 0, off_tmpl = 0;
   int nblk_max = 0;
   long n_max = 0, L_max = 0, M_max = 0;
   long TL_max = 0;             // longest template FFT
@@ -110,6 +112,10 @@ struct fstat_plan_s {
   // graph replay: a plan-owned stream joined to the caller's stream by events
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // the per-sky stage of the next sky batch runs on its own stream (default priority)
+  // while the current batch's templates run; events order the two and the buffers
+  hipStream_t sstream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_sky[2] = {nullptr, nullptr}, ev_tmpl[2] = {nullptr, nullptr};
   std::vector<GraphEntry> graphs;
   // candidate vetting: patch capture after the F kernel
   fstat_vet_t vet = nullptr;
@@ -184,23 +190,31 @@ static int tw_of(int len) {
 static size_t layout(fstat_plan_t p, int Sb, int B, bool commit) {
   const size_t cx = p->cx_bytes;
   size_t off = 0;
-  const size_t o_sp = off;
-  off = align256(off + (size_t)Sb * sizeof(SkyParams));
+  size_t o_sp[2], o_zt[2];
+  for (int k = 0; k < 2; ++k) {
+    o_sp[k] = off;
+    off = align256(off + (size_t)Sb * sizeof(SkyParams));
+  }
   const size_t o_part = off;
   off = align256(off + (size_t)Sb * p->nblk_max * 3 * sizeof(double));
-  const size_t o_zt = off;
-  off = align256(off + (size_t)Sb * 2 * p->n_max * cx);
-  const size_t o_sh = off;
-  // per-sky scratch: za [2][M], Z [2][M], tmp [2][L], u [2][L]; aliased by the
-  // template intermediate [B][tL][2] (per-sky scratch is dead once zt is built)
-  const size_t sky_scratch = (size_t)Sb * (4 * p->M_max + 4 * p->L_max) * cx;
-  const size_t tmpl = (size_t)B * 2 * p->TL_max * cx;
-  off = align256(off + std::max(sky_scratch, tmpl));
+  for (int k = 0; k < 2; ++k) {
+    o_zt[k] = off;
+    off = align256(off + (size_t)Sb * 2 * p->n_max * cx);
+  }
+  // per-sky scratch: za [2][M], Z [2][M], tmp [2][L], u [2][L] per sky
+  const size_t o_sky = off;
+  off = align256(off + (size_t)Sb * (4 * p->M_max + 4 * p->L_max) * cx);
+  // template intermediate [B][tL][2]
+  const size_t o_tmpl = off;
+  off = align256(off + (size_t)B * 2 * p->TL_max * cx);
   if (commit) {
-    p->off_sp = o_sp;
+    for (int k = 0; k < 2; ++k) {
+      p->off_sp[k] = o_sp[k];
+      p->off_zt[k] = o_zt[k];
+    }
     p->off_part = o_part;
-    p->off_zt = o_zt;
-    p->off_shared = o_sh;
+    p->off_sky = o_sky;
+    p->off_tmpl = o_tmpl;
   }
   return off;
 }
@@ -322,10 +336,12 @@ struct Dev {
     g = (const T*)((const char*)p->tab.dev + p->tab.off_g[w]);
     twst = (const cx<T>*)((const char*)p->tab.dev + p->tab.off_stage[w]);
   }
-  SkyParams* sp() const { return (SkyParams*)((char*)p->ws + p->off_sp); }
+  int buf = 0;   // which of the two per-sky buffers
+  SkyParams* sp() const { return (SkyParams*)((char*)p->ws + p->off_sp[buf]); }
   double* part() const { return (double*)((char*)p->ws + p->off_part); }
-  cx<T>* zt() const { return (cx<T>*)((char*)p->ws + p->off_zt); }
-  cx<T>* shared() const { return (cx<T>*)((char*)p->ws + p->off_shared); }
+  cx<T>* zt() const { return (cx<T>*)((char*)p->ws + p->off_zt[buf]); }
+  cx<T>* sky() const { return (cx<T>*)((char*)p->ws + p->off_sky); }
+  cx<T>* tmpl() const { return (cx<T>*)((char*)p->ws + p->off_tmpl); }
 };
 
 // forward or inverse L-point FFT of `items` pairs of series, two passes
@@ -360,7 +376,7 @@ static fstat_status run_sky_batch(fstat_plan_t p, const Dev<T>& d, const SegInfo
   const SegConst sc = seg_const(si);
   const int n = sc.n, L = si.nfft, M = si.M;
   const int nblk = (n + NT - 1) / NT;
-  cx<T>* za = d.shared();                          // [nb][2][M]
+  cx<T>* za = d.sky();                             // [nb][2][M]
   cx<T>* Z = za + (size_t)nb * 2 * M;              // [nb][2][M]
   cx<T>* tmp = Z + (size_t)nb * 2 * M;             // [nb][2][L]
   cx<T>* u = tmp + (size_t)nb * 2 * L;             // [nb][2][L]
@@ -411,7 +427,7 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
   ta.fdot = fdot;
   ta.ldzt = si.s.n;
   const int total = nb * nfdot;
-  cx<T>* tbuf = d.shared();
+  cx<T>* tbuf = d.tmpl();
   for (int t0 = 0; t0 < total; t0 += p->B) {
     const int nt = std::min(p->B, total - t0);
     ta.t0 = t0;
@@ -561,12 +577,33 @@ static fstat_status search_impl(fstat_plan_t p, int segment, const double* alpha
     oa.segment = s;
     oa.k_min = si.kmin;
     oa.k_max = si.kmax;
-    for (int sky0 = 0; sky0 < nsky; sky0 += p->Sb) {
-      const int nb = std::min(p->Sb, nsky - sky0);
-      fstat_status r = run_sky_batch<T>(p, d, si, alpha, delta, sky0, nb, st);
+    // Sky batch b is prepared on the plan's sky stream into buffer b % 2 while batch b - 1
+    // is searched on `st`: the sky stream waits for the templates of batch b - 2 (the last
+    // reader of that buffer), the templates of batch b for its sky stage.
+    const int nbatch = (nsky + p->Sb - 1) / p->Sb;
+    HIP_TRY(p, hipEventRecord(p->ev_fork, st), "sky stream fork");
+    HIP_TRY(p, hipStreamWaitEvent(p->sstream, p->ev_fork, 0), "sky stream fork");
+    auto sky_stage = [&](int b) -> fstat_status {
+      Dev<T> db = d;
+      db.buf = b & 1;
+      if (b >= 2) HIP_TRY(p, hipStreamWaitEvent(p->sstream, p->ev_tmpl[b & 1], 0), "sky stream order");
+      const int sky0 = b * p->Sb;
+      fstat_status r = run_sky_batch<T>(p, db, si, alpha, delta, sky0, std::min(p->Sb, nsky - sky0), p->sstream);
       if (r != FSTAT_OK) return r;
-      r = run_templates<T>(p, d, si, sky0, nb, fdot, nfdot, mode, oa, st);
+      HIP_TRY(p, hipEventRecord(p->ev_sky[b & 1], p->sstream), "sky stream order");
+      return FSTAT_OK;
+    };
+    fstat_status r = sky_stage(0);
+    if (r != FSTAT_OK) return r;
+    for (int b = 0; b < nbatch; ++b) {
+      if (b + 1 < nbatch && (r = sky_stage(b + 1)) != FSTAT_OK) return r;
+      HIP_TRY(p, hipStreamWaitEvent(st, p->ev_sky[b & 1], 0), "sky stream join");
+      Dev<T> db = d;
+      db.buf = b & 1;
+      const int sky0 = b * p->Sb;
+      r = run_templates<T>(p, db, si, sky0, std::min(p->Sb, nsky - sky0), fdot, nfdot, mode, oa, st);
       if (r != FSTAT_OK) return r;
+      HIP_TRY(p, hipEventRecord(p->ev_tmpl[b & 1], st), "sky stream order");
     }
   }
   return FSTAT_OK;
@@ -575,6 +612,14 @@ static fstat_status search_impl(fstat_plan_t p, int segment, const double* alpha
 // All launches of one search call (begin-search marker first).
 static fstat_status enqueue_search(fstat_plan_t p, int segment, const double* alpha, const double* delta, int nsky,
                                    const double* fdot, int nfdot, int mode, void* spectrum, hipStream_t st) {
+  if (!p->sstream) {
+    HIP_TRY(p, hipStreamCreateWithFlags(&p->sstream, hipStreamNonBlocking), "sky stream");
+    HIP_TRY(p, hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming), "sky stream event");
+    for (int k = 0; k < 2; ++k) {
+      HIP_TRY(p, hipEventCreateWithFlags(&p->ev_sky[k], hipEventDisableTiming), "sky stream event");
+      HIP_TRY(p, hipEventCreateWithFlags(&p->ev_tmpl[k], hipEventDisableTiming), "sky stream event");
+    }
+  }
   if (mode == 0) {
     hipLaunchKernelGGL(k_begin_search, dim3(1), dim3(1), 0, st, p->d_search_next);
     HIP_TRY(p, hipGetLastError(), "search marker launch");
@@ -1305,7 +1350,7 @@ static fstat_status sky_stages_impl(fstat_plan_t plan, const SegInfo& si, const 
   fstat_status r = run_sky_batch<T>(plan, d, si, ad, ad + 1, 0, 1, st);
   if (r != FSTAT_OK) return r;
   const size_t n = si.s.n, M = si.M, L = si.nfft, cb = sizeof(cx<T>);
-  cx<T>* zab = d.shared();
+  cx<T>* zab = d.sky();
   cx<T>* u = zab + 4 * M + 2 * L;
   auto cp = [&](void* dst, const void* src, size_t bytes) {
     return dst ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st) : hipSuccess;
@@ -1606,6 +1651,13 @@ fstat_status fstat_destroy(fstat_plan_t plan) {
       (void)hipEventDestroy(pr.b);
     }
   }
+  if (plan->sstream) (void)hipStreamSynchronize(plan->sstream);
+  for (int k = 0; k < 2; ++k) {
+    if (plan->ev_sky[k]) (void)hipEventDestroy(plan->ev_sky[k]);
+    if (plan->ev_tmpl[k]) (void)hipEventDestroy(plan->ev_tmpl[k]);
+  }
+  if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
+  if (plan->sstream) (void)hipStreamDestroy(plan->sstream);
   if (plan->ev_in) (void)hipEventDestroy(plan->ev_in);
   if (plan->ev_out) (void)hipEventDestroy(plan->ev_out);
   if (plan->gstream) (void)hipStreamDestroy(plan->gstream);
