@@ -80,6 +80,11 @@ struct fstat_vet_s {
   float *u, *z1, *z2, *z3, *z4, *z5, *a5, *logit, *dlogit, *lterm, *dz5, *dh4, *dx, *da, *dwm, *loss;
   float* scratch = nullptr;      // split-K partial tiles and reduction partials
   uint16_t *a1b, *a2b, *a3b, *a4b, *colA, *colB, *colC, *dz5b, *dz4b, *dzb;
+  uint16_t* a3b2 = nullptr;      // second convolution-output buffer of pipelined scoring
+  // scoring: the convolutions of the next batch run on the vetter's stream (default
+  // priority) while the current batch's dense layers run on the caller's stream
+  hipStream_t cstream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_conv[2] = {nullptr, nullptr}, ev_read[2] = {nullptr, nullptr};
   std::string last_error;
 };
 
@@ -813,13 +818,21 @@ void vet_prepare(fstat_vet_t v, hipStream_t st) {
 // inference of n <= max_batch patches (logits to `out`): fused LDS convolutions, the
 // 8192 -> 128 layer as an LDS-tiled product split four ways along K, then the small layers
 constexpr int INFER_SPLITS = 4;
-void vet_infer_batch(fstat_vet_t v, const float* patches, int n, float* out, hipStream_t st) {
+// Scoring of n <= max_batch patches in two parts: the three convolutions into x (one
+// fused kernel, bound by the matrix cores and LDS), then the dense layers from x (the
+// 8192 -> 128 product reads x from HBM); `read` is recorded once x has been read.
+void vet_conv_stage(fstat_vet_t v, const float* patches, int n, uint16_t* x, hipStream_t st) {
+  using namespace vet;
+  hipLaunchKernelGGL(k_vet_conv_infer, dim3((n + CV_NP - 1) / CV_NP), dim3(CV_NT), 0, st, patches, n, v->theta, v->wq2,
+                     v->wq3, x);
+}
+
+void vet_dense_stage(fstat_vet_t v, const uint16_t* x, int n, float* out, hipEvent_t read, hipStream_t st) {
   using namespace vet;
   const int nbp = (n + GT - 1) / GT * GT;
-  hipLaunchKernelGGL(k_vet_conv_infer, dim3((n + CV_NP - 1) / CV_NP), dim3(CV_NT), 0, st, patches, n, v->theta, v->wq2,
-                     v->wq3, v->a3b);
-  hipLaunchKernelGGL(k_gemm_nt_lds, dim3(H / GT, nbp / GT, INFER_SPLITS), dim3(256), 0, st, nbp, H, X, v->a3b,
-                     v->w4b, v->scratch, X / INFER_SPLITS);
+  hipLaunchKernelGGL(k_gemm_nt_lds, dim3(H / GT, nbp / GT, INFER_SPLITS), dim3(256), 0, st, nbp, H, X, x, v->w4b,
+                     v->scratch, X / INFER_SPLITS);
+  if (read) (void)hipEventRecord(read, st);
   const long count = (long)nbp * H;
   hipLaunchKernelGGL(k_vet_sum_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->scratch, INFER_SPLITS, count,
                      n, H, v->theta + O_B4, v->a4b);
@@ -827,6 +840,41 @@ void vet_infer_batch(fstat_vet_t v, const float* patches, int n, float* out, hip
   hipLaunchKernelGGL(k_vet_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->z5, (long)n, H, v->theta + O_B5,
                      (uint16_t*)nullptr, v->a5);
   hipLaunchKernelGGL(k_vet_fc3, blocks_for(n), dim3(256), 0, st, v->a5, n, v->theta, out);
+}
+
+// All n patches in batches of max_batch, pipelined: batch k's convolutions go to the
+// vetter's stream into buffer k % 2 (after batch k - 2's product has read it), its dense
+// layers to `st` after them; `tail(i, b, logits)` enqueues work on `st` that uses a
+// batch's logits (written to out_of(i) by the dense stage).
+template <typename OutOf, typename Tail>
+static fstat_status vet_score_all(fstat_vet_t v, const float* patches, long long n, hipStream_t st, OutOf out_of,
+                                  Tail tail) {
+  if (!v->cstream) {
+    VET_TRY(v, hipStreamCreateWithFlags(&v->cstream, hipStreamNonBlocking), "vetter stream");
+    VET_TRY(v, hipEventCreateWithFlags(&v->ev_fork, hipEventDisableTiming), "vetter event");
+    for (int k = 0; k < 2; ++k) {
+      VET_TRY(v, hipEventCreateWithFlags(&v->ev_conv[k], hipEventDisableTiming), "vetter event");
+      VET_TRY(v, hipEventCreateWithFlags(&v->ev_read[k], hipEventDisableTiming), "vetter event");
+    }
+  }
+  VET_TRY(v, hipEventRecord(v->ev_fork, st), "vetter fork");
+  VET_TRY(v, hipStreamWaitEvent(v->cstream, v->ev_fork, 0), "vetter fork");
+  long long k = 0;
+  for (long long i = 0; i < n; i += v->max_batch, ++k) {
+    const int b = (int)std::min<long long>(v->max_batch, n - i);
+    const int buf = (int)(k & 1);
+    uint16_t* x = buf ? v->a3b2 : v->a3b;
+    if (k >= 2) VET_TRY(v, hipStreamWaitEvent(v->cstream, v->ev_read[buf], 0), "vetter order");
+    vet_conv_stage(v, patches + i * vet::L, b, x, v->cstream);
+    VET_TRY(v, hipGetLastError(), "scoring launch");
+    VET_TRY(v, hipEventRecord(v->ev_conv[buf], v->cstream), "vetter order");
+    VET_TRY(v, hipStreamWaitEvent(st, v->ev_conv[buf], 0), "vetter join");
+    float* out = out_of(i);
+    vet_dense_stage(v, x, b, out, v->ev_read[buf], st);
+    VET_TRY(v, hipGetLastError(), "scoring launch");
+    tail(i, b, out);
+  }
+  return FSTAT_OK;
 }
 
 // forward of n <= max_batch patches; logits to `out`
@@ -929,7 +977,8 @@ fstat_status fstat_vet_create(int32_t max_batch, fstat_vet_t* out) {
       {(void**)&v->dh4, nb * H * 4}, {(void**)&v->dx, NL * C * 4}, {(void**)&v->da, NL * C * 4},
       {(void**)&v->dwm, KC * C * 4}, {(void**)&v->loss, 4}, {(void**)&v->scratch, (size_t)VET_SCRATCH * 4},
       {(void**)&v->a1b, NL * C * 2},
-      {(void**)&v->a2b, NL * C * 2}, {(void**)&v->a3b, nbp * X * 2}, {(void**)&v->a4b, nb * H * 2},
+      {(void**)&v->a2b, NL * C * 2}, {(void**)&v->a3b, nbp * X * 2}, {(void**)&v->a3b2, nbp * X * 2},
+      {(void**)&v->a4b, nb * H * 2},
       {(void**)&v->colA, NL * KC * 2}, {(void**)&v->colB, NL * KC * 2}, {(void**)&v->colC, NL * KC * 2},
       {(void**)&v->dz5b, nb * H * 2}, {(void**)&v->dz4b, nb * H * 2}, {(void**)&v->dzb, NL * C * 2}};
   size_t total = 0;
@@ -975,12 +1024,7 @@ fstat_status fstat_vet_get_params(fstat_vet_t v, float* params, int64_t n) {
 fstat_status fstat_vet_forward(fstat_vet_t v, const float* patches, int64_t n, float* logits, void* stream) {
   if (!v || n < 0 || (n > 0 && (!patches || !logits))) return vet_fail(v, FSTAT_E_INVAL, "bad arguments");
   hipStream_t st = (hipStream_t)stream;
-  for (int64_t i = 0; i < n; i += v->max_batch) {
-    const int b = (int)std::min<int64_t>(v->max_batch, n - i);
-    vet_infer_batch(v, patches + i * vet::L, b, logits + i, st);
-    VET_TRY(v, hipGetLastError(), "forward launch");
-  }
-  return FSTAT_OK;
+  return vet_score_all(v, patches, n, st, [&](long long i) { return logits + i; }, [](long long, int, float*) {});
 }
 
 fstat_status fstat_vet_gradient(fstat_vet_t v, const float* patches, const float* labels, int64_t n, float* loss,
@@ -1011,6 +1055,12 @@ fstat_status fstat_vet_adam_step(fstat_vet_t v, float lr, float beta1, float bet
 fstat_status fstat_vet_destroy(fstat_vet_t v) {
   if (!v) return FSTAT_OK;
   (void)hipDeviceSynchronize();
+  for (int k = 0; k < 2; ++k) {
+    if (v->ev_conv[k]) (void)hipEventDestroy(v->ev_conv[k]);
+    if (v->ev_read[k]) (void)hipEventDestroy(v->ev_read[k]);
+  }
+  if (v->ev_fork) (void)hipEventDestroy(v->ev_fork);
+  if (v->cstream) (void)hipStreamDestroy(v->cstream);
   if (v->mem) (void)hipFree(v->mem);
   delete v;
   return FSTAT_OK;
@@ -1061,12 +1111,13 @@ fstat_status fstat_plan_vet_candidates(fstat_plan_t plan, void* stream) {
   const long long n = std::min<long long>({(long long)count, plan->opt.candidate_capacity, plan->patch_capacity});
   // batches of the vetter's size: logits into its own buffer, scores into the entries
   fstat_vet_t v = plan->vet;
-  for (long long i = 0; i < n; i += v->max_batch) {
-    const int b = (int)std::min<long long>(v->max_batch, n - i);
-    vet_infer_batch(v, plan->d_patches + i * vet::L, b, v->logit, st);
-    hipLaunchKernelGGL(k_vet_store_scores, blocks_for(b), dim3(256), 0, st, plan->d_cand + i, v->logit, (long)b);
-    HIP_TRY(plan, hipGetLastError(), "scoring launch");
-  }
+  const fstat_status rs = vet_score_all(
+      v, plan->d_patches, n, st, [&](long long) { return v->logit; },
+      [&](long long i, int b, float* logits) {
+        hipLaunchKernelGGL(k_vet_store_scores, blocks_for(b), dim3(256), 0, st, plan->d_cand + i, logits, (long)b);
+      });
+  if (rs != FSTAT_OK) return fail(plan, rs, v->last_error);
+  HIP_TRY(plan, hipGetLastError(), "scoring launch");
   HIP_TRY(plan, hipStreamSynchronize(st), "scoring");
   plan->scored = true;
   plan->last_stream = st;
