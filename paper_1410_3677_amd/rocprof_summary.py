@@ -20,7 +20,7 @@ import sys
 
 
 def _short(name: str) -> str:
-    n = name.split("(")[0]
+    n = name.replace("(anonymous namespace)::", "").split("(")[0]
     return n.replace("void ", "").replace("fstat::", "")
 
 
