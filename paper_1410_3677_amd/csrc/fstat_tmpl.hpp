@@ -203,11 +203,15 @@ __device__ __forceinline__ const cx<T>& at32(const cx<T>* base, unsigned o) {
 // The intermediate between the two passes holds a template's two series interleaved:
 // value (k2, j1) of series s at 2 (k2 P + j1) + s, so that the pair (a, b) of one
 // position is one 16-byte access in FP32 and eight adjacent columns fill a 128-byte line.
+// It is stored non-temporally: a launch's intermediate (GBs) is read back only after the
+// whole launch, so caching it only leaves dirty lines whose write-back competes with the
+// second pass's reads (0.71 against 0.68 us per template for that pass).
 typedef float f4v_t __attribute__((ext_vector_type(4)));
 template <typename T>
 __device__ __forceinline__ void store_pair(cx<T>* base, unsigned o, cx<T> a, cx<T> b) {
   if constexpr (sizeof(T) == 4) {
-    *reinterpret_cast<f4v_t*>(reinterpret_cast<char*>(base) + o * 16u) = f4v_t{a.re, a.im, b.re, b.im};
+    __builtin_nontemporal_store(f4v_t{a.re, a.im, b.re, b.im},
+                                reinterpret_cast<f4v_t*>(reinterpret_cast<char*>(base) + o * 16u));
   } else {
     at32(base, 2 * o) = a;
     at32(base, 2 * o + 1) = b;
