@@ -584,31 +584,39 @@ static fstat_status search_impl(fstat_plan_t p, int segment, const double* alpha
     oa.k_max = si.kmax;
     // Sky batch b is prepared on the plan's sky stream into buffer b % 2 while batch b - 1
     // is searched on `st`: the sky stream waits for the templates of batch b - 2 (the last
-    // reader of that buffer), the templates of batch b for its sky stage.
+    // reader of that buffer), the templates of batch b for its sky stage.  With per-launch
+    // profiling on, the sky stage stays on `st`, so that each timed kernel runs alone.
     const int nbatch = (nsky + p->Sb - 1) / p->Sb;
-    HIP_TRY(p, hipEventRecord(p->ev_fork, st), "sky stream fork");
-    HIP_TRY(p, hipStreamWaitEvent(p->sstream, p->ev_fork, 0), "sky stream fork");
+    hipStream_t sst = p->profiling ? st : p->sstream;
+    if (sst != st) {
+      HIP_TRY(p, hipEventRecord(p->ev_fork, st), "sky stream fork");
+      HIP_TRY(p, hipStreamWaitEvent(sst, p->ev_fork, 0), "sky stream fork");
+    }
     auto sky_stage = [&](int b) -> fstat_status {
       Dev<T> db = d;
       db.buf = b & 1;
-      if (b >= 2) HIP_TRY(p, hipStreamWaitEvent(p->sstream, p->ev_tmpl[b & 1], 0), "sky stream order");
+      if (b >= 2 && sst != st) HIP_TRY(p, hipStreamWaitEvent(sst, p->ev_tmpl[b & 1], 0), "sky stream order");
       const int sky0 = b * p->Sb;
-      fstat_status r = run_sky_batch<T>(p, db, si, alpha, delta, sky0, std::min(p->Sb, nsky - sky0), p->sstream);
+      fstat_status r = run_sky_batch<T>(p, db, si, alpha, delta, sky0, std::min(p->Sb, nsky - sky0), sst);
       if (r != FSTAT_OK) return r;
-      HIP_TRY(p, hipEventRecord(p->ev_sky[b & 1], p->sstream), "sky stream order");
+      if (sst != st) HIP_TRY(p, hipEventRecord(p->ev_sky[b & 1], sst), "sky stream order");
       return FSTAT_OK;
     };
     fstat_status r = sky_stage(0);
     if (r != FSTAT_OK) return r;
     for (int b = 0; b < nbatch; ++b) {
-      if (b + 1 < nbatch && (r = sky_stage(b + 1)) != FSTAT_OK) return r;
-      HIP_TRY(p, hipStreamWaitEvent(st, p->ev_sky[b & 1], 0), "sky stream join");
+      if (sst != st) {
+        if (b + 1 < nbatch && (r = sky_stage(b + 1)) != FSTAT_OK) return r;
+        HIP_TRY(p, hipStreamWaitEvent(st, p->ev_sky[b & 1], 0), "sky stream join");
+      } else if (b > 0 && (r = sky_stage(b)) != FSTAT_OK) {
+        return r;
+      }
       Dev<T> db = d;
       db.buf = b & 1;
       const int sky0 = b * p->Sb;
       r = run_templates<T>(p, db, si, sky0, std::min(p->Sb, nsky - sky0), fdot, nfdot, mode, oa, st);
       if (r != FSTAT_OK) return r;
-      HIP_TRY(p, hipEventRecord(p->ev_tmpl[b & 1], st), "sky stream order");
+      if (sst != st) HIP_TRY(p, hipEventRecord(p->ev_tmpl[b & 1], st), "sky stream order");
     }
   }
   return FSTAT_OK;
