@@ -21,6 +21,12 @@
  *    buffer and (unless the caller supplies one) its workspace.
  *  - Calls on one plan are not thread-safe; distinct plans are independent.
  *  - Stream arguments are hipStream_t passed as void*; NULL is the null stream.
+ *    Work "asynchronous on `stream`" starts after the work already enqueued on
+ *    that stream and finishes before the work enqueued on it afterwards.  Parts
+ *    of it may run on streams the plan or the network owns (default priority),
+ *    joined to `stream` with events: the per-sky stage of the next sky batch
+ *    beside the current batch's templates, the next batch's convolutions beside
+ *    the current batch's dense layers.
  */
 #ifndef FSTAT_H
 #define FSTAT_H
@@ -175,7 +181,9 @@ fstat_status fstat_sky_stages(fstat_plan_t plan, int32_t segment, double alpha, 
 /* Per-kernel timing.  When enabled, the plan brackets each launch of the
  * kernel classes below with HIP events on the launch stream;
  * fstat_profile_read waits for them and reports the number of launches and
- * their summed duration since the last reset. */
+ * their summed duration since the last reset.  While enabled, searches run
+ * eagerly (no graphs) and entirely on the caller's stream, so that each timed
+ * launch runs alone. */
 typedef enum {
   FSTAT_KERNEL_SKY_PREP = 0,      /* demodulation + antenna sums */
   FSTAT_KERNEL_RESAMPLE = 1,      /* upsampling FFTs + spline */
