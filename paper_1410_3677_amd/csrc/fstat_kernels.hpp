@@ -300,9 +300,22 @@ __global__ void __launch_bounds__(NT) k_fft_pass_b(const cx<T>* __restrict__ in,
 // both ends: G(p, q) = g(p-q) - g(p+q) - g(2(L-1)-p-q), truncated at |k| <= KT
 // (|z|^KT below the working precision).
 template <typename T, int KT>
-__device__ __forceinline__ cx<T> spline_moment(int p, int L, const cx<T>* d, int dlo, const T* g) {
+__device__ __forceinline__ cx<T> spline_moment(int p, int L, const cx<T>* d, int dlo, const T* g,
+                                               const T* __restrict__ gg) {
   // d[q - dlo] = d_q for q in [max(1, p - KT), min(L - 2, p + KT)]
   if (p <= 0 || p >= L - 1) return mk<T>(0, 0);
+  if (p > KT && p < L - 1 - KT) {
+    // interior knot: no image terms, the symmetric 2 KT + 1 taps with the weights read as
+    // uniform values (gg: the same table in global memory)
+    const cx<T>* c = d + (p - dlo);
+    cx<T> acc = mk<T>(gg[0] * c[0].re, gg[0] * c[0].im);
+#pragma unroll
+    for (int k = 1; k <= KT; ++k) {
+      const cx<T> a = c[-k], b = c[k];
+      acc = mk<T>(acc.re + gg[k] * (a.re + b.re), acc.im + gg[k] * (a.im + b.im));
+    }
+    return acc;
+  }
   cx<T> acc = mk<T>(0, 0);
   const int q0 = max(1, p - KT), q1 = min(L - 2, p + KT);
   for (int q = q0; q <= q1; ++q) {
@@ -363,9 +376,18 @@ __global__ void __launch_bounds__(NT) k_spline(SegConst sc, const SkyParams* __r
     sminmax[1] = -1;
   }
   __syncthreads();
-  if (valid) {
-    atomicMin(&sminmax[0], kn);
-    atomicMax(&sminmax[1], kn);
+  {
+    // the tile's knot range: a wavefront reduction, then one LDS atomic per wavefront
+    int mn = valid ? kn : 0x7fffffff, mx = valid ? kn : -1;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      mn = min(mn, __shfl_xor(mn, off, 64));
+      mx = max(mx, __shfl_xor(mx, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomicMin(&sminmax[0], mn);
+      atomicMax(&sminmax[1], mx);
+    }
   }
   __syncthreads();
   const int pmin = sminmax[0], pmax = sminmax[1];
@@ -395,8 +417,8 @@ __global__ void __launch_bounds__(NT) k_spline(SegConst sc, const SkyParams* __r
     }
     __syncthreads();
     for (int q = pmin + threadIdx.x; q <= pmax + 1; q += NT) {
-      sm[0][q - pmin] = spline_moment<T, KT>(q, L, sd[0], dlo, sg);
-      sm[1][q - pmin] = spline_moment<T, KT>(q, L, sd[1], dlo, sg);
+      sm[0][q - pmin] = spline_moment<T, KT>(q, L, sd[0], dlo, sg, gtab);
+      sm[1][q - pmin] = spline_moment<T, KT>(q, L, sd[1], dlo, sg, gtab);
     }
     __syncthreads();
     if (j < n) {
