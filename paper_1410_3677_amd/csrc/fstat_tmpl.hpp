@@ -740,6 +740,97 @@ __device__ __forceinline__ void load_stream(const cx<double>* p, cx<double>& a, 
 // Candidates a wavefront stages in LDS before it reserves their slots with one atomic.
 constexpr int STAGE_CAP = 32;
 
+// Candidate staging of one wavefront in the streaming second passes: crossings are
+// compacted with ballots into the wavefront's STAGE_CAP-entry LDS area, and one atomic
+// reserves the slots of a whole area (a burst larger than the area goes straight out).
+struct WaveStage {
+  int* item;
+  int* bin;
+  float* val;
+  int n = 0;
+
+  template <typename T>
+  __device__ __forceinline__ static void emit(const OutArgs& oa, const TmplArgs& ta, int search,
+                                              unsigned long long slot, int it, int b, T v) {
+    if (slot < (unsigned long long)oa.capacity) {
+      const int t = ta.t0 + it;
+      const int skyl = t / ta.nfdot;
+      CandEntry ce;
+      ce.search = search;
+      ce.segment = oa.segment;
+      ce.sky = ta.sky0 + skyl;
+      ce.fdot_idx = t - skyl * ta.nfdot;
+      ce.bin = b;
+      ce.pad = 0;
+      ce.twoF = (double)v;
+      oa.cand[slot] = ce;
+    }
+  }
+
+  // `count` slots for the whole wavefront (the same base in every lane)
+  __device__ __forceinline__ static unsigned long long reserve(const OutArgs& oa, int lane, int count) {
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(oa.count, (unsigned long long)count);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)base);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(base >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+  }
+
+  __device__ __forceinline__ void flush(const OutArgs& oa, const TmplArgs& ta, int search, int lane) {
+    if (n == 0) return;
+    stage_sync<true>();
+    const unsigned long long base = reserve(oa, lane, n);
+    if (lane < n) emit(oa, ta, search, base + lane, item[lane], bin[lane], val[lane]);
+    stage_sync<true>();
+    n = 0;
+  }
+
+  // Crossings of this lane: bit q of `mask` for value v[q] of bin bin_of(q), template it.
+  // TWO_PASS counts the ballots first and places them in a second round, keeping no
+  // per-value offsets (fewer registers for long value lists).
+  template <bool TWO_PASS, int NV, typename T, typename BinOf>
+  __device__ __forceinline__ void add(const OutArgs& oa, const TmplArgs& ta, int search, int lane, uint32_t mask,
+                                      const T (&v)[NV], int it, BinOf bin_of) {
+    if (!__ballot(mask != 0)) return;
+    auto rank = [&](unsigned long long bi) {
+      return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bi >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bi, 0u));
+    };
+    int total = 0;
+    int off[TWO_PASS ? 1 : NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const unsigned long long bi = __ballot((mask >> q) & 1u);
+      if constexpr (!TWO_PASS) off[q] = total + rank(bi);
+      total += __popcll(bi);
+    }
+    if (n + total > STAGE_CAP) flush(oa, ta, search, lane);
+    const bool direct = total > STAGE_CAP;
+    const unsigned long long base = direct ? reserve(oa, lane, total) : 0ull;
+    int run = 0;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      int o;
+      if constexpr (TWO_PASS) {
+        const unsigned long long bi = __ballot((mask >> q) & 1u);
+        o = run + rank(bi);
+        run += __popcll(bi);
+      } else {
+        o = off[q];
+      }
+      if ((mask >> q) & 1u) {
+        if (direct) {
+          emit(oa, ta, search, base + (unsigned long long)o, it, bin_of(q), v[q]);
+        } else {
+          item[n + o] = it;
+          bin[n + o] = bin_of(q);
+          val[n + o] = (float)v[q];
+        }
+      }
+    }
+    if (!direct) n += total;
+  }
+};
+
 // Row units per wavefront step: RPW rows of P points.
 template <int P>
 __host__ __device__ constexpr int stream_rpw() { return 64 / groups_per_col<P>(); }
@@ -791,35 +882,7 @@ __global__ void __launch_bounds__(256) k_tmpl_b_stream(TmplArgs ta, int ntmpl, c
       for (int r = 0; r < R1; ++r) load_stream(p + 2 * (lofs + G * b + NB1 * r), ca[b][r], cb[b][r]);
   };
 
-  auto emit = [&](unsigned long long slot, int item, int bin, T v) {
-    if (slot < (unsigned long long)oa.capacity) {
-      const int t = ta.t0 + item;
-      const int skyl = t / ta.nfdot;
-      CandEntry ce;
-      ce.search = search;
-      ce.segment = oa.segment;
-      ce.sky = ta.sky0 + skyl;
-      ce.fdot_idx = t - skyl * ta.nfdot;
-      ce.bin = bin;
-      ce.pad = 0;
-      ce.twoF = (double)v;
-      oa.cand[slot] = ce;
-    }
-  };
-  // one atomic reserves the slots of all staged candidates
-  int nstaged = 0;
-  auto flush = [&]() {
-    if (nstaged == 0) return;
-    stage_sync<true>();
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(oa.count, (unsigned long long)nstaged);
-    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)base);
-    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(base >> 32));
-    base = ((unsigned long long)hi << 32) | lo;
-    if (lane < nstaged) emit(base + lane, st_item[wave][lane], st_bin[wave][lane], (T)st_val[wave][lane]);
-    stage_sync<true>();
-    nstaged = 0;
-  };
+  WaveStage stg{st_item[wave], st_bin[wave], st_val[wave]};
 
   // Wavefront w takes units w, w + nw, w + 2 nw, ...: the grid is about one resident
   // round of wavefronts, so the rows being read at any time form one contiguous window.
@@ -875,44 +938,11 @@ __global__ void __launch_bounds__(256) k_tmpl_b_stream(TmplArgs ta, int ntmpl, c
           if (MODE == 2 && inr) srow[k - oa.k_min] = (float)v;
           if (inr && v > thr) mask |= 1u << (b * ROUT + r);
         }
-      if (__ballot(mask != 0)) {
-        int off[NOUT];
-        int total = 0;
-#pragma unroll
-        for (int q = 0; q < NOUT; ++q) {
-          const unsigned long long bi = __ballot((mask >> q) & 1u);
-          off[q] = total + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bi >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo((unsigned)bi, 0u));
-          total += __popcll(bi);
-        }
-        if (nstaged + total > STAGE_CAP) flush();
-        if (total > STAGE_CAP) {
-          // a burst larger than the staging buffer goes straight out
-          unsigned long long base = 0;
-          if (lane == 0) base = atomicAdd(oa.count, (unsigned long long)total);
-          const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)base);
-          const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(base >> 32));
-          base = ((unsigned long long)hi << 32) | lo;
-#pragma unroll
-          for (int q = 0; q < NOUT; ++q)
-            if ((mask >> q) & 1u)
-              emit(base + (unsigned long long)off[q], item, ta.Q * (g + G * (q / ROUT) + NSL * (q % ROUT)) + k2,
-                   val[q]);
-        } else {
-#pragma unroll
-          for (int q = 0; q < NOUT; ++q)
-            if ((mask >> q) & 1u) {
-              const int e = nstaged + off[q];
-              st_item[wave][e] = item;
-              st_bin[wave][e] = ta.Q * (g + G * (q / ROUT) + NSL * (q % ROUT)) + k2;
-              st_val[wave][e] = (float)val[q];
-            }
-          nstaged += total;
-        }
-      }
+      stg.add<false>(oa, ta, search, lane, mask, val, item,
+                     [&](int q) { return ta.Q * (g + G * (q / ROUT) + NSL * (q % ROUT)) + k2; });
     }
   }
-  if constexpr (MODE != 1) flush();
+  if constexpr (MODE != 1) stg.flush(oa, ta, search, lane);
 }
 
 // ---------------------------------------------------------------- pass B with interbinning (FP32)
@@ -1037,34 +1067,7 @@ __global__ void __launch_bounds__(256) k_tmpl_b_ib(TmplArgs ta, int ntmpl, const
     }
   };
 
-  auto emit = [&](unsigned long long slot, int item, int bin, T v) {
-    if (slot < (unsigned long long)oa.capacity) {
-      const int t = ta.t0 + item;
-      const int skyl = t / ta.nfdot;
-      CandEntry ce;
-      ce.search = search;
-      ce.segment = oa.segment;
-      ce.sky = ta.sky0 + skyl;
-      ce.fdot_idx = t - skyl * ta.nfdot;
-      ce.bin = bin;
-      ce.pad = 0;
-      ce.twoF = (double)v;
-      oa.cand[slot] = ce;
-    }
-  };
-  int nstaged = 0;
-  auto flush = [&]() {
-    if (nstaged == 0) return;
-    stage_sync<true>();
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(oa.count, (unsigned long long)nstaged);
-    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)base);
-    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(base >> 32));
-    base = ((unsigned long long)hi << 32) | lo;
-    if (lane < nstaged) emit(base + lane, st_item[wave][lane], st_bin[wave][lane], (T)st_val[wave][lane]);
-    stage_sync<true>();
-    nstaged = 0;
-  };
+  WaveStage stg{st_item[wave], st_bin[wave], st_val[wave]};
 
   // Even and odd bins of unit V (outputs pa, pb) with the neighbours of its rows in the unit
   // just transformed (outputs fa, fb); `wrap`: that unit is the template's first unit again.
@@ -1141,39 +1144,7 @@ __global__ void __launch_bounds__(256) k_tmpl_b_ib(TmplArgs ta, int ntmpl, const
         if (MODE == 2 && inr) srow[k - oa.k_min] = (float)val[v];
         if (inr && val[v] > thr) mask |= 1u << v;
       }
-      if (__ballot(mask != 0)) {
-        // two passes over the ballots (count, then place) keep no per-value offsets
-        int tot = 0;
-#pragma unroll
-        for (int q = 0; q < NV; ++q) tot += __popcll(__ballot((mask >> q) & 1u));
-        if (nstaged + tot > STAGE_CAP) flush();
-        const bool direct = tot > STAGE_CAP;   // a burst larger than the staging area goes straight out
-        unsigned long long base = 0;
-        if (direct) {
-          if (lane == 0) base = atomicAdd(oa.count, (unsigned long long)tot);
-          const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)base);
-          const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(base >> 32));
-          base = ((unsigned long long)hi << 32) | lo;
-        }
-        int run = 0;
-#pragma unroll
-        for (int q = 0; q < NV; ++q) {
-          const unsigned long long bi = __ballot((mask >> q) & 1u);
-          const int off = run + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bi >> 32),
-                                                               __builtin_amdgcn_mbcnt_lo((unsigned)bi, 0u));
-          if ((mask >> q) & 1u) {
-            if (direct) {
-              emit(base + (unsigned long long)off, item, bin_of(q), val[q]);
-            } else {
-              st_item[wave][nstaged + off] = item;
-              st_bin[wave][nstaged + off] = bin_of(q);
-              st_val[wave][nstaged + off] = (float)val[q];
-            }
-          }
-          run += __popcll(bi);
-        }
-        if (!direct) nstaged += tot;
-      }
+      stg.add<true>(oa, ta, search, lane, mask, val, item, bin_of);
     }
   };
 
@@ -1221,7 +1192,7 @@ __global__ void __launch_bounds__(256) k_tmpl_b_ib(TmplArgs ta, int ntmpl, const
     u0 = n_u0;
     j = n_j;
   }
-  if constexpr (MODE != 1) flush();
+  if constexpr (MODE != 1) stg.flush(oa, ta, search, lane);
 }
 
 // Count of candidates before a launch (read by the patch capture after it).
