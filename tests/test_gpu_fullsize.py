@@ -8,6 +8,7 @@
            drained set stays small (the launch configuration is that of the benchmark;
            only the threshold differs); sampled templates, including the loudest
            template of every injection, are checked against the oracle.
+* batched with interbinning: the same, against the oracle's interbinned transform.
 Tolerances are those of the other parity tests (1e-4 relative, floor 4; key sets equal
 outside a 1e-4 x threshold guard band).
 """
@@ -16,6 +17,7 @@ import pytest
 import torch as _torch  # noqa: F401  (first import on a fresh box is slow)
 
 import synth
+from oracle import fstat_oracle as ora
 from tests.gpu_util import compare_candidates, dev, make_plan, note, oracle_spectrum
 
 pytestmark = pytest.mark.gpu
@@ -29,14 +31,20 @@ def torch():
     return t
 
 
-def _check_templates(seg, w, recs, keys, picks, thr):
+def _interbinned_spectrum(seg, alpha, delta, fdot, nfft):
+    sky = ora.sky_stage(seg, float(alpha[0]), float(delta[0]), nfft)
+    return np.array([[ora.template_two_f_interbin(seg, sky, float(fdot[0]), nfft)]])
+
+
+def _check_templates(seg, w, recs, keys, picks, thr, interbinning=False):
     nfft = synth.nfft_for(seg.n)
+    spectrum = _interbinned_spectrum if interbinning else oracle_spectrum
     worst = 0.0
     for (i, s) in picks:
         m = (keys["sky"] == i) & (keys["fdot_idx"] == s)
         key3 = np.stack([np.zeros(int(m.sum()), dtype=np.int64), np.zeros(int(m.sum()), dtype=np.int64),
                          keys["bin"][m]], 1)
-        ref = oracle_spectrum(seg, w.alpha[i:i + 1], w.delta[i:i + 1], w.fdot[s:s + 1], nfft)
+        ref = spectrum(seg, w.alpha[i:i + 1], w.delta[i:i + 1], w.fdot[s:s + 1], nfft)
         ng, no, flips, mism, err = compare_candidates(key3, recs["twoF"][m], ref, thr, 1e-4)
         note(f"template (sky {i}, fdot {s}): gpu {ng} oracle {no} flips {flips} mismatches {len(mism)} err {err:.2e}")
         assert not mism and err < 1e-4
@@ -62,14 +70,15 @@ def test_full_workload_plain_path_sampled_parity(torch):
     _check_templates(seg, w, recs, keys, picks, w.threshold)
 
 
-def test_batched_workload_full_size_sampled_parity(torch):
+@pytest.mark.parametrize("ib", [0, 1])
+def test_batched_workload_full_size_sampled_parity(torch, ib):
     from paper_1410_3677_amd import fstat as F
     w = synth.workload("batched")
     seg = w.segments[0]
     thr = 40.0
-    note(f"batched workload at full size: {len(w.alpha)} x {len(w.fdot)} templates, 2F > {thr}")
+    note(f"batched workload at full size: {len(w.alpha)} x {len(w.fdot)} templates, 2F > {thr}, interbinning={ib}")
     plan = F.Plan([F.segment_to_device(seg)], workspace_from_torch=False, threshold_2F=thr,
-                  candidate_capacity=1 << 25)
+                  candidate_capacity=1 << 25, interbinning=ib)
     plan.autotune(0, budget_ms=3000.0)
     info = plan.info(0)
     note(f"launch configuration {info}")
@@ -91,5 +100,5 @@ def test_batched_workload_full_size_sampled_parity(torch):
     rng = np.random.default_rng(72)
     picks += [(int(rng.integers(len(w.alpha))), int(rng.integers(len(w.fdot)))) for _ in range(2)]
     assert len(picks) >= 3
-    _check_templates(seg, w, recs, keys, picks, thr)
+    _check_templates(seg, w, recs, keys, picks, thr, interbinning=bool(ib))
     plan.destroy()
