@@ -94,7 +94,7 @@ struct fstat_plan_s {
   bool fp64 = false;
   int device = 0;
   int Sb = 1, B = 1;           // skies per batch, templates per launch
-  int variant_a = 0;           // pass A kernel variant (0 sequential series, 1 paired)
+  int variant_a = 1;           // pass A kernel variant (0 sequential series, 1 paired; the autotuner may pick 0)
   int variant_b = 1;           // pass B kernel variant (0 row tiles, 1 streaming wavefronts)
   int n_cu = 256;              // compute units of the device
   size_t cx_bytes = 8;
