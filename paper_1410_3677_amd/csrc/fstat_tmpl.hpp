@@ -398,6 +398,8 @@ __global__ void __launch_bounds__((tmpl_nt_a<T, Q>())) k_tmpl_a(TmplArgs ta, con
       }
     }
   }
+  // series a's outputs wait in registers so that both series leave as (a, b) pairs
+  cx<T> ka[PBL][RL];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     if (s == 1) __syncthreads();  // series a's last stage has read the tile
@@ -413,7 +415,8 @@ __global__ void __launch_bounds__((tmpl_nt_a<T, Q>())) k_tmpl_a(TmplArgs ta, con
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
         const unsigned o = (unsigned)(j + NSL * r) * (unsigned)ta.P + (unsigned)j1;
-        at32(out, 2 * o + s) = cmul(v[b][r], tw[b][r]);
+        if (s == 0) ka[b][r] = cmul(v[b][r], tw[b][r]);
+        else store_pair(out, o, ka[b][r], cmul(v[b][r], tw[b][r]));
       }
     }
   }
