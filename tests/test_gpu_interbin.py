@@ -184,3 +184,27 @@ def test_interbinning_needs_mixed_precision_and_a_long_enough_transform(torch):
     with pytest.raises(F.FstatError) as ei:
         make_plan([seg], interbinning=1)
     assert ei.value.status == F.E_INVAL
+
+
+def test_ragged_segments_in_one_call_equal_separate_plans(torch):
+    """All segments in one call (segment = -1): each segment has its own template length
+    (nfft/2 from 2^15 to 2^18) in one workspace sized for the longest."""
+    w = synth.workload("ragged")
+    segs = w.segments[:5]
+    note("interbinning, ragged: " + ", ".join(f"n={s.n}" for s in segs))
+    al, de, fd = dev(w.alpha[:3]), dev(w.delta[:3]), dev(w.fdot[:6])
+    plan = make_plan(segs, interbinning=1)
+    plan.search_batch(-1, al, de, fd)
+    r_all, k_all, n_all = plan.candidates()
+    assert n_all > 0
+    for si, seg in enumerate(segs):
+        one = make_plan([seg], interbinning=1)
+        one.search_batch(0, al, de, fd)
+        r1, k1, n1 = one.candidates()
+        m = k_all["segment"] == si
+        assert int(m.sum()) == n1, (si, int(m.sum()), n1)
+        np.testing.assert_array_equal(k_all["sky"][m], k1["sky"])
+        np.testing.assert_array_equal(k_all["fdot_idx"][m], k1["fdot_idx"])
+        np.testing.assert_array_equal(k_all["bin"][m], k1["bin"])
+        np.testing.assert_allclose(r_all["twoF"][m], r1["twoF"], rtol=1e-6, atol=0)
+        one.destroy()
