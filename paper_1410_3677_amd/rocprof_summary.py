@@ -1,7 +1,9 @@
 """Summaries of rocprofv3 result databases (SQLite, as written by rocprofv3 on ROCm 7).
 
-    python -m paper_1410_3677_amd.rocprof_summary trace RESULTS.db [--match k_tmpl]
-        per-kernel dispatch statistics (calls, total, average, min, max duration) as markdown
+    python -m paper_1410_3677_amd.rocprof_summary trace RESULTS.db [--match k_tmpl] [--last N]
+        per-kernel dispatch statistics (calls, total, average, min, max duration) as markdown;
+        --last N: only the last N dispatches of each kernel (for instance the timed steps
+        of a run that starts with warm-up steps)
 
     python -m paper_1410_3677_amd.rocprof_summary traffic FETCH.db WRITE.db --copy-bytes B \
             --copy-match MulFunctor --templates-per-launch T [--kernel KEY=SUBSTRING ...] [--json OUT]
@@ -24,10 +26,20 @@ def _short(name: str) -> str:
     return n.replace("void ", "").replace("fstat::", "")
 
 
-def trace(db: str, match: str = ""):
+def trace(db: str, match: str = "", last: int = 0):
     c = sqlite3.connect(db)
-    rows = c.execute("select name, count(*), sum(duration), avg(duration), min(duration), max(duration) "
-                     "from kernels group by name order by sum(duration) desc").fetchall()
+    if last > 0:
+        per = collections.defaultdict(list)
+        for name, start, dur in c.execute("select name, start, duration from kernels order by start"):
+            per[name].append(dur)
+        rows = []
+        for name, d in per.items():
+            d = d[-last:]
+            rows.append((name, len(d), sum(d), sum(d) / len(d), min(d), max(d)))
+        rows.sort(key=lambda r: -r[2])
+    else:
+        rows = c.execute("select name, count(*), sum(duration), avg(duration), min(duration), max(duration) "
+                         "from kernels group by name order by sum(duration) desc").fetchall()
     out = ["| kernel | calls | total (us) | avg (us) | min (us) | max (us) |", "|---|---|---|---|---|---|"]
     for name, n, tot, avg, mn, mx in rows:
         if match and match not in name:
@@ -79,6 +91,7 @@ def main(argv=None):
     t = sub.add_parser("trace")
     t.add_argument("db")
     t.add_argument("--match", default="")
+    t.add_argument("--last", type=int, default=0)
     f = sub.add_parser("traffic")
     f.add_argument("fetch_db")
     f.add_argument("write_db")
@@ -92,7 +105,7 @@ def main(argv=None):
                    help="kernel variants of the profiled plan: pass_a_variant + 2 pass_b_variant")
     a = ap.parse_args(argv)
     if a.cmd == "trace":
-        print(trace(a.db, a.match))
+        print(trace(a.db, a.match, a.last))
     else:
         keys = [tuple(x.split("=", 1)) for x in a.kernel] or None
         res = traffic(a.fetch_db, a.write_db, a.copy_bytes, a.copy_match, a.templates_per_launch, keys)
