@@ -1596,7 +1596,7 @@ fstat_status fstat_autotune(fstat_plan_t plan, int32_t segment, double budget_ms
   std::vector<Cand> cands;
   for (int v = 0; v < 2; ++v)
     for (int b : {64, 128, 256, 512})
-      for (int sb : {8, 16})
+      for (int sb : {16, 32})
         if (!plan->opt.workspace_budget_bytes || layout(plan, sb, b, false) <= plan->opt.workspace_budget_bytes)
           cands.push_back({b, sb, v});
   const int B0 = plan->B, Sb0 = plan->Sb, V0 = plan->variant_a;

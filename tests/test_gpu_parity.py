@@ -343,7 +343,7 @@ def test_autotune_writes_cache_and_plans_pick_it_up(torch, full, tmp_path):
     info = plan.autotune(0, budget_ms=600.0)
     note(f"tuned {info}")
     assert info["templates_per_launch"] in (64, 128, 256, 512)
-    assert info["skies_per_batch"] in (8, 16) and info["pass_a_variant"] in (0, 1)
+    assert info["skies_per_batch"] in (16, 32) and info["pass_a_variant"] in (0, 1)
     line = open(cache).read().split()
     assert len(line) == 6 and int(line[1]) == synth.nfft_for(seg.n)
     again = F.Plan([F.segment_to_device(seg)], tuning_cache_path=cache)
