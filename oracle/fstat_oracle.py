@@ -43,6 +43,23 @@ neighbours as c (X_k - X_{k+1}), with c chosen so that a sinusoid midway
 between two bins, over the N nonzero samples, comes out exactly (at N = nfft/2
 this is the classic interbinning weight, about pi/4).
 
+Lattice grid (Sect. 2: the grid generating matrix and the integers n, m, s;
+Sect. 1.1: grid points reconciled with the Fourier frequencies, resampling once
+per sky position), read as follows.  Grid points are the integer combinations
+k M0 + s M1 + n M2 + m M3 of the rows of a 4x4 matrix M over the phase
+parameters (w0, w1, w2, w3): w0 = 2 pi f dt (frequency above f_off, radians per
+sample), w1 = pi fdot dt^2 (spindown phase w1 j^2 at sample j), and
+(w2, w3) = W (x_e, y_e), the source direction's two components in the ecliptic
+plane (x_e toward the vernal equinox) scaled by W = 2 pi f_ref (1 AU / c).
+Row 0 is the frequency vector (along w0 only, a whole number of Fourier bins),
+row 1 the spindown vector (no sky components), rows 2 and 3 the sky vectors.
+The third ecliptic component is +-sqrt(1 - x_e^2 - y_e^2) (one hemisphere per
+sign); the obliquity rotates ecliptic axes to equatorial ones.  For every
+(s, n, m) the FFT evaluates the frequencies w0(s, n, m) + 2 pi k / nfft: the
+series is demodulated by the template's spindown phase and by the fraction u of
+a bin that the grid's frequencies lie above the Fourier bins, and bin k of the
+transform is the frequency f_off + (k + u) / (nfft dt).
+
 Every floating-point step is FP64.  numpy's FFT and scipy's banded solver are
 used as library primitives.
 """
@@ -275,6 +292,97 @@ def template_two_f_interbin(seg, sky, fdot: float, nfft: int, k_min: int = 0, k_
     return two_f(fa, fb, sky["A"], sky["B"], seg.n, seg.sigma2)
 
 
+# -------------------------------------------------------------- lattice grid
+AU_SECONDS = 149597870700.0 / 299792458.0   # light travel time over one astronomical unit, s
+SHIFT_SNAP = 1e-6                           # a grid frequency within this many bins below a bin is on it
+
+
+def lattice_sky_scale(f_ref: float) -> float:
+    """W = 2 pi f_ref (1 AU / c): radius, in the sky coordinates (w2, w3), of the whole sky."""
+    return 2.0 * math.pi * f_ref * AU_SECONDS
+
+
+def ecliptic_to_equatorial(xe: float, ye: float, ze: float, eps: float):
+    """Rotation by the obliquity about the vernal-equinox axis, ecliptic to equatorial axes."""
+    ce, se = math.cos(eps), math.sin(eps)
+    return xe, ce * ye - se * ze, se * ye + ce * ze
+
+
+def lattice_sky_position(M: np.ndarray, n: int, m: int, hemisphere: int, eps: float, f_ref: float):
+    """Sky loop, 'sky position recovered' (Sect. 2): integers (n, m) to (alpha, delta),
+    or None when the point (w2, w3) = n M2 + m M3 lies outside the sky's disk."""
+    w = lattice_sky_scale(f_ref)
+    w2 = n * float(M[2, 2]) + m * float(M[3, 2])
+    w3 = n * float(M[2, 3]) + m * float(M[3, 3])
+    xe = w2 / w
+    ye = w3 / w
+    r2 = xe * xe + ye * ye
+    if r2 > 1.0:
+        return None
+    ze = hemisphere * math.sqrt(1.0 - r2)
+    x, y, z = ecliptic_to_equatorial(xe, ye, ze, eps)
+    alpha = math.atan2(y, x)
+    if alpha < 0.0:
+        alpha += 2.0 * math.pi
+    return alpha, math.asin(min(1.0, max(-1.0, z)))
+
+
+def lattice_sky_range(M: np.ndarray, f_ref: float):
+    """Smallest box [n_lo, n_hi] x [m_lo, m_hi] holding every (n, m) on the sky: the disk
+    |(w2, w3)| <= W mapped through the inverse of the sky rows."""
+    w = lattice_sky_scale(f_ref)
+    det = float(M[2, 2]) * float(M[3, 3]) - float(M[2, 3]) * float(M[3, 2])
+    n_hi = int(math.floor(w * math.hypot(float(M[3, 2]), float(M[3, 3])) / abs(det)))
+    m_hi = int(math.floor(w * math.hypot(float(M[2, 2]), float(M[2, 3])) / abs(det)))
+    return -n_hi, n_hi, -m_hi, m_hi
+
+
+def lattice_sky_points(M: np.ndarray, box, hemisphere: int, eps: float, f_ref: float):
+    """Every (n, m) of the box on the sky, in order of (n, m): rows (n, m, alpha, delta,
+    w0, w1), where (w0, w1) are the frequency and spindown parts of n M2 + m M3."""
+    n_lo, n_hi, m_lo, m_hi = box
+    rows = []
+    for n in range(n_lo, n_hi + 1):
+        for m in range(m_lo, m_hi + 1):
+            p = lattice_sky_position(M, n, m, hemisphere, eps, f_ref)
+            if p is None:
+                continue
+            rows.append((n, m, p[0], p[1], n * float(M[2, 0]) + m * float(M[3, 0]),
+                         n * float(M[2, 1]) + m * float(M[3, 1])))
+    return rows
+
+
+def lattice_template(M: np.ndarray, s: int, w0_sky: float, w1_sky: float, nfft: int):
+    """(w1, u) of the template (s, sky): its spindown phase coefficient and the shift, in
+    bins of the nfft grid, of its frequencies above the Fourier bins."""
+    w0 = s * float(M[1, 0]) + w0_sky
+    w1 = s * float(M[1, 1]) + w1_sky
+    x = w0 * (nfft / (2.0 * math.pi))
+    return w1, x - math.floor(x + SHIFT_SNAP)
+
+
+def lattice_demodulate(zt: np.ndarray, w1: float, u: float, nfft: int) -> np.ndarray:
+    """Multiply by exp(-i (w1 j^2 + 2 pi u j / nfft)): the spindown phase and the grid's
+    frequency shift, so that bin k of the transform is frequency (k + u) / (nfft dt)."""
+    j = np.arange(zt.shape[0], dtype=np.float64)
+    cyc = w1 * j * j / (2.0 * math.pi) + u * j / nfft
+    cyc = cyc - np.floor(cyc)
+    return zt * np.exp(-2j * math.pi * cyc)
+
+
+def lattice_template_two_f(seg, sky, w1: float, u: float, nfft: int, k_min: int = 0, k_max: int = -1,
+                           full: bool = False, interbin: bool = False) -> np.ndarray:
+    """2F over bins [k_min, k_max) of one lattice template (zero-padded or interbinned)."""
+    if k_max < 0:
+        k_max = nfft // 2
+    tr = interbinned_transform if interbin else fourier_transform
+    fa = tr(lattice_demodulate(sky["za_t"], w1, u, nfft), nfft)[k_min:k_max]
+    fb = tr(lattice_demodulate(sky["zb_t"], w1, u, nfft), nfft)[k_min:k_max]
+    if full:
+        return two_f_full(fa, fb, sky["A"], sky["B"], sky["C"], seg.n, seg.sigma2)
+    return two_f(fa, fb, sky["A"], sky["B"], seg.n, seg.sigma2)
+
+
 # ---------------------------------------------------------------- candidates
 CANDIDATE_DTYPE = np.dtype([("segment", np.int32), ("sky", np.int32), ("fdot_idx", np.int32),
                             ("bin", np.int32), ("f_hz", np.float64), ("fdot", np.float64),
@@ -312,5 +420,35 @@ def search(seg, alpha, delta, fdot, threshold: float, nfft: int = 0, k_min: int 
                 kk = int(k) + k_min
                 rows.append((segment_index, i, s, kk, seg.f_off + kk / (nfft * seg.dt),
                              float(fdot[s]), float(alpha[i]), float(delta[i]), float(tf[k])))
+    out = np.array(rows, dtype=CANDIDATE_DTYPE)
+    return np.sort(out, order=["segment", "sky", "fdot_idx", "bin"])
+
+
+def search_lattice(seg, M, points, s_lo: int, s_hi: int, threshold: float, nfft: int = 0,
+                   k_min: int = 0, k_max: int = -1, segment_index: int = 0, full: bool = False,
+                   interbin: bool = False, skies=None, spins=None):
+    """Threshold crossings over lattice templates: the sky points `points` (rows of
+    lattice_sky_points) times the spindown integers s_lo..s_hi.  The key's spindown index
+    is s - s_lo; a candidate's frequency is f_off + (bin + u) / (nfft dt) and its spindown
+    w1 / (pi dt^2).  `skies` / `spins` restrict the search to subsets (same indices)."""
+    M = np.asarray(M, dtype=np.float64).reshape(4, 4)
+    if nfft <= 0:
+        nfft = default_nfft(seg.n)
+    if k_max < 0:
+        k_max = nfft // 2
+    skies = range(len(points)) if skies is None else skies
+    spins = range(s_hi - s_lo + 1) if spins is None else spins
+    rows = []
+    for i in skies:
+        _, _, alpha, delta, w0_sky, w1_sky = points[i]
+        sky = sky_stage(seg, alpha, delta, nfft)
+        for si in spins:
+            w1, u = lattice_template(M, s_lo + si, w0_sky, w1_sky, nfft)
+            tf = lattice_template_two_f(seg, sky, w1, u, nfft, k_min, k_max, full, interbin)
+            fdot = w1 / (math.pi * seg.dt * seg.dt)
+            for k in np.nonzero(tf > threshold)[0]:
+                kk = int(k) + k_min
+                rows.append((segment_index, i, si, kk, seg.f_off + (kk + u) / (nfft * seg.dt),
+                             fdot, alpha, delta, float(tf[k])))
     out = np.array(rows, dtype=CANDIDATE_DTYPE)
     return np.sort(out, order=["segment", "sky", "fdot_idx", "bin"])

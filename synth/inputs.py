@@ -89,6 +89,35 @@ def spindown_grid(nfdot: int, fdot_min: float = -1e-9) -> np.ndarray:
     return fdot_min * np.arange(nfdot, dtype=np.float64) / (nfdot - 1)
 
 
+def lattice_matrix(nfft: int, dt: float, f_ref: float, sky_points: int, fdot_step: float, seed: int,
+                   freq_bins: int = 1) -> np.ndarray:
+    """A 4x4 grid generating matrix of the constrained form, standing in for the grid file.
+
+    Rows over the phase parameters (w0, w1, w2, w3) (frequency in radians per sample,
+    spindown phase coefficient, two ecliptic-plane sky coordinates of radius
+    2 pi f_ref AU/c): row 0 = `freq_bins` Fourier bins of the nfft grid along w0; row 1 =
+    the spindown step pi fdot_step dt^2 with a random fraction of a bin along w0; rows 2
+    and 3 = a hexagonal sky lattice, rotated at random, with about `sky_points` points
+    per hemisphere, each with random fractions of a bin and of a spindown step.
+    """
+    rng = np.random.default_rng(seed)
+    bin_w = 2.0 * math.pi / nfft
+    w_sky = 2.0 * math.pi * f_ref * AU_LS
+    h = w_sky * math.sqrt(2.0 * math.pi / (math.sqrt(3.0) * sky_points))
+    rot = float(rng.uniform(0.0, 2.0 * math.pi))
+    w1_step = math.pi * fdot_step * dt * dt
+    M = np.zeros((4, 4), dtype=np.float64)
+    M[0, 0] = freq_bins * bin_w
+    M[1, 0] = float(rng.uniform(0.0, 1.0)) * bin_w
+    M[1, 1] = w1_step
+    for r, ang in ((2, rot), (3, rot + math.pi / 3.0)):
+        M[r, 0] = float(rng.uniform(0.0, 1.0)) * bin_w
+        M[r, 1] = float(rng.uniform(-0.5, 0.5)) * w1_step
+        M[r, 2] = h * math.cos(ang)
+        M[r, 3] = h * math.sin(ang)
+    return M
+
+
 # --- injected signals ----------------------------------------------------------
 @dataclasses.dataclass
 class Injection:

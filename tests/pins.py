@@ -252,3 +252,81 @@ def ib_direct_sum_error(n: int = 500, nfft: int = 2048, seed: int = 12) -> float
 def ib_weight_error() -> float:
     """Deviation of the full-length weight from the classic pi/4."""
     return abs(oracle.interbin_weight(4096, 4096) - math.pi / 4)
+
+
+# ---- lattice grid ------------------------------------------------------------------------
+def lattice_setup(n: int, dt: float = 2.0, f_off: float = 100.0, sky_points: int = 40, seed: int = 31,
+                  fdot_step: float = -2e-10):
+    """(nfft, f_ref, M, north-hemisphere sky points) of a synthetic constrained lattice."""
+    nfft = oracle.default_nfft(n)
+    f_ref = f_off + 0.5 / dt
+    M = synth.lattice_matrix(nfft, dt, f_ref, sky_points, fdot_step, seed)
+    box = oracle.lattice_sky_range(M, f_ref)
+    return nfft, f_ref, M, oracle.lattice_sky_points(M, box, +1, synth.OBLIQUITY, f_ref)
+
+
+def lattice_injection(n: int = synth.N_FULL, k_frac: float = 0.113):
+    """A noiseless SNR-10 source exactly at a lattice grid point whose frequencies lie a
+    fraction u in [0.3, 0.7] of a bin above the Fourier bins and whose spindown carries a
+    sky offset.  Returns (2F of its template with the shift, with u = 0, with -u, all at
+    bin k0; the closed form; the peak bin with the shift; k0), or None when no grid point
+    near the middle of the lattice has such a shift."""
+    dt, f_off = 2.0, 100.0
+    nfft, f_ref, M, pts = lattice_setup(n, dt, f_off)
+    # the source's parameters straight from the grid point s M1 + n M2 + m M3
+    pick = None
+    for p in pts:
+        n_, m_ = p[0], p[1]
+        for s in range(-4, 5):
+            w0 = s * M[1, 0] + n_ * M[2, 0] + m_ * M[3, 0]
+            w1 = s * M[1, 1] + n_ * M[2, 1] + m_ * M[3, 1]
+            u = (w0 / (2.0 * math.pi) * nfft) % 1.0
+            if 0.3 < u < 0.7 and n_ * M[2, 1] + m_ * M[3, 1] != 0.0 and w1 < 0.0:
+                pick = (p, s, w1, u)
+                break
+        if pick:
+            break
+    if pick is None:
+        return None
+    p, s, w1, u = pick
+    k0 = int(round(k_frac * nfft))
+    inj = synth.Injection(f=(k0 + u) / (nfft * dt), fdot=w1 / (math.pi * dt * dt), alpha=p[2], delta=p[3],
+                          psi=0.9, cosi=0.2, phi0=1.3, snr=10.0)
+    seg = synth.make_segment(n, dt, f_off, 1.0, None, [inj])
+    sky = oracle.sky_stage(seg, p[2], p[3], nfft)
+    # the oracle's template for the same integers
+    tw1, tu = oracle.lattice_template(M, s, p[4], p[5], nfft)
+    tf = oracle.lattice_template_two_f(seg, sky, tw1, tu, nfft)
+    tf0 = oracle.lattice_template_two_f(seg, sky, tw1, 0.0, nfft)
+    tfm = oracle.lattice_template_two_f(seg, sky, tw1, -tu, nfft)
+    cf = closed_form_two_f(seg.injections[0], sky["A"], sky["B"], sky["C"], n, seg.sigma2)
+    return float(tf[k0]), float(tf0[k0]), float(tfm[k0]), float(cf), int(np.argmax(tf)), k0
+
+
+def lattice_doppler_amplitude_error(seed: int = 5, trials: int = 8) -> float:
+    """The sky coordinates (w2, w3) / (2 pi f_ref) must equal the amplitudes of the annual
+    Roemer delay n.r(t) along cos and sin of the orbital longitude (a year of the
+    synthetic ephemeris, least squares with the daily term); worst relative error."""
+    f_ref = 100.25
+    w = 2.0 * math.pi * f_ref
+    nfft = 8192
+    M = synth.lattice_matrix(nfft, 2.0, f_ref, 30, -2e-10, seed)
+    box = oracle.lattice_sky_range(M, f_ref)
+    pts = [p for h in (+1, -1) for p in oracle.lattice_sky_points(M, box, h, synth.OBLIQUITY, f_ref)]
+    rng = np.random.default_rng(seed)
+    dt = 3600.0
+    nt = int(366 * 86400 / dt)
+    r = synth.ephemeris(nt, dt)
+    t = np.arange(nt) * dt
+    lo = synth.OMEGA_O * t + synth.ORBIT_PHI_O
+    th = synth.OMEGA_R * t + synth.DET_PHI_R
+    basis = np.stack([np.cos(lo), np.sin(lo), np.cos(th), np.sin(th), np.ones(nt)], axis=1)
+    worst = 0.0
+    for i in rng.choice(len(pts), size=min(trials, len(pts)), replace=False):
+        n_, m_, alpha, delta = pts[i][:4]
+        k = np.array([math.cos(delta) * math.cos(alpha), math.cos(delta) * math.sin(alpha), math.sin(delta)])
+        coef = np.linalg.lstsq(basis, k @ r, rcond=None)[0]
+        w2 = n_ * M[2, 2] + m_ * M[3, 2]
+        w3 = n_ * M[2, 3] + m_ * M[3, 3]
+        worst = max(worst, abs(w * coef[0] - w2) / abs(w * synth.AU_LS), abs(w * coef[1] - w3) / abs(w * synth.AU_LS))
+    return worst

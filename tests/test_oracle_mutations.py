@@ -165,3 +165,58 @@ def test_interbinning_weight_for_the_full_length_is_caught(monkeypatch):
     # the classic pi/4 used although the data fill only part of the transform
     monkeypatch.setattr(fo, "interbin_weight", lambda n, length: math.pi / 4)
     assert pins.ib_midway_error() > 0.05
+
+
+# ---- lattice grid -------------------------------------------------------------------------
+def _lattice_injection_ok():
+    r = pins.lattice_injection()
+    if r is None:
+        return False
+    got, no_shift, neg_shift, cf, peak, k0 = r
+    return peak == k0 and abs(got - cf) / cf < 1e-3
+
+
+def test_lattice_pins_pass_on_unmodified_oracle():
+    assert _lattice_injection_ok()
+    assert pins.lattice_doppler_amplitude_error() < 1e-6
+
+
+def test_obliquity_rotated_the_wrong_way_is_caught(monkeypatch):
+    orig = fo.ecliptic_to_equatorial
+    monkeypatch.setattr(fo, "ecliptic_to_equatorial", lambda x, y, z, eps: orig(x, y, z, -eps))
+    assert pins.lattice_doppler_amplitude_error() > 1e-3
+
+
+def test_swapped_sky_coordinates_are_caught(monkeypatch):
+    orig = fo.lattice_sky_position
+
+    def wrong(M, n, m, h, eps, f_ref):
+        M2 = M.copy()
+        M2[:, [2, 3]] = M[:, [3, 2]]
+        return orig(M2, n, m, h, eps, f_ref)
+    monkeypatch.setattr(fo, "lattice_sky_position", wrong)
+    assert pins.lattice_doppler_amplitude_error() > 1e-3
+
+
+def test_dropped_frequency_shift_is_caught(monkeypatch):
+    orig = fo.lattice_template
+    monkeypatch.setattr(fo, "lattice_template", lambda *a: (orig(*a)[0], 0.0))
+    assert not _lattice_injection_ok()
+
+
+def test_frequency_shift_of_the_wrong_sign_is_caught(monkeypatch):
+    orig = fo.lattice_demodulate
+    monkeypatch.setattr(fo, "lattice_demodulate", lambda zt, w1, u, nfft: orig(zt, w1, -u, nfft))
+    assert not _lattice_injection_ok()
+
+
+def test_spindown_coefficient_off_by_two_is_caught(monkeypatch):
+    orig = fo.lattice_demodulate
+    monkeypatch.setattr(fo, "lattice_demodulate", lambda zt, w1, u, nfft: orig(zt, 2.0 * w1, u, nfft))
+    assert not _lattice_injection_ok()
+
+
+def test_sky_offset_of_the_spindown_dropped_is_caught(monkeypatch):
+    orig = fo.lattice_template
+    monkeypatch.setattr(fo, "lattice_template", lambda M, s, w0, w1, nfft: orig(M, s, w0, 0.0, nfft))
+    assert not _lattice_injection_ok()
