@@ -178,6 +178,66 @@ fstat_status fstat_sky_stages(fstat_plan_t plan, int32_t segment, double alpha, 
                               double* abc, void* za, void* zb, void* ua, void* ub,
                               void* zta, void* ztb, void* stream);
 
+/* ---- Lattice grid (Sect. 2: grid generating matrix, sky loop over the
+ * integers n, m, spindown loop over s; Sect. 1.1: grid points reconciled
+ * with the Fourier frequencies, resampling once per sky position) ----
+ *
+ * Grid points are the integer combinations k M0 + s M1 + n M2 + m M3 of the
+ * rows of M over the phase parameters (w0, w1, w2, w3):
+ *   w0 = 2 pi f dt        frequency above f_off, radians per sample;
+ *   w1 = pi fdot dt^2     spindown: phase w1 j^2 at sample j;
+ *   (w2, w3) = W (x_e, y_e), W = 2 pi f_ref (1 AU / c): the source
+ *                         direction's components in the ecliptic plane,
+ *                         x_e toward the vernal equinox.
+ * dt is the sampling interval of the segment searched.  Row 0 is the
+ * frequency vector: (w_F, 0, 0, 0) with w_F a whole number of bins
+ * 2 pi / nfft of every segment searched.  Row 1 is the spindown vector, with
+ * no sky components.  Rows 2 and 3 are the sky vectors.  A sky point is on
+ * the sky when x_e^2 + y_e^2 <= 1; its third ecliptic component is
+ * hemisphere * sqrt(1 - x_e^2 - y_e^2), and the obliquity epsilon turns
+ * ecliptic axes into equatorial ones. */
+typedef struct {
+  double M[16];      /* row-major 4 x 4: M[4 r + c] is component c of row r */
+  double epsilon;    /* obliquity of the ecliptic, rad */
+  double f_ref;      /* Hz, > 0: scale W of the sky coordinates (the band's upper edge) */
+} fstat_lattice;
+
+/* Host only.  The smallest box n in [box[0], box[1]], m in [box[2], box[3]]
+ * that holds every (n, m) on the sky.  FSTAT_E_INVAL for a NULL argument,
+ * non-finite values or parallel sky rows. */
+fstat_status fstat_lattice_sky_range(const fstat_lattice* lat, int32_t box[4]);
+
+/* Sky loop of the grid (Sect. 2, "sky position recovered"): every (n, m) of
+ * the box (host array, as above) whose point is on the sky, in order of n,
+ * then m, on the hemisphere given (+1 north, -1 south of the ecliptic).
+ * Point i (i < capacity) is written to the device arrays alpha[i], delta[i]
+ * (rad, alpha in [0, 2 pi]), w_freq[i], w_spin[i] (the w0 and w1 components
+ * of n M2 + m M3) and nm[2 i], nm[2 i + 1] (nm may be NULL).  The device
+ * int64 *count receives the number of points on the sky, also when it
+ * exceeds capacity.  At most 2^26 box points.  Asynchronous on `stream`;
+ * the caller owns every array.  FSTAT_E_INVAL for bad arguments. */
+fstat_status fstat_lattice_sky(const fstat_lattice* lat, int32_t hemisphere, const int32_t box[4],
+                               int64_t capacity, double* alpha, double* delta, double* w_freq,
+                               double* w_spin, int32_t* nm, int64_t* count, void* stream);
+
+/* Search of the lattice templates: the nsky sky points of device arrays
+ * alpha, delta, w_freq, w_spin (as written by fstat_lattice_sky) times the
+ * spindown integers s = s_lo .. s_hi, on one segment or on every segment
+ * (segment = -1).  Template (i, s) has spindown phase coefficient
+ * w1 = s M1[1] + w_spin[i] and frequency component w0 = s M1[0] + w_freq[i];
+ * the FFT evaluates the frequencies f_off + (k + u) / (nfft dt), where u is
+ * the fraction of w0 nfft / (2 pi) above the integer below it (a value within
+ * 1e-6 below an integer counts as that integer).  Candidates carry
+ * fdot_idx = s - s_lo, f_hz = f_off + (bin + u) / (nfft dt) and
+ * fdot = w1 / (pi dt^2).  With spectrum NULL, candidates are registered as by
+ * fstat_search_batch; otherwise 2F of one segment is stored to spectrum as by
+ * fstat_twoF_spectrum.  FSTAT_E_INVAL when row 0 or row 1 breaks the
+ * constraints above.  Asynchronous on `stream`. */
+fstat_status fstat_search_lattice(fstat_plan_t plan, int32_t segment, const fstat_lattice* lat,
+                                  const double* alpha, const double* delta, const double* w_freq,
+                                  const double* w_spin, int32_t nsky, int32_t s_lo, int32_t s_hi,
+                                  void* spectrum, void* stream);
+
 /* Per-kernel timing.  When enabled, the plan brackets each launch of the
  * kernel classes below with HIP events on the launch stream;
  * fstat_profile_read waits for them and reports the number of launches and
@@ -283,8 +343,9 @@ fstat_status fstat_plan_vet_candidates(fstat_plan_t plan, void* stream);
 /* Static text for a status code. */
 const char* fstat_strerror(fstat_status status);
 
-/* Text of the last failure on this plan ("" if none); the global text of
- * the last failed fstat_plan when plan is NULL.  Valid until the next call. */
+/* Text of the last failure on this plan ("" if none); with plan NULL, the
+ * global text of the last failed call that has no plan (fstat_plan,
+ * fstat_lattice_sky_range, fstat_lattice_sky).  Valid until the next call. */
 const char* fstat_last_error(fstat_plan_t plan);
 
 #ifdef __cplusplus

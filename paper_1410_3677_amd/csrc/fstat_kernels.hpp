@@ -474,9 +474,46 @@ struct TmplArgs {
   int t0;               // first template of this launch (within the sky batch)
   int sky0;             // global index of the batch's first sky
   double dt;
-  const double* fdot;   // device list
+  const double* fdot;   // device list (explicit spindowns), or NULL on a lattice grid
   long ldzt;            // stride between series in zt
+  // lattice grid (fdot NULL): template (sky, index) has spindown integer s = s_lo + index
+  const double* w_freq; // per sky: w0 component of the sky vectors' combination
+  const double* w_spin; // per sky: w1 component
+  double m10, m11;      // w0 and w1 components of the spindown row
+  double bins_per_rad;  // nfft / (2 pi)
+  int s_lo, nfft;
 };
+
+// Lattice arithmetic shared by the kernels and the host's candidate records, with
+// contraction off so that both round every product and sum the same way.
+// s row + sky: a component of the grid point s M1 + (n M2 + m M3).
+__host__ __device__ inline double lattice_w(int s, double row, double sky) {
+#pragma clang fp contract(off)
+  return (double)s * row + sky;
+}
+
+// Shift u, in bins of the nfft grid, of a template's frequencies above the Fourier bins:
+// the fraction of w0 nfft / (2 pi) above the integer below it, where a value within 1e-6
+// below an integer counts as that integer (u in [-1e-6, 1 - 1e-6)).
+__host__ __device__ inline double lattice_shift_bins(double w0, double bins_per_rad) {
+#pragma clang fp contract(off)
+  const double x = w0 * bins_per_rad;
+  return x - floor(x + 1e-6);
+}
+
+// Spindown chirp of one template in cycles, (c2 j + c1) j at resampled sample j:
+// c2 = fdot dt^2 / 2 for an explicit spindown; on a lattice c2 = w1 / (2 pi) and
+// c1 = u / nfft, the shift that puts the grid's frequencies on the transform's bins.
+__device__ __forceinline__ void template_chirp(const TmplArgs& ta, int skyl, int sidx, double& c2, double& c1) {
+  if (ta.fdot) {
+    c2 = 0.5 * ta.fdot[sidx] * ta.dt * ta.dt;
+    c1 = 0.0;
+  } else {
+    const int sky = ta.sky0 + skyl, s = ta.s_lo + sidx;
+    c2 = lattice_w(s, ta.m11, ta.w_spin[sky]) * (0.5 / M_PI);
+    c1 = lattice_shift_bins(lattice_w(s, ta.m10, ta.w_freq[sky]), ta.bins_per_rad) / (double)ta.nfft;
+  }
+}
 
 // Where pass B puts its results.
 struct OutArgs {
@@ -518,6 +555,75 @@ __device__ __forceinline__ int block_exclusive_scan_n(int v, int* total) {
   }
   *total = all;
   return before + x - v;
+}
+
+// ------------------------------------------------------------ lattice sky loop
+struct LatSkyArgs {
+  double r2x, r2y, r3x, r3y;   // sky components (w2, w3) of rows 2 and 3
+  double r2f, r2s, r3f, r3s;   // their w0 and w1 components
+  double w;                    // W = 2 pi f_ref (1 AU / c)
+  double ce, se;               // cos, sin of the obliquity
+  double hemi;                 // +1 or -1
+  int n_lo, m_lo, mspan;       // box origin and its extent in m
+  long long total, capacity;   // box points; output capacity
+  double *alpha, *delta, *w_freq, *w_spin;
+  int* nm;
+  long long* count;
+};
+
+// Sky loop of the lattice grid: every (n, m) of the box whose point (w2, w3) lies on the
+// sky's disk, numbered in (n, m) order and written at its number.  One workgroup walks
+// the box 256 points at a time (a workgroup scan numbers the points of each step), so
+// the order needs no device-wide synchronisation.  The on-sky test and the w components
+// are rounded as plain IEEE products and sums (no contraction).
+__global__ __launch_bounds__(256) void k_lattice_sky(LatSkyArgs a) {
+  long long base = 0;
+  for (long long i0 = 0; i0 < a.total; i0 += 256) {
+    const long long i = i0 + threadIdx.x;
+    int on = 0, n = 0, m = 0;
+    double xe = 0.0, ye = 0.0, r2 = 0.0;
+    if (i < a.total) {
+      n = a.n_lo + (int)(i / a.mspan);
+      m = a.m_lo + (int)(i % a.mspan);
+      {
+#pragma clang fp contract(off)
+        const double w2 = (double)n * a.r2x + (double)m * a.r3x;
+        const double w3 = (double)n * a.r2y + (double)m * a.r3y;
+        xe = w2 / a.w;
+        ye = w3 / a.w;
+        r2 = xe * xe + ye * ye;
+      }
+      on = r2 <= 1.0 ? 1 : 0;
+    }
+    int total = 0;
+    const long long k = base + block_exclusive_scan_n<256>(on, &total);
+    if (on && k < a.capacity) {
+      double ze, wf, ws;
+      {
+#pragma clang fp contract(off)
+        ze = a.hemi * sqrt(1.0 - r2);
+        wf = (double)n * a.r2f + (double)m * a.r3f;
+        ws = (double)n * a.r2s + (double)m * a.r3s;
+      }
+      // ecliptic to equatorial axes: rotation by the obliquity about the x axis
+      const double x = xe;
+      const double y = a.ce * ye - a.se * ze;
+      const double z = a.se * ye + a.ce * ze;
+      double al = atan2(y, x);
+      if (al < 0.0) al += 2.0 * M_PI;
+      a.alpha[k] = al;
+      a.delta[k] = asin(fmin(1.0, fmax(-1.0, z)));
+      a.w_freq[k] = wf;
+      a.w_spin[k] = ws;
+      if (a.nm) {
+        a.nm[2 * k] = n;
+        a.nm[2 * k + 1] = m;
+      }
+    }
+    base += total;
+    __syncthreads();   // the scan's LDS is reused by the next step
+  }
+  if (threadIdx.x == 0) *a.count = base;
 }
 
 }  // namespace fstat

@@ -35,9 +35,29 @@ struct SegInfo {
   double ibw = 0.0;            // interbinning weight (0 without interbinning)
 };
 
+// The templates of one search call: nsky sky positions times nfdot spindowns, given
+// either as an explicit spindown list or as the spindown integers of a lattice grid.
+struct Grid {
+  const double *alpha = nullptr, *delta = nullptr;
+  int nsky = 0, nfdot = 0;
+  const double* fdot = nullptr;                        // explicit list, or NULL on a lattice
+  const double *w_freq = nullptr, *w_spin = nullptr;   // lattice: per-sky w0, w1 components
+  int s_lo = 0;                                        // lattice: spindown integer of index 0
+  double m10 = 0.0, m11 = 0.0;                         // lattice: w0, w1 of the spindown row
+  bool operator==(const Grid& o) const {
+    return alpha == o.alpha && delta == o.delta && nsky == o.nsky && nfdot == o.nfdot && fdot == o.fdot &&
+           w_freq == o.w_freq && w_spin == o.w_spin && s_lo == o.s_lo && m10 == o.m10 && m11 == o.m11;
+  }
+};
+
 struct SearchRecord {
   int nsky = 0, nfdot = 0;
-  double* host = nullptr;      // pinned: alpha[nsky], delta[nsky], fdot[nfdot]
+  // pinned: alpha[nsky], delta[nsky], then fdot[nfdot] (explicit list) or
+  // w_freq[nsky], w_spin[nsky] (lattice grid)
+  double* host = nullptr;
+  bool lattice = false;
+  int s_lo = 0;
+  double m10 = 0.0, m11 = 0.0;
 };
 
 struct ProfRec {
@@ -48,8 +68,8 @@ struct ProfRec {
 
 // A captured search call, replayed while the call's arguments stay the same.
 struct GraphEntry {
-  int segment = 0, nsky = 0, nfdot = 0, mode = 0;
-  const double *alpha = nullptr, *delta = nullptr, *fdot = nullptr;
+  int segment = 0, mode = 0;
+  Grid grid;
   void* spectrum = nullptr;
   void* ws = nullptr;
   bool profiled = false;
@@ -419,7 +439,8 @@ constexpr int IB_WG_PER_CU_HALF = 3, IB_WG_PER_CU_FULL = 2;
 
 template <typename T>
 static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo& si, int sky0, int nb,
-                                  const double* fdot, int nfdot, int mode, OutArgs oa, hipStream_t st) {
+                                  const Grid& g, int mode, OutArgs oa, hipStream_t st) {
+  const int nfdot = g.nfdot;
   TmplArgs ta;
   ta.n = (int)si.s.n;
   ta.P = si.tP;
@@ -429,8 +450,15 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
   ta.nfdot = nfdot;
   ta.sky0 = sky0;
   ta.dt = si.s.dt;
-  ta.fdot = fdot;
+  ta.fdot = g.fdot;
   ta.ldzt = si.s.n;
+  ta.w_freq = g.w_freq;
+  ta.w_spin = g.w_spin;
+  ta.m10 = g.m10;
+  ta.m11 = g.m11;
+  ta.bins_per_rad = (double)si.nfft / (2.0 * M_PI);
+  ta.s_lo = g.s_lo;
+  ta.nfft = si.nfft;
   const int total = nb * nfdot;
   cx<T>* tbuf = d.tmpl();
   for (int t0 = 0; t0 < total; t0 += p->B) {
@@ -565,8 +593,9 @@ static fstat_status ensure_workspace(fstat_plan_t p) {
 }
 
 template <typename T>
-static fstat_status search_impl(fstat_plan_t p, int segment, const double* alpha, const double* delta, int nsky,
-                                const double* fdot, int nfdot, int mode, void* spectrum, hipStream_t st) {
+static fstat_status search_impl(fstat_plan_t p, int segment, const Grid& g, int mode, void* spectrum,
+                                hipStream_t st) {
+  const int nsky = g.nsky;
   Dev<T> d(p);
   OutArgs oa;
   oa.threshold = p->opt.threshold_2F;
@@ -597,7 +626,7 @@ static fstat_status search_impl(fstat_plan_t p, int segment, const double* alpha
       db.buf = b & 1;
       if (b >= 2 && sst != st) HIP_TRY(p, hipStreamWaitEvent(sst, p->ev_tmpl[b & 1], 0), "sky stream order");
       const int sky0 = b * p->Sb;
-      fstat_status r = run_sky_batch<T>(p, db, si, alpha, delta, sky0, std::min(p->Sb, nsky - sky0), sst);
+      fstat_status r = run_sky_batch<T>(p, db, si, g.alpha, g.delta, sky0, std::min(p->Sb, nsky - sky0), sst);
       if (r != FSTAT_OK) return r;
       if (sst != st) HIP_TRY(p, hipEventRecord(p->ev_sky[b & 1], sst), "sky stream order");
       return FSTAT_OK;
@@ -614,7 +643,7 @@ static fstat_status search_impl(fstat_plan_t p, int segment, const double* alpha
       Dev<T> db = d;
       db.buf = b & 1;
       const int sky0 = b * p->Sb;
-      r = run_templates<T>(p, db, si, sky0, std::min(p->Sb, nsky - sky0), fdot, nfdot, mode, oa, st);
+      r = run_templates<T>(p, db, si, sky0, std::min(p->Sb, nsky - sky0), g, mode, oa, st);
       if (r != FSTAT_OK) return r;
       if (sst != st) HIP_TRY(p, hipEventRecord(p->ev_tmpl[b & 1], st), "sky stream order");
     }
@@ -623,8 +652,8 @@ static fstat_status search_impl(fstat_plan_t p, int segment, const double* alpha
 }
 
 // All launches of one search call (begin-search marker first).
-static fstat_status enqueue_search(fstat_plan_t p, int segment, const double* alpha, const double* delta, int nsky,
-                                   const double* fdot, int nfdot, int mode, void* spectrum, hipStream_t st) {
+static fstat_status enqueue_search(fstat_plan_t p, int segment, const Grid& g, int mode, void* spectrum,
+                                   hipStream_t st) {
   if (!p->sstream) {
     HIP_TRY(p, hipStreamCreateWithFlags(&p->sstream, hipStreamNonBlocking), "sky stream");
     HIP_TRY(p, hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming), "sky stream event");
@@ -637,20 +666,20 @@ static fstat_status enqueue_search(fstat_plan_t p, int segment, const double* al
     hipLaunchKernelGGL(k_begin_search, dim3(1), dim3(1), 0, st, p->d_search_next);
     HIP_TRY(p, hipGetLastError(), "search marker launch");
   }
-  return p->fp64 ? search_impl<double>(p, segment, alpha, delta, nsky, fdot, nfdot, mode, spectrum, st)
-                 : search_impl<float>(p, segment, alpha, delta, nsky, fdot, nfdot, mode, spectrum, st);
+  return p->fp64 ? search_impl<double>(p, segment, g, mode, spectrum, st)
+                 : search_impl<float>(p, segment, g, mode, spectrum, st);
 }
 
 // Eagerly, or as a captured HIP graph that is replayed while the call's arguments are
 // unchanged.  Graphs run on a plan-owned stream (default priority) that waits for the
 // caller's stream and that the caller's stream then waits for, so the call stays
 // asynchronous and ordered on the caller's stream.
-static fstat_status run_search(fstat_plan_t p, int segment, const double* alpha, const double* delta, int nsky,
-                               const double* fdot, int nfdot, int mode, void* spectrum, hipStream_t st) {
+static fstat_status run_search(fstat_plan_t p, int segment, const Grid& grid, int mode, void* spectrum,
+                               hipStream_t st) {
   // per-launch event timing needs eager launches (events recorded by graph nodes do not
   // report elapsed times)
   if (!p->opt.use_graph || p->profiling)
-    return enqueue_search(p, segment, alpha, delta, nsky, fdot, nfdot, mode, spectrum, st);
+    return enqueue_search(p, segment, grid, mode, spectrum, st);
   if (!p->gstream) {
     HIP_TRY(p, hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking), "graph stream");
     HIP_TRY(p, hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming), "graph event");
@@ -658,26 +687,22 @@ static fstat_status run_search(fstat_plan_t p, int segment, const double* alpha,
   }
   GraphEntry* ge = nullptr;
   for (auto& g : p->graphs)
-    if (g.segment == segment && g.alpha == alpha && g.delta == delta && g.nsky == nsky && g.fdot == fdot &&
-        g.nfdot == nfdot && g.mode == mode && g.spectrum == spectrum && g.ws == p->ws && g.profiled == p->profiling)
+    if (g.segment == segment && g.grid == grid && g.mode == mode && g.spectrum == spectrum && g.ws == p->ws &&
+        g.profiled == p->profiling)
       ge = &g;
   HIP_TRY(p, hipEventRecord(p->ev_in, st), "graph join");
   HIP_TRY(p, hipStreamWaitEvent(p->gstream, p->ev_in, 0), "graph join");
   if (!ge) {
     GraphEntry g;
     g.segment = segment;
-    g.alpha = alpha;
-    g.delta = delta;
-    g.nsky = nsky;
-    g.fdot = fdot;
-    g.nfdot = nfdot;
+    g.grid = grid;
     g.mode = mode;
     g.spectrum = spectrum;
     g.ws = p->ws;
     g.profiled = p->profiling;
     const size_t nprof = p->prof.size();
     HIP_TRY(p, hipStreamBeginCapture(p->gstream, hipStreamCaptureModeThreadLocal), "graph capture");
-    fstat_status r = enqueue_search(p, segment, alpha, delta, nsky, fdot, nfdot, mode, spectrum, p->gstream);
+    fstat_status r = enqueue_search(p, segment, grid, mode, spectrum, p->gstream);
     hipError_t ec = hipStreamEndCapture(p->gstream, &g.graph);
     // the event pairs recorded during capture belong to the graph's nodes
     g.events.assign(p->prof.begin() + nprof, p->prof.end());
@@ -1364,6 +1389,41 @@ static fstat_status check_lists(fstat_plan_t plan, int32_t segment, const double
   return FSTAT_OK;
 }
 
+// Pinned host copies of a search call's lists, for the candidate records.
+static fstat_status record_search(fstat_plan_t plan, const Grid& g, hipStream_t st) {
+  SearchRecord rec;
+  rec.nsky = g.nsky;
+  rec.nfdot = g.nfdot;
+  rec.lattice = g.fdot == nullptr;
+  rec.s_lo = g.s_lo;
+  rec.m10 = g.m10;
+  rec.m11 = g.m11;
+  const size_t nd = rec.lattice ? 4 * (size_t)g.nsky : 2 * (size_t)g.nsky + g.nfdot;
+  HIP_TRY(plan, hipHostMalloc((void**)&rec.host, nd * sizeof(double), hipHostMallocDefault), "pinned list copy");
+  plan->searches.push_back(rec);
+  const size_t ns = (size_t)g.nsky * sizeof(double);
+  HIP_TRY(plan, hipMemcpyAsync(rec.host, g.alpha, ns, hipMemcpyDeviceToHost, st), "list copy");
+  HIP_TRY(plan, hipMemcpyAsync(rec.host + g.nsky, g.delta, ns, hipMemcpyDeviceToHost, st), "list copy");
+  if (rec.lattice) {
+    HIP_TRY(plan, hipMemcpyAsync(rec.host + 2 * g.nsky, g.w_freq, ns, hipMemcpyDeviceToHost, st), "list copy");
+    HIP_TRY(plan, hipMemcpyAsync(rec.host + 3 * g.nsky, g.w_spin, ns, hipMemcpyDeviceToHost, st), "list copy");
+  } else {
+    HIP_TRY(plan, hipMemcpyAsync(rec.host + 2 * g.nsky, g.fdot, g.nfdot * sizeof(double), hipMemcpyDeviceToHost, st),
+            "list copy");
+  }
+  return FSTAT_OK;
+}
+
+static Grid explicit_grid(const double* alpha, const double* delta, int nsky, const double* fdot, int nfdot) {
+  Grid g;
+  g.alpha = alpha;
+  g.delta = delta;
+  g.nsky = nsky;
+  g.fdot = fdot;
+  g.nfdot = nfdot;
+  return g;
+}
+
 fstat_status fstat_search_batch(fstat_plan_t plan, int32_t segment, const double* alpha, const double* delta,
                                 int32_t nsky, const double* fdot, int32_t nfdot, void* stream) {
   fstat_status r = check_lists(plan, segment, alpha, delta, nsky, fdot, nfdot);
@@ -1371,19 +1431,11 @@ fstat_status fstat_search_batch(fstat_plan_t plan, int32_t segment, const double
   r = ensure_workspace(plan);
   if (r != FSTAT_OK) return r;
   hipStream_t st = (hipStream_t)stream;
-  SearchRecord rec;
-  rec.nsky = nsky;
-  rec.nfdot = nfdot;
-  const size_t nd = 2 * (size_t)nsky + nfdot;
-  HIP_TRY(plan, hipHostMalloc((void**)&rec.host, nd * sizeof(double), hipHostMallocDefault), "pinned list copy");
-  plan->searches.push_back(rec);
-  HIP_TRY(plan, hipMemcpyAsync(rec.host, alpha, nsky * sizeof(double), hipMemcpyDeviceToHost, st), "list copy");
-  HIP_TRY(plan, hipMemcpyAsync(rec.host + nsky, delta, nsky * sizeof(double), hipMemcpyDeviceToHost, st), "list copy");
-  HIP_TRY(plan, hipMemcpyAsync(rec.host + 2 * nsky, fdot, nfdot * sizeof(double), hipMemcpyDeviceToHost, st),
-          "list copy");
+  const Grid g = explicit_grid(alpha, delta, nsky, fdot, nfdot);
+  if ((r = record_search(plan, g, st)) != FSTAT_OK) return r;
   plan->last_stream = st;
   plan->used_stream = true;
-  r = run_search(plan, segment, alpha, delta, nsky, fdot, nfdot, 0, nullptr, st);
+  r = run_search(plan, segment, g, 0, nullptr, st);
   plan->search_count++;
   return r;
 }
@@ -1399,7 +1451,143 @@ fstat_status fstat_twoF_spectrum(fstat_plan_t plan, int32_t segment, const doubl
   hipStream_t st = (hipStream_t)stream;
   plan->last_stream = st;
   plan->used_stream = true;
-  return run_search(plan, segment, alpha, delta, nsky, fdot, nfdot, 1, out, st);
+  return run_search(plan, segment, explicit_grid(alpha, delta, nsky, fdot, nfdot), 1, out, st);
+}
+
+// ------------------------------------------------------------------ lattice grid
+static constexpr double AU_SECONDS = 149597870700.0 / 299792458.0;  // light time over 1 AU
+
+static bool finite_lattice(const fstat_lattice* lat) {
+  for (double v : lat->M)
+    if (!std::isfinite(v)) return false;
+  return std::isfinite(lat->epsilon) && std::isfinite(lat->f_ref) && lat->f_ref > 0.0;
+}
+
+// sky components of the two sky rows and the box bound of |n|, |m| on the sky's disk
+static bool sky_rows(const fstat_lattice* lat, double* n_max, double* m_max) {
+  const double* M = lat->M;
+  const double det = M[10] * M[15] - M[11] * M[14];
+  const double w = 2.0 * M_PI * lat->f_ref * AU_SECONDS;
+  if (!(std::fabs(det) > 0.0)) return false;
+  *n_max = w * std::hypot(M[14], M[15]) / std::fabs(det);
+  *m_max = w * std::hypot(M[10], M[11]) / std::fabs(det);
+  return std::isfinite(*n_max) && std::isfinite(*m_max);
+}
+
+fstat_status fstat_lattice_sky_range(const fstat_lattice* lat, int32_t box[4]) {
+  if (!lat || !box) return fail(nullptr, FSTAT_E_INVAL, "NULL argument");
+  if (!finite_lattice(lat)) return fail(nullptr, FSTAT_E_INVAL, "lattice values must be finite, f_ref > 0");
+  double nm, mm;
+  if (!sky_rows(lat, &nm, &mm)) return fail(nullptr, FSTAT_E_INVAL, "the sky rows are parallel");
+  if (nm >= 1e9 || mm >= 1e9) return fail(nullptr, FSTAT_E_INVAL, "sky range beyond int32");
+  const int32_t n_hi = (int32_t)std::floor(nm), m_hi = (int32_t)std::floor(mm);
+  box[0] = -n_hi;
+  box[1] = n_hi;
+  box[2] = -m_hi;
+  box[3] = m_hi;
+  return FSTAT_OK;
+}
+
+fstat_status fstat_lattice_sky(const fstat_lattice* lat, int32_t hemisphere, const int32_t box[4],
+                               int64_t capacity, double* alpha, double* delta, double* w_freq, double* w_spin,
+                               int32_t* nm, int64_t* count, void* stream) {
+  if (!lat || !box || !count) return fail(nullptr, FSTAT_E_INVAL, "NULL argument");
+  if (!finite_lattice(lat)) return fail(nullptr, FSTAT_E_INVAL, "lattice values must be finite, f_ref > 0");
+  if (hemisphere != 1 && hemisphere != -1) return fail(nullptr, FSTAT_E_INVAL, "hemisphere must be +1 or -1");
+  if (box[1] < box[0] || box[3] < box[2]) return fail(nullptr, FSTAT_E_INVAL, "empty box");
+  const long long nspan = (long long)box[1] - box[0] + 1, mspan = (long long)box[3] - box[2] + 1;
+  if (nspan > (1LL << 26) || mspan > (1LL << 26) || nspan * mspan > (1LL << 26))
+    return fail(nullptr, FSTAT_E_INVAL, "box holds more than 2^26 points");
+  if (capacity < 0) return fail(nullptr, FSTAT_E_INVAL, "capacity < 0");
+  if (capacity > 0 && (!alpha || !delta || !w_freq || !w_spin))
+    return fail(nullptr, FSTAT_E_INVAL, "output arrays must be device pointers");
+  const double* M = lat->M;
+  LatSkyArgs a;
+  a.r2x = M[10];
+  a.r2y = M[11];
+  a.r3x = M[14];
+  a.r3y = M[15];
+  a.r2f = M[8];
+  a.r2s = M[9];
+  a.r3f = M[12];
+  a.r3s = M[13];
+  a.w = 2.0 * M_PI * lat->f_ref * AU_SECONDS;
+  a.ce = std::cos(lat->epsilon);
+  a.se = std::sin(lat->epsilon);
+  a.hemi = (double)hemisphere;
+  a.n_lo = box[0];
+  a.m_lo = box[2];
+  a.mspan = (int)mspan;
+  a.total = nspan * mspan;
+  a.capacity = capacity;
+  a.alpha = alpha;
+  a.delta = delta;
+  a.w_freq = w_freq;
+  a.w_spin = w_spin;
+  a.nm = capacity > 0 ? nm : nullptr;
+  a.count = (long long*)count;
+  hipLaunchKernelGGL(k_lattice_sky, dim3(1), dim3(256), 0, (hipStream_t)stream, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(nullptr, e, "lattice sky launch");
+  return FSTAT_OK;
+}
+
+// The constraints that let the FFT and one resampling per sky serve the grid.
+static fstat_status check_lattice_search(fstat_plan_t plan, int32_t segment, const fstat_lattice* lat) {
+  const double* M = lat->M;
+  for (double v : lat->M)
+    if (!std::isfinite(v)) return fail(plan, FSTAT_E_INVAL, "lattice values must be finite");
+  if (!(M[0] > 0.0) || M[1] != 0.0 || M[2] != 0.0 || M[3] != 0.0)
+    return fail(plan, FSTAT_E_INVAL, "row 0 of the lattice must be (w_F > 0, 0, 0, 0)");
+  if (M[6] != 0.0 || M[7] != 0.0) return fail(plan, FSTAT_E_INVAL, "row 1 of the lattice must have no sky components");
+  const int s0 = segment < 0 ? 0 : segment, s1 = segment < 0 ? (int)plan->segs.size() : segment + 1;
+  for (int i = s0; i < s1; ++i) {
+    const double q = M[0] * (double)plan->segs[i].nfft / (2.0 * M_PI);
+    if (q < 0.5 || std::fabs(q - std::round(q)) > 1e-6 * std::max(1.0, q)) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "segment %d: row 0 is %.9g bins of nfft=%d, not a whole number", i, q,
+                    plan->segs[i].nfft);
+      return fail(plan, FSTAT_E_INVAL, msg);
+    }
+  }
+  return FSTAT_OK;
+}
+
+fstat_status fstat_search_lattice(fstat_plan_t plan, int32_t segment, const fstat_lattice* lat,
+                                  const double* alpha, const double* delta, const double* w_freq,
+                                  const double* w_spin, int32_t nsky, int32_t s_lo, int32_t s_hi,
+                                  void* spectrum, void* stream) {
+  if (!plan) return fail(plan, FSTAT_E_INVAL, "NULL plan");
+  if (!lat) return fail(plan, FSTAT_E_INVAL, "NULL lattice");
+  if (s_hi < s_lo) return fail(plan, FSTAT_E_INVAL, "s_hi < s_lo");
+  if ((long long)s_hi - s_lo + 1 > (1LL << 30)) return fail(plan, FSTAT_E_INVAL, "too many spindowns");
+  const int nfdot = s_hi - s_lo + 1;
+  // the explicit-list checks, with w_freq standing in for the spindown list
+  fstat_status r = check_lists(plan, segment, alpha, delta, nsky, w_freq, nfdot);
+  if (r != FSTAT_OK) return r;
+  if (!w_spin) return fail(plan, FSTAT_E_INVAL, "template lists must be device pointers");
+  if ((r = check_lattice_search(plan, segment, lat)) != FSTAT_OK) return r;
+  if (spectrum && segment < 0) return fail(plan, FSTAT_E_INVAL, "spectrum needs one segment");
+  r = ensure_workspace(plan);
+  if (r != FSTAT_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  Grid g;
+  g.alpha = alpha;
+  g.delta = delta;
+  g.nsky = nsky;
+  g.nfdot = nfdot;
+  g.w_freq = w_freq;
+  g.w_spin = w_spin;
+  g.s_lo = s_lo;
+  g.m10 = lat->M[4];
+  g.m11 = lat->M[5];
+  plan->last_stream = st;
+  plan->used_stream = true;
+  if (spectrum) return run_search(plan, segment, g, 1, spectrum, st);
+  if ((r = record_search(plan, g, st)) != FSTAT_OK) return r;
+  r = run_search(plan, segment, g, 0, nullptr, st);
+  plan->search_count++;
+  return r;
 }
 
 template <typename T>
@@ -1503,8 +1691,17 @@ fstat_status fstat_candidates(fstat_plan_t plan, fstat_candidate* out, fstat_can
     if (out) {
       const SegInfo& si = plan->segs[c.segment];
       const SearchRecord& sr = plan->searches[(size_t)c.search - (plan->search_count - plan->searches.size())];
-      out[i].f_hz = si.s.f_off + (double)c.bin / ((double)si.nfft * si.s.dt);
-      out[i].fdot = sr.host[2 * sr.nsky + c.fdot_idx];
+      if (sr.lattice) {
+        // the template's frequency shift and spindown, as the kernels formed them
+        const int s = sr.s_lo + c.fdot_idx;
+        const double u = lattice_shift_bins(lattice_w(s, sr.m10, sr.host[2 * sr.nsky + c.sky]),
+                                            (double)si.nfft / (2.0 * M_PI));
+        out[i].f_hz = si.s.f_off + ((double)c.bin + u) / ((double)si.nfft * si.s.dt);
+        out[i].fdot = lattice_w(s, sr.m11, sr.host[3 * sr.nsky + c.sky]) / (M_PI * si.s.dt * si.s.dt);
+      } else {
+        out[i].f_hz = si.s.f_off + (double)c.bin / ((double)si.nfft * si.s.dt);
+        out[i].fdot = sr.host[2 * sr.nsky + c.fdot_idx];
+      }
       out[i].alpha = sr.host[c.sky];
       out[i].delta = sr.host[sr.nsky + c.sky];
       out[i].twoF = c.twoF;
@@ -1626,13 +1823,17 @@ fstat_status fstat_autotune(fstat_plan_t plan, int32_t segment, double budget_ms
     if ((r = ensure_workspace(plan)) != FSTAT_OK) break;
     // warm-up on one sky batch, then time whole batches until the share of the budget is used
     const int ns = std::min(nsky, c.Sb);
-    if ((r = run_search(plan, segment, dl, dl + nsky, ns, dl + 2 * nsky, nfdot, 0, nullptr, st)) != FSTAT_OK) break;
+    if ((r = run_search(plan, segment, explicit_grid(dl, dl + nsky, ns, dl + 2 * nsky, nfdot), 0, nullptr, st)) !=
+        FSTAT_OK)
+      break;
     double ms_sum = 0.0;
     long tmpl = 0;
     int reps = 0;
     while (reps < 8 && (reps < 1 || ms_sum < per_cand_ms)) {
       (void)hipEventRecord(e0, st);
-      if ((r = run_search(plan, segment, dl, dl + nsky, nsky, dl + 2 * nsky, nfdot, 0, nullptr, st)) != FSTAT_OK) break;
+      if ((r = run_search(plan, segment, explicit_grid(dl, dl + nsky, nsky, dl + 2 * nsky, nfdot), 0, nullptr, st)) !=
+          FSTAT_OK)
+        break;
       (void)hipEventRecord(e1, st);
       if ((e = hipEventSynchronize(e1)) != hipSuccess) {
         r = hip_fail(plan, e, "autotune timing");

@@ -299,15 +299,16 @@ __device__ __forceinline__ void dft8_pruned(cx<T>* v) {
 }
 
 // First stage of pass A for both series: y[j1 + P j2], j2 = j + NB1 r (zero for
-// j1 + P j2 >= n), times the spindown chirp exp(-i pi fdot (j dt)^2) whose phase is
-// evaluated in FP64 and reduced to [0, 1) cycles, then a radix-R1 DFT in registers.
+// j1 + P j2 >= n), times the template's chirp exp(-2 pi i (c2 jj + c1) jj) at sample jj
+// (the spindown phase, plus a lattice grid's frequency shift) whose phase is evaluated
+// in FP64 and reduced to [0, 1) cycles, then a radix-R1 DFT in registers.
 // All loads are issued before any chirp is computed so that they overlap.  RNZ < R1
 // states that inputs r >= RNZ are zero for every column (n <= RNZ L / 8, L the transform
 // length), so they are neither loaded nor transformed.
 template <typename T, int Q, int G, int R1, int NB1, int PB1, int RNZ = R1>
 __device__ __forceinline__ void chirped_first_stage(cx<T> (&va)[PB1][R1], cx<T> (&vb)[PB1][R1],
                                                     const cx<T>* __restrict__ za, const cx<T>* __restrict__ zb,
-                                                    int j1, int g, int P, int n, double half_fdot_dt2) {
+                                                    int j1, int g, int P, int n, double c2, double c1) {
 #pragma unroll
   for (int b = 0; b < PB1; ++b) {
     const unsigned j = (unsigned)(g + G * b);
@@ -326,7 +327,7 @@ __device__ __forceinline__ void chirped_first_stage(cx<T> (&va)[PB1][R1], cx<T> 
       const unsigned jj = (unsigned)j1 + (unsigned)P * (j + (unsigned)(NB1 * r));
       if (jj < (unsigned)n) {
         const double x = (double)jj;
-        double cyc = half_fdot_dt2 * x * x;
+        double cyc = fma(c2, x, c1) * x;
         cyc -= floor(cyc);
         T s, co;
         if constexpr (sizeof(T) == 8) {
@@ -376,14 +377,15 @@ __global__ void __launch_bounds__((tmpl_nt_a<T, Q>())) k_tmpl_a(TmplArgs ta, con
   const int c = threadIdx.x % TW, g = threadIdx.x / TW;
   const int t = ta.t0 + item;
   const int skyl = t / ta.nfdot, sidx = t % ta.nfdot;
-  const double half_fdot_dt2 = 0.5 * ta.fdot[sidx] * ta.dt * ta.dt;
+  double c2, c1;
+  template_chirp(ta, skyl, sidx, c2, c1);
   const cx<T>* za = zt + (long)(2 * skyl) * ta.ldzt;
   const cx<T>* zb = za + ta.ldzt;
   const int j1 = tile * TW + c;
   cx<T>* col = lds + c * ST;
   // first stage: y[j1 + P j2] with the spindown chirp, radix-R1 butterflies in registers
   cx<T> va[PB1][R1], vb[PB1][R1];
-  chirped_first_stage<T, Q, G, R1, NB1, PB1, RNZ>(va, vb, za, zb, j1, g, ta.P, ta.n, half_fdot_dt2);
+  chirped_first_stage<T, Q, G, R1, NB1, PB1, RNZ>(va, vb, za, zb, j1, g, ta.P, ta.n, c2, c1);
   // twiddles W^(j1 k2) of the last-stage outputs k2 = j + NSL r: W^(j1 j) times powers of W^(j1 NSL)
   constexpr int NSL = last_ns<Q, 1>();
   constexpr int RL = stage_radix<Q, NSL>();
@@ -447,7 +449,8 @@ __global__ void __launch_bounds__((tmpl_nt_a<T, Q>())) k_tmpl_a_pair(TmplArgs ta
   const int c = threadIdx.x % TW, g = threadIdx.x / TW;
   const int t = ta.t0 + item;
   const int skyl = t / ta.nfdot, sidx = t % ta.nfdot;
-  const double half_fdot_dt2 = 0.5 * ta.fdot[sidx] * ta.dt * ta.dt;
+  double c2, c1;
+  template_chirp(ta, skyl, sidx, c2, c1);
   const cx<T>* za = zt + (long)(2 * skyl) * ta.ldzt;
   const cx<T>* zb = za + ta.ldzt;
   const int j1 = tile * TW + c;
@@ -455,7 +458,7 @@ __global__ void __launch_bounds__((tmpl_nt_a<T, Q>())) k_tmpl_a_pair(TmplArgs ta
   cx<T>* colb = lds + (TW + c) * ST;
   {
     cx<T> va[PB1][R1], vb[PB1][R1];
-    chirped_first_stage<T, Q, G, R1, NB1, PB1, RNZ>(va, vb, za, zb, j1, g, ta.P, ta.n, half_fdot_dt2);
+    chirped_first_stage<T, Q, G, R1, NB1, PB1, RNZ>(va, vb, za, zb, j1, g, ta.P, ta.n, c2, c1);
     stage_to_lds_off<T, Q, G, 1, R1, PB1>(va, cola, g);
     stage_to_lds_off<T, Q, G, 1, R1, PB1>(vb, colb, g);
     __syncthreads();

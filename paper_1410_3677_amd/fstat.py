@@ -28,7 +28,8 @@ EXPORTED = ("fstat_options_default", "fstat_plan", "fstat_plan_workspace_size", 
             "fstat_profile_enable", "fstat_profile_read", "fstat_plan_info", "fstat_autotune", "fstat_destroy",
             "fstat_strerror", "fstat_last_error", "fstat_vet_param_count", "fstat_vet_create",
             "fstat_vet_set_params", "fstat_vet_get_params", "fstat_vet_forward", "fstat_vet_gradient",
-            "fstat_vet_adam_step", "fstat_vet_destroy", "fstat_plan_attach_vetter", "fstat_plan_vet_candidates")
+            "fstat_vet_adam_step", "fstat_vet_destroy", "fstat_plan_attach_vetter", "fstat_plan_vet_candidates",
+            "fstat_lattice_sky_range", "fstat_lattice_sky", "fstat_search_lattice")
 
 
 class fstat_segment(ctypes.Structure):
@@ -54,6 +55,21 @@ class fstat_candidate(ctypes.Structure):
 class fstat_candidate_key(ctypes.Structure):
     _fields_ = [("search", ctypes.c_int32), ("segment", ctypes.c_int32), ("sky", ctypes.c_int32),
                 ("fdot_idx", ctypes.c_int32), ("bin", ctypes.c_int32), ("vet_score", ctypes.c_float)]
+
+
+class fstat_lattice(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_double * 16), ("epsilon", ctypes.c_double), ("f_ref", ctypes.c_double)]
+
+
+def lattice(M, epsilon: float, f_ref: float) -> fstat_lattice:
+    """fstat_lattice from a 4x4 generator matrix (rows: frequency, spindown, sky, sky)."""
+    lat = fstat_lattice()
+    flat = np.ascontiguousarray(np.asarray(M, dtype=np.float64).reshape(16))
+    for i in range(16):
+        lat.M[i] = float(flat[i])
+    lat.epsilon = float(epsilon)
+    lat.f_ref = float(f_ref)
+    return lat
 
 
 CANDIDATE_NP = np.dtype([("f_hz", "<f8"), ("fdot", "<f8"), ("alpha", "<f8"), ("delta", "<f8"), ("twoF", "<f8")])
@@ -99,6 +115,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "fstat_plan_attach_vetter": (i32, [P, P, i64]),
         "fstat_plan_vet_candidates": (i32, [P, P]),
         "fstat_last_error": (ctypes.c_char_p, [P]),
+        "fstat_lattice_sky_range": (i32, [ctypes.POINTER(fstat_lattice), ctypes.POINTER(i32)]),
+        "fstat_lattice_sky": (i32, [ctypes.POINTER(fstat_lattice), i32, ctypes.POINTER(i32), i64, P, P, P, P, P, P,
+                                    P]),
+        "fstat_search_lattice": (i32, [P, i32, ctypes.POINTER(fstat_lattice), P, P, P, P, i32, i32, i32, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -225,6 +245,16 @@ class Plan:
             _check(st, self.handle)
         return n.value
 
+    def search_lattice(self, segment: int, lat: fstat_lattice, sky: dict, s_lo: int, s_hi: int, spectrum=None,
+                       stream=None):
+        """Search the lattice templates: `sky` as returned by lattice_sky (device tensors),
+        spindown integers s_lo..s_hi.  With `spectrum` (device tensor), store 2F instead."""
+        self._keep_lists = (sky, spectrum)
+        _check(self.lib.fstat_search_lattice(self.handle, segment, ctypes.byref(lat), _ptr(sky["alpha"]),
+                                             _ptr(sky["delta"]), _ptr(sky["w_freq"]), _ptr(sky["w_spin"]),
+                                             int(sky["alpha"].numel()), int(s_lo), int(s_hi), _ptr(spectrum),
+                                             _stream_handle(stream)), self.handle)
+
     def twoF_spectrum(self, segment: int, alpha, delta, fdot, out, stream=None):
         _check(self.lib.fstat_twoF_spectrum(self.handle, segment, _ptr(alpha), _ptr(delta), int(alpha.numel()),
                                             _ptr(fdot), int(fdot.numel()), _ptr(out), _stream_handle(stream)),
@@ -263,6 +293,35 @@ class Plan:
             self.destroy()
         except Exception:
             pass
+
+
+def lattice_sky_range(lat: fstat_lattice):
+    """(n_lo, n_hi, m_lo, m_hi): the box of the sky integers (host computation)."""
+    box = (ctypes.c_int32 * 4)()
+    _check(load().fstat_lattice_sky_range(ctypes.byref(lat), box))
+    return tuple(int(v) for v in box)
+
+
+def lattice_sky(lat: fstat_lattice, hemisphere: int, box=None, capacity: Optional[int] = None, stream=None) -> dict:
+    """Sky points of the lattice on one hemisphere, computed on the current device:
+    {"alpha", "delta", "w_freq", "w_spin", "nm", "count"} (device tensors cut to the
+    points written; "count" is the number on the sky, which may exceed the capacity)."""
+    import torch
+    if box is None:
+        box = lattice_sky_range(lat)
+    if capacity is None:
+        capacity = (box[1] - box[0] + 1) * (box[3] - box[2] + 1)
+    cap = max(int(capacity), 1)
+    out = torch.empty((4, cap), dtype=torch.float64, device="cuda")
+    nm = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    b = (ctypes.c_int32 * 4)(*[int(v) for v in box])
+    _check(load().fstat_lattice_sky(ctypes.byref(lat), int(hemisphere), b, int(capacity), _ptr(out[0]), _ptr(out[1]),
+                                    _ptr(out[2]), _ptr(out[3]), _ptr(nm), _ptr(count), _stream_handle(stream)))
+    total = int(count.item())
+    k = min(total, int(capacity))
+    return {"alpha": out[0, :k], "delta": out[1, :k], "w_freq": out[2, :k], "w_spin": out[3, :k], "nm": nm[:k],
+            "count": total}
 
 
 def segment_to_device(seg) -> dict:

@@ -150,3 +150,50 @@ def test_vetting_entry_points_validate_arguments():
     assert lib.fstat_plan_attach_vetter(None, None, 1) == F.E_INVAL
     assert lib.fstat_plan_vet_candidates(None, None) == F.E_INVAL
     assert lib.fstat_vet_destroy(None) == F.OK
+
+
+# ---- lattice grid: host-side range and argument checks ------------------------------------
+def _lat(seed=3, sky_points=50):
+    import synth
+    M = synth.lattice_matrix(8192, 2.0, 100.25, sky_points, -2e-10, seed)
+    return M, F.lattice(M, synth.OBLIQUITY, 100.25)
+
+
+@pytest.mark.parametrize("seed,sky_points", [(3, 50), (4, 400), (5, 7)])
+def test_lattice_sky_range_matches_the_oracle(seed, sky_points):
+    from oracle import fstat_oracle as fo
+    M, lat = _lat(seed, sky_points)
+    assert F.lattice_sky_range(lat) == fo.lattice_sky_range(M, 100.25)
+
+
+def test_lattice_range_rejects_parallel_sky_rows_and_bad_values():
+    M, lat = _lat()
+    M2 = M.copy()
+    M2[3, 2:] = 2.0 * M2[2, 2:]
+    with pytest.raises(F.FstatError) as ei:
+        F.lattice_sky_range(F.lattice(M2, 0.4, 100.25))
+    assert ei.value.status == F.E_INVAL and "parallel" in str(ei.value)
+    with pytest.raises(F.FstatError) as ei:
+        F.lattice_sky_range(F.lattice(M, 0.4, 0.0))
+    assert ei.value.status == F.E_INVAL and "f_ref" in str(ei.value)
+    M3 = M.copy()
+    M3[2, 0] = float("nan")
+    with pytest.raises(F.FstatError):
+        F.lattice_sky_range(F.lattice(M3, 0.4, 100.25))
+
+
+@pytest.mark.parametrize("hemi,box,cap,ptrs,needle", [
+    (0, (-2, 2, -2, 2), 10, True, "hemisphere"),
+    (1, (2, 1, -2, 2), 10, True, "empty box"),
+    (1, (-5000, 5000, -5000, 5000), 10, True, "2^26"),
+    (1, (-2, 2, -2, 2), -1, True, "capacity"),
+    (-1, (-2, 2, -2, 2), 10, False, "device pointers"),
+])
+def test_lattice_sky_rejects_bad_arguments(hemi, box, cap, ptrs, needle):
+    lib = F.load()
+    _, lat = _lat()
+    b = (ctypes.c_int32 * 4)(*box)
+    p = FAKE_PTR if ptrs else None
+    st = lib.fstat_lattice_sky(ctypes.byref(lat), hemi, b, cap, p, p, p, p, None, FAKE_PTR, None)
+    assert st == F.E_INVAL
+    assert needle in lib.fstat_last_error(None).decode()
