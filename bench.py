@@ -14,7 +14,9 @@ Printed: one JSON line with templates/s, the per-kernel HIP-event timings,
 the roofline of the dominant kernel, the plain one-template-per-launch path
 (256 x 64 templates), the CPU oracle timed on a bounded sample, and the same
 batched workload searched with interbinning (template transforms of nfft/2
-points, odd bins from their neighbours) as a separate entry.
+points, odd bins from their neighbours) as a separate entry, and the batched
+search driven by a lattice grid (sky points and spindowns from the integers of
+a generator matrix, frequencies shifted onto the grid) as another.
 """
 from __future__ import annotations
 
@@ -189,6 +191,50 @@ def timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbin
             "tuning": tuned, "template_fft": tlen}
 
 
+def lattice_leg(args, F, torch, seg, nfft, info, log):
+    """The batched search on lattice templates: a synthetic constrained generator matrix
+    with about args.nsky sky points on the northern ecliptic hemisphere, spindown
+    integers 0 .. args.nfdot - 1 (0 to -1e-9 Hz/s plus each sky point's offset), every
+    template's frequencies shifted onto its own fraction of a bin.  Batch sizes of the
+    explicit-list plan; its own throughput, not the headline value."""
+    import synth
+    f_ref = seg.f_off + 0.5 / seg.dt
+    M = synth.lattice_matrix(nfft, seg.dt, f_ref, args.nsky, -1e-9 / max(args.nfdot - 1, 1), 4242)
+    lat = F.lattice(M, synth.OBLIQUITY, f_ref)
+    F.lattice_sky(lat, 1)           # first call loads the kernel
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sky = F.lattice_sky(lat, 1)
+    t_sky = time.perf_counter() - t0
+    nsky = int(sky["alpha"].numel())
+    templates = nsky * args.nfdot
+    cap = int(max(1 << 20, 2.0 * 1.1e-3 * (nfft // 2) * templates * max(args.steps, 1)))
+    plan = F.Plan([F.segment_to_device(seg)], candidate_capacity=cap,
+                  templates_per_launch=info["templates_per_launch"], skies_per_batch=info["skies_per_batch"],
+                  use_graph=0 if args.no_graph else 1)
+    for _ in range(args.warmup):
+        plan.search_lattice(0, lat, sky, 0, args.nfdot - 1)
+        torch.cuda.synchronize()
+        plan.candidate_count(allow_overflow=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.search_lattice(0, lat, sky, 0, args.nfdot - 1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n_cand = plan.candidate_count(allow_overflow=True)
+    plan.destroy()
+    value = templates / ((t1 - t0) / args.steps)
+    log(f"lattice: {nsky} sky points (box {sky['count']} on the sky), {value:.4g} templates/s, sky loop "
+        f"{t_sky * 1e3:.2f} ms including allocation and the count read-back")
+    return {"value": value, "unit": "templates/s", "ms_per_step": (t1 - t0) * 1e3 / args.steps,
+            "candidates_per_step": n_cand / args.steps, "sky_points": nsky, "sky_loop_ms": t_sky * 1e3,
+            "config": {"workload": f"lattice templates, N={seg.n}, nfft=2^{int(math.log2(nfft))}, {nsky} sky points "
+                                   f"(northern ecliptic hemisphere) x {args.nfdot} spindown integers, 2F>20",
+                       "templates": templates, "templates_per_launch": info["templates_per_launch"],
+                       "skies_per_batch": info["skies_per_batch"]}}
+
+
 def ib_summary(ib, templates, nfft):
     """The interbinning leg for the JSON line (its own throughput; not the headline value)."""
     if ib is None:
@@ -307,6 +353,7 @@ def main():
                     help="tuning cache file: reused if it exists, else written by the autotuner")
     ap.add_argument("--no-vetting", action="store_true")
     ap.add_argument("--no-interbinning", action="store_true")
+    ap.add_argument("--no-lattice", action="store_true")
     ap.add_argument("--vet-epochs", type=int, default=3)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
@@ -356,6 +403,11 @@ def main():
     ib = None
     if not args.no_interbinning:
         ib = timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbinning=1)
+
+    # ---------------- the same search driven by a lattice grid (sky loop over grid integers)
+    lat_leg = None
+    if not args.no_lattice:
+        lat_leg = lattice_leg(args, F, torch, seg, nfft, info, log)
 
     # ---------------- plain path: one template per launch, 256 x 64
     plain = None
@@ -457,6 +509,7 @@ def main():
         "f_rel_err_vs_fp64": f_err, "candidates_per_step": n_cand / args.steps, "kernels": kernels,
         "vetting": vetting,
         "interbinning": ib_summary(ib, templates, nfft),
+        "lattice": lat_leg,
         "source_sha256": source_digest(),
     }
     print(json.dumps(out), flush=True)

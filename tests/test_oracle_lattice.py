@@ -129,3 +129,27 @@ def test_lattice_without_offsets_matches_the_plain_search():
     assert np.allclose(a["twoF"], b["twoF"], rtol=1e-9)
     assert np.allclose(a["fdot"], b["fdot"], rtol=1e-12, atol=0)
     assert np.array_equal(a["f_hz"], b["f_hz"])
+
+
+def test_synthetic_sky_lattice_covering_radius():
+    """The synthetic generator's sky rows form a hexagonal lattice of spacing h, whose
+    covering radius is h / sqrt(3): every point of the sky's disk lies within it of a
+    lattice point (brute force over random points), and the bound is nearly reached."""
+    nfft, f_ref, M, _ = pins.lattice_setup(4096, sky_points=200, seed=12)
+    w = fo.lattice_sky_scale(f_ref)
+    e1, e2 = M[2, 2:], M[3, 2:]
+    h = float(np.hypot(*e1))
+    assert abs(float(np.hypot(*e2)) - h) < 1e-9 * h and abs(float(e1 @ e2) - 0.5 * h * h) < 1e-9 * h * h
+    rng = np.random.default_rng(3)
+    r = w * np.sqrt(rng.uniform(0, 1, 4000))
+    t = rng.uniform(0, 2 * math.pi, 4000)
+    pts = np.stack([r * np.cos(t), r * np.sin(t)], 1)
+    S = np.array([e1, e2])
+    nm = np.linalg.solve(S.T, pts.T).T
+    best = np.full(len(pts), np.inf)
+    for dn in (-1, 0, 1, 2):
+        for dm in (-1, 0, 1, 2):
+            cand = (np.floor(nm) + [dn, dm]) @ S
+            best = np.minimum(best, np.hypot(*(pts - cand).T))
+    assert best.max() <= h / math.sqrt(3) * (1 + 1e-9)
+    assert best.max() > 0.9 * h / math.sqrt(3)
