@@ -101,8 +101,9 @@ typedef struct {
                                      h = pi/nfft; about pi/4 when n = nfft/2).  Halves the template
                                      stage's memory traffic; the odd bins are an approximation
                                      (exact for a sinusoid midway between bins; odd bins of pure
-                                     noise have a larger mean than even ones).  Mixed precision
-                                     only (FSTAT_E_NOT_IMPLEMENTED otherwise); needs nfft >= 2^13. */
+                                     noise have a larger mean than even ones).  Both precisions
+                                     (FP64 stores the transforms, then forms 2F in a pass of its
+                                     own); needs nfft >= 2^13. */
 } fstat_options;
 
 /* The paper's five numbers of a candidate (Sect. 2). */
@@ -264,8 +265,9 @@ fstat_status fstat_profile_read(fstat_plan_t plan, int32_t kernel_class, int64_t
  * resident round of wavefronts that walk the launch's rows, prefetching the
  * next row and staging candidates in LDS; variant 1 applies to the mixed
  * precision path with P <= 512, other segments use row tiles; with
- * interbinning the second pass is always a walk of wavefronts, each over an
- * even share of the launch's rows in order).  Any output pointer may be NULL. */
+ * interbinning the mixed-precision second pass is always a walk of wavefronts
+ * over chunks of consecutive rows, and the FP64 one row tiles that store the
+ * transforms for a separate 2F pass).  Any output pointer may be NULL. */
 fstat_status fstat_plan_info(fstat_plan_t plan, int32_t segment, int32_t* nfft, int32_t* p,
                              int32_t* q, int32_t* templates_per_launch, int32_t* skies_per_batch,
                              int32_t* pass_a_variant, int32_t* pass_b_variant);

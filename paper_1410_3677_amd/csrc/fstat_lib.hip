@@ -125,6 +125,7 @@ struct fstat_plan_s {
   // per-sky parameters and resampled series twice (the sky batch being prepared and the
   // one being searched), per-sky scratch, template intermediate
   size_t off_sp[2] = {0, 0}, off_part = 0, off_zt[2] = {0, 0}, off_sky = 0, off_tmpl = 0;
+  size_t off_xs = 0;   // FP64 with interbinning: the second pass's transforms [B][tL][2]
   int nblk_max = 0;
   long n_max = 0, L_max = 0, M_max = 0;
   long TL_max = 0;             // longest template FFT
@@ -232,6 +233,9 @@ static size_t layout(fstat_plan_t p, int Sb, int B, bool commit) {
   // template intermediate [B][tL][2]
   const size_t o_tmpl = off;
   off = align256(off + (size_t)B * 2 * p->TL_max * cx);
+  // FP64 with interbinning: the transforms themselves, for the interbinning epilogue
+  const size_t o_xs = off;
+  if (p->fp64 && p->opt.interbinning) off = align256(off + (size_t)B * 2 * p->TL_max * cx);
   if (commit) {
     for (int k = 0; k < 2; ++k) {
       p->off_sp[k] = o_sp[k];
@@ -240,6 +244,7 @@ static size_t layout(fstat_plan_t p, int Sb, int B, bool commit) {
     p->off_part = o_part;
     p->off_sky = o_sky;
     p->off_tmpl = o_tmpl;
+    p->off_xs = o_xs;
   }
   return off;
 }
@@ -367,6 +372,7 @@ struct Dev {
   cx<T>* zt() const { return (cx<T>*)((char*)p->ws + p->off_zt[buf]); }
   cx<T>* sky() const { return (cx<T>*)((char*)p->ws + p->off_sky); }
   cx<T>* tmpl() const { return (cx<T>*)((char*)p->ws + p->off_tmpl); }
+  cx<T>* xs() const { return (cx<T>*)((char*)p->ws + p->off_xs); }
 };
 
 // forward or inverse L-point FFT of `items` pairs of series, two passes
@@ -555,6 +561,27 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
         }
         if constexpr (PP >= 64) {
           const int ntiles = si.tQ / tw_b<T, PP>();
+          if (sizeof(T) == 8 && si.ibw != 0.0) {
+            // interbinning in FP64: the tiled pass stores the transforms, then an epilogue
+            // forms the interbinned 2F of the launch's templates
+            OutArgs ox = oa;
+            ox.spectrum = d.xs();
+            hipLaunchKernelGGL((k_tmpl_b<T, PP, 3>), dim3(ntiles * nt), dim3(tmpl_nt_b<T, PP>()), 0, st, ta, d.sp(),
+                               tbuf, ox, d.twst);
+            err = hipGetLastError();
+            if (err != hipSuccess) return;
+            const int kc0 = oa.k_min / 2, nkc = (oa.k_max + 1) / 2 - kc0;
+            const dim3 grid((unsigned)((nkc + 255) / 256), (unsigned)nt);
+            const cx<T>* xs = d.xs();
+            if (capture)
+              hipLaunchKernelGGL((k_interbin_2f<T, 2>), grid, dim3(256), 0, st, ta, d.sp(), xs, oa, si.ibw, kc0, nkc);
+            else if (mode == 0)
+              hipLaunchKernelGGL((k_interbin_2f<T, 0>), grid, dim3(256), 0, st, ta, d.sp(), xs, oa, si.ibw, kc0, nkc);
+            else
+              hipLaunchKernelGGL((k_interbin_2f<T, 1>), grid, dim3(256), 0, st, ta, d.sp(), xs, oa, si.ibw, kc0, nkc);
+            err = hipGetLastError();
+            return;
+          }
           if (capture)
             hipLaunchKernelGGL((k_tmpl_b<T, PP, 2>), dim3(ntiles * nt), dim3(tmpl_nt_b<T, PP>()), 0, st, ta, d.sp(),
                                tbuf, oa, d.twst);
@@ -1216,8 +1243,6 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_opt
   if (opt.k_min < 0 || opt.k_max < 0 || (opt.k_max != 0 && opt.k_max <= opt.k_min))
     return fail(nullptr, FSTAT_E_INVAL, "bad bin range");
   if (opt.interbinning != 0 && opt.interbinning != 1) return fail(nullptr, FSTAT_E_INVAL, "interbinning must be 0 or 1");
-  if (opt.interbinning && opt.precision != FSTAT_PREC_MIXED)
-    return fail(nullptr, FSTAT_E_NOT_IMPLEMENTED, "interbinning is implemented for the mixed precision only");
 
   auto p = new (std::nothrow) fstat_plan_s();
   if (!p) return fail(nullptr, FSTAT_E_NOMEM, "plan allocation");

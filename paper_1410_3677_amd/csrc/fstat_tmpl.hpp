@@ -556,6 +556,20 @@ __global__ void __launch_bounds__((tmpl_nt_b<T, P>())) k_tmpl_b(TmplArgs ta, con
   cx<T> va[PBL][RL], vb[PBL][RL];
   stage_from_lds<T, P, G, NSL, RL, PBL, false>(va, cola, g, twst);
   stage_from_lds<T, P, G, NSL, RL, PBL, false>(vb, colb, g, twst);
+  if constexpr (MODE == 3) {
+    // the transform itself, for an epilogue of its own: oa.spectrum as [item][k][a|b]
+    cx<T>* xs = (cx<T>*)oa.spectrum + (long)(2 * item) * ta.L;
+#pragma unroll
+    for (int b = 0; b < PBL; ++b) {
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int k = ta.Q * (g + G * b + NSL * r) + k2;
+        xs[2 * k] = va[b][r];
+        xs[2 * k + 1] = vb[b][r];
+      }
+    }
+    return;
+  }
   const SkyParams& pr = sp[skyl];
   const T cfa = (T)pr.cfa, cfb = (T)pr.cfb, cfab = (T)pr.cfab;
   if constexpr (MODE == 2) {
@@ -632,6 +646,79 @@ __global__ void __launch_bounds__((tmpl_nt_b<T, P>())) k_tmpl_b(TmplArgs ta, con
         }
         ++slot;
       }
+    }
+  }
+}
+
+// ------------------------------------------------ interbinned 2F from stored transforms (FP64)
+// The tiled second pass (mode 3) has stored each template's transform of L points,
+// xs = [item][k][a|b].  Bin 2k of the nfft grid is X_k and bin 2k + 1 is
+// c (X_k - X_{k+1 mod L}), for both series; 2F, threshold and compaction as in the
+// tiled pass (one atomic per workgroup).  Grid: (coarse-bin blocks, templates of the
+// launch); thread = one coarse bin k in [kc0, kc0 + nkc).
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_interbin_2f(TmplArgs ta, const SkyParams* __restrict__ sp,
+                                                     const cx<T>* __restrict__ xs, OutArgs oa, double c, int kc0,
+                                                     int nkc) {
+  __shared__ unsigned long long sbase;
+  const int item = blockIdx.y;
+  const int t = ta.t0 + item;
+  const int skyl = t / ta.nfdot, sidx = t % ta.nfdot;
+  const int kc = kc0 + (int)blockIdx.x * 256 + (int)threadIdx.x;
+  const SkyParams& pr = sp[skyl];
+  const T cfa = (T)pr.cfa, cfb = (T)pr.cfb, cfab = (T)pr.cfab;
+  T v[2] = {(T)0, (T)0};
+  bool in[2] = {false, false};
+  if (kc < kc0 + nkc) {
+    const cx<T>* x = xs + (long)(2 * item) * ta.L;
+    const int kn = kc + 1 == ta.L ? 0 : kc + 1;
+    const cx<T> a0 = x[2 * kc], b0 = x[2 * kc + 1], a1 = x[2 * kn], b1 = x[2 * kn + 1];
+    const T w = (T)c;
+    const cx<T> da = a0 - a1, db = b0 - b1;
+    v[0] = two_f_value(a0, b0, cfa, cfb, cfab);
+    v[1] = two_f_value(mk<T>(w * da.re, w * da.im), mk<T>(w * db.re, w * db.im), cfa, cfb, cfab);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) in[e] = 2 * kc + e >= oa.k_min && 2 * kc + e < oa.k_max;
+  }
+  if constexpr (MODE == 1) {
+    T* out = (T*)oa.spectrum + ((long)(ta.sky0 + skyl) * ta.nfdot + sidx) * (long)(oa.k_max - oa.k_min);
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      if (in[e]) out[2 * kc + e - oa.k_min] = v[e];
+    return;
+  }
+  if constexpr (MODE == 2) {
+    float* out = (float*)oa.spectrum + (long)item * (long)(oa.k_max - oa.k_min);
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      if (in[e]) out[2 * kc + e - oa.k_min] = (float)v[e];
+  }
+  uint32_t mask = 0;
+#pragma unroll
+  for (int e = 0; e < 2; ++e)
+    if (in[e] && v[e] > (T)oa.threshold) mask |= 1u << e;
+  int total;
+  const int off = block_exclusive_scan_n<256>(__popc(mask), &total);
+  if (total == 0) return;
+  if (threadIdx.x == 0) sbase = atomicAdd(oa.count, (unsigned long long)total);
+  __syncthreads();
+  const int search = oa.search_next[0] - 1;
+  unsigned long long slot = sbase + (unsigned long long)off;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    if (mask & (1u << e)) {
+      if (slot < (unsigned long long)oa.capacity) {
+        CandEntry ce;
+        ce.search = search;
+        ce.segment = oa.segment;
+        ce.sky = ta.sky0 + skyl;
+        ce.fdot_idx = sidx;
+        ce.bin = 2 * kc + e;
+        ce.pad = 0;
+        ce.twoF = (double)v[e];
+        oa.cand[slot] = ce;
+      }
+      ++slot;
     }
   }
 }

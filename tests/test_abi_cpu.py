@@ -94,9 +94,6 @@ def test_invalid_arguments_are_rejected(seg, opts, needle):
 def test_interbinning_option_is_validated_on_the_host():
     st, h, msg = _plan([_seg()], interbinning=2)
     assert st == F.E_INVAL and h.value is None and "interbinning" in msg
-    # only the mixed-precision path implements interbinning
-    st, h, msg = _plan([_seg()], interbinning=1, precision=F.PREC_FP64)
-    assert st == F.E_NOT_IMPLEMENTED and h.value is None and "mixed" in msg
     # the transforms of nfft/2 points need nfft >= 2^13 (n = 2048 gives nfft = 2^12)
     st, h, msg = _plan([_seg(n=2048)], interbinning=1)
     assert st == F.E_INVAL and h.value is None and "2^13" in msg

@@ -174,12 +174,8 @@ def test_even_bins_match_the_zero_padded_search(torch):
     assert err < TOL
 
 
-def test_interbinning_needs_mixed_precision_and_a_long_enough_transform(torch):
+def test_interbinning_needs_a_long_enough_transform(torch):
     from paper_1410_3677_amd import fstat as F
-    w = synth.workload("tiny")
-    with pytest.raises(F.FstatError) as ei:
-        make_plan(w.segments, precision=0, interbinning=1)
-    assert ei.value.status == F.E_NOT_IMPLEMENTED
     seg = synth.make_segment(2048, 2.0, 100.0, 1.0, 4242, [])
     with pytest.raises(F.FstatError) as ei:
         make_plan([seg], interbinning=1)
@@ -208,3 +204,65 @@ def test_ragged_segments_in_one_call_equal_separate_plans(torch):
         np.testing.assert_array_equal(k_all["bin"][m], k1["bin"])
         np.testing.assert_allclose(r_all["twoF"][m], r1["twoF"], rtol=1e-6, atol=0)
         one.destroy()
+
+
+# ---- FP64: the tiled second pass stores the transforms, a separate pass forms 2F ------------
+TOL64 = 1e-10
+
+
+def _gpu64(plan, al, de, fd, nbins):
+    import torch
+    out = torch.empty(len(al) * len(fd) * nbins, dtype=torch.float64, device="cuda")
+    plan.twoF_spectrum(0, dev(al), dev(de), dev(fd), out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().reshape(len(al), len(fd), nbins)
+
+
+@pytest.mark.parametrize("case", ["tiny", "full", "n3000", "n120000", "tiny-range", "full-wrap", "tiny-fullform"])
+def test_fp64_interbinned_spectra(torch, case):
+    if case.startswith("n"):
+        n = int(case[1:])
+        seg = synth.make_segment(n, 2.0, 100.0, 1.0, 5100 + n, synth.draw_injections(np.random.default_rng(n), 1,
+                                                                                       15.0, 15.0))
+        al, de, fd = np.array([0.3, seg.injections[0].alpha]), np.array([-0.2, seg.injections[0].delta]), \
+            np.array([0.0, seg.injections[0].fdot])
+    else:
+        w = synth.workload("full" if case.startswith("full") else "tiny")
+        seg = w.segments[0]
+        al, de, fd = w.alpha[:2], w.delta[:2], w.fdot[:2]
+    nfft = synth.nfft_for(seg.n)
+    k0, k1 = 0, nfft // 2
+    if case == "tiny-range":
+        k0, k1 = 777, 5001
+    if case == "full-wrap":
+        k0, k1 = 131071, nfft
+    full = case.endswith("fullform")
+    note(f"FP64 interbinning spectrum, {case}: n={seg.n}, bins [{k0}, {k1})")
+    plan = make_plan([seg], precision=0, interbinning=1, k_min=k0, k_max=k1, form=int(full))
+    got = _gpu64(plan, al, de, fd, k1 - k0)
+    ref = _oracle(seg, al, de, fd, nfft, k0, k1, full=full)
+    err = rel_err_floor(got, ref)
+    note(f"max rel err {err:.3e}")
+    assert err < TOL64
+
+
+def test_fp64_interbinned_candidates_batched(torch):
+    w = synth.workload("full")
+    seg = w.segments[0]
+    nfft = synth.nfft_for(seg.n)
+    al, de, fd = w.alpha[[5, 77]], w.delta[[5, 77]], w.fdot[:6]
+    note("FP64 interbinning candidates, N=86164, 2 sky x 6 spindowns, 4 templates per launch")
+    plan = make_plan([seg], precision=0, interbinning=1, templates_per_launch=4, skies_per_batch=2)
+    plan.search_batch(0, dev(al), dev(de), dev(fd))
+    recs, keys, n = plan.candidates()
+    ref = _oracle(seg, al, de, fd, nfft)
+    key3 = np.stack([keys["sky"], keys["fdot_idx"], keys["bin"]], 1)
+    ng, no, flips, mism, err = compare_candidates(key3, recs["twoF"], ref, w.threshold, 1e-9)
+    note(f"gpu {ng} oracle {no} flips {flips} mismatches {len(mism)} err {err:.3e}")
+    assert no > 1000 and not mism and err < TOL64
+    assert len(np.unique(key3, axis=0)) == len(key3)
+    # mixed and FP64 interbinning agree on every key away from the threshold
+    m = make_plan([seg], precision=1, interbinning=1)
+    m.search_batch(0, dev(al), dev(de), dev(fd))
+    rm, km, nm_ = m.candidates()
+    assert abs(nm_ - n) <= flips + int(np.sum(np.abs(ref - w.threshold) <= 1e-4 * w.threshold))

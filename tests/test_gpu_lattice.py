@@ -244,3 +244,42 @@ def test_full_size_source_at_a_shifted_grid_point(torch):
              f"err {err:.2e}")
         assert not mism and err < 1e-4
     note(f"source: 2F {rec['twoF']:.2f} at f {rec['f_hz']:.12f} Hz")
+
+
+@pytest.mark.parametrize("ib", [0, 1])
+def test_ragged_segments_in_one_lattice_call_equal_separate_plans(torch, ib):
+    """All segments in one lattice call (segment = -1): every segment has its own nfft, so
+    its own frequency shifts u; the frequency row is one bin of the shortest transform,
+    a whole number of bins of every longer one."""
+    from paper_1410_3677_amd import fstat as F
+    w = synth.workload("ragged")
+    segs = w.segments[:4]
+    nffts = [synth.nfft_for(s.n) for s in segs]
+    f_ref = 100.25
+    M = synth.lattice_matrix(min(nffts), 2.0, f_ref, 12, -2e-10, 17)
+    lat = F.lattice(M, EPS, f_ref)
+    note(f"lattice, ragged, interbinning={ib}: " + ", ".join(f"n={s.n}" for s in segs))
+    sky = _gpu_sky(F, lat, 1, 3)
+    pts = ora.lattice_sky_points(M, ora.lattice_sky_range(M, f_ref), 1, EPS, f_ref)[:3]
+    plan = make_plan(segs, interbinning=ib)
+    plan.search_lattice(-1, lat, sky, -2, 2)
+    r_all, k_all, n_all = plan.candidates()
+    assert n_all > 0
+    for si, seg in enumerate(segs):
+        one = make_plan([seg], interbinning=ib)
+        one.search_lattice(0, lat, sky, -2, 2)
+        r1, k1, n1 = one.candidates()
+        m = k_all["segment"] == si
+        assert int(m.sum()) == n1, (si, int(m.sum()), n1)
+        for f in ("sky", "fdot_idx", "bin"):
+            np.testing.assert_array_equal(k_all[f][m], k1[f])
+        np.testing.assert_allclose(r_all["twoF"][m], r1["twoF"], rtol=1e-6, atol=0)
+        np.testing.assert_array_equal(r_all["f_hz"][m], r1["f_hz"])
+        # each record's frequency uses its own segment's nfft and shift
+        nfft = nffts[si]
+        for j in np.nonzero(m)[0][:20]:
+            p = pts[k_all["sky"][j]]
+            w1, u = ora.lattice_template(M, -2 + int(k_all["fdot_idx"][j]), p[4], p[5], nfft)
+            assert r_all["f_hz"][j] == seg.f_off + (int(k_all["bin"][j]) + u) / (nfft * seg.dt)
+            assert r_all["fdot"][j] == w1 / (math.pi * seg.dt * seg.dt)
+        one.destroy()
