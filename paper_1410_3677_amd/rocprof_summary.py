@@ -5,6 +5,10 @@
         --last N: only the last N dispatches of each kernel (for instance the timed steps
         of a run that starts with warm-up steps)
 
+    python -m paper_1410_3677_amd.rocprof_summary counters RESULTS.db [--match k_tmpl]
+        average of every collected counter per dispatch of each kernel (summed over
+        hardware instances) as markdown
+
     python -m paper_1410_3677_amd.rocprof_summary traffic FETCH.db WRITE.db --copy-bytes B \
             --copy-match MulFunctor --templates-per-launch T [--kernel KEY=SUBSTRING ...] [--json OUT]
         average FETCH_SIZE / WRITE_SIZE per dispatch of each kernel, scaled by what the
@@ -59,6 +63,22 @@ def counter_means(db: str, counter: str):
     return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
 
 
+def counters(db: str, match: str = ""):
+    """Per-kernel averages of every counter in a --pmc results database."""
+    c = sqlite3.connect(db)
+    names = [r[0] for r in c.execute("select distinct counter_name from counters_collection order by counter_name")]
+    cols = {n: counter_means(db, n) for n in names}
+    kernels = sorted({k for m in cols.values() for k in m})
+    out = ["| kernel | dispatches | " + " | ".join(names) + " |", "|---|---|" + "---|" * len(names)]
+    for k in kernels:
+        if match and match not in k:
+            continue
+        n = max(cols[nm].get(k, (0.0, 0))[1] for nm in names)
+        vals = " | ".join(f"{cols[nm].get(k, (0.0, 0))[0]:.6g}" for nm in names)
+        out.append(f"| `{_short(k)}` | {n} | {vals} |")
+    return "\n".join(out)
+
+
 def traffic(fetch_db: str, write_db: str, copy_bytes: int, copy_match: str, tpl: int, kernel_keys=None):
     keys = kernel_keys or [("template_a", "k_tmpl_a"), ("template_b", "k_tmpl_b")]
     fetch = counter_means(fetch_db, "FETCH_SIZE")
@@ -92,6 +112,9 @@ def main(argv=None):
     t.add_argument("db")
     t.add_argument("--match", default="")
     t.add_argument("--last", type=int, default=0)
+    cn = sub.add_parser("counters")
+    cn.add_argument("db")
+    cn.add_argument("--match", default="")
     f = sub.add_parser("traffic")
     f.add_argument("fetch_db")
     f.add_argument("write_db")
@@ -106,6 +129,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         print(trace(a.db, a.match, a.last))
+    elif a.cmd == "counters":
+        print(counters(a.db, a.match))
     else:
         keys = [tuple(x.split("=", 1)) for x in a.kernel] or None
         res = traffic(a.fetch_db, a.write_db, a.copy_bytes, a.copy_match, a.templates_per_launch, keys)
