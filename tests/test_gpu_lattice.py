@@ -283,3 +283,36 @@ def test_ragged_segments_in_one_lattice_call_equal_separate_plans(torch, ib):
             assert r_all["f_hz"][j] == seg.f_off + (int(k_all["bin"][j]) + u) / (nfft * seg.dt)
             assert r_all["fdot"][j] == w1 / (math.pi * seg.dt * seg.dt)
         one.destroy()
+
+
+def test_graph_replays_follow_the_lattice(torch):
+    """Searches are captured as HIP graphs keyed on their arguments: a repeated lattice call
+    replays its graph with the same result, and a call with another spindown row (same
+    device arrays) is not served by the stale graph."""
+    from paper_1410_3677_amd import fstat as F
+    n = 4096
+    M, f_ref, lat = _lattice(n, 12, 9)
+    M2 = M.copy()
+    M2[1, 0] += 0.37 * 2 * math.pi / synth.nfft_for(n)
+    M2[1, 1] *= 1.5
+    lat2 = F.lattice(M2, EPS, f_ref)
+    seg = synth.make_segment(n, 2.0, 100.0, 1.0, 909, [])
+    sky = _gpu_sky(F, lat, 1, 3)
+    plan = make_plan([seg], threshold_2F=8.0)
+    res = []
+    for lt in (lat, lat, lat2, lat2, lat):
+        plan.search_lattice(0, lt, sky, -2, 2)
+        r, k, cnt = plan.candidates()
+        res.append((r, k))
+    fresh = []
+    for lt in (lat, lat2):
+        p = make_plan([seg], threshold_2F=8.0, use_graph=0)
+        p.search_lattice(0, lt, sky, -2, 2)
+        r, k, cnt = p.candidates()
+        fresh.append((r, k))
+    for got, want in zip(res, [fresh[0], fresh[0], fresh[1], fresh[1], fresh[0]]):
+        assert len(got[0]) == len(want[0]) > 10
+        for f in ("sky", "fdot_idx", "bin"):
+            np.testing.assert_array_equal(got[1][f], want[1][f])
+        np.testing.assert_array_equal(got[0], want[0])
+    assert not np.array_equal(res[0][0]["f_hz"][:10], res[2][0]["f_hz"][:10])
