@@ -272,15 +272,16 @@ fstat_status fstat_plan_info(fstat_plan_t plan, int32_t segment, int32_t* nfft, 
                              int32_t* q, int32_t* templates_per_launch, int32_t* skies_per_batch,
                              int32_t* pass_a_variant, int32_t* pass_b_variant);
 
-/* Autotuner: time the search of `segment` (its own data, a synthetic sky and
- * spindown grid) for candidate templates-per-launch, skies-per-batch and
+/* Autotuner: time the search of `segment` (its own data, a synthetic grid of
+ * 128 sky positions and 256 spindowns) for candidate templates-per-launch, skies-per-batch and
  * first-pass kernel variants that fit the workspace budget, keep the fastest,
  * and append it to options.tuning_cache_path if set (one line per device,
  * FFT length and precision: "<device> <nfft> <precision + 2 interbinning>
  * <templates per launch> <skies per batch> <pass_a_variant + 2
  * pass_b_variant>"; the last
  * matching line wins).  Runs synchronously on `stream` for roughly
- * budget_ms.  Must be called before fstat_plan_set_workspace: the workspace
+ * budget_ms, and at least one warm-up and one timed search per candidate
+ * (about 1.5 s at nfft = 2^18).  Must be called before fstat_plan_set_workspace: the workspace
  * size changes with the batch sizes (query it again afterwards), and before
  * fstat_plan_attach_vetter.  Candidates found by the trial searches are
  * discarded. */

@@ -1804,8 +1804,10 @@ fstat_status fstat_autotune(fstat_plan_t plan, int32_t segment, double budget_ms
   if (plan->vet) return fail(plan, FSTAT_E_STATE, "autotune must precede fstat_plan_attach_vetter");
   hipStream_t st = (hipStream_t)stream;
   const SegInfo& si = plan->segs[segment];
-  // trial template lists: 32 sky positions spread over the sphere, 256 spindowns
-  const int nsky = 32, nfdot = 256;
+  // trial template lists: 128 sky positions spread over the sphere (several batches of
+  // every candidate batch size, so that the first batch's sky stage, which no template
+  // work hides, weighs little), 256 spindowns
+  const int nsky = 128, nfdot = 256;
   std::vector<double> h(2 * nsky + nfdot);
   for (int i = 0; i < nsky; ++i) {
     h[i] = std::fmod(2.0 * M_PI * i * 0.6180339887498949, 2.0 * M_PI);
