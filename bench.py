@@ -431,6 +431,21 @@ def main():
                  "workload": f"plain FP64-phase path, one template per launch, N=86164, {len(w2.alpha)} sky x "
                              f"{len(w2.fdot)} spindown", "candidates": n2}
         log(f"plain: {plain['value']:.4g} templates/s")
+        if not args.no_cpu:
+            # F error of the plain path against the FP64 oracle: 1 sky x 16 spindowns, all bins
+            from oracle import fstat_oracle as ora
+            nf2 = synth.nfft_for(seg2.n)
+            nb2 = nf2 // 2
+            fsel = w2.fdot[:: max(1, len(w2.fdot) // 16)][:16]
+            spec2 = torch.empty(len(fsel) * nb2, dtype=torch.float32, device="cuda")
+            p2.twoF_spectrum(0, a2[:1], d2[:1], dev(fsel), spec2)
+            g2 = spec2.view(len(fsel), nb2).cpu().numpy().astype(np.float64)
+            sky2 = ora.sky_stage(seg2, float(w2.alpha[0]), float(w2.delta[0]), nf2)
+            e2 = max(float(np.max(np.abs(g2[j] - ref) / np.maximum(ref, 4.0)))
+                     for j, ref in enumerate(ora.template_two_f(seg2, sky2, float(f), nf2) for f in fsel))
+            plain["f_rel_err_vs_fp64"] = e2
+            plain["accuracy_sample"] = f"1 sky x {len(fsel)} spindown templates of the plain workload, all bins"
+            log(f"plain: max F rel err vs FP64 {e2:.3e}")
         p2.destroy()
 
     # ---------------- CPU oracle baseline on a bounded sample (+ F error vs FP64 there)
