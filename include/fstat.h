@@ -102,8 +102,9 @@ typedef struct {
                                      stage's memory traffic; the odd bins are an approximation
                                      (exact for a sinusoid midway between bins; odd bins of pure
                                      noise have a larger mean than even ones).  Both precisions
-                                     (FP64 stores the transforms, then forms 2F in a pass of its
-                                     own); needs nfft >= 2^13. */
+                                     (FP64, and mixed precision at nfft = 2^20, store the
+                                     transforms, then form 2F in a pass of their own); needs
+                                     nfft >= 2^13. */
 } fstat_options;
 
 /* The paper's five numbers of a candidate (Sect. 2). */
@@ -265,9 +266,10 @@ fstat_status fstat_profile_read(fstat_plan_t plan, int32_t kernel_class, int64_t
  * resident round of wavefronts that walk the launch's rows, prefetching the
  * next row and staging candidates in LDS; variant 1 applies to the mixed
  * precision path with P <= 512, other segments use row tiles; with
- * interbinning the mixed-precision second pass is always a walk of wavefronts
- * over chunks of consecutive rows, and the FP64 one row tiles that store the
- * transforms for a separate 2F pass).  Any output pointer may be NULL. */
+ * interbinning the mixed-precision second pass with P <= 512 is always a walk
+ * of wavefronts over chunks of consecutive rows; FP64 and P = 1024 use row
+ * tiles that store the transforms for a separate 2F pass).  Any output pointer
+ * may be NULL. */
 fstat_status fstat_plan_info(fstat_plan_t plan, int32_t segment, int32_t* nfft, int32_t* p,
                              int32_t* q, int32_t* templates_per_launch, int32_t* skies_per_batch,
                              int32_t* pass_a_variant, int32_t* pass_b_variant);

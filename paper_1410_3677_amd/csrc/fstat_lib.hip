@@ -212,6 +212,16 @@ static int tw_of(int len) {
   return tw;
 }
 
+// Interbinning whose second pass is the tiled kernel plus a separate 2F pass: FP64, and
+// mixed precision for template transforms with P > 512 rows' length (nfft = 2^20).
+static bool tiled_interbinning(fstat_plan_t p) {
+  if (!p->opt.interbinning) return false;
+  if (p->fp64) return true;
+  for (const SegInfo& si : p->segs)
+    if (si.tP > 512) return true;
+  return false;
+}
+
 // Workspace layout for Sb skies and B templates (bytes).
 static size_t layout(fstat_plan_t p, int Sb, int B, bool commit) {
   const size_t cx = p->cx_bytes;
@@ -233,9 +243,10 @@ static size_t layout(fstat_plan_t p, int Sb, int B, bool commit) {
   // template intermediate [B][tL][2]
   const size_t o_tmpl = off;
   off = align256(off + (size_t)B * 2 * p->TL_max * cx);
-  // FP64 with interbinning: the transforms themselves, for the interbinning epilogue
+  // interbinning through the tiled second pass (FP64, or P > 512): the transforms
+  // themselves, for the interbinning epilogue
   const size_t o_xs = off;
-  if (p->fp64 && p->opt.interbinning) off = align256(off + (size_t)B * 2 * p->TL_max * cx);
+  if (tiled_interbinning(p)) off = align256(off + (size_t)B * 2 * p->TL_max * cx);
   if (commit) {
     for (int k = 0; k < 2; ++k) {
       p->off_sp[k] = o_sp[k];
@@ -561,9 +572,9 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
         }
         if constexpr (PP >= 64) {
           const int ntiles = si.tQ / tw_b<T, PP>();
-          if (sizeof(T) == 8 && si.ibw != 0.0) {
-            // interbinning in FP64: the tiled pass stores the transforms, then an epilogue
-            // forms the interbinned 2F of the launch's templates
+          if (si.ibw != 0.0) {
+            // interbinning through the tiled pass (FP64, or P > 512): it stores the
+            // transforms, then an epilogue forms the interbinned 2F of the launch's templates
             OutArgs ox = oa;
             ox.spectrum = d.xs();
             hipLaunchKernelGGL((k_tmpl_b<T, PP, 3>), dim3(ntiles * nt), dim3(tmpl_nt_b<T, PP>()), 0, st, ta, d.sp(),

@@ -266,3 +266,33 @@ def test_fp64_interbinned_candidates_batched(torch):
     m.search_batch(0, dev(al), dev(de), dev(fd))
     rm, km, nm_ = m.candidates()
     assert abs(nm_ - n) <= flips + int(np.sum(np.abs(ref - w.threshold) <= 1e-4 * w.threshold))
+
+
+@pytest.mark.parametrize("n,precision", [(524288, 1), (524288, 0), (262145, 1)])
+def test_interbinning_at_the_longest_transforms(torch, n, precision):
+    """Segments above 2^18 samples have nfft = 2^20, so the interbinned transform has
+    P = 1024 rows: the tiled second pass stores the transforms and the interbinning pass
+    forms 2F, in both precisions (n = 2^19 is the longest segment the library takes)."""
+    rng = np.random.default_rng(n + 3)
+    injs = synth.draw_injections(rng, 1, 15.0, 15.0)
+    seg = synth.make_segment(n, 2.0, 100.0, 1.0, 6100 + n, injs)
+    nfft = synth.nfft_for(n)
+    note(f"interbinning at the longest transforms: n={n} nfft={nfft} precision={precision}")
+    plan = make_plan([seg], precision=precision, interbinning=1)
+    inf = plan.info(0)
+    assert inf["nfft"] == 1 << 20 and inf["p"] == 1024 and inf["q"] == 512
+    al, de = np.array([0.3, injs[0].alpha]), np.array([-0.2, injs[0].delta])
+    fd = np.array([injs[0].fdot])
+    got = _gpu64(plan, al, de, fd, nfft // 2) if precision == 0 else _gpu(plan, al, de, fd, nfft // 2)
+    ref = _oracle(seg, al, de, fd, nfft)
+    err = rel_err_floor(got, ref)
+    note(f"max rel err {err:.3e}")
+    assert err < (TOL64 if precision == 0 else TOL)
+    # candidates of the same templates
+    plan2 = make_plan([seg], precision=precision, interbinning=1)
+    plan2.search_batch(0, dev(al), dev(de), dev(fd))
+    recs, keys, cnt = plan2.candidates()
+    key3 = np.stack([keys["sky"], keys["fdot_idx"], keys["bin"]], 1)
+    ng, no, flips, mism, cerr = compare_candidates(key3, recs["twoF"], ref, 20.0, 1e-9 if precision == 0 else GUARD)
+    note(f"candidates gpu {ng} oracle {no} flips {flips} mismatches {len(mism)}")
+    assert no > 100 and not mism

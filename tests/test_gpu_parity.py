@@ -433,3 +433,25 @@ def test_ragged_admission_with_small_budget_gives_same_candidates(torch, ragged)
     with pytest.raises(F.FstatError) as ei:
         make_plan(segs, workspace_budget_bytes=4 << 20)
     assert ei.value.status == F.E_ADMISSION
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_longest_segment(torch, precision):
+    """n = 2^19, the longest segment the library takes: nfft = 2^20, P = Q = 1024 (the
+    tiled second pass in both precisions)."""
+    n = 1 << 19
+    rng = np.random.default_rng(19)
+    injs = synth.draw_injections(rng, 1, 15.0, 15.0)
+    seg = synth.make_segment(n, 2.0, 100.0, 1.0, 5119, injs)
+    nfft = synth.nfft_for(n)
+    note(f"longest segment n={n} nfft={nfft} precision={precision}")
+    plan = make_plan([seg], precision=precision)
+    inf = plan.info(0)
+    assert inf["nfft"] == 1 << 20 and inf["p"] * inf["q"] == 1 << 20
+    al, de = np.array([0.3, injs[0].alpha]), np.array([-0.2, injs[0].delta])
+    fd = np.array([injs[0].fdot])
+    got = gpu_spectrum(plan, 0, al, de, fd, nfft // 2, precision == 0)
+    ref = oracle_spectrum(seg, al, de, fd, nfft)
+    err = rel_err_floor(got, ref)
+    note(f"max rel err {err:.3e}")
+    assert err < (TOL_FP64 if precision == 0 else TOL_MIXED)
