@@ -125,10 +125,10 @@ def test_training_on_oracle_patches_beats_the_threshold_alone(torch):
     assert far < 0.5
 
 
-@pytest.mark.parametrize("ib", [0, 1])
-def test_fused_capture_scores_equal_network_on_search_spectra(torch, ib):
+@pytest.mark.parametrize("precision,ib", [(1, 0), (1, 1), (0, 0), (0, 1)])
+def test_fused_capture_scores_equal_network_on_search_spectra(torch, precision, ib):
     from paper_1410_3677_amd import fstat as F
-    note(f"fused patch capture after the F kernel, interbinning={ib}")
+    note(f"fused patch capture after the F kernel, precision={precision}, interbinning={ib}")
     w = synth.workload("full")
     seg = w.segments[0]
     nfft = synth.nfft_for(seg.n)
@@ -136,17 +136,18 @@ def test_fused_capture_scores_equal_network_on_search_spectra(torch, ib):
     al, de, fd = w.alpha[:2], w.delta[:2], w.fdot[:3]
     v = F.Vetter(512)
     v.set_params(_theta(5).astype(np.float32))
-    plan = make_plan([seg], use_graph=0, interbinning=ib)
+    plan = make_plan([seg], use_graph=0, interbinning=ib, precision=precision)
     plan.attach_vetter(v, 1 << 16)
     plan.search_batch(0, dev(al), dev(de), dev(fd))
     plan.vet_candidates()
     recs, keys, n = plan.candidates()
     assert n > 100 and np.all(np.isfinite(keys["vet_score"]))
     # the same network on windows of the 2F spectrum of the same templates
-    spec = torch.empty(len(al) * len(fd) * nb, dtype=torch.float32, device="cuda")
-    plain = make_plan([seg], use_graph=0, interbinning=ib)
+    spec = torch.empty(len(al) * len(fd) * nb, dtype=torch.float64 if precision == 0 else torch.float32,
+                       device="cuda")
+    plain = make_plan([seg], use_graph=0, interbinning=ib, precision=precision)
     plain.twoF_spectrum(0, dev(al), dev(de), dev(fd), spec)
-    s = spec.view(len(al), len(fd), nb).cpu().numpy()
+    s = spec.view(len(al), len(fd), nb).cpu().numpy().astype(np.float32)   # the capture's FP32 rows
     win = np.zeros((n, 256), np.float32)
     for i, (a, f, b) in enumerate(zip(keys["sky"], keys["fdot_idx"], keys["bin"])):
         lo, hi = b - 128, b + 128
