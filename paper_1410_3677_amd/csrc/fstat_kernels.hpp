@@ -206,7 +206,7 @@ constexpr int tile_width() {
   return p2;
 }
 
-enum SrcKind { SRC_PLAIN = 0, SRC_UPSPEC = 1 };
+enum SrcKind { SRC_PLAIN = 0, SRC_HALFSHIFT = 1 };
 
 // Map a linear workgroup id to (tile, item) so that each XCD (workgroups are
 // dealt round-robin over 8 XCDs) keeps a fixed subset of tiles for all items.
@@ -224,15 +224,19 @@ __device__ __forceinline__ void xcd_tile_item(int ntiles, int& tile, int& item) 
 }
 
 // Pass A of an L = P*Q FFT (DFT length Q along j2), two series per item.
-//   SRC_PLAIN:  x_s[j] = in[(2 item + s) * ld_in + j] for j < nvalid, else 0
-//   SRC_UPSPEC: x_s[k] = U[k] built from the length-M = L/2 spectrum Z:
-//               Z[k] for k < M/2, Z[k - M] for k >= 3M/2, else 0
+//   SRC_PLAIN:     x_s[j] = in[(2 item + s) * ld_in + j] for j < nvalid, else 0
+//   SRC_HALFSHIFT: x_s[k] = Z[k] exp(i pi k_s / L), k_s = k for k < L/2, k - L otherwise
+//                  (Z = in, the spectrum of a series of L samples; shlo, shhi: the
+//                  twiddle tables of length 2L).  The inverse transform of x is the
+//                  series half a sample later, the odd samples of its band-limited 2x
+//                  upsampling with the Nyquist term on the negative side.
 // Output T_s[k2 * P + j1] at out + (2 item + s) * L.
 template <typename T, int Q, bool INV, int SRC>
 __global__ void __launch_bounds__(NT) k_fft_pass_a(const cx<T>* __restrict__ in, long ld_in, int nvalid,
                                                    cx<T>* __restrict__ out, int P, int L,
                                                    const cx<T>* __restrict__ tw1024,
-                                                   const cx<T>* __restrict__ twlo, const cx<T>* __restrict__ twhi) {
+                                                   const cx<T>* __restrict__ twlo, const cx<T>* __restrict__ twhi,
+                                                   const cx<T>* __restrict__ shlo, const cx<T>* __restrict__ shhi) {
   constexpr int TW = tile_width<T, Q>();
   constexpr int ST = lds_stride<Q>();
   __shared__ cx<T> lds[2 * TW * ST];
@@ -248,9 +252,9 @@ __global__ void __launch_bounds__(NT) k_fft_pass_a(const cx<T>* __restrict__ in,
     if (SRC == SRC_PLAIN) {
       if (j < nvalid) v = src[j];
     } else {
-      const int M = L >> 1;
-      if (j < (M >> 1)) v = src[j];
-      else if (j >= M + (M >> 1)) v = src[j - M];
+      cx<T> w = twiddle_L<T, true>(shlo, shhi, j);
+      if (j >= (L >> 1)) w = mk<T>(-w.re, -w.im);
+      v = cmul(src[j], w);
     }
     lds[(s * TW + c) * ST + j2] = v;
   }
@@ -292,6 +296,23 @@ __global__ void __launch_bounds__(NT) k_fft_pass_b(const cx<T>* __restrict__ in,
 }
 
 // ----------------------------------------------------------------- resampling
+// Sample q of the 2x upsampled series: the even samples are the series z itself (zero
+// from n on), the odd samples the series o half a sample later.
+template <typename T>
+__device__ __forceinline__ cx<T> upsampled(const cx<T>* __restrict__ z, const cx<T>* __restrict__ o, int q, int n) {
+  const int h = q >> 1;
+  if (q & 1) return o[h];
+  return h < n ? z[h] : mk<T>(0, 0);
+}
+
+// The 2x upsampled series of a batch of skies, for stage-by-stage checks: u[q] of each
+// series of z and o (stride ldz) into out (stride L).
+template <typename T>
+__global__ void __launch_bounds__(NT) k_upsampled(const cx<T>* __restrict__ z, const cx<T>* __restrict__ o,
+                                                  long ldz, int n, int L, cx<T>* __restrict__ out) {
+  const int q = blockIdx.x * NT + threadIdx.x, s = blockIdx.y;
+  if (q < L) out[(long)s * L + q] = upsampled(z + s * ldz, o + s * ldz, q, n);
+}
 // Natural cubic spline through the upsampled series u[0..L) (unit spacing),
 // evaluated at 2 s_j with s_j = j - D_j/dt; zero where s_j is outside [0, n-1].
 // Spline moments: m_0 = m_{L-1} = 0, m_{p-1} + 4 m_p + m_{p+1} = d_p = 6 (u_{p+1} - 2u_p + u_{p-1}).
@@ -343,8 +364,8 @@ __device__ __forceinline__ cx<T> spline_eval(cx<T> u0, cx<T> u1, cx<T> m0, cx<T>
 // LDS together with the curvature sources d_q within KT of it.
 template <typename T, int KT>
 __global__ void __launch_bounds__(NT) k_spline(SegConst sc, const SkyParams* __restrict__ sp,
-                                               const cx<T>* __restrict__ u, cx<T>* __restrict__ zt, long ldzt,
-                                               const T* __restrict__ gtab) {
+                                               const cx<T>* __restrict__ z, const cx<T>* __restrict__ o, long ldz,
+                                               cx<T>* __restrict__ zt, long ldzt, const T* __restrict__ gtab) {
   constexpr int CAP = 2 * NT + 64;              // knots held for one tile
   constexpr int DCAP = CAP + 2 * KT + 2;        // curvature sources held
   __shared__ cx<T> su[2][DCAP + 2];
@@ -398,15 +419,17 @@ __global__ void __launch_bounds__(NT) k_spline(SegConst sc, const SkyParams* __r
     }
     return;
   }
-  const cx<T>* ua = u + (long)(2 * i) * L;
-  const cx<T>* ub = u + (long)(2 * i + 1) * L;
+  const cx<T>* za = z + (long)(2 * i) * ldz;
+  const cx<T>* zb = z + (long)(2 * i + 1) * ldz;
+  const cx<T>* oa = o + (long)(2 * i) * ldz;
+  const cx<T>* ob = o + (long)(2 * i + 1) * ldz;
   if (pmax + 1 - pmin + 1 <= CAP) {
     // knots needed for moments [pmin, pmax+1]: sources q in [pmin-KT, pmax+1+KT], each uses u[q-1..q+1]
     const int dlo = max(1, pmin - KT), dhi = min(L - 2, pmax + 1 + KT);
     const int ulo = dlo - 1, uhi = dhi + 1;
     for (int q = ulo + threadIdx.x; q <= uhi; q += NT) {
-      su[0][q - ulo] = ua[q];
-      su[1][q - ulo] = ub[q];
+      su[0][q - ulo] = upsampled(za, oa, q, n);
+      su[1][q - ulo] = upsampled(zb, ob, q, n);
     }
     __syncthreads();
     for (int q = dlo + threadIdx.x; q <= dhi; q += NT) {
@@ -437,7 +460,9 @@ __global__ void __launch_bounds__(NT) k_spline(SegConst sc, const SkyParams* __r
       cx<T> out[2] = {mk<T>(0, 0), mk<T>(0, 0)};
       if (valid) {
         for (int s = 0; s < 2; ++s) {
-          const cx<T>* us = s ? ub : ua;
+          const cx<T>* zs = s ? zb : za;
+          const cx<T>* os = s ? ob : oa;
+          auto us = [&](int q) { return upsampled(zs, os, q, n); };
           cx<T> m01[2];
           for (int h = 0; h < 2; ++h) {
             const int pp = kn + h;
@@ -445,7 +470,7 @@ __global__ void __launch_bounds__(NT) k_spline(SegConst sc, const SkyParams* __r
             if (pp > 0 && pp < L - 1) {
               const int q0 = max(1, pp - KT), q1 = min(L - 2, pp + KT);
               for (int q = q0; q <= q1; ++q) {
-                const cx<T> a = us[q - 1], b = us[q], c = us[q + 1];
+                const cx<T> a = us(q - 1), b = us(q), c = us(q + 1);
                 const cx<T> dq = mk<T>((T)6 * (c.re - (T)2 * b.re + a.re), (T)6 * (c.im - (T)2 * b.im + a.im));
                 const int dpq = pp > q ? pp - q : q - pp;
                 T w = sg[dpq];
@@ -457,7 +482,7 @@ __global__ void __launch_bounds__(NT) k_spline(SegConst sc, const SkyParams* __r
             }
             m01[h] = acc;
           }
-          out[s] = spline_eval(us[kn], us[kn + 1], m01[0], m01[1], tf);
+          out[s] = spline_eval(us(kn), us(kn + 1), m01[0], m01[1], tf);
         }
       }
       zt[(2 * i) * ldzt + j] = out[0];

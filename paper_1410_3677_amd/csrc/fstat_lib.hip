@@ -390,14 +390,14 @@ struct Dev {
 template <typename T, bool INV, int SRC>
 static hipError_t fft_two_pass(const Dev<T>& d, int logL, int P, int Q, const cx<T>* in, long ld_in,
                                int nvalid, cx<T>* tmp, cx<T>* out, long ld_out, int items, T scale,
-                               hipStream_t st) {
+                               hipStream_t st, const cx<T>* shlo = nullptr, const cx<T>* shhi = nullptr) {
   const int L = 1 << logL;
   hipError_t err = hipSuccess;
   with_len(Q, [&](auto c) {
     constexpr int QQ = decltype(c)::value;
     const int ntiles = P / tile_width<T, QQ>();
     hipLaunchKernelGGL((k_fft_pass_a<T, QQ, INV, SRC>), dim3(ntiles * items), dim3(NT), 0, st, in, ld_in,
-                       nvalid, tmp, P, L, d.tw1024, d.lo(logL), d.hi(logL));
+                       nvalid, tmp, P, L, d.tw1024, d.lo(logL), d.hi(logL), shlo, shhi);
     err = hipGetLastError();
   });
   if (err != hipSuccess) return err;
@@ -420,8 +420,8 @@ static fstat_status run_sky_batch(fstat_plan_t p, const Dev<T>& d, const SegInfo
   const int nblk = (n + NT - 1) / NT;
   cx<T>* za = d.sky();                             // [nb][2][M]
   cx<T>* Z = za + (size_t)nb * 2 * M;              // [nb][2][M]
-  cx<T>* tmp = Z + (size_t)nb * 2 * M;             // [nb][2][L]
-  cx<T>* u = tmp + (size_t)nb * 2 * L;             // [nb][2][L]
+  cx<T>* tmp = Z + (size_t)nb * 2 * M;             // [nb][2][L] (M used)
+  cx<T>* o = tmp + (size_t)nb * 2 * L;             // [nb][2][M]: odd samples of the 2x upsampling
   {
     ProfScope ps(p, FSTAT_KERNEL_SKY_PREP, st);
     hipLaunchKernelGGL(k_sky_setup, dim3((nb + 63) / 64), dim3(64), 0, st, alpha, delta, sky0, nb, sc, d.sp());
@@ -434,10 +434,14 @@ static fstat_status run_sky_batch(fstat_plan_t p, const Dev<T>& d, const SegInfo
     ProfScope ps(p, FSTAT_KERNEL_RESAMPLE, st);
     HIP_TRY(p, (fft_two_pass<T, false, SRC_PLAIN>(d, si.logL - 1, si.PM, si.QM, za, M, n, tmp, Z, M, nb, (T)1, st)),
             "upsampling forward FFT");
-    HIP_TRY(p, (fft_two_pass<T, true, SRC_UPSPEC>(d, si.logL, si.P, si.Q, Z, M, 0, tmp, u, L, nb, (T)(2.0 / L), st)),
+    // 2x band-limited upsampling: the even samples are za itself, the odd ones the inverse
+    // M-point transform of the spectrum shifted by half a sample
+    HIP_TRY(p, (fft_two_pass<T, true, SRC_HALFSHIFT>(d, si.logL - 1, si.PM, si.QM, Z, M, 0, tmp, o, M, nb,
+                                                      (T)(1.0 / M), st, d.lo(si.logL), d.hi(si.logL))),
             "upsampling inverse FFT");
     constexpr int KT = sizeof(T) == 8 ? KT_F64 : KT_F32;
-    hipLaunchKernelGGL((k_spline<T, KT>), dim3(nblk, nb), dim3(NT), 0, st, sc, d.sp(), u, d.zt(), (long)n, d.g);
+    hipLaunchKernelGGL((k_spline<T, KT>), dim3(nblk, nb), dim3(NT), 0, st, sc, d.sp(), za, o, (long)M, d.zt(),
+                       (long)n, d.g);
     HIP_TRY(p, hipGetLastError(), "spline launch");
   }
   return FSTAT_OK;
@@ -1634,12 +1638,17 @@ static fstat_status sky_stages_impl(fstat_plan_t plan, const SegInfo& si, const 
   if (r != FSTAT_OK) return r;
   const size_t n = si.s.n, M = si.M, L = si.nfft, cb = sizeof(cx<T>);
   cx<T>* zab = d.sky();
-  cx<T>* u = zab + 4 * M + 2 * L;
+  cx<T>* o = zab + 4 * M + 2 * L;
   auto cp = [&](void* dst, const void* src, size_t bytes) {
     return dst ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st) : hipSuccess;
   };
   HIP_TRY(plan, cp(za, zab, n * cb), "stage copy");
   HIP_TRY(plan, cp(zb, zab + M, n * cb), "stage copy");
+  // the 2x upsampled series, assembled from the series and its half-sample shift
+  cx<T>* u = zab + 2 * M;   // the spectrum's space, no longer needed
+  hipLaunchKernelGGL((k_upsampled<T>), dim3((unsigned)((L + NT - 1) / NT), 2), dim3(NT), 0, st, zab, o, (long)M,
+                     (int)n, (int)L, u);
+  HIP_TRY(plan, hipGetLastError(), "upsampled series launch");
   HIP_TRY(plan, cp(ua, u, L * cb), "stage copy");
   HIP_TRY(plan, cp(ub, u + L, L * cb), "stage copy");
   HIP_TRY(plan, cp(zta, d.zt(), n * cb), "stage copy");
