@@ -59,13 +59,9 @@ def _two_f(fa, fb, A, B):
     return (2.0 / N) * ((fa.real ** 2 + fa.imag ** 2) / A + (fb.real ** 2 + fb.imag ** 2) / B)
 
 
-def shape_patches(seed: int, n_inj: int, n_noise_templates: int, snr_lo: float, snr_hi: float):
-    """Patches of one shape: (inj_patches, noise_patches, n_dismissed, info)."""
-    rng = np.random.default_rng(seed)
-    nfft = ora.default_nfft(N)
-    nb = nfft // 2
-    r = synth.ephemeris(N, DT)
-    # template and a nearby injected source
+def draw_shape(rng):
+    """A template (sky, spindown) and a nearby source's sky, frequency and spindown (the
+    polarisation, inclination, phase and amplitude are left to the injections)."""
     al_t = float(rng.uniform(0, 2 * math.pi))
     de_t = float(math.asin(rng.uniform(-0.95, 0.95)))
     fd_t = float(rng.uniform(-1e-9, 0.0))
@@ -73,28 +69,64 @@ def shape_patches(seed: int, n_inj: int, n_noise_templates: int, snr_lo: float, 
     inj = synth.Injection(f=float(rng.uniform(0.02, 0.23)), fdot=fd_t + float(rng.uniform(-2e-12, 2e-12)),
                           alpha=al_t + off[0] / max(math.cos(de_t), 0.2), delta=de_t + off[1],
                           psi=0.0, cosi=0.0, phi0=0.0, snr=0.0)
+    return dict(alpha=al_t, delta=de_t, fdot=fd_t, source=inj)
+
+
+def shape_transforms(shape, nfft: int):
+    """The oracle's Fa, Fb of the source's four basis waveforms (synth.cw_basis) at the
+    template, over the window [lo, hi) of WIN bins either side of the source's bin, with
+    the template's A, B and the basis Gram matrix."""
+    nb = nfft // 2
+    inj = shape["source"]
+    r = synth.ephemeris(N, DT)
     k_sig = int(round(inj.f * nfft * DT))
     lo, hi = max(k_sig - WIN, 0), min(k_sig + WIN, nb)
     basis = synth.cw_basis(inj, N, DT, F_OFF, r)
-    gram = basis @ basis.T
     seg = synth.make_segment(N, DT, F_OFF, 1.0, None, [])
     fa_mu, fb_mu = [], []
     A = B = None
     for mu in range(4):
         seg.x = basis[mu]
-        sky = ora.sky_stage(seg, al_t, de_t, nfft)
+        sky = ora.sky_stage(seg, shape["alpha"], shape["delta"], nfft)
         A, B = sky["A"], sky["B"]
-        fa, fb = _fa_fb(seg, sky, fd_t, nfft)
+        fa, fb = _fa_fb(seg, sky, shape["fdot"], nfft)
         fa_mu.append(fa[lo:hi])
         fb_mu.append(fb[lo:hi])
-    fa_mu, fb_mu = np.array(fa_mu), np.array(fb_mu)
+    return dict(k_sig=k_sig, lo=lo, hi=hi, fa=np.array(fa_mu), fb=np.array(fb_mu), A=A, B=B,
+                gram=basis @ basis.T)
+
+
+def signal_two_f(tr, snr: float, psi: float, cosi: float, phi0: float, noise=None):
+    """2F over the window of a signal of the shape with these polarisation, inclination,
+    phase and SNR (h0 such that sum h^2 = SNR^2 at unit noise variance), assembled from the
+    basis transforms with the JKS amplitudes; `noise` = (Fa, Fb) of noise over the window
+    is added before |.|^2."""
+    amp = jks_amplitudes(1.0, psi, cosi, phi0)
+    h0 = snr / math.sqrt(float(amp @ tr["gram"] @ amp))
+    fa = h0 * (amp @ tr["fa"])
+    fb = h0 * (amp @ tr["fb"])
+    if noise is not None:
+        fa = fa + noise[0]
+        fb = fb + noise[1]
+    return _two_f(fa, fb, tr["A"], tr["B"])
+
+
+def shape_patches(seed: int, n_inj: int, n_noise_templates: int, snr_lo: float, snr_hi: float):
+    """Patches of one shape: (inj_patches, noise_patches, n_dismissed, info)."""
+    rng = np.random.default_rng(seed)
+    nfft = ora.default_nfft(N)
+    nb = nfft // 2
+    shape = draw_shape(rng)
+    tr = shape_transforms(shape, nfft)
+    k_sig, lo, hi, A, B = tr["k_sig"], tr["lo"], tr["hi"], tr["A"], tr["B"]
     # noise of the same template, and a few more spindowns of it for noise crossings
+    seg = synth.make_segment(N, DT, F_OFF, 1.0, None, [])
     seg.x = np.random.default_rng(seed + 7_000_000).standard_normal(N)
-    sky_n = ora.sky_stage(seg, al_t, de_t, nfft)
-    fa_n, fb_n = _fa_fb(seg, sky_n, fd_t, nfft)
+    sky_n = ora.sky_stage(seg, shape["alpha"], shape["delta"], nfft)
+    fa_n, fb_n = _fa_fb(seg, sky_n, shape["fdot"], nfft)
     noise_patches = []
     for s in range(n_noise_templates):
-        fd = fd_t if s == 0 else float(rng.uniform(-1e-9, 0.0))
+        fd = shape["fdot"] if s == 0 else float(rng.uniform(-1e-9, 0.0))
         tf = _two_f(*(_fa_fb(seg, sky_n, fd, nfft) if s else (fa_n, fb_n)), A, B)
         ks = np.nonzero(tf[HALF:nb - HALF] > THRESHOLD)[0] + HALF
         for k in ks:
@@ -102,13 +134,9 @@ def shape_patches(seed: int, n_inj: int, n_noise_templates: int, snr_lo: float, 
     inj_patches, dismissed = [], 0
     for _ in range(n_inj):
         snr = float(rng.uniform(snr_lo, snr_hi))
-        amp = jks_amplitudes(1.0, float(rng.uniform(0, math.pi)), float(rng.uniform(-1, 1)),
-                             float(rng.uniform(0, 2 * math.pi)))
-        h0 = snr / math.sqrt(float(amp @ gram @ amp))
+        psi, cosi, phi0 = float(rng.uniform(0, math.pi)), float(rng.uniform(-1, 1)), float(rng.uniform(0, 2 * math.pi))
         shift = int(rng.integers(HALF + WIN, nb - HALF - WIN)) - k_sig
-        fa = h0 * (amp @ fa_mu) + fa_n[lo + shift:hi + shift]
-        fb = h0 * (amp @ fb_mu) + fb_n[lo + shift:hi + shift]
-        tf = _two_f(fa, fb, A, B)
+        tf = signal_two_f(tr, snr, psi, cosi, phi0, (fa_n[lo + shift:hi + shift], fb_n[lo + shift:hi + shift]))
         c0 = k_sig - lo
         near = tf[c0 - 4:c0 + 5]
         kc = int(np.argmax(near)) + c0 - 4
@@ -116,7 +144,7 @@ def shape_patches(seed: int, n_inj: int, n_noise_templates: int, snr_lo: float, 
             dismissed += 1
             continue
         inj_patches.append(tf[kc - HALF:kc + HALF])
-    info = dict(k_sig=k_sig, alpha=al_t, delta=de_t)
+    info = dict(k_sig=k_sig, alpha=shape["alpha"], delta=shape["delta"])
     return (np.array(inj_patches, dtype=np.float32).reshape(-1, 2 * HALF),
             np.array(noise_patches, dtype=np.float32).reshape(-1, 2 * HALF), dismissed, info)
 

@@ -330,3 +330,24 @@ def lattice_doppler_amplitude_error(seed: int = 5, trials: int = 8) -> float:
         w3 = n_ * M[2, 3] + m_ * M[3, 3]
         worst = max(worst, abs(w * coef[0] - w2) / abs(w * synth.AU_LS), abs(w * coef[1] - w3) / abs(w * synth.AU_LS))
     return worst
+
+
+def vet_signal_assembly_error(seed: int) -> float:
+    """Largest deviation, relative to the window's peak, between a noiseless signal window
+    assembled by linearity for the vetting data (basis transforms combined with the JKS
+    amplitudes A1..A4) and the same source injected into a segment and run through the
+    oracle's sky stage and template transform at the same template."""
+    import dataclasses
+    from oracle import vet_data
+    rng = np.random.default_rng(seed)
+    shape = vet_data.draw_shape(rng)
+    nfft = oracle.default_nfft(vet_data.N)
+    tr = vet_data.shape_transforms(shape, nfft)
+    snr = float(rng.uniform(6.0, 20.0))
+    psi, cosi, phi0 = float(rng.uniform(0, math.pi)), float(rng.uniform(-1, 1)), float(rng.uniform(0, 2 * math.pi))
+    lin = vet_data.signal_two_f(tr, snr, psi, cosi, phi0)
+    src = dataclasses.replace(shape["source"], psi=psi, cosi=cosi, phi0=phi0, snr=snr)
+    seg = synth.make_segment(vet_data.N, vet_data.DT, vet_data.F_OFF, 1.0, None, [src])
+    sky = oracle.sky_stage(seg, shape["alpha"], shape["delta"], nfft)
+    direct = oracle.template_two_f(seg, sky, shape["fdot"], nfft)[tr["lo"]:tr["hi"]]
+    return float(np.max(np.abs(lin - direct)) / np.max(direct))

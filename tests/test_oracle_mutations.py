@@ -220,3 +220,16 @@ def test_sky_offset_of_the_spindown_dropped_is_caught(monkeypatch):
     orig = fo.lattice_template
     monkeypatch.setattr(fo, "lattice_template", lambda M, s, w0, w1, nfft: orig(M, s, w0, 0.0, nfft))
     assert not _lattice_injection_ok()
+
+
+def test_swapped_jks_amplitudes_in_vetting_data_are_caught(monkeypatch):
+    from oracle import vet_data
+    orig = vet_data.jks_amplitudes
+    monkeypatch.setattr(vet_data, "jks_amplitudes", lambda *a: orig(*a)[[0, 2, 1, 3]])
+    assert pins.vet_signal_assembly_error(31) > 1e-3
+
+
+def test_basis_order_slip_in_vetting_data_is_caught(monkeypatch):
+    orig = synth.cw_basis
+    monkeypatch.setattr(synth, "cw_basis", lambda *a, **k: orig(*a, **k)[[0, 1, 3, 2]])
+    assert pins.vet_signal_assembly_error(32) > 1e-3

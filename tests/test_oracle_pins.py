@@ -103,6 +103,39 @@ def test_search_candidates_are_sorted_and_above_threshold():
     np.testing.assert_allclose(c["f_hz"], seg.f_off + c["bin"] / (nfft * seg.dt), rtol=0, atol=1e-12)
 
 
+def test_golden_fft_lengths():
+    # Sect. 2: the Fourier transform is twice as long as the data, zero-padded to a
+    # power of two; the oracle and the input generator each state it
+    rows = np.loadtxt(os.path.join(GOLDEN, "nfft_lengths.txt"), dtype=np.int64)
+    for n, nfft in rows:
+        assert oracle.default_nfft(int(n)) == nfft
+        assert synth.nfft_for(int(n)) == nfft
+
+
+def test_search_returns_every_crossing_of_the_bin_range():
+    # every bin of [k_min, k_max) whose 2F exceeds the threshold, and no other, with the
+    # bin numbered on the whole transform and its frequency f_off + bin/(nfft dt)
+    w = synth.workload("tiny")
+    seg = w.segments[0]
+    nfft = oracle.default_nfft(seg.n)
+    k_min, k_max = 1000, 3001
+    c = oracle.search(seg, w.alpha[:2], w.delta[:2], w.fdot[:3], w.threshold, k_min=k_min, k_max=k_max)
+    n_all = 0
+    for i in range(2):
+        sky = oracle.sky_stage(seg, float(w.alpha[i]), float(w.delta[i]), nfft)
+        for s in range(3):
+            full = oracle.template_two_f(seg, sky, float(w.fdot[s]), nfft)
+            want = np.nonzero(full > w.threshold)[0]
+            want = want[(want >= k_min) & (want < k_max)]
+            got = c[(c["sky"] == i) & (c["fdot_idx"] == s)]
+            np.testing.assert_array_equal(got["bin"], want)
+            np.testing.assert_allclose(got["twoF"], full[want], rtol=1e-12, atol=0)
+            np.testing.assert_allclose(got["f_hz"], seg.f_off + want / (nfft * seg.dt), rtol=0, atol=1e-12)
+            assert np.all(got["fdot"] == w.fdot[s]) and np.all(got["alpha"] == w.alpha[i])
+            n_all += len(want)
+    assert n_all == len(c) and n_all > 0
+
+
 def test_golden_band_offsets_eq1():
     # Eq. 1: f_off = 100 + (1 - 2^-5) b; the bands overlap by 2^-5 Hz (Sect. 2)
     rows = np.loadtxt(os.path.join(GOLDEN, "eq1_band_offsets.txt"))

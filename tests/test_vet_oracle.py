@@ -7,6 +7,7 @@ import scipy.signal
 
 from oracle import vet_data
 from oracle import vet_oracle as vo
+from tests import pins
 
 
 def test_parameter_count():
@@ -76,3 +77,11 @@ def test_patch_generator_small():
     # injection patches are centred on a local maximum of the window searched
     assert np.all(x[y == 1, 128] >= x[y == 1, 124:133].max(axis=1) - 1e-3)
     assert st["threshold_false_dismissal"] < 0.2
+
+
+@pytest.mark.parametrize("seed", [31, 32, 33])
+def test_signal_assembly_equals_injected_segment(seed):
+    # the training and evaluation signals are combinations of basis transforms with the
+    # JKS amplitudes; the same source injected into a segment (its own waveform, polarisation
+    # and inclination through the antenna patterns) gives the same 2F window at the template
+    assert pins.vet_signal_assembly_error(seed) < 1e-9
