@@ -120,7 +120,9 @@ typedef struct { int32_t search, segment, sky, fdot_idx, bin; float vet_score; }
  * capacity 1<<24, no budget, library-chosen batching, graphs on. */
 void fstat_options_default(fstat_options* opt);
 
-/* Create a plan for nseg segments (host array, copied).  Validates every
+/* Create a plan for nseg segments (host array, copied): the problem statement of
+ * Sect. 2 (data segments of Eq. 1's bands, their ephemeris, the F threshold).
+ * Validates every
  * argument, chooses FFT factorizations and batch sizes, and performs the
  * admission check: FSTAT_E_ADMISSION when even one sky and one template of
  * the largest segment need more workspace than workspace_budget_bytes.
@@ -129,7 +131,8 @@ void fstat_options_default(fstat_options* opt);
 fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_options* opt,
                         fstat_plan_t* out_plan);
 
-/* Workspace bytes the plan needs (its chosen batch sizes). */
+/* Workspace bytes the plan needs (its chosen batch sizes; memory of the search
+ * loop of Sect. 2 held between calls). */
 fstat_status fstat_plan_workspace_size(fstat_plan_t plan, size_t* bytes);
 
 /* Hand the plan a caller-owned device workspace of at least
@@ -137,7 +140,10 @@ fstat_status fstat_plan_workspace_size(fstat_plan_t plan, size_t* bytes);
  * plan allocates its own on first use. */
 fstat_status fstat_plan_set_workspace(fstat_plan_t plan, void* dev_ptr, size_t bytes);
 
-/* Enqueue the search of every (sky, spindown) template on one segment
+/* The search loop of Sect. 2 (Fig. 3): for every sky position, demodulation and
+ * resampling; for every spindown, spindown demodulation, the two FFTs twice as long
+ * as the data, F on every bin and each bin above the threshold as a candidate.
+ * Enqueue the search of every (sky, spindown) template on one segment
  * (segment >= 0) or on every segment of the plan (segment = -1) with the
  * same template lists.  alpha, delta (nsky) and fdot (nfdot) are device
  * arrays of doubles.  Asynchronous on `stream`; candidates are appended to
@@ -147,7 +153,9 @@ fstat_status fstat_search_batch(fstat_plan_t plan, int32_t segment,
                                 const double* alpha, const double* delta, int32_t nsky,
                                 const double* fdot, int32_t nfdot, void* stream);
 
-/* Wait for the plan's work, then copy out and drain the candidates found
+/* The candidates of Sect. 2: every crossing as the five numbers frequency,
+ * spindown, sky position (alpha, delta) and 2F, plus its integer key.
+ * Wait for the plan's work, then copy out and drain the candidates found
  * since the previous call, sorted by key (search, segment, sky, fdot_idx,
  * bin).  out / keys are host arrays of `capacity` entries (either may be
  * NULL).  *n_found receives the true number of crossings, also when it
@@ -160,7 +168,8 @@ fstat_status fstat_search_batch(fstat_plan_t plan, int32_t segment,
 fstat_status fstat_candidates(fstat_plan_t plan, fstat_candidate* out, fstat_candidate_key* keys,
                               int64_t capacity, int64_t* n_found);
 
-/* Enqueue 2F over bins [k_min, k_max) of every template of one segment into
+/* F on every bin (Sect. 2), stored instead of thresholded.
+ * Enqueue 2F over bins [k_min, k_max) of every template of one segment into
  * the device array out, laid out [sky][fdot][bin - k_min], float for MIXED
  * and double for FP64.  Same kernels as the search, with the threshold
  * stage replaced by a store.  Asynchronous on `stream`. */
@@ -168,7 +177,9 @@ fstat_status fstat_twoF_spectrum(fstat_plan_t plan, int32_t segment,
                                  const double* alpha, const double* delta, int32_t nsky,
                                  const double* fdot, int32_t nfdot, void* out, void* stream);
 
-/* Per-sky intermediates of one sky position, for stage-by-stage checks.
+/* The per-sky steps of Sect. 2 (direction, Roemer delay, a(t), b(t), phase
+ * demodulation, resampling with the FFT and splines), exposed one by one.
+ * Per-sky intermediates of one sky position, for stage-by-stage checks.
  * Device outputs (complex values interleaved re, im; float for MIXED,
  * double for FP64), any may be NULL:
  *   abc    3 doubles: A = <a^2>, B = <b^2>, C = <ab>
