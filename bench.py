@@ -79,6 +79,26 @@ def cache_has_line(path, nfft: int, precision_key: int) -> bool:
     return False
 
 
+def fit_capacity(cap: int, torch, log, share: float = 0.5) -> int:
+    """Candidate entries for a plan's device buffer: `cap`, cut to `share` of the device
+    memory free now (the plan reports the true count of crossings also beyond it)."""
+    free, _ = torch.cuda.mem_get_info()
+    fit = int(share * free) // CAND_BYTES
+    if cap > fit:
+        log(f"candidate capacity {cap} cut to {fit} entries ({free / 2**30:.1f} GiB free)")
+        return max(fit, 1)
+    return cap
+
+
+def guarded(name, log, fn, *a, **k):
+    """Run a side entry of the bench; a failure is recorded in its entry instead of ending the run."""
+    try:
+        return fn(*a, **k)
+    except Exception as e:  # noqa: BLE001 - recorded in the JSON line
+        log(f"{name}: failed: {type(e).__name__}: {e}")
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
 def _oracle_sky_worker(job):
     """One sky of the oracle sample: its sky stage and every spindown template (2F + threshold)."""
     import numpy as np
@@ -116,16 +136,20 @@ def cpu_multicore_leg(args, log):
                       f"per core (numpy FP64, one thread each), {dt:.1f} s wall"}
 
 
-def timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbinning=0):
-    """Plan (autotuned, from the cache or fixed), warm up, time args.steps searches of the
-    whole template list, and read the per-kernel HIP-event timings of the timed steps."""
+def timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbinning=0, steps=None, warmup=None):
+    """Plan (autotuned, from the cache or fixed), warm up, time `steps` searches of the
+    whole template list (each followed by its count drain), and read the per-kernel
+    HIP-event timings of the timed steps."""
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     label = "interbinning" if interbinning else "mixed"
     tlen = nfft // 2 if interbinning else nfft          # template transform length
     # crossings at 2F > 20 on the batched workload: about 1.1e-3 of the bins (2.1e-3 with
     # interbinning, whose odd bins of noise have a larger mean); capacity for the timed
     # steps with a margin (entries are 32 bytes)
     rate = 2.1e-3 if interbinning else 1.1e-3
-    cap = int(max(1 << 20, 2.0 * rate * (nfft // 2) * templates * max(args.steps, 1)))
+    # the buffer holds one step's crossings (every step is drained by count before the next)
+    cap = fit_capacity(int(max(1 << 20, 1.3 * rate * (nfft // 2) * templates)), torch, log)
     fixed = bool(args.templates_per_launch or args.skies_per_batch or args.no_autotune)
     cache = args.tuning_cache or None
     have_cache = cache_has_line(cache, nfft, 1 + 2 * interbinning)
@@ -141,7 +165,7 @@ def timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbin
         plan._set_torch_workspace()
     info = plan.info(0)
     log(f"{label}: plan {info}, capacity {cap}")
-    for i in range(args.warmup):
+    for i in range(warmup):
         plan.search_batch(0, al, de, fd)
         torch.cuda.synchronize()
         log(f"{label}: warmup {i} done, {plan.candidate_count(allow_overflow=True)} candidates")
@@ -149,15 +173,20 @@ def timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbin
     for c in range(4):
         plan.profile_read(c, reset=True)
     torch.cuda.synchronize()
+    # one step = one search of every template plus the count drain of its crossings (which
+    # waits for the search and resets the device counter for the next step)
+    counts = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         plan.search_batch(0, al, de, fd)
+        counts.append(plan.candidate_count(allow_overflow=True))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    n_cand = plan.candidate_count(allow_overflow=True)
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    value = templates / ((t1 - t0) / args.steps)
-    log(f"{label}: {ms_step:.1f} ms/step, {value:.4g} templates/s, {n_cand / args.steps:.4g} candidates/step")
+    n_cand = sum(counts)
+    ms_step = (t1 - t0) * 1e3 / steps
+    value = templates / ((t1 - t0) / steps)
+    log(f"{label}: {ms_step:.1f} ms/step, {value:.4g} templates/s, {n_cand / steps:.4g} candidates/step"
+        f"{'' if len(set(counts)) == 1 else f' (varying: {sorted(set(counts))})'}")
 
     kernels = {}
     for c, name in enumerate(F.KERNEL_NAMES):
@@ -165,7 +194,7 @@ def timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbin
         kernels[name] = {"launches": n, "total_ms": ms, "avg_ms": ms / n if n else None}
     B = info["templates_per_launch"]
     N = seg.n
-    cand_per_template = n_cand / max(templates * args.steps, 1)
+    cand_per_template = n_cand / max(templates * steps, 1)
     # algorithmic bytes per launch of the two template kernels:
     #  pass A writes the 2 x tlen complex FP32 intermediate of each template and reads the
     #  resampled series (2 x N complex FP32) once per launch (one sky per launch);
@@ -186,9 +215,9 @@ def timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbin
         for k in ("template_a", "template_b"):
             kernels[k]["achieved_GBs"] = algo[k] / (kernels[k]["avg_ms"] / 1e3) / 1e9
     plan.destroy()
-    return {"value": value, "unit": "templates/s", "ms_per_step": ms_step, "n_cand": n_cand,
-            "candidates_per_step": n_cand / args.steps, "info": info, "kernels": kernels, "roofline": roofline,
-            "tuning": tuned, "template_fft": tlen}
+    return {"value": value, "unit": "templates/s", "ms_per_step": ms_step, "n_cand": n_cand, "steps": steps,
+            "candidates_per_step": n_cand / steps, "info": info, "kernels": kernels, "roofline": roofline,
+            "tuning": tuned, "template_fft": tlen, "candidate_capacity": cap}
 
 
 def lattice_leg(args, F, torch, seg, nfft, info, log):
@@ -208,27 +237,29 @@ def lattice_leg(args, F, torch, seg, nfft, info, log):
     t_sky = time.perf_counter() - t0
     nsky = int(sky["alpha"].numel())
     templates = nsky * args.nfdot
-    cap = int(max(1 << 20, 2.0 * 1.1e-3 * (nfft // 2) * templates * max(args.steps, 1)))
+    cap = fit_capacity(int(max(1 << 20, 1.3 * 1.1e-3 * (nfft // 2) * templates)), torch, log)
+    steps, warmup = min(args.steps, args.side_steps), min(args.warmup, 1)
     plan = F.Plan([F.segment_to_device(seg)], candidate_capacity=cap,
                   templates_per_launch=info["templates_per_launch"], skies_per_batch=info["skies_per_batch"],
                   use_graph=0 if args.no_graph else 1)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         plan.search_lattice(0, lat, sky, 0, args.nfdot - 1)
         torch.cuda.synchronize()
         plan.candidate_count(allow_overflow=True)
     torch.cuda.synchronize()
+    n_cand = 0
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         plan.search_lattice(0, lat, sky, 0, args.nfdot - 1)
+        n_cand += plan.candidate_count(allow_overflow=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    n_cand = plan.candidate_count(allow_overflow=True)
     plan.destroy()
-    value = templates / ((t1 - t0) / args.steps)
+    value = templates / ((t1 - t0) / steps)
     log(f"lattice: {nsky} sky points (box {sky['count']} on the sky), {value:.4g} templates/s, sky loop "
         f"{t_sky * 1e3:.2f} ms including allocation and the count read-back")
-    return {"value": value, "unit": "templates/s", "ms_per_step": (t1 - t0) * 1e3 / args.steps,
-            "candidates_per_step": n_cand / args.steps, "sky_points": nsky, "sky_loop_ms": t_sky * 1e3,
+    return {"value": value, "unit": "templates/s", "ms_per_step": (t1 - t0) * 1e3 / steps, "steps": steps,
+            "candidates_per_step": n_cand / steps, "sky_points": nsky, "sky_loop_ms": t_sky * 1e3,
             "config": {"workload": f"lattice templates, N={seg.n}, nfft=2^{int(math.log2(nfft))}, {nsky} sky points "
                                    f"(northern ecliptic hemisphere) x {args.nfdot} spindown integers, 2F>20",
                        "templates": templates, "templates_per_launch": info["templates_per_launch"],
@@ -237,8 +268,8 @@ def lattice_leg(args, F, torch, seg, nfft, info, log):
 
 def ib_summary(ib, templates, nfft):
     """The interbinning leg for the JSON line (its own throughput; not the headline value)."""
-    if ib is None:
-        return None
+    if ib is None or "error" in ib:
+        return ib
     keep = ("value", "unit", "ms_per_step", "candidates_per_step", "kernels", "roofline", "tuning",
             "f_rel_err_vs_fp64_interbinned", "even_bins_rel_dev_vs_zero_padded",
             "odd_bins_mean_2F_ratio_vs_zero_padded", "accuracy_sample")
@@ -333,6 +364,164 @@ def vetting_leg(args, F, torch, np, dev, log):
             "inference_roofline": roof}
 
 
+def plain_leg(args, F, torch, np, dev, log):
+    """The plain FP64-phase path: the full-segment workload (256 sky x 64 spindown), one
+    template per launch, eager; then a full drain of its crossings (device-to-host copy and
+    key ordering) timed on its own, and its F error against the FP64 oracle on a sample."""
+    import synth
+    w2 = synth.workload("full")
+    seg2 = w2.segments[0]
+    cap = 1 << 22
+    p2 = F.Plan([F.segment_to_device(seg2)], templates_per_launch=1, skies_per_batch=1,
+                candidate_capacity=cap, use_graph=0)
+    a2, d2, f2 = dev(w2.alpha), dev(w2.delta), dev(w2.fdot)
+    p2.search_batch(0, a2[:2], d2[:2], f2)
+    torch.cuda.synchronize()
+    p2.candidate_count(allow_overflow=True)
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    p2.search_batch(0, a2, d2, f2)
+    torch.cuda.synchronize()
+    s1 = time.perf_counter()
+    bufs = F.candidate_buffers(cap)
+    d0 = time.perf_counter()
+    recs, keys, n2 = p2.candidates(out=bufs)
+    d1 = time.perf_counter()
+    t2 = len(w2.alpha) * len(w2.fdot)
+    ordered = bool(np.all(np.diff(keys["sky"].astype(np.int64) * (1 << 40) + keys["fdot_idx"].astype(np.int64)
+                                  * (1 << 20) + keys["bin"]) > 0)) if n2 > 1 else True
+    plain = {"value": t2 / (s1 - s0), "unit": "templates/s", "ms_per_step": (s1 - s0) * 1e3,
+             "workload": f"plain FP64-phase path, one template per launch, N=86164, {len(w2.alpha)} sky x "
+                         f"{len(w2.fdot)} spindown", "candidates": n2,
+             "drain": {"candidates": n2, "ms": (d1 - d0) * 1e3, "ordered_by_key": ordered,
+                       "what": "fstat_candidates after the search: wait, device-to-host copy, key ordering on the host, "
+                               "records and keys written"}}
+    log(f"plain: {plain['value']:.4g} templates/s; full drain of {n2} candidates {(d1 - d0) * 1e3:.1f} ms")
+    if not args.no_cpu:
+        # F error of the plain path against the FP64 oracle: 1 sky x 16 spindowns, all bins
+        from oracle import fstat_oracle as ora
+        nf2 = synth.nfft_for(seg2.n)
+        nb2 = nf2 // 2
+        fsel = w2.fdot[:: max(1, len(w2.fdot) // 16)][:16]
+        spec2 = torch.empty(len(fsel) * nb2, dtype=torch.float32, device="cuda")
+        p2.twoF_spectrum(0, a2[:1], d2[:1], dev(fsel), spec2)
+        g2 = spec2.view(len(fsel), nb2).cpu().numpy().astype(np.float64)
+        sky2 = ora.sky_stage(seg2, float(w2.alpha[0]), float(w2.delta[0]), nf2)
+        e2 = max(float(np.max(np.abs(g2[j] - ref) / np.maximum(ref, 4.0)))
+                 for j, ref in enumerate(ora.template_two_f(seg2, sky2, float(f), nf2) for f in fsel))
+        plain["f_rel_err_vs_fp64"] = e2
+        plain["accuracy_sample"] = f"1 sky x {len(fsel)} spindown templates of the plain workload, all bins"
+        log(f"plain: max F rel err vs FP64 {e2:.3e}")
+    p2.destroy()
+    return plain
+
+
+def ragged_leg(args, F, torch, np, dev, log):
+    """Ragged batching: 32 segments of uneven length (N ~ U{20000..172328}, nfft 2^16..2^19,
+    each with its own band offset and injections), 1024 sky x 128 spindown templates per
+    segment, all segments in one search call (segment = -1) under a workspace budget that
+    the plan's admission shrinks its batch sizes to."""
+    import synth
+    w = synth.workload("ragged", args.ragged_nsky, args.ragged_nfdot)
+    segs = [F.segment_to_device(s) for s in w.segments]
+    per_seg = len(w.alpha) * len(w.fdot)
+    templates = per_seg * len(segs)
+    bins = sum(synth.nfft_for(s.n) // 2 for s in w.segments)
+    # crossings at 2F > 20: about 1.1e-3 of the bins on whole sidereal days, more where
+    # the simplified form leaves out a large <ab>
+    cap = fit_capacity(int(max(1 << 20, 1.6e-3 * bins * per_seg)), torch, log)
+    budget = int(args.ragged_budget_gib * 2**30)
+    plan = F.Plan(segs, candidate_capacity=cap, workspace_budget_bytes=budget,
+                  use_graph=0 if args.no_graph else 1)
+    info = plan.info(0)
+    ws = plan.workspace.numel() if plan.workspace is not None else 0
+    a, d, f = dev(w.alpha), dev(w.delta), dev(w.fdot)
+    steps, warmup = min(args.steps, args.ragged_steps), min(args.warmup, 1)
+    for _ in range(warmup):
+        plan.search_batch(-1, a, d, f)
+        plan.candidate_count(allow_overflow=True)
+    torch.cuda.synchronize()
+    counts = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.search_batch(-1, a, d, f)
+        counts.append(plan.candidate_count(allow_overflow=True))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.destroy()
+    value = templates / ((t1 - t0) / steps)
+    ns = sorted(s.n for s in w.segments)
+    log(f"ragged: {len(segs)} segments, {templates} templates, {value:.4g} templates/s, "
+        f"{counts[-1]} candidates/step, batches {info['templates_per_launch']} x {info['skies_per_batch']}")
+    return {"value": value, "unit": "templates/s", "ms_per_step": (t1 - t0) * 1e3 / steps, "steps": steps,
+            "candidates_per_step": sum(counts) / steps, "overflowed": max(counts) > cap,
+            "config": {"workload": f"{len(segs)} segments, N from {ns[0]} to {ns[-1]}, nfft 2^"
+                                   f"{int(math.log2(synth.nfft_for(ns[0])))}..2^{int(math.log2(synth.nfft_for(ns[-1])))}, "
+                                   f"{len(w.alpha)} sky x {len(w.fdot)} spindown per segment, one call, 2F>20",
+                       "templates": templates, "workspace_budget_bytes": budget, "workspace_bytes": ws,
+                       "templates_per_launch": info["templates_per_launch"],
+                       "skies_per_batch": info["skies_per_batch"]}}
+
+
+def cpu_sample_leg(args, F, torch, np, dev, log, w, seg, fd, nfft, ib, cpu_mc):
+    """The oracle on one core over a bounded sample of the batched workload, and the GPU's
+    F error against it there (and, with interbinning, against the interbinned oracle)."""
+    from oracle import fstat_oracle as ora
+    sk = list(range(args.cpu_skies))
+    p3 = F.Plan([F.segment_to_device(seg)])
+    nb = nfft // 2
+    spec = torch.empty(len(sk) * args.nfdot * nb, dtype=torch.float32, device="cuda")
+    p3.twoF_spectrum(0, dev(w.alpha[sk]), dev(w.delta[sk]), fd, spec)
+    torch.cuda.synchronize()
+    g = spec.view(len(sk), args.nfdot, nb).cpu().numpy()
+    p3.destroy()
+    gi = None
+    ib_ok = ib is not None and "error" not in ib
+    if ib_ok:
+        p4 = F.Plan([F.segment_to_device(seg)], interbinning=1)
+        p4.twoF_spectrum(0, dev(w.alpha[sk]), dev(w.delta[sk]), fd, spec)
+        torch.cuda.synchronize()
+        gi = spec.view(len(sk), args.nfdot, nb).cpu().numpy()
+        p4.destroy()
+    del spec
+    errs = []
+    ib_err, ib_even, ib_odd_mean, zp_odd_mean = [], [], 0.0, 0.0
+    c0 = time.perf_counter()
+    for i in sk:
+        sky = ora.sky_stage(seg, float(w.alpha[i]), float(w.delta[i]), nfft)
+        for s in range(args.nfdot):
+            tf = ora.template_two_f(seg, sky, float(w.fdot[s]), nfft)
+            np.nonzero(tf > w.threshold)
+            errs.append(float(np.max(np.abs(g[i, s] - tf) / np.maximum(tf, 4.0))))
+            if gi is not None:
+                # outside the timed oracle sample's cost: parity of the interbinned GPU
+                # spectrum and the method's deviation from the zero-padded transform
+                c_ib = time.perf_counter()
+                ti = ora.template_two_f_interbin(seg, sky, float(w.fdot[s]), nfft)
+                ib_err.append(float(np.max(np.abs(gi[i, s] - ti) / np.maximum(ti, 4.0))))
+                ib_even.append(float(np.max(np.abs(ti[0::2] - tf[0::2]) / np.maximum(tf[0::2], 4.0))))
+                ib_odd_mean += float(np.mean(ti[1::2]))
+                zp_odd_mean += float(np.mean(tf[1::2]))
+                c0 += time.perf_counter() - c_ib
+    c1 = time.perf_counter()
+    ntpl = len(sk) * args.nfdot
+    single = {"value": ntpl / (c1 - c0), "unit": "templates/s", "cores": 1,
+              "sample": f"{len(sk)} sky x {args.nfdot} spindown templates of the same workload "
+                        f"(numpy FP64, single thread), {c1 - c0:.1f} s"}
+    cpu = dict(cpu_mc) if cpu_mc else {}
+    cpu["single_core"] = single
+    f_err = max(errs)
+    log(f"cpu oracle, one core: {single['value']:.3g} templates/s, max F rel err vs FP64 {f_err:.3e}")
+    if ib_ok and ib_err:
+        ib["f_rel_err_vs_fp64_interbinned"] = max(ib_err)
+        ib["even_bins_rel_dev_vs_zero_padded"] = max(ib_even)
+        ib["odd_bins_mean_2F_ratio_vs_zero_padded"] = ib_odd_mean / zp_odd_mean
+        ib["accuracy_sample"] = f"{len(sk)} sky x {args.nfdot} spindown templates, all bins, FP64 oracle"
+        log(f"interbinning: max F rel err vs the FP64 interbinned oracle {max(ib_err):.3e}; oracle even bins vs "
+            f"zero-padded {max(ib_even):.2e}; odd-bin mean 2F ratio {ib_odd_mean / zp_odd_mean:.3f}")
+    return {"cpu": cpu, "f_err": f_err}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -355,6 +544,14 @@ def main():
     ap.add_argument("--no-interbinning", action="store_true")
     ap.add_argument("--no-lattice", action="store_true")
     ap.add_argument("--vet-epochs", type=int, default=3)
+    ap.add_argument("--side-steps", type=int, default=5,
+                    help="timed steps of the interbinning and lattice entries (at most --steps)")
+    ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--ragged-nsky", type=int, default=1024)
+    ap.add_argument("--ragged-nfdot", type=int, default=128)
+    ap.add_argument("--ragged-steps", type=int, default=2)
+    ap.add_argument("--ragged-budget-gib", type=float, default=4.0,
+                    help="workspace budget of the ragged plan (admission shrinks its batch sizes to it)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -399,116 +596,35 @@ def main():
     info, kernels, roofline, tuned = main_leg["info"], main_leg["kernels"], main_leg["roofline"], main_leg["tuning"]
     B, N = info["templates_per_launch"], seg.n
 
-    # ---------------- the same workload with interbinning (template transforms of nfft/2 points)
+    # ---------------- side entries: each records its failure instead of ending the run
+    side = min(args.steps, args.side_steps)
     ib = None
     if not args.no_interbinning:
-        ib = timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbinning=1)
-
-    # ---------------- the same search driven by a lattice grid (sky loop over grid integers)
+        # the same workload with interbinning (template transforms of nfft/2 points)
+        ib = guarded("interbinning", log, timed_search, args, F, torch, seg, al, de, fd, templates, nfft, log,
+                     interbinning=1, steps=side, warmup=min(args.warmup, 1))
     lat_leg = None
     if not args.no_lattice:
-        lat_leg = lattice_leg(args, F, torch, seg, nfft, info, log)
-
-    # ---------------- plain path: one template per launch, 256 x 64
+        # the same search driven by a lattice grid (sky loop over grid integers)
+        lat_leg = guarded("lattice", log, lattice_leg, args, F, torch, seg, nfft, info, log)
     plain = None
     if not args.no_plain:
-        w2 = synth.workload("full")
-        seg2 = w2.segments[0]
-        p2 = F.Plan([F.segment_to_device(seg2)], templates_per_launch=1, skies_per_batch=1,
-                    candidate_capacity=1 << 22, use_graph=0)
-        a2, d2, f2 = dev(w2.alpha), dev(w2.delta), dev(w2.fdot)
-        p2.search_batch(0, a2[:2], d2[:2], f2)
-        torch.cuda.synchronize()
-        p2.candidate_count(allow_overflow=True)
-        torch.cuda.synchronize()
-        s0 = time.perf_counter()
-        p2.search_batch(0, a2, d2, f2)
-        torch.cuda.synchronize()
-        s1 = time.perf_counter()
-        n2 = p2.candidate_count(allow_overflow=True)
-        t2 = len(w2.alpha) * len(w2.fdot)
-        plain = {"value": t2 / (s1 - s0), "unit": "templates/s", "ms_per_step": (s1 - s0) * 1e3,
-                 "workload": f"plain FP64-phase path, one template per launch, N=86164, {len(w2.alpha)} sky x "
-                             f"{len(w2.fdot)} spindown", "candidates": n2}
-        log(f"plain: {plain['value']:.4g} templates/s")
-        if not args.no_cpu:
-            # F error of the plain path against the FP64 oracle: 1 sky x 16 spindowns, all bins
-            from oracle import fstat_oracle as ora
-            nf2 = synth.nfft_for(seg2.n)
-            nb2 = nf2 // 2
-            fsel = w2.fdot[:: max(1, len(w2.fdot) // 16)][:16]
-            spec2 = torch.empty(len(fsel) * nb2, dtype=torch.float32, device="cuda")
-            p2.twoF_spectrum(0, a2[:1], d2[:1], dev(fsel), spec2)
-            g2 = spec2.view(len(fsel), nb2).cpu().numpy().astype(np.float64)
-            sky2 = ora.sky_stage(seg2, float(w2.alpha[0]), float(w2.delta[0]), nf2)
-            e2 = max(float(np.max(np.abs(g2[j] - ref) / np.maximum(ref, 4.0)))
-                     for j, ref in enumerate(ora.template_two_f(seg2, sky2, float(f), nf2) for f in fsel))
-            plain["f_rel_err_vs_fp64"] = e2
-            plain["accuracy_sample"] = f"1 sky x {len(fsel)} spindown templates of the plain workload, all bins"
-            log(f"plain: max F rel err vs FP64 {e2:.3e}")
-        p2.destroy()
-
-    # ---------------- CPU oracle baseline on a bounded sample (+ F error vs FP64 there)
-    cpu = None
-    f_err = None
+        plain = guarded("plain", log, plain_leg, args, F, torch, np, dev, log)
+    ragged = None
+    if not args.no_ragged:
+        ragged = guarded("ragged", log, ragged_leg, args, F, torch, np, dev, log)
+    cpu, f_err = None, None
     if not args.no_cpu:
-        from oracle import fstat_oracle as ora
-        sk = list(range(args.cpu_skies))
-        p3 = F.Plan([F.segment_to_device(seg)])
-        nb = nfft // 2
-        spec = torch.empty(len(sk) * args.nfdot * nb, dtype=torch.float32, device="cuda")
-        p3.twoF_spectrum(0, dev(w.alpha[sk]), dev(w.delta[sk]), fd, spec)
-        torch.cuda.synchronize()
-        g = spec.view(len(sk), args.nfdot, nb).cpu().numpy()
-        p3.destroy()
-        gi = None
-        if ib is not None:
-            p4 = F.Plan([F.segment_to_device(seg)], interbinning=1)
-            p4.twoF_spectrum(0, dev(w.alpha[sk]), dev(w.delta[sk]), fd, spec)
-            torch.cuda.synchronize()
-            gi = spec.view(len(sk), args.nfdot, nb).cpu().numpy()
-            p4.destroy()
-        del spec
-        errs = []
-        ib_err, ib_even, ib_odd_mean, zp_odd_mean = [], [], 0.0, 0.0
-        c0 = time.perf_counter()
-        for i in sk:
-            sky = ora.sky_stage(seg, float(w.alpha[i]), float(w.delta[i]), nfft)
-            for s in range(args.nfdot):
-                tf = ora.template_two_f(seg, sky, float(w.fdot[s]), nfft)
-                np.nonzero(tf > w.threshold)
-                errs.append(float(np.max(np.abs(g[i, s] - tf) / np.maximum(tf, 4.0))))
-                if gi is not None:
-                    # outside the timed oracle sample's cost: parity of the interbinned GPU
-                    # spectrum and the method's deviation from the zero-padded transform
-                    c_ib = time.perf_counter()
-                    ti = ora.template_two_f_interbin(seg, sky, float(w.fdot[s]), nfft)
-                    ib_err.append(float(np.max(np.abs(gi[i, s] - ti) / np.maximum(ti, 4.0))))
-                    ib_even.append(float(np.max(np.abs(ti[0::2] - tf[0::2]) / np.maximum(tf[0::2], 4.0))))
-                    ib_odd_mean += float(np.mean(ti[1::2]))
-                    zp_odd_mean += float(np.mean(tf[1::2]))
-                    c0 += time.perf_counter() - c_ib
-        c1 = time.perf_counter()
-        ntpl = len(sk) * args.nfdot
-        single = {"value": ntpl / (c1 - c0), "unit": "templates/s", "cores": 1,
-                  "sample": f"{len(sk)} sky x {args.nfdot} spindown templates of the same workload "
-                            f"(numpy FP64, single thread), {c1 - c0:.1f} s"}
-        cpu = dict(cpu_mc)
-        cpu["single_core"] = single
-        f_err = max(errs)
-        log(f"cpu oracle, one core: {single['value']:.3g} templates/s, max F rel err vs FP64 {f_err:.3e}")
-        if ib is not None and ib_err:
-            ib["f_rel_err_vs_fp64_interbinned"] = max(ib_err)
-            ib["even_bins_rel_dev_vs_zero_padded"] = max(ib_even)
-            ib["odd_bins_mean_2F_ratio_vs_zero_padded"] = ib_odd_mean / zp_odd_mean
-            ib["accuracy_sample"] = f"{len(sk)} sky x {args.nfdot} spindown templates, all bins, FP64 oracle"
-            log(f"interbinning: max F rel err vs the FP64 interbinned oracle {max(ib_err):.3e}; oracle even bins vs "
-                f"zero-padded {max(ib_even):.2e}; odd-bin mean 2F ratio {ib_odd_mean / zp_odd_mean:.3f}")
-
-    # ---------------- learned vetting: train on oracle patches, then score the plain search's crossings
+        res = guarded("cpu sample", log, cpu_sample_leg, args, F, torch, np, dev, log, w, seg, fd, nfft, ib, cpu_mc)
+        if "error" in res:
+            cpu = dict(cpu_mc)
+            cpu["single_core"] = res
+        else:
+            cpu, f_err = res["cpu"], res["f_err"]
     vetting = None
     if not args.no_vetting:
-        vetting = vetting_leg(args, F, torch, np, dev, log)
+        # learned vetting: train on oracle patches, then score the plain search's crossings
+        vetting = guarded("vetting", log, vetting_leg, args, F, torch, np, dev, log)
 
     out = {
         "metric": METRIC, "value": value, "unit": "templates/s", "n_gpus": 1, "steps": args.steps,
@@ -522,9 +638,11 @@ def main():
                    "tuning": tuned},
         "roofline": roofline, "cpu_baseline": cpu, "plain": plain,
         "f_rel_err_vs_fp64": f_err, "candidates_per_step": n_cand / args.steps, "kernels": kernels,
+        "candidate_capacity": main_leg["candidate_capacity"],
         "vetting": vetting,
         "interbinning": ib_summary(ib, templates, nfft),
         "lattice": lat_leg,
+        "ragged": ragged,
         "context": {"paper_cray_xe6": {
             "value": 1e4 / 1900.0, "unit": "templates/s per core",
             "note": "derived from the paper's weak-scaling test (Sect. 4, weak-scaling figure): one task of 1e4 "

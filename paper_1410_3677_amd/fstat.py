@@ -223,13 +223,18 @@ class Plan:
         _check(self.lib.fstat_search_batch(self.handle, segment, _ptr(alpha), _ptr(delta), int(alpha.numel()),
                                            _ptr(fdot), int(fdot.numel()), _stream_handle(stream)), self.handle)
 
-    def candidates(self, capacity: Optional[int] = None, allow_overflow: bool = False):
-        """Drain the candidates: (records, keys, n_found) as numpy structured arrays."""
+    def candidates(self, capacity: Optional[int] = None, allow_overflow: bool = False, out=None):
+        """Drain the candidates: (records, keys, n_found) as numpy structured arrays.
+        `out` = (records, keys) from candidate_buffers() is filled instead of new arrays."""
         n = ctypes.c_int64()
-        if capacity is None:
-            capacity = int(self.options.candidate_capacity)
-        recs = np.zeros(capacity, dtype=CANDIDATE_NP)
-        keys = np.zeros(capacity, dtype=KEY_NP)
+        if out is not None:
+            recs, keys = out
+            capacity = min(len(recs), len(keys)) if capacity is None else min(capacity, len(recs), len(keys))
+        else:
+            if capacity is None:
+                capacity = int(self.options.candidate_capacity)
+            recs = np.zeros(capacity, dtype=CANDIDATE_NP)
+            keys = np.zeros(capacity, dtype=KEY_NP)
         st = self.lib.fstat_candidates(self.handle, recs.ctypes.data, keys.ctypes.data, capacity, ctypes.byref(n))
         if st == E_OVERFLOW and allow_overflow:
             m = min(capacity, n.value, int(self.options.candidate_capacity))
@@ -293,6 +298,11 @@ class Plan:
             self.destroy()
         except Exception:
             pass
+
+
+def candidate_buffers(capacity: int):
+    """Host arrays (records, keys) of `capacity` entries for Plan.candidates(out=...)."""
+    return np.empty(capacity, dtype=CANDIDATE_NP), np.empty(capacity, dtype=KEY_NP)
 
 
 def lattice_sky_range(lat: fstat_lattice):
