@@ -81,3 +81,20 @@ def compare_candidates(keys, twoF, ora_spec, threshold, guard_rel, k_min=0, sky_
     err = max([abs(g[k] - ora_spec[k[0], k[1], k[2] - k_min]) / max(ora_spec[k[0], k[1], k[2] - k_min], 4.0)
                for k in set(g) & o], default=0.0)
     return len(g), len(o), flips, mism, err
+
+
+def per_sky_oracle(seg, alpha, delta, fdot, nfft, check, full=False, workers=None):
+    """Call check(i, ref) for every sky i, ref[s, k] being the oracle's 2F of template
+    (sky i, spindown s) over all bins, the skies spread over threads (the oracle's FFTs
+    and array arithmetic release the interpreter lock); returns the results in sky order.
+    Only one sky's spectra per thread are held at a time."""
+    import concurrent.futures
+    import os
+
+    def one(i):
+        sky = ora.sky_stage(seg, float(alpha[i]), float(delta[i]), nfft)
+        ref = np.array([ora.template_two_f(seg, sky, float(f), nfft, 0, -1, full) for f in fdot])
+        return check(i, ref)
+    workers = workers or max(1, min(16, len(os.sched_getaffinity(0))))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(one, range(len(alpha))))
