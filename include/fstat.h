@@ -177,6 +177,26 @@ fstat_status fstat_twoF_spectrum(fstat_plan_t plan, int32_t segment,
                                  const double* alpha, const double* delta, int32_t nsky,
                                  const double* fdot, int32_t nfdot, void* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): fstat_twoF_spectrum with
+ * the same arguments, layout and results, run on a static device scratch of
+ * FSTAT_STATIC_SCRATCH_BYTES instead of the plan's workspace.  Each GPU the library
+ * runs on holds its own such scratch, from when the library's device code is loaded
+ * on it until the process ends.  The call allocates nothing and creates nothing: every launch goes
+ * to `stream` in order (no graph, no second stream, no timing events), with the
+ * plan's batch sizes shrunk until the workspace of the plan's largest segment fits
+ * the scratch.  FSTAT_E_INVAL when even one sky position and one template do not fit
+ * (mixed precision fits nfft <= 2^19, FP64 nfft <= 2^18), or for the arguments
+ * fstat_twoF_spectrum rejects; FSTAT_E_STATE when the plan's device is not current.
+ * Every call on one GPU uses that GPU's one scratch, whatever the plan: calls that
+ * overlap on one GPU (on different streams, threads or plans) race on it and give
+ * wrong spectra, so order them on one stream.  Nothing in the scratch needs to start
+ * at zero: every kernel writes what it reads.  Asynchronous on `stream`. */
+#define FSTAT_STATIC_SCRATCH_BYTES (64ull << 20)
+fstat_status fstat_twoF_spectrum_static(fstat_plan_t plan, int32_t segment, const double* alpha,
+                                        const double* delta, int32_t nsky, const double* fdot, int32_t nfdot,
+                                        void* out, void* stream);
+
 /* The per-sky steps of Sect. 2 (direction, Roemer delay, a(t), b(t), phase
  * demodulation, resampling with the FFT and splines), exposed one by one.
  * Per-sky intermediates of one sky position, for stage-by-stage checks.

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <utility>
@@ -155,6 +156,11 @@ struct fstat_plan_s {
   bool used_stream = false;
   // profiling
   bool profiling = false;
+  // every launch on the caller's stream (no sky stream, no events): the static-scratch call
+  bool single_stream = false;
+  // this device's copy of the static scratch (address taken when the plan was made)
+  void* static_ws = nullptr;
+  std::string static_err;
   std::vector<hipEvent_t> ev_pool;
   std::vector<ProfRec> prof;
   std::string last_error;
@@ -320,6 +326,33 @@ static SegConst seg_const(const SegInfo& si) {
   sc.x = si.s.x;
   sc.r = si.s.r_ssb;
   return sc;
+}
+
+// ------------------------------------------------------------- static scratch
+// Device memory of the entry point that allocates nothing (fstat_twoF_spectrum_static):
+// the search workspace of one call, in a static array of which each GPU the library runs
+// on holds its own copy until the process ends.  Host code never uses the array's name
+// as an address: the address of this device's copy comes from hipGetSymbolAddress, once
+// per device with that device current (static_scratch_address), and is kept per device.
+static __device__ __align__(256) unsigned char scratch[FSTAT_STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[MAX_DEVICES] = {};
+
+static hipError_t static_scratch_address(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
 }
 
 // ------------------------------------------------------------- profiling
@@ -658,7 +691,7 @@ static fstat_status search_impl(fstat_plan_t p, int segment, const Grid& g, int 
     // reader of that buffer), the templates of batch b for its sky stage.  With per-launch
     // profiling on, the sky stage stays on `st`, so that each timed kernel runs alone.
     const int nbatch = (nsky + p->Sb - 1) / p->Sb;
-    hipStream_t sst = p->profiling ? st : p->sstream;
+    hipStream_t sst = (p->profiling || p->single_stream) ? st : p->sstream;
     if (sst != st) {
       HIP_TRY(p, hipEventRecord(p->ev_fork, st), "sky stream fork");
       HIP_TRY(p, hipStreamWaitEvent(sst, p->ev_fork, 0), "sky stream fork");
@@ -696,7 +729,7 @@ static fstat_status search_impl(fstat_plan_t p, int segment, const Grid& g, int 
 // All launches of one search call (begin-search marker first).
 static fstat_status enqueue_search(fstat_plan_t p, int segment, const Grid& g, int mode, void* spectrum,
                                    hipStream_t st) {
-  if (!p->sstream) {
+  if (!p->sstream && !p->single_stream) {
     HIP_TRY(p, hipStreamCreateWithFlags(&p->sstream, hipStreamNonBlocking), "sky stream");
     HIP_TRY(p, hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming), "sky stream event");
     for (int k = 0; k < 2; ++k) {
@@ -1378,6 +1411,11 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_opt
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && ncu > 0)
       p->n_cu = ncu;
   }
+  {
+    // the static scratch of this device, for fstat_twoF_spectrum_static
+    const hipError_t es = static_scratch_address(p->device, &p->static_ws);
+    if (es != hipSuccess) p->static_err = std::string("static scratch address: ") + hipGetErrorString(es);
+  }
   std::vector<unsigned char> tb;
   fill_tables<float>(tb, p->tab, 0, KT_F32);
   fill_tables<double>(tb, p->tab, 1, KT_F64);
@@ -1492,6 +1530,54 @@ fstat_status fstat_twoF_spectrum(fstat_plan_t plan, int32_t segment, const doubl
   plan->last_stream = st;
   plan->used_stream = true;
   return run_search(plan, segment, explicit_grid(alpha, delta, nsky, fdot, nfdot), 1, out, st);
+}
+
+fstat_status fstat_twoF_spectrum_static(fstat_plan_t plan, int32_t segment, const double* alpha,
+                                        const double* delta, int32_t nsky, const double* fdot, int32_t nfdot,
+                                        void* out, void* stream) {
+  fstat_status r = check_lists(plan, segment, alpha, delta, nsky, fdot, nfdot);
+  if (r != FSTAT_OK) return r;
+  if (segment < 0) return fail(plan, FSTAT_E_INVAL, "spectrum needs one segment");
+  if (!out) return fail(plan, FSTAT_E_INVAL, "out is NULL");
+  if (!plan->static_ws) return fail(plan, FSTAT_E_DEVICE, plan->static_err);
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != plan->device)
+    return fail(plan, FSTAT_E_STATE, "the plan's device is not the current device");
+  const size_t cap = FSTAT_STATIC_SCRATCH_BYTES;
+  if (layout(plan, 1, 1, false) > cap) {
+    char msg[200];
+    std::snprintf(msg, sizeof msg, "the plan's largest segment needs %zu workspace bytes with one sky and one "
+                  "template; the static scratch holds %zu", layout(plan, 1, 1, false), cap);
+    return fail(plan, FSTAT_E_INVAL, msg);
+  }
+  // the plan's batch sizes, shrunk as by admission until the workspace fits the scratch
+  int Sb = std::min(plan->Sb, (int)nsky), B = plan->B;
+  while (layout(plan, Sb, B, false) > cap && (Sb > 1 || B > 1)) {
+    if (B > 1 && (B >= 2 * Sb || Sb == 1)) B = (B + 1) / 2;
+    else Sb = (Sb + 1) / 2;
+  }
+  // run on the scratch, every launch on `stream`, then restore the plan's own workspace,
+  // batch sizes and layout (the enqueued kernels hold their arguments by value)
+  void* const ws0 = plan->ws;
+  const int Sb0 = plan->Sb, B0 = plan->B;
+  const bool prof0 = plan->profiling;
+  plan->ws = plan->static_ws;
+  plan->Sb = Sb;
+  plan->B = B;
+  layout(plan, Sb, B, true);
+  plan->single_stream = true;
+  plan->profiling = false;
+  hipStream_t st = (hipStream_t)stream;
+  r = enqueue_search(plan, segment, explicit_grid(alpha, delta, nsky, fdot, nfdot), 1, out, st);
+  plan->single_stream = false;
+  plan->profiling = prof0;
+  plan->ws = ws0;
+  plan->Sb = Sb0;
+  plan->B = B0;
+  layout(plan, Sb0, B0, true);
+  plan->last_stream = st;
+  plan->used_stream = true;
+  return r;
 }
 
 // ------------------------------------------------------------------ lattice grid

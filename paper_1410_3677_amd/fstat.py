@@ -24,7 +24,8 @@ KERNEL_SKY_PREP, KERNEL_RESAMPLE, KERNEL_TEMPLATE_A, KERNEL_TEMPLATE_B = range(4
 KERNEL_NAMES = ("sky_prep", "resample", "template_a", "template_b")
 
 EXPORTED = ("fstat_options_default", "fstat_plan", "fstat_plan_workspace_size", "fstat_plan_set_workspace",
-            "fstat_search_batch", "fstat_candidates", "fstat_twoF_spectrum", "fstat_sky_stages",
+            "fstat_search_batch", "fstat_candidates", "fstat_twoF_spectrum", "fstat_twoF_spectrum_static",
+            "fstat_sky_stages",
             "fstat_profile_enable", "fstat_profile_read", "fstat_plan_info", "fstat_autotune", "fstat_destroy",
             "fstat_strerror", "fstat_last_error", "fstat_vet_param_count", "fstat_vet_create",
             "fstat_vet_set_params", "fstat_vet_get_params", "fstat_vet_forward", "fstat_vet_gradient",
@@ -97,6 +98,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "fstat_search_batch": (i32, [P, i32, P, P, i32, P, i32, P]),
         "fstat_candidates": (i32, [P, P, P, i64, ctypes.POINTER(i64)]),
         "fstat_twoF_spectrum": (i32, [P, i32, P, P, i32, P, i32, P, P]),
+        "fstat_twoF_spectrum_static": (i32, [P, i32, P, P, i32, P, i32, P, P]),
         "fstat_sky_stages": (i32, [P, i32, dbl, dbl, P, P, P, P, P, P, P, P]),
         "fstat_profile_enable": (i32, [P, i32]),
         "fstat_profile_read": (i32, [P, i32, ctypes.POINTER(i64), ctypes.POINTER(dbl), i32]),
@@ -264,6 +266,12 @@ class Plan:
         _check(self.lib.fstat_twoF_spectrum(self.handle, segment, _ptr(alpha), _ptr(delta), int(alpha.numel()),
                                             _ptr(fdot), int(fdot.numel()), _ptr(out), _stream_handle(stream)),
                self.handle)
+
+    def twoF_spectrum_static(self, segment: int, alpha, delta, fdot, out, stream=None):
+        """twoF_spectrum on the library's static device scratch (allocates nothing)."""
+        _check(self.lib.fstat_twoF_spectrum_static(self.handle, segment, _ptr(alpha), _ptr(delta),
+                                                   int(alpha.numel()), _ptr(fdot), int(fdot.numel()), _ptr(out),
+                                                   _stream_handle(stream)), self.handle)
 
     def sky_stages(self, segment: int, alpha: float, delta: float, abc=None, za=None, zb=None, ua=None, ub=None,
                    zta=None, ztb=None, stream=None):
