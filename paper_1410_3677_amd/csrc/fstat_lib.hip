@@ -8,12 +8,16 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <type_traits>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
 #include "../../include/fstat.h"
 #include "fstat_kernels.hpp"
+#include "fstat_launch.hpp"
+#include "fstat_drain.hpp"
 #include "fstat_tmpl.hpp"
 #include "fstat_vet.hpp"
 
@@ -152,6 +156,9 @@ struct fstat_plan_s {
   unsigned long long* d_first = nullptr;
   bool scored = false;
   std::vector<SearchRecord> searches;
+  // device memory of the key-ordering drain (grown on demand, kept until destroy)
+  void* drain_ws = nullptr;
+  size_t drain_bytes = 0;
   hipStream_t last_stream = nullptr;
   bool used_stream = false;
   // profiling
@@ -173,8 +180,95 @@ static fstat_status fail(fstat_plan_t plan, fstat_status st, const std::string& 
   return st;
 }
 
+// ------------------------------------------------------------- launch checks
+// Every launch goes through FSTAT_LAUNCH: its grid, workgroup and LDS are checked on the
+// host (launch_problem) against the device's limits and the kernel's compiled maximum
+// workgroup size and static LDS, read once per kernel and device.  A launch outside them
+// is not dispatched: it is refused, later launches on this thread are refused too until
+// launch_status() reports the refusal (as hipErrorInvalidConfiguration; the text names the
+// kernel and the limit), so that no kernel runs on the results of one that did not.
+constexpr int MAX_DEVICES = 64;
+static thread_local bool g_refused = false;
+static thread_local std::string g_refusal, g_last_refusal;
+static thread_local bool g_dlim_ok[MAX_DEVICES] = {};
+static thread_local DeviceLaunchLimits g_dlim[MAX_DEVICES];
+static thread_local std::unordered_map<const void*, KernelLaunchLimits> g_klim[MAX_DEVICES];
+
+static bool read_launch_limits(const void* fn, DeviceLaunchLimits* d, KernelLaunchLimits* k) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return false;
+  if (!g_dlim_ok[dev]) {
+    DeviceLaunchLimits lim;
+    auto get = [&](hipDeviceAttribute_t a, int64_t* out) {
+      int v = 0;
+      if (hipDeviceGetAttribute(&v, a, dev) == hipSuccess && v > 0) *out = v;
+    };
+    get(hipDeviceAttributeMaxThreadsPerBlock, &lim.max_threads_per_block);
+    get(hipDeviceAttributeMaxBlockDimX, &lim.max_block[0]);
+    get(hipDeviceAttributeMaxBlockDimY, &lim.max_block[1]);
+    get(hipDeviceAttributeMaxBlockDimZ, &lim.max_block[2]);
+    get(hipDeviceAttributeMaxGridDimX, &lim.max_grid[0]);
+    get(hipDeviceAttributeMaxGridDimY, &lim.max_grid[1]);
+    get(hipDeviceAttributeMaxGridDimZ, &lim.max_grid[2]);
+    get(hipDeviceAttributeMaxSharedMemoryPerBlock, &lim.max_lds_per_block);
+    g_dlim[dev] = lim;
+    g_dlim_ok[dev] = true;
+  }
+  *d = g_dlim[dev];
+  auto it = g_klim[dev].find(fn);
+  if (it == g_klim[dev].end()) {
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, fn) != hipSuccess) return false;
+    KernelLaunchLimits kl;
+    if (a.maxThreadsPerBlock > 0) kl.max_threads_per_block = a.maxThreadsPerBlock;
+    kl.static_lds = (int64_t)a.sharedSizeBytes;
+    it = g_klim[dev].emplace(fn, kl).first;
+  }
+  *k = it->second;
+  return true;
+}
+
+static bool launch_allowed(const void* fn, const char* name, dim3 g, dim3 b, long long dyn_lds) {
+  if (g_refused) return false;
+  DeviceLaunchLimits d;
+  KernelLaunchLimits k;
+  if (!read_launch_limits(fn, &d, &k)) return true;   // limits unknown: the runtime decides
+  const int64_t grid[3] = {g.x, g.y, g.z}, block[3] = {b.x, b.y, b.z};
+  const std::string why = launch_problem(d, k, grid, block, dyn_lds);
+  if (why.empty()) return true;
+  g_refused = true;
+  g_refusal = std::string(name) + ": " + why;
+  return false;
+}
+
+// The status of the launches since the last call: a refusal, else the runtime's last error.
+static hipError_t launch_status() {
+  if (g_refused) {
+    g_refused = false;
+    g_last_refusal = g_refusal;
+    return hipErrorInvalidConfiguration;
+  }
+  return hipGetLastError();
+}
+
+// Text of a HIP error, with the refused launch when the error is a refusal.
+static std::string hip_error_text(hipError_t e) {
+  std::string t = hipGetErrorString(e);
+  if (e == hipErrorInvalidConfiguration && !g_last_refusal.empty()) {
+    t += " (launch refused before dispatch, " + g_last_refusal + ")";
+    g_last_refusal.clear();
+  }
+  return t;
+}
+
+#define FSTAT_LAUNCH(kernel, grid, block, lds, stream, ...)                                                    \
+  do {                                                                                                          \
+    if (launch_allowed(reinterpret_cast<const void*>(&kernel), #kernel, dim3(grid), dim3(block), (long long)(lds))) \
+      hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);                                        \
+  } while (0)
+
 static fstat_status hip_fail(fstat_plan_t plan, hipError_t e, const char* what) {
-  std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+  std::string msg = std::string(what) + ": " + hip_error_text(e);
   return fail(plan, e == hipErrorOutOfMemory ? FSTAT_E_NOMEM : FSTAT_E_DEVICE, msg);
 }
 
@@ -336,7 +430,6 @@ static SegConst seg_const(const SegInfo& si) {
 // per device with that device current (static_scratch_address), and is kept per device.
 static __device__ __align__(256) unsigned char scratch[FSTAT_STATIC_SCRATCH_BYTES];
 
-constexpr int MAX_DEVICES = 64;
 static std::mutex g_scratch_mu;
 static void* g_scratch_ptr[MAX_DEVICES] = {};
 
@@ -429,17 +522,17 @@ static hipError_t fft_two_pass(const Dev<T>& d, int logL, int P, int Q, const cx
   with_len(Q, [&](auto c) {
     constexpr int QQ = decltype(c)::value;
     const int ntiles = P / tile_width<T, QQ>();
-    hipLaunchKernelGGL((k_fft_pass_a<T, QQ, INV, SRC>), dim3(ntiles * items), dim3(NT), 0, st, in, ld_in,
+    FSTAT_LAUNCH((k_fft_pass_a<T, QQ, INV, SRC>), dim3(ntiles * items), dim3(NT), 0, st, in, ld_in,
                        nvalid, tmp, P, L, d.tw1024, d.lo(logL), d.hi(logL), shlo, shhi);
-    err = hipGetLastError();
+    err = launch_status();
   });
   if (err != hipSuccess) return err;
   with_len(P, [&](auto c) {
     constexpr int PP = decltype(c)::value;
     const int ntiles = Q / tile_width<T, PP>();
-    hipLaunchKernelGGL((k_fft_pass_b<T, PP, INV>), dim3(ntiles * items), dim3(NT), 0, st, tmp, out, ld_out, Q,
+    FSTAT_LAUNCH((k_fft_pass_b<T, PP, INV>), dim3(ntiles * items), dim3(NT), 0, st, tmp, out, ld_out, Q,
                        L, scale, d.tw1024);
-    err = hipGetLastError();
+    err = launch_status();
   });
   return err;
 }
@@ -457,11 +550,11 @@ static fstat_status run_sky_batch(fstat_plan_t p, const Dev<T>& d, const SegInfo
   cx<T>* o = tmp + (size_t)nb * 2 * L;             // [nb][2][M]: odd samples of the 2x upsampling
   {
     ProfScope ps(p, FSTAT_KERNEL_SKY_PREP, st);
-    hipLaunchKernelGGL(k_sky_setup, dim3((nb + 63) / 64), dim3(64), 0, st, alpha, delta, sky0, nb, sc, d.sp());
-    hipLaunchKernelGGL((k_sky_demod<T>), dim3(nblk, nb), dim3(NT), 0, st, sc, d.sp(), za, (long)M, d.part());
-    hipLaunchKernelGGL(k_sky_finalize, dim3(nb), dim3(NT), 0, st, sc, d.sp(), d.part(), nblk,
+    FSTAT_LAUNCH(k_sky_setup, dim3((nb + 63) / 64), dim3(64), 0, st, alpha, delta, sky0, nb, sc, d.sp());
+    FSTAT_LAUNCH((k_sky_demod<T>), dim3(nblk, nb), dim3(NT), 0, st, sc, d.sp(), za, (long)M, d.part());
+    FSTAT_LAUNCH(k_sky_finalize, dim3(nb), dim3(NT), 0, st, sc, d.sp(), d.part(), nblk,
                        p->opt.form == FSTAT_FORM_FULL ? 1 : 0);
-    HIP_TRY(p, hipGetLastError(), "sky stage launch");
+    HIP_TRY(p, launch_status(), "sky stage launch");
   }
   {
     ProfScope ps(p, FSTAT_KERNEL_RESAMPLE, st);
@@ -473,9 +566,9 @@ static fstat_status run_sky_batch(fstat_plan_t p, const Dev<T>& d, const SegInfo
                                                       (T)(1.0 / M), st, d.lo(si.logL), d.hi(si.logL))),
             "upsampling inverse FFT");
     constexpr int KT = sizeof(T) == 8 ? KT_F64 : KT_F32;
-    hipLaunchKernelGGL((k_spline<T, KT>), dim3(nblk, nb), dim3(NT), 0, st, sc, d.sp(), za, o, (long)M, d.zt(),
+    FSTAT_LAUNCH((k_spline<T, KT>), dim3(nblk, nb), dim3(NT), 0, st, sc, d.sp(), za, o, (long)M, d.zt(),
                        (long)n, d.g);
-    HIP_TRY(p, hipGetLastError(), "spline launch");
+    HIP_TRY(p, launch_status(), "spline launch");
   }
   return FSTAT_OK;
 }
@@ -532,10 +625,10 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
           auto go = [&](auto rnz_c) {
             constexpr int RZ = decltype(rnz_c)::value;
             if (p->variant_a == 1)
-              hipLaunchKernelGGL((k_tmpl_a_pair<T, QQ, RZ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T, QQ>()), 0, st, ta,
+              FSTAT_LAUNCH((k_tmpl_a_pair<T, QQ, RZ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T, QQ>()), 0, st, ta,
                                  d.zt(), tbuf, d.twst, d.lo(si.tlog), d.hi(si.tlog));
             else
-              hipLaunchKernelGGL((k_tmpl_a<T, QQ, RZ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T, QQ>()), 0, st, ta, d.zt(),
+              FSTAT_LAUNCH((k_tmpl_a<T, QQ, RZ>), dim3(ntiles * nt), dim3(tmpl_nt_a<T, QQ>()), 0, st, ta, d.zt(),
                                  tbuf, d.twst, d.lo(si.tlog), d.hi(si.tlog));
           };
           switch (rnz) {
@@ -546,7 +639,7 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
             case 7: go(std::integral_constant<int, 7>{}); break;
             default: go(std::integral_constant<int, 8>{}); break;
           }
-          err = hipGetLastError();
+          err = launch_status();
         } else {
           err = hipErrorInvalidValue;
         }
@@ -555,7 +648,7 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
     HIP_TRY(p, err, "template pass A launch");
     const bool capture = (mode == 0 && p->vet != nullptr);
     if (capture) {
-      hipLaunchKernelGGL(k_record_count, dim3(1), dim3(1), 0, st, p->d_count, p->d_first);
+      FSTAT_LAUNCH(k_record_count, dim3(1), dim3(1), 0, st, p->d_count, p->d_first);
       oa.spectrum = p->d_spec;
     }
     {
@@ -572,7 +665,7 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
             auto go = [&](auto mode_c, auto half_c) {
               constexpr int MD = decltype(mode_c)::value;
               constexpr bool HF = decltype(half_c)::value;
-              hipLaunchKernelGGL((k_tmpl_b_ib<PP, MD, HF>), dim3((unsigned)wgs), dim3(256), 0, st, ta, nt, d.sp(),
+              FSTAT_LAUNCH((k_tmpl_b_ib<PP, MD, HF>), dim3((unsigned)wgs), dim3(256), 0, st, ta, nt, d.sp(),
                                  (const cx<float>*)tbuf, oa, (const cx<float>*)d.twst);
             };
             using BT = std::true_type;
@@ -580,7 +673,7 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
             if (capture) half ? go(std::integral_constant<int, 2>{}, BT{}) : go(std::integral_constant<int, 2>{}, BF{});
             else if (mode == 0) half ? go(std::integral_constant<int, 0>{}, BT{}) : go(std::integral_constant<int, 0>{}, BF{});
             else half ? go(std::integral_constant<int, 1>{}, BT{}) : go(std::integral_constant<int, 1>{}, BF{});
-            err = hipGetLastError();
+            err = launch_status();
             return;
           }
           if (p->variant_b == 1) {
@@ -592,7 +685,7 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
           auto go = [&](auto mode_c, auto half_c) {
             constexpr int MD = decltype(mode_c)::value;
             constexpr bool HF = decltype(half_c)::value;
-            hipLaunchKernelGGL((k_tmpl_b_stream<T, PP, MD, HF>), grid, dim3(256), 0, st, ta, nt, d.sp(), tbuf, oa,
+            FSTAT_LAUNCH((k_tmpl_b_stream<T, PP, MD, HF>), grid, dim3(256), 0, st, ta, nt, d.sp(), tbuf, oa,
                                d.twst);
           };
           using I0 = std::integral_constant<int, 0>;
@@ -603,7 +696,7 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
           if (capture) half ? go(I2{}, BT{}) : go(I2{}, BF{});
           else if (mode == 0) half ? go(I0{}, BT{}) : go(I0{}, BF{});
           else half ? go(I1{}, BT{}) : go(I1{}, BF{});
-          err = hipGetLastError();
+          err = launch_status();
           return;
           }
         }
@@ -614,32 +707,32 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
             // transforms, then an epilogue forms the interbinned 2F of the launch's templates
             OutArgs ox = oa;
             ox.spectrum = d.xs();
-            hipLaunchKernelGGL((k_tmpl_b<T, PP, 3>), dim3(ntiles * nt), dim3(tmpl_nt_b<T, PP>()), 0, st, ta, d.sp(),
+            FSTAT_LAUNCH((k_tmpl_b<T, PP, 3>), dim3(ntiles * nt), dim3(tmpl_nt_b<T, PP>()), 0, st, ta, d.sp(),
                                tbuf, ox, d.twst);
-            err = hipGetLastError();
+            err = launch_status();
             if (err != hipSuccess) return;
             const int kc0 = oa.k_min / 2, nkc = (oa.k_max + 1) / 2 - kc0;
             const dim3 grid((unsigned)((nkc + 255) / 256), (unsigned)nt);
             const cx<T>* xs = d.xs();
             if (capture)
-              hipLaunchKernelGGL((k_interbin_2f<T, 2>), grid, dim3(256), 0, st, ta, d.sp(), xs, oa, si.ibw, kc0, nkc);
+              FSTAT_LAUNCH((k_interbin_2f<T, 2>), grid, dim3(256), 0, st, ta, d.sp(), xs, oa, si.ibw, kc0, nkc);
             else if (mode == 0)
-              hipLaunchKernelGGL((k_interbin_2f<T, 0>), grid, dim3(256), 0, st, ta, d.sp(), xs, oa, si.ibw, kc0, nkc);
+              FSTAT_LAUNCH((k_interbin_2f<T, 0>), grid, dim3(256), 0, st, ta, d.sp(), xs, oa, si.ibw, kc0, nkc);
             else
-              hipLaunchKernelGGL((k_interbin_2f<T, 1>), grid, dim3(256), 0, st, ta, d.sp(), xs, oa, si.ibw, kc0, nkc);
-            err = hipGetLastError();
+              FSTAT_LAUNCH((k_interbin_2f<T, 1>), grid, dim3(256), 0, st, ta, d.sp(), xs, oa, si.ibw, kc0, nkc);
+            err = launch_status();
             return;
           }
           if (capture)
-            hipLaunchKernelGGL((k_tmpl_b<T, PP, 2>), dim3(ntiles * nt), dim3(tmpl_nt_b<T, PP>()), 0, st, ta, d.sp(),
+            FSTAT_LAUNCH((k_tmpl_b<T, PP, 2>), dim3(ntiles * nt), dim3(tmpl_nt_b<T, PP>()), 0, st, ta, d.sp(),
                                tbuf, oa, d.twst);
           else if (mode == 0)
-            hipLaunchKernelGGL((k_tmpl_b<T, PP, 0>), dim3(ntiles * nt), dim3(tmpl_nt_b<T, PP>()), 0, st, ta, d.sp(),
+            FSTAT_LAUNCH((k_tmpl_b<T, PP, 0>), dim3(ntiles * nt), dim3(tmpl_nt_b<T, PP>()), 0, st, ta, d.sp(),
                                tbuf, oa, d.twst);
           else
-            hipLaunchKernelGGL((k_tmpl_b<T, PP, 1>), dim3(ntiles * nt), dim3(tmpl_nt_b<T, PP>()), 0, st, ta, d.sp(),
+            FSTAT_LAUNCH((k_tmpl_b<T, PP, 1>), dim3(ntiles * nt), dim3(tmpl_nt_b<T, PP>()), 0, st, ta, d.sp(),
                                tbuf, oa, d.twst);
-          err = hipGetLastError();
+          err = launch_status();
         } else {
           err = hipErrorInvalidValue;
         }
@@ -647,10 +740,10 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
     }
     HIP_TRY(p, err, "template pass B launch");
     if (capture) {
-      hipLaunchKernelGGL(k_capture_patches, dim3(2048), dim3(256), 0, st, p->d_cand, p->d_spec, p->d_patches,
+      FSTAT_LAUNCH(k_capture_patches, dim3(2048), dim3(256), 0, st, p->d_cand, p->d_spec, p->d_patches,
                          (unsigned long long)p->patch_capacity, p->d_count, p->d_first, oa.k_min, oa.k_max, t0,
                          nfdot, sky0);
-      HIP_TRY(p, hipGetLastError(), "patch capture launch");
+      HIP_TRY(p, launch_status(), "patch capture launch");
     }
   }
   return FSTAT_OK;
@@ -738,8 +831,8 @@ static fstat_status enqueue_search(fstat_plan_t p, int segment, const Grid& g, i
     }
   }
   if (mode == 0) {
-    hipLaunchKernelGGL(k_begin_search, dim3(1), dim3(1), 0, st, p->d_search_next);
-    HIP_TRY(p, hipGetLastError(), "search marker launch");
+    FSTAT_LAUNCH(k_begin_search, dim3(1), dim3(1), 0, st, p->d_search_next);
+    HIP_TRY(p, launch_status(), "search marker launch");
   }
   return p->fp64 ? search_impl<double>(p, segment, g, mode, spectrum, st)
                  : search_impl<float>(p, segment, g, mode, spectrum, st);
@@ -873,7 +966,7 @@ fstat_status vet_fail(fstat_vet_t v, fstat_status st, const std::string& msg) {
     hipError_t e_ = (expr);                                                           \
     if (e_ != hipSuccess)                                                             \
       return vet_fail(v, e_ == hipErrorOutOfMemory ? FSTAT_E_NOMEM : FSTAT_E_DEVICE,  \
-                      std::string(what) + ": " + hipGetErrorString(e_));              \
+                      std::string(what) + ": " + hip_error_text(e_));                 \
   } while (0)
 
 // C[m][n] = sum_k A(m, k) B(k, n) on the matrix cores.  Products with a long K and a small
@@ -891,13 +984,13 @@ void gemm(hipStream_t st, int M, int N, int K, const uint16_t* A, long sam, long
   const int kchunk = ((K + splits - 1) / splits + 15) / 16 * 16;
   dim3 grid((N + 63) / 64, (M + 63) / 64, splits);
   if (splits == 1) {
-    hipLaunchKernelGGL(vet::k_gemm_bf16, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, Cm, ldc, 0L,
+    FSTAT_LAUNCH(vet::k_gemm_bf16, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, Cm, ldc, 0L,
                        kchunk);
   } else {
     const long count = (long)M * N;
-    hipLaunchKernelGGL(vet::k_gemm_bf16, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, scratch, (long)N,
+    FSTAT_LAUNCH(vet::k_gemm_bf16, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, scratch, (long)N,
                        count, kchunk);
-    hipLaunchKernelGGL(vet::k_vet_sum_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, scratch, splits,
+    FSTAT_LAUNCH(vet::k_vet_sum_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, scratch, splits,
                        count, N, ldc, Cm);
   }
 }
@@ -906,8 +999,8 @@ void gemm(hipStream_t st, int M, int N, int K, const uint16_t* A, long sam, long
 void colsum(hipStream_t st, const float* m, long rows, int cols, float* out, float* scratch) {
   const long per = 4096;
   const int chunks = (int)((rows + per - 1) / per);
-  hipLaunchKernelGGL(vet::k_vet_colsum_part, dim3(cols, chunks), dim3(256), 0, st, m, rows, cols, per, scratch);
-  hipLaunchKernelGGL(vet::k_vet_colsum_final, dim3((cols + 255) / 256), dim3(256), 0, st, scratch, chunks, cols, out);
+  FSTAT_LAUNCH(vet::k_vet_colsum_part, dim3(cols, chunks), dim3(256), 0, st, m, rows, cols, per, scratch);
+  FSTAT_LAUNCH(vet::k_vet_colsum_final, dim3((cols + 255) / 256), dim3(256), 0, st, scratch, chunks, cols, out);
 }
 
 __global__ void k_vet_store_scores(CandEntry* cand, const float* logit, long n) {
@@ -918,9 +1011,9 @@ __global__ void k_vet_store_scores(CandEntry* cand, const float* logit, long n) 
 }
 
 void vet_prepare(fstat_vet_t v, hipStream_t st) {
-  hipLaunchKernelGGL(vet::k_vet_prepare, blocks_for((long)vet::H * vet::X), dim3(256), 0, st, v->theta, v->wf2,
+  FSTAT_LAUNCH(vet::k_vet_prepare, blocks_for((long)vet::H * vet::X), dim3(256), 0, st, v->theta, v->wf2,
                      v->wt2, v->wf3, v->wt3, v->w4b, v->w5b);
-  hipLaunchKernelGGL(vet::k_vet_prepare_frag, blocks_for(vet::WQ_ELEMS), dim3(256), 0, st, v->theta, v->wq2, v->wq3);
+  FSTAT_LAUNCH(vet::k_vet_prepare_frag, blocks_for(vet::WQ_ELEMS), dim3(256), 0, st, v->theta, v->wq2, v->wq3);
 }
 
 // inference of n <= max_batch patches (logits to `out`): fused LDS convolutions, the
@@ -931,23 +1024,23 @@ constexpr int INFER_SPLITS = 4;
 // 8192 -> 128 product reads x from HBM); `read` is recorded once x has been read.
 void vet_conv_stage(fstat_vet_t v, const float* patches, int n, uint16_t* x, hipStream_t st) {
   using namespace vet;
-  hipLaunchKernelGGL(k_vet_conv_infer, dim3((n + CV_NP - 1) / CV_NP), dim3(CV_NT), 0, st, patches, n, v->theta, v->wq2,
+  FSTAT_LAUNCH(k_vet_conv_infer, dim3((n + CV_NP - 1) / CV_NP), dim3(CV_NT), 0, st, patches, n, v->theta, v->wq2,
                      v->wq3, x);
 }
 
 void vet_dense_stage(fstat_vet_t v, const uint16_t* x, int n, float* out, hipEvent_t read, hipStream_t st) {
   using namespace vet;
   const int nbp = (n + GT - 1) / GT * GT;
-  hipLaunchKernelGGL(k_gemm_nt_lds, dim3(H / GT, nbp / GT, INFER_SPLITS), dim3(256), 0, st, nbp, H, X, x, v->w4b,
+  FSTAT_LAUNCH(k_gemm_nt_lds, dim3(H / GT, nbp / GT, INFER_SPLITS), dim3(256), 0, st, nbp, H, X, x, v->w4b,
                      v->scratch, X / INFER_SPLITS);
   if (read) (void)hipEventRecord(read, st);
   const long count = (long)nbp * H;
-  hipLaunchKernelGGL(k_vet_sum_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->scratch, INFER_SPLITS, count,
+  FSTAT_LAUNCH(k_vet_sum_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->scratch, INFER_SPLITS, count,
                      n, H, v->theta + O_B4, v->a4b);
   gemm(st, n, H, H, v->a4b, H, 1, v->w5b, 1, H, v->z5, H);
-  hipLaunchKernelGGL(k_vet_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->z5, (long)n, H, v->theta + O_B5,
+  FSTAT_LAUNCH(k_vet_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->z5, (long)n, H, v->theta + O_B5,
                      (uint16_t*)nullptr, v->a5);
-  hipLaunchKernelGGL(k_vet_fc3, blocks_for(n), dim3(256), 0, st, v->a5, n, v->theta, out);
+  FSTAT_LAUNCH(k_vet_fc3, blocks_for(n), dim3(256), 0, st, v->a5, n, v->theta, out);
 }
 
 // All n patches in batches of max_batch, pipelined: batch k's convolutions go to the
@@ -974,12 +1067,12 @@ static fstat_status vet_score_all(fstat_vet_t v, const float* patches, long long
     uint16_t* x = buf ? v->a3b2 : v->a3b;
     if (k >= 2) VET_TRY(v, hipStreamWaitEvent(v->cstream, v->ev_read[buf], 0), "vetter order");
     vet_conv_stage(v, patches + i * vet::L, b, x, v->cstream);
-    VET_TRY(v, hipGetLastError(), "scoring launch");
+    VET_TRY(v, launch_status(), "scoring launch");
     VET_TRY(v, hipEventRecord(v->ev_conv[buf], v->cstream), "vetter order");
     VET_TRY(v, hipStreamWaitEvent(st, v->ev_conv[buf], 0), "vetter join");
     float* out = out_of(i);
     vet_dense_stage(v, x, b, out, v->ev_read[buf], st);
-    VET_TRY(v, hipGetLastError(), "scoring launch");
+    VET_TRY(v, launch_status(), "scoring launch");
     tail(i, b, out);
   }
   return FSTAT_OK;
@@ -989,15 +1082,15 @@ static fstat_status vet_score_all(fstat_vet_t v, const float* patches, long long
 void vet_forward_batch(fstat_vet_t v, const float* patches, int n, float* out, hipStream_t st) {
   using namespace vet;
   const long NL = (long)n * L;
-  hipLaunchKernelGGL(k_vet_input, blocks_for(NL), dim3(256), 0, st, patches, NL, v->u);
-  hipLaunchKernelGGL(k_vet_conv1, blocks_for(NL * C), dim3(256), 0, st, v->u, n, v->theta, v->z1, v->a1b);
-  hipLaunchKernelGGL(k_vet_im2col, blocks_for(NL * KC), dim3(256), 0, st, v->a1b, n, 1, v->colA);
+  FSTAT_LAUNCH(k_vet_input, blocks_for(NL), dim3(256), 0, st, patches, NL, v->u);
+  FSTAT_LAUNCH(k_vet_conv1, blocks_for(NL * C), dim3(256), 0, st, v->u, n, v->theta, v->z1, v->a1b);
+  FSTAT_LAUNCH(k_vet_im2col, blocks_for(NL * KC), dim3(256), 0, st, v->a1b, n, 1, v->colA);
   gemm(st, (int)NL, C, KC, v->colA, KC, 1, v->wf2, C, 1, v->z2, C);
-  hipLaunchKernelGGL(k_vet_bias_relu, blocks_for(NL * C), dim3(256), 0, st, v->z2, NL, C, v->theta + O_B2, v->a2b,
+  FSTAT_LAUNCH(k_vet_bias_relu, blocks_for(NL * C), dim3(256), 0, st, v->z2, NL, C, v->theta + O_B2, v->a2b,
                      (float*)nullptr);
-  hipLaunchKernelGGL(k_vet_im2col, blocks_for(NL * KC), dim3(256), 0, st, v->a2b, n, 1, v->colB);
+  FSTAT_LAUNCH(k_vet_im2col, blocks_for(NL * KC), dim3(256), 0, st, v->a2b, n, 1, v->colB);
   gemm(st, (int)NL, C, KC, v->colB, KC, 1, v->wf3, C, 1, v->z3, C);
-  hipLaunchKernelGGL(k_vet_bias_relu, blocks_for(NL * C), dim3(256), 0, st, v->z3, NL, C, v->theta + O_B3, v->a3b,
+  FSTAT_LAUNCH(k_vet_bias_relu, blocks_for(NL * C), dim3(256), 0, st, v->z3, NL, C, v->theta + O_B3, v->a3b,
                      (float*)nullptr);
   {
     // the 8192 -> 128 layer: LDS-tiled product, K split so that the grid fills the chip
@@ -1005,18 +1098,18 @@ void vet_forward_batch(fstat_vet_t v, const float* patches, int n, float* out, h
     const int tiles = (H / GT) * (nbp / GT);
     int splits = 1;
     while (splits < 32 && tiles * splits < 256) splits <<= 1;
-    hipLaunchKernelGGL(k_gemm_nt_lds, dim3(H / GT, nbp / GT, splits), dim3(256), 0, st, nbp, H, X, v->a3b, v->w4b,
+    FSTAT_LAUNCH(k_gemm_nt_lds, dim3(H / GT, nbp / GT, splits), dim3(256), 0, st, nbp, H, X, v->a3b, v->w4b,
                        v->scratch, X / splits);
     const long count = (long)nbp * H;
-    hipLaunchKernelGGL(k_vet_sum_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, v->scratch, splits,
+    FSTAT_LAUNCH(k_vet_sum_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, v->scratch, splits,
                        count, H, (long)H, v->z4);
   }
-  hipLaunchKernelGGL(k_vet_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->z4, (long)n, H, v->theta + O_B4,
+  FSTAT_LAUNCH(k_vet_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->z4, (long)n, H, v->theta + O_B4,
                      v->a4b, (float*)nullptr);
   gemm(st, n, H, H, v->a4b, H, 1, v->w5b, 1, H, v->z5, H);
-  hipLaunchKernelGGL(k_vet_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->z5, (long)n, H, v->theta + O_B5,
+  FSTAT_LAUNCH(k_vet_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->z5, (long)n, H, v->theta + O_B5,
                      (uint16_t*)nullptr, v->a5);
-  hipLaunchKernelGGL(k_vet_fc3, blocks_for(n), dim3(256), 0, st, v->a5, n, v->theta, out);
+  FSTAT_LAUNCH(k_vet_fc3, blocks_for(n), dim3(256), 0, st, v->a5, n, v->theta, out);
 }
 
 void vet_backward(fstat_vet_t v, const float* labels, int n, hipStream_t st) {
@@ -1024,37 +1117,37 @@ void vet_backward(fstat_vet_t v, const float* labels, int n, hipStream_t st) {
   const long NL = (long)n * L;
   float* g = v->grad;
   float* sc = v->scratch;
-  hipLaunchKernelGGL(k_vet_head_backward, blocks_for((long)n * H), dim3(256), 0, st, v->logit, labels, n, v->theta,
+  FSTAT_LAUNCH(k_vet_head_backward, blocks_for((long)n * H), dim3(256), 0, st, v->logit, labels, n, v->theta,
                      v->z5, v->dz5, v->dz5b, v->dlogit, v->lterm);
-  hipLaunchKernelGGL(k_vet_head_reduce, dim3(1), dim3(1024), 0, st, v->dlogit, v->a5, v->lterm, n, g, v->loss);
+  FSTAT_LAUNCH(k_vet_head_reduce, dim3(1), dim3(1024), 0, st, v->dlogit, v->a5, v->lterm, n, g, v->loss);
   gemm(st, H, H, n, v->dz5b, 1, H, v->a4b, H, 1, g + O_W5, H, sc);             // dW5 = dz5^T a4
   colsum(st, v->dz5, (long)n, H, g + O_B5, sc);
   gemm(st, n, H, H, v->dz5b, H, 1, v->w5b, H, 1, v->dh4, H);                   // dh4 = dz5 W5
-  hipLaunchKernelGGL(k_vet_relu_mask, blocks_for((long)n * H), dim3(256), 0, st, v->dh4, v->z4, (long)n * H, v->dz4b);
+  FSTAT_LAUNCH(k_vet_relu_mask, blocks_for((long)n * H), dim3(256), 0, st, v->dh4, v->z4, (long)n * H, v->dz4b);
   gemm(st, H, X, n, v->dz4b, 1, H, v->a3b, X, 1, g + O_W4, X, sc);             // dW4 = dz4^T x
   colsum(st, v->dh4, (long)n, H, g + O_B4, sc);
   gemm(st, n, X, H, v->dz4b, H, 1, v->w4b, X, 1, v->dx, X);                    // dx = dz4 W4
-  hipLaunchKernelGGL(k_vet_relu_mask, blocks_for(NL * C), dim3(256), 0, st, v->dx, v->z3, NL * C, v->dzb);
+  FSTAT_LAUNCH(k_vet_relu_mask, blocks_for(NL * C), dim3(256), 0, st, v->dx, v->z3, NL * C, v->dzb);
   gemm(st, KC, C, (int)NL, v->colB, 1, KC, v->dzb, C, 1, v->dwm, C, sc);        // dW3 (im2col layout)
-  hipLaunchKernelGGL(k_vet_scatter_conv_grad, blocks_for(C * C * KW), dim3(256), 0, st, v->dwm, g + O_W3);
+  FSTAT_LAUNCH(k_vet_scatter_conv_grad, blocks_for(C * C * KW), dim3(256), 0, st, v->dwm, g + O_W3);
   colsum(st, v->dx, NL, C, g + O_B3, sc);
-  hipLaunchKernelGGL(k_vet_im2col, blocks_for(NL * KC), dim3(256), 0, st, v->dzb, n, -1, v->colC);
+  FSTAT_LAUNCH(k_vet_im2col, blocks_for(NL * KC), dim3(256), 0, st, v->dzb, n, -1, v->colC);
   gemm(st, (int)NL, C, KC, v->colC, KC, 1, v->wt3, C, 1, v->da, C);             // da2
-  hipLaunchKernelGGL(k_vet_relu_mask, blocks_for(NL * C), dim3(256), 0, st, v->da, v->z2, NL * C, v->dzb);
+  FSTAT_LAUNCH(k_vet_relu_mask, blocks_for(NL * C), dim3(256), 0, st, v->da, v->z2, NL * C, v->dzb);
   gemm(st, KC, C, (int)NL, v->colA, 1, KC, v->dzb, C, 1, v->dwm, C, sc);        // dW2
-  hipLaunchKernelGGL(k_vet_scatter_conv_grad, blocks_for(C * C * KW), dim3(256), 0, st, v->dwm, g + O_W2);
+  FSTAT_LAUNCH(k_vet_scatter_conv_grad, blocks_for(C * C * KW), dim3(256), 0, st, v->dwm, g + O_W2);
   colsum(st, v->da, NL, C, g + O_B2, sc);
-  hipLaunchKernelGGL(k_vet_im2col, blocks_for(NL * KC), dim3(256), 0, st, v->dzb, n, -1, v->colC);
+  FSTAT_LAUNCH(k_vet_im2col, blocks_for(NL * KC), dim3(256), 0, st, v->dzb, n, -1, v->colC);
   gemm(st, (int)NL, C, KC, v->colC, KC, 1, v->wt2, C, 1, v->da, C);             // da1
-  hipLaunchKernelGGL(k_vet_relu_mask, blocks_for(NL * C), dim3(256), 0, st, v->da, v->z1, NL * C, v->dzb);
+  FSTAT_LAUNCH(k_vet_relu_mask, blocks_for(NL * C), dim3(256), 0, st, v->da, v->z1, NL * C, v->dzb);
   {
     const long per = 256;
     const int chunks = (int)((NL + per - 1) / per);
     const int ncols = C * (KW + 1);
-    hipLaunchKernelGGL(k_vet_conv1_backward_part, dim3(chunks), dim3(256), 0, st, v->da, v->u, NL, per, sc);
-    hipLaunchKernelGGL(k_vet_colsum_final, dim3((ncols + 255) / 256), dim3(256), 0, st, sc, chunks, ncols,
+    FSTAT_LAUNCH(k_vet_conv1_backward_part, dim3(chunks), dim3(256), 0, st, v->da, v->u, NL, per, sc);
+    FSTAT_LAUNCH(k_vet_colsum_final, dim3((ncols + 255) / 256), dim3(256), 0, st, sc, chunks, ncols,
                        sc + (long)chunks * ncols);
-    hipLaunchKernelGGL(k_vet_conv1_scatter, dim3(1), dim3(256), 0, st, sc + (long)chunks * ncols, g);
+    FSTAT_LAUNCH(k_vet_conv1_scatter, dim3(1), dim3(256), 0, st, sc + (long)chunks * ncols, g);
   }
 }
 }  // namespace
@@ -1117,7 +1210,7 @@ fstat_status fstat_vet_set_params(fstat_vet_t v, const float* params, int64_t n)
   VET_TRY(v, hipMemset(v->m2, 0, n * 4), "optimiser reset");
   v->steps = 0;
   vet_prepare(v, nullptr);
-  VET_TRY(v, hipGetLastError(), "weight preparation");
+  VET_TRY(v, launch_status(), "weight preparation");
   VET_TRY(v, hipDeviceSynchronize(), "weight preparation");
   return FSTAT_OK;
 }
@@ -1141,7 +1234,7 @@ fstat_status fstat_vet_gradient(fstat_vet_t v, const float* patches, const float
   hipStream_t st = (hipStream_t)stream;
   vet_forward_batch(v, patches, (int)n, v->logit, st);
   vet_backward(v, labels, (int)n, st);
-  VET_TRY(v, hipGetLastError(), "gradient launch");
+  VET_TRY(v, launch_status(), "gradient launch");
   if (loss) VET_TRY(v, hipMemcpyAsync(loss, v->loss, 4, hipMemcpyDeviceToDevice, st), "loss copy");
   if (grad) VET_TRY(v, hipMemcpyAsync(grad, v->grad, vet::N_PARAMS * 4, hipMemcpyDeviceToDevice, st), "grad copy");
   return FSTAT_OK;
@@ -1153,10 +1246,10 @@ fstat_status fstat_vet_adam_step(fstat_vet_t v, float lr, float beta1, float bet
   hipStream_t st = (hipStream_t)stream;
   v->steps += 1;
   const double step = lr * std::sqrt(1.0 - std::pow((double)beta2, v->steps)) / (1.0 - std::pow((double)beta1, v->steps));
-  hipLaunchKernelGGL(vet::k_vet_adam, blocks_for(vet::N_PARAMS), dim3(256), 0, st, v->theta, v->grad, v->m1, v->m2,
+  FSTAT_LAUNCH(vet::k_vet_adam, blocks_for(vet::N_PARAMS), dim3(256), 0, st, v->theta, v->grad, v->m1, v->m2,
                      (long)vet::N_PARAMS, (float)step, beta1, beta2, eps);
   vet_prepare(v, st);
-  VET_TRY(v, hipGetLastError(), "optimiser launch");
+  VET_TRY(v, launch_status(), "optimiser launch");
   return FSTAT_OK;
 }
 
@@ -1222,10 +1315,10 @@ fstat_status fstat_plan_vet_candidates(fstat_plan_t plan, void* stream) {
   const fstat_status rs = vet_score_all(
       v, plan->d_patches, n, st, [&](long long) { return v->logit; },
       [&](long long i, int b, float* logits) {
-        hipLaunchKernelGGL(k_vet_store_scores, blocks_for(b), dim3(256), 0, st, plan->d_cand + i, logits, (long)b);
+        FSTAT_LAUNCH(k_vet_store_scores, blocks_for(b), dim3(256), 0, st, plan->d_cand + i, logits, (long)b);
       });
   if (rs != FSTAT_OK) return fail(plan, rs, v->last_error);
-  HIP_TRY(plan, hipGetLastError(), "scoring launch");
+  HIP_TRY(plan, launch_status(), "scoring launch");
   HIP_TRY(plan, hipStreamSynchronize(st), "scoring");
   plan->scored = true;
   plan->last_stream = st;
@@ -1652,8 +1745,8 @@ fstat_status fstat_lattice_sky(const fstat_lattice* lat, int32_t hemisphere, con
   a.w_spin = w_spin;
   a.nm = capacity > 0 ? nm : nullptr;
   a.count = (long long*)count;
-  hipLaunchKernelGGL(k_lattice_sky, dim3(1), dim3(256), 0, (hipStream_t)stream, a);
-  hipError_t e = hipGetLastError();
+  FSTAT_LAUNCH(k_lattice_sky, dim3(1), dim3(256), 0, (hipStream_t)stream, a);
+  hipError_t e = launch_status();
   if (e != hipSuccess) return hip_fail(nullptr, e, "lattice sky launch");
   return FSTAT_OK;
 }
@@ -1732,9 +1825,9 @@ static fstat_status sky_stages_impl(fstat_plan_t plan, const SegInfo& si, const 
   HIP_TRY(plan, cp(zb, zab + M, n * cb), "stage copy");
   // the 2x upsampled series, assembled from the series and its half-sample shift
   cx<T>* u = zab + 2 * M;   // the spectrum's space, no longer needed
-  hipLaunchKernelGGL((k_upsampled<T>), dim3((unsigned)((L + NT - 1) / NT), 2), dim3(NT), 0, st, zab, o, (long)M,
+  FSTAT_LAUNCH((k_upsampled<T>), dim3((unsigned)((L + NT - 1) / NT), 2), dim3(NT), 0, st, zab, o, (long)M,
                      (int)n, (int)L, u);
-  HIP_TRY(plan, hipGetLastError(), "upsampled series launch");
+  HIP_TRY(plan, launch_status(), "upsampled series launch");
   HIP_TRY(plan, cp(ua, u, L * cb), "stage copy");
   HIP_TRY(plan, cp(ub, u + L, L * cb), "stage copy");
   HIP_TRY(plan, cp(zta, d.zt(), n * cb), "stage copy");
@@ -1773,6 +1866,111 @@ fstat_status fstat_sky_stages(fstat_plan_t plan, int32_t segment, double alpha, 
   return r;
 }
 
+static bool key_less(const CandEntry& a, const CandEntry& b) {
+  if (a.search != b.search) return a.search < b.search;
+  if (a.segment != b.segment) return a.segment < b.segment;
+  if (a.sky != b.sky) return a.sky < b.sky;
+  if (a.fdot_idx != b.fdot_idx) return a.fdot_idx < b.fdot_idx;
+  return a.bin < b.bin;
+}
+
+// Key order on the device (fstat_drain.hpp: count -> offsets -> write, then each
+// template's range by bin), leaving d_cand[0, stored) ordered.  Returns false, with the
+// entries left where they were, when the host must order them instead: more templates
+// than the counting tables take, an entry whose key lies outside its search, or the
+// device memory not available; `*from_grouped` is set when d_cand was given up for the
+// grouped copy (a template with more crossings than one workgroup orders).
+static fstat_status order_on_device(fstat_plan_t p, long long stored, bool* done, const CandEntry** src) {
+  *done = false;
+  *src = p->d_cand;
+  const int nsearch = (int)p->searches.size();
+  const int search0 = p->search_count - nsearch;
+  const int nseg = (int)p->segs.size();
+  std::vector<DrainSearch> hs((size_t)nsearch);
+  long long ntpl = 0;
+  for (int i = 0; i < nsearch; ++i) {
+    hs[(size_t)i].base = ntpl;
+    hs[(size_t)i].nsky = p->searches[(size_t)i].nsky;
+    hs[(size_t)i].nfdot = p->searches[(size_t)i].nfdot;
+    ntpl += (long long)nseg * p->searches[(size_t)i].nsky * p->searches[(size_t)i].nfdot;
+  }
+  if (nsearch == 0 || ntpl > (1LL << 28)) return FSTAT_OK;
+  const long long ntiles = (ntpl + SCAN_TILE - 1) / SCAN_TILE;
+  size_t o = 0;
+  auto put = [&](size_t bytes) { const size_t at = o; o = align256(o + bytes); return at; };
+  const size_t o_grp = put((size_t)stored * sizeof(CandEntry)), o_rank = put((size_t)stored * 4),
+               o_cnt = put((size_t)ntpl * 4), o_off = put((size_t)(ntpl + 1) * 8), o_sums = put((size_t)ntiles * 8),
+               o_srch = put((size_t)nsearch * sizeof(DrainSearch)), o_flag = put(2 * 4);
+  if (o > p->drain_bytes) {
+    if (p->drain_ws) (void)hipFree(p->drain_ws);
+    p->drain_ws = nullptr;
+    p->drain_bytes = 0;
+    if (hipMalloc(&p->drain_ws, o) != hipSuccess) {
+      (void)launch_status();   // clear the allocation error: the host orders instead
+      p->drain_ws = nullptr;
+      return FSTAT_OK;
+    }
+    p->drain_bytes = o;
+  }
+  char* w = (char*)p->drain_ws;
+  CandEntry* grouped = (CandEntry*)(w + o_grp);
+  unsigned* rank = (unsigned*)(w + o_rank);
+  unsigned* counts = (unsigned*)(w + o_cnt);
+  unsigned long long* off = (unsigned long long*)(w + o_off);
+  unsigned long long* sums = (unsigned long long*)(w + o_sums);
+  DrainSearch* ds = (DrainSearch*)(w + o_srch);
+  unsigned* flags = (unsigned*)(w + o_flag);   // [0] key outside its search, [1] template too long
+  HIP_TRY(p, hipMemcpy(ds, hs.data(), hs.size() * sizeof(DrainSearch), hipMemcpyHostToDevice), "drain tables");
+  const hipStream_t st = nullptr;
+  const unsigned gblk = (unsigned)std::min<long long>((stored + DRAIN_NT - 1) / DRAIN_NT, 1LL << 20);
+  FSTAT_LAUNCH(k_drain_zero, dim3((unsigned)std::min<long long>((ntpl + DRAIN_NT - 1) / DRAIN_NT, 1LL << 20)),
+               dim3(DRAIN_NT), 0, st, counts, ntpl);
+  FSTAT_LAUNCH(k_drain_zero, dim3(1), dim3(DRAIN_NT), 0, st, flags, 2LL);
+  FSTAT_LAUNCH(k_drain_count, dim3(gblk), dim3(DRAIN_NT), 0, st, p->d_cand, stored, ds, nsearch, search0, nseg, counts,
+               rank, flags);
+  HIP_TRY(p, launch_status(), "drain count launch");
+  unsigned hf[2] = {0, 0};
+  HIP_TRY(p, hipMemcpy(hf, flags, sizeof hf, hipMemcpyDeviceToHost), "drain flags");
+  if (hf[0]) return FSTAT_OK;
+  FSTAT_LAUNCH(k_scan_tile_sums, dim3((unsigned)ntiles), dim3(DRAIN_NT), 0, st, counts, ntpl, sums);
+  FSTAT_LAUNCH(k_scan_sums, dim3(1), dim3(DRAIN_NT), 0, st, sums, ntiles);
+  FSTAT_LAUNCH(k_scan_apply, dim3((unsigned)ntiles), dim3(DRAIN_NT), 0, st, counts, ntpl, sums, off);
+  FSTAT_LAUNCH(k_drain_scatter, dim3(gblk), dim3(DRAIN_NT), 0, st, p->d_cand, stored, ds, nsearch, search0, nseg, off,
+               rank, grouped, flags);
+  FSTAT_LAUNCH(k_drain_order, dim3((unsigned)std::min<long long>(ntpl, 1LL << 18)), dim3(DRAIN_NT), 0, st, grouped, off,
+               ntpl, p->d_cand, flags + 1);
+  HIP_TRY(p, launch_status(), "drain ordering launch");
+  HIP_TRY(p, hipMemcpy(hf, flags, sizeof hf, hipMemcpyDeviceToHost), "drain flags");
+  if (hf[0]) return FSTAT_OK;        // not reached: the count pass saw the same keys
+  if (hf[1]) {
+    *src = grouped;                  // every entry, grouped by template: the host orders them
+    return FSTAT_OK;
+  }
+  *done = true;
+  return FSTAT_OK;
+}
+
+// The first `nout` of the `stored` entries in key order, into `ent`.
+static fstat_status drain_in_key_order(fstat_plan_t p, long long stored, long long nout, std::vector<CandEntry>* ent) {
+  ent->clear();
+  if (stored == 0 || nout == 0) return FSTAT_OK;
+  bool done = false;
+  const CandEntry* src = p->d_cand;
+  fstat_status r = order_on_device(p, stored, &done, &src);
+  if (r != FSTAT_OK) return r;
+  if (done) {
+    ent->resize((size_t)nout);
+    HIP_TRY(p, hipMemcpy(ent->data(), p->d_cand, (size_t)nout * sizeof(CandEntry), hipMemcpyDeviceToHost),
+            "candidate copy");
+    return FSTAT_OK;
+  }
+  ent->resize((size_t)stored);
+  HIP_TRY(p, hipMemcpy(ent->data(), src, (size_t)stored * sizeof(CandEntry), hipMemcpyDeviceToHost), "candidate copy");
+  std::sort(ent->begin(), ent->end(), key_less);
+  ent->resize((size_t)nout);
+  return FSTAT_OK;
+}
+
 fstat_status fstat_candidates(fstat_plan_t plan, fstat_candidate* out, fstat_candidate_key* keys, int64_t capacity,
                               int64_t* n_found) {
   if (!plan || !n_found) return fail(plan, FSTAT_E_INVAL, "NULL argument");
@@ -1794,49 +1992,54 @@ fstat_status fstat_candidates(fstat_plan_t plan, fstat_candidate* out, fstat_can
       return fail(plan, FSTAT_E_OVERFLOW, "more candidates than the device buffer holds");
     return FSTAT_OK;
   }
-  std::vector<CandEntry> ent((size_t)stored);
-  if (stored > 0)
-    HIP_TRY(plan, hipMemcpy(ent.data(), plan->d_cand, (size_t)stored * sizeof(CandEntry), hipMemcpyDeviceToHost),
-            "candidate copy");
-  HIP_TRY(plan, hipMemset(plan->d_count, 0, sizeof(unsigned long long)), "count reset");
-  std::sort(ent.begin(), ent.end(), [](const CandEntry& a, const CandEntry& b) {
-    if (a.search != b.search) return a.search < b.search;
-    if (a.segment != b.segment) return a.segment < b.segment;
-    if (a.sky != b.sky) return a.sky < b.sky;
-    if (a.fdot_idx != b.fdot_idx) return a.fdot_idx < b.fdot_idx;
-    return a.bin < b.bin;
-  });
   const long long nout = std::min<long long>(stored, capacity);
-  for (long long i = 0; i < nout; ++i) {
-    const CandEntry& c = ent[(size_t)i];
-    if (keys) {
-      keys[i].search = c.search;
-      keys[i].segment = c.segment;
-      keys[i].sky = c.sky;
-      keys[i].fdot_idx = c.fdot_idx;
-      keys[i].bin = c.bin;
-      float score = std::nanf("");
-      if (plan->scored) std::memcpy(&score, &c.pad, sizeof score);
-      keys[i].vet_score = score;
-    }
-    if (out) {
-      const SegInfo& si = plan->segs[c.segment];
-      const SearchRecord& sr = plan->searches[(size_t)c.search - (plan->search_count - plan->searches.size())];
-      if (sr.lattice) {
-        // the template's frequency shift and spindown, as the kernels formed them
-        const int s = sr.s_lo + c.fdot_idx;
-        const double u = lattice_shift_bins(lattice_w(s, sr.m10, sr.host[2 * sr.nsky + c.sky]),
-                                            (double)si.nfft / (2.0 * M_PI));
-        out[i].f_hz = si.s.f_off + ((double)c.bin + u) / ((double)si.nfft * si.s.dt);
-        out[i].fdot = lattice_w(s, sr.m11, sr.host[3 * sr.nsky + c.sky]) / (M_PI * si.s.dt * si.s.dt);
-      } else {
-        out[i].f_hz = si.s.f_off + (double)c.bin / ((double)si.nfft * si.s.dt);
-        out[i].fdot = sr.host[2 * sr.nsky + c.fdot_idx];
+  std::vector<CandEntry> ent;
+  fstat_status r = drain_in_key_order(plan, stored, nout, &ent);
+  if (r != FSTAT_OK) return r;
+  HIP_TRY(plan, hipMemset(plan->d_count, 0, sizeof(unsigned long long)), "count reset");
+  // records and keys, in threads over slices for large drains
+  auto fill = [&](long long i0, long long i1) {
+    for (long long i = i0; i < i1; ++i) {
+      const CandEntry& c = ent[(size_t)i];
+      if (keys) {
+        keys[i].search = c.search;
+        keys[i].segment = c.segment;
+        keys[i].sky = c.sky;
+        keys[i].fdot_idx = c.fdot_idx;
+        keys[i].bin = c.bin;
+        float score = std::nanf("");
+        if (plan->scored) std::memcpy(&score, &c.pad, sizeof score);
+        keys[i].vet_score = score;
       }
-      out[i].alpha = sr.host[c.sky];
-      out[i].delta = sr.host[sr.nsky + c.sky];
-      out[i].twoF = c.twoF;
+      if (out) {
+        const SegInfo& si = plan->segs[c.segment];
+        const SearchRecord& sr = plan->searches[(size_t)c.search - (plan->search_count - plan->searches.size())];
+        if (sr.lattice) {
+          // the template's frequency shift and spindown, as the kernels formed them
+          const int s = sr.s_lo + c.fdot_idx;
+          const double u = lattice_shift_bins(lattice_w(s, sr.m10, sr.host[2 * sr.nsky + c.sky]),
+                                              (double)si.nfft / (2.0 * M_PI));
+          out[i].f_hz = si.s.f_off + ((double)c.bin + u) / ((double)si.nfft * si.s.dt);
+          out[i].fdot = lattice_w(s, sr.m11, sr.host[3 * sr.nsky + c.sky]) / (M_PI * si.s.dt * si.s.dt);
+        } else {
+          out[i].f_hz = si.s.f_off + (double)c.bin / ((double)si.nfft * si.s.dt);
+          out[i].fdot = sr.host[2 * sr.nsky + c.fdot_idx];
+        }
+        out[i].alpha = sr.host[c.sky];
+        out[i].delta = sr.host[sr.nsky + c.sky];
+        out[i].twoF = c.twoF;
+      }
     }
+  };
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const long long slices = nout >= (1LL << 20) ? (long long)hw : 1;
+  if (slices == 1) {
+    fill(0, nout);
+  } else {
+    std::vector<std::thread> th;
+    for (long long k = 0; k < slices; ++k)
+      th.emplace_back(fill, nout * k / slices, nout * (k + 1) / slices);
+    for (auto& t : th) t.join();
   }
   for (auto& sr : plan->searches) (void)hipHostFree(sr.host);
   plan->searches.clear();
@@ -2036,6 +2239,7 @@ fstat_status fstat_destroy(fstat_plan_t plan) {
   if (plan->d_patches) (void)hipFree(plan->d_patches);
   if (plan->d_spec) (void)hipFree(plan->d_spec);
   if (plan->d_first) (void)hipFree(plan->d_first);
+  if (plan->drain_ws) (void)hipFree(plan->drain_ws);
   for (auto& ge : plan->graphs) {
     if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
     if (ge.graph) (void)hipGraphDestroy(ge.graph);
