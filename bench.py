@@ -136,7 +136,8 @@ def cpu_multicore_leg(args, log):
                       f"per core (numpy FP64, one thread each), {dt:.1f} s wall"}
 
 
-def timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbinning=0, steps=None, warmup=None):
+def timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbinning=0, steps=None, warmup=None,
+                 full_drain=False):
     """Plan (autotuned, from the cache or fixed), warm up, time `steps` searches of the
     whole template list (each followed by its count drain), and read the per-kernel
     HIP-event timings of the timed steps."""
@@ -192,6 +193,23 @@ def timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbin
     for c, name in enumerate(F.KERNEL_NAMES):
         n, ms = plan.profile_read(c, reset=True)
         kernels[name] = {"launches": n, "total_ms": ms, "avg_ms": ms / n if n else None}
+    drain = None
+    if full_drain and counts:
+        # one more search, then a full drain of its crossings timed on its own: key ordering
+        # on the device, copy of the ordered entries, records and keys formed on the host
+        plan.profile_enable(False)
+        plan.search_batch(0, al, de, fd)
+        torch.cuda.synchronize()
+        bufs = F.candidate_buffers(max(counts[-1], 1))
+        d0 = time.perf_counter()
+        _, dkeys, nd = plan.candidates(out=bufs, allow_overflow=True)
+        d1 = time.perf_counter()
+        drain = {"candidates": nd, "ms": (d1 - d0) * 1e3, "entries_per_s": nd / (d1 - d0),
+                 "what": "fstat_candidates after one search of the workload: device key ordering (count, scan, "
+                         "scatter, per-template order), device-to-host copy of the ordered entries, records "
+                         "and keys written by host threads"}
+        del bufs, dkeys
+        log(f"{label}: full drain of {nd} candidates {(d1 - d0) * 1e3:.0f} ms")
     B = info["templates_per_launch"]
     N = seg.n
     cand_per_template = n_cand / max(templates * steps, 1)
@@ -217,7 +235,7 @@ def timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbin
     plan.destroy()
     return {"value": value, "unit": "templates/s", "ms_per_step": ms_step, "n_cand": n_cand, "steps": steps,
             "candidates_per_step": n_cand / steps, "info": info, "kernels": kernels, "roofline": roofline,
-            "tuning": tuned, "template_fft": tlen, "candidate_capacity": cap}
+            "tuning": tuned, "template_fft": tlen, "candidate_capacity": cap, "full_drain": drain}
 
 
 def lattice_leg(args, F, torch, seg, nfft, info, log):
@@ -394,8 +412,8 @@ def plain_leg(args, F, torch, np, dev, log):
              "workload": f"plain FP64-phase path, one template per launch, N=86164, {len(w2.alpha)} sky x "
                          f"{len(w2.fdot)} spindown", "candidates": n2,
              "drain": {"candidates": n2, "ms": (d1 - d0) * 1e3, "ordered_by_key": ordered,
-                       "what": "fstat_candidates after the search: wait, device-to-host copy, key ordering on the host, "
-                               "records and keys written"}}
+                       "what": "fstat_candidates after the search: wait, device key ordering, device-to-host copy of "
+                               "the ordered entries, records and keys written"}}
     log(f"plain: {plain['value']:.4g} templates/s; full drain of {n2} candidates {(d1 - d0) * 1e3:.1f} ms")
     if not args.no_cpu:
         # F error of the plain path against the FP64 oracle: 1 sky x 16 spindowns, all bins
@@ -547,6 +565,8 @@ def main():
     ap.add_argument("--side-steps", type=int, default=5,
                     help="timed steps of the interbinning and lattice entries (at most --steps)")
     ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--no-full-drain", action="store_true",
+                    help="skip the timed full drain (ordered copy of every crossing) of one batched search")
     ap.add_argument("--ragged-nsky", type=int, default=1024)
     ap.add_argument("--ragged-nfdot", type=int, default=128)
     ap.add_argument("--ragged-steps", type=int, default=2)
@@ -591,7 +611,8 @@ def main():
     nfft = synth.nfft_for(seg.n)
     al, de, fd = dev(w.alpha), dev(w.delta), dev(w.fdot)
     templates = args.nsky * args.nfdot
-    main_leg = timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbinning=0)
+    main_leg = timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbinning=0,
+                            full_drain=not args.no_full_drain)
     value, ms_step, n_cand = main_leg["value"], main_leg["ms_per_step"], main_leg["n_cand"]
     info, kernels, roofline, tuned = main_leg["info"], main_leg["kernels"], main_leg["roofline"], main_leg["tuning"]
     B, N = info["templates_per_launch"], seg.n
@@ -638,7 +659,7 @@ def main():
                    "tuning": tuned},
         "roofline": roofline, "cpu_baseline": cpu, "plain": plain,
         "f_rel_err_vs_fp64": f_err, "candidates_per_step": n_cand / args.steps, "kernels": kernels,
-        "candidate_capacity": main_leg["candidate_capacity"],
+        "candidate_capacity": main_leg["candidate_capacity"], "full_drain": main_leg["full_drain"],
         "vetting": vetting,
         "interbinning": ib_summary(ib, templates, nfft),
         "lattice": lat_leg,

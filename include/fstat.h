@@ -206,7 +206,8 @@ fstat_status fstat_twoF_spectrum_static(fstat_plan_t plan, int32_t segment, cons
  *   za, zb n complex: amplitude- and phase-demodulated series
  *   ua, ub nfft complex: 2x upsampled series
  *   zta, ztb n complex: resampled series on the barycentric grid
- * Asynchronous on `stream`. */
+ * Synchronous: waits for `stream`, runs the sky stage on it and returns once the
+ * outputs are written.  Uses the plan's workspace (allocating it on first use). */
 fstat_status fstat_sky_stages(fstat_plan_t plan, int32_t segment, double alpha, double delta,
                               double* abc, void* za, void* zb, void* ua, void* ub,
                               void* zta, void* ztb, void* stream);

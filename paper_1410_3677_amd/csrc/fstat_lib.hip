@@ -139,6 +139,7 @@ struct fstat_plan_s {
   CandEntry* d_cand = nullptr;
   unsigned long long* d_count = nullptr;
   int* d_search_next = nullptr;   // device copy of the search index (advanced by the search itself)
+  double* d_sky_pos = nullptr;    // (alpha, delta) of fstat_sky_stages
   int search_count = 0;
   // graph replay: a plan-owned stream joined to the caller's stream by events
   hipStream_t gstream = nullptr;
@@ -1519,6 +1520,7 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_opt
       (e = hipMalloc((void**)&p->d_count, sizeof(unsigned long long))) != hipSuccess ||
       (e = hipMemset(p->d_count, 0, sizeof(unsigned long long))) != hipSuccess ||
       (e = hipMalloc((void**)&p->d_search_next, sizeof(int))) != hipSuccess ||
+      (e = hipMalloc((void**)&p->d_sky_pos, 2 * sizeof(double))) != hipSuccess ||
       (e = hipMemset(p->d_search_next, 0, sizeof(int))) != hipSuccess) {
     std::string msg = std::string("plan device allocation: ") + hipGetErrorString(e);
     fstat_destroy(p);
@@ -1846,21 +1848,15 @@ fstat_status fstat_sky_stages(fstat_plan_t plan, int32_t segment, double alpha, 
   fstat_status r = ensure_workspace(plan);
   if (r != FSTAT_OK) return r;
   hipStream_t st = (hipStream_t)stream;
-  // the sky position goes through a small device array, as for a search
-  double* ad = nullptr;
-  HIP_TRY(plan, hipMalloc(&ad, 2 * sizeof(double)), "sky position");
+  // the sky position goes through the plan's small device array, as a search's lists do
+  double* ad = plan->d_sky_pos;
   double h[2] = {alpha, delta};
-  hipError_t e = hipMemcpyAsync(ad, h, sizeof h, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) {
-    (void)hipFree(ad);
-    return hip_fail(plan, e, "sky position copy");
-  }
+  HIP_TRY(plan, hipStreamSynchronize(st), "sky position copy");
+  HIP_TRY(plan, hipMemcpy(ad, h, sizeof h, hipMemcpyHostToDevice), "sky position copy");
   const SegInfo& si = plan->segs[segment];
   r = plan->fp64 ? sky_stages_impl<double>(plan, si, ad, abc, za, zb, ua, ub, zta, ztb, st)
                  : sky_stages_impl<float>(plan, si, ad, abc, za, zb, ua, ub, zta, ztb, st);
   (void)hipStreamSynchronize(st);
-  (void)hipFree(ad);
   plan->last_stream = st;
   plan->used_stream = true;
   return r;
@@ -2236,6 +2232,7 @@ fstat_status fstat_destroy(fstat_plan_t plan) {
   if (plan->d_cand) (void)hipFree(plan->d_cand);
   if (plan->d_count) (void)hipFree(plan->d_count);
   if (plan->d_search_next) (void)hipFree(plan->d_search_next);
+  if (plan->d_sky_pos) (void)hipFree(plan->d_sky_pos);
   if (plan->d_patches) (void)hipFree(plan->d_patches);
   if (plan->d_spec) (void)hipFree(plan->d_spec);
   if (plan->d_first) (void)hipFree(plan->d_first);

@@ -1,13 +1,14 @@
 """GPU parity at the workloads' full sizes, in the launch configurations the benchmark times.
 
 * full:    256 sky x 64 spindown at N = 86164, one template per launch (the plain path),
-           threshold 2F > 20: every crossing drained; sampled templates checked bin by bin
-           against the FP64 oracle, and the injection's loudest template among them.
+           threshold 2F > 20: every crossing drained and every template's crossings
+           (keys and 2F) checked against the FP64 oracle's spectrum of that template.
 * batched: 4096 sky x 256 spindown (1 048 576 templates), autotuned batch sizes and
            kernel variants, HIP graph: the threshold is raised to 2F > 40 so that the
            drained set stays small (the launch configuration is that of the benchmark;
-           only the threshold differs); sampled templates, including the loudest
-           template of every injection, are checked against the oracle.
+           only the threshold differs); the loudest template of every injection and a
+           seeded 1% sample of the templates (41 whole sky positions) are checked
+           against the oracle template by template.
 * batched with interbinning: the same, against the oracle's interbinned transform.
 Tolerances are those of the other parity tests (1e-4 relative, floor 4; key sets equal
 outside a 1e-4 x threshold guard band).
@@ -52,9 +53,11 @@ def _check_templates(seg, w, recs, keys, picks, thr, interbinning=False):
     return worst
 
 
-def test_full_workload_plain_path_sampled_parity(torch):
+def test_full_workload_plain_path_every_template(torch):
+    from tests.gpu_util import per_sky_oracle
     w = synth.workload("full")
     seg = w.segments[0]
+    nfft = synth.nfft_for(seg.n)
     note(f"full workload, plain path: {len(w.alpha)} x {len(w.fdot)} templates, one per launch")
     plan = make_plan([seg], templates_per_launch=1, skies_per_batch=1, use_graph=0, candidate_capacity=1 << 22)
     plan.search_batch(0, dev(w.alpha), dev(w.delta), dev(w.fdot))
@@ -63,11 +66,21 @@ def test_full_workload_plain_path_sampled_parity(torch):
     assert np.all(recs["twoF"] > w.threshold)
     key3 = np.stack([keys["sky"], keys["fdot_idx"], keys["bin"]], 1)
     assert len(np.unique(key3, axis=0)) == n
-    rng = np.random.default_rng(71)
-    picks = [(int(rng.integers(len(w.alpha))), int(rng.integers(len(w.fdot)))) for _ in range(3)]
-    top = int(np.argmax(recs["twoF"]))
-    picks.append((int(keys["sky"][top]), int(keys["fdot_idx"][top])))
-    _check_templates(seg, w, recs, keys, picks, w.threshold)
+
+    # every template's crossings against the oracle's spectrum, sky by sky
+    starts = np.searchsorted(keys["sky"], np.arange(len(w.alpha) + 1))
+
+    def check(i, ref):
+        a, b = starts[i], starts[i + 1]
+        k3 = np.stack([np.zeros(b - a, np.int64), keys["fdot_idx"][a:b], keys["bin"][a:b]], 1)
+        return compare_candidates(k3, recs["twoF"][a:b], ref[None], w.threshold, 1e-4)
+    res = per_sky_oracle(seg, w.alpha, w.delta, w.fdot, nfft, check)
+    flips = sum(r[2] for r in res)
+    err = max(r[4] for r in res)
+    note(f"all {len(w.alpha) * len(w.fdot)} templates: gpu {sum(r[0] for r in res)} oracle "
+         f"{sum(r[1] for r in res)} flips {flips} max rel err {err:.2e}")
+    for ng, no, fl, mism, e in res:
+        assert not mism and e < 1e-4
 
 
 @pytest.mark.parametrize("ib", [0, 1])
@@ -97,8 +110,26 @@ def test_batched_workload_full_size_sampled_parity(torch, ib):
         if near.any():
             j = int(np.flatnonzero(near)[np.argmax(recs["twoF"][near])])
             picks.append((int(keys["sky"][j]), int(keys["fdot_idx"][j])))
-    rng = np.random.default_rng(72)
-    picks += [(int(rng.integers(len(w.alpha))), int(rng.integers(len(w.fdot)))) for _ in range(2)]
     assert len(picks) >= 3
     _check_templates(seg, w, recs, keys, picks, thr, interbinning=bool(ib))
     plan.destroy()
+    if ib:
+        return
+    # a seeded 1% sample of the templates: 41 whole sky positions x 256 spindowns, every
+    # template's crossings against the oracle
+    from tests.gpu_util import per_sky_oracle
+    rng = np.random.default_rng(72)
+    skies = np.sort(rng.choice(len(w.alpha), size=41, replace=False))
+    starts = np.searchsorted(keys["sky"], np.arange(len(w.alpha) + 1))
+    nfft = synth.nfft_for(seg.n)
+
+    def check(j, ref):
+        i = int(skies[j])
+        a, b = starts[i], starts[i + 1]
+        k3 = np.stack([np.zeros(b - a, np.int64), keys["fdot_idx"][a:b], keys["bin"][a:b]], 1)
+        return compare_candidates(k3, recs["twoF"][a:b], ref[None], thr, 1e-4)
+    res = per_sky_oracle(seg, w.alpha[skies], w.delta[skies], w.fdot, nfft, check)
+    note(f"1% sample ({len(skies)} skies x {len(w.fdot)} spindowns): gpu {sum(r[0] for r in res)} oracle "
+         f"{sum(r[1] for r in res)} flips {sum(r[2] for r in res)} max rel err {max(r[4] for r in res):.2e}")
+    for ng, no, fl, mism, e in res:
+        assert not mism and e < 1e-4
