@@ -97,6 +97,7 @@ struct Tables {
 
 struct fstat_vet_s {
   int max_batch = 0;
+  int n_cu = 256;                // compute units of the device
   int steps = 0;                 // Adam steps taken
   void* mem = nullptr;           // one allocation for everything below
   float *theta = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
@@ -1004,13 +1005,6 @@ void colsum(hipStream_t st, const float* m, long rows, int cols, float* out, flo
   FSTAT_LAUNCH(vet::k_vet_colsum_final, dim3((cols + 255) / 256), dim3(256), 0, st, scratch, chunks, cols, out);
 }
 
-__global__ void k_vet_store_scores(CandEntry* cand, const float* logit, long n) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float s = 1.f / (1.f + expf(-logit[i]));
-  cand[i].pad = __float_as_int(s);
-}
-
 void vet_prepare(fstat_vet_t v, hipStream_t st) {
   FSTAT_LAUNCH(vet::k_vet_prepare, blocks_for((long)vet::H * vet::X), dim3(256), 0, st, v->theta, v->wf2,
                      v->wt2, v->wf3, v->wt3, v->w4b, v->w5b);
@@ -1025,32 +1019,31 @@ constexpr int INFER_SPLITS = 4;
 // 8192 -> 128 product reads x from HBM); `read` is recorded once x has been read.
 void vet_conv_stage(fstat_vet_t v, const float* patches, int n, uint16_t* x, hipStream_t st) {
   using namespace vet;
-  FSTAT_LAUNCH(k_vet_conv_infer, dim3((n + CV_NP - 1) / CV_NP), dim3(CV_NT), 0, st, patches, n, v->theta, v->wq2,
+  FSTAT_LAUNCH(k_vet_conv_infer, dim3((unsigned)((n + CV_NP - 1) / CV_NP)), dim3(CV_NT), 0, st, patches, n, v->theta,
+               v->wq2,
                      v->wq3, x);
 }
 
-void vet_dense_stage(fstat_vet_t v, const uint16_t* x, int n, float* out, hipEvent_t read, hipStream_t st) {
+void vet_dense_stage(fstat_vet_t v, const uint16_t* x, int n, float* out, hipEvent_t read, hipStream_t st,
+                     CandEntry* cand) {
   using namespace vet;
   const int nbp = (n + GT - 1) / GT * GT;
   FSTAT_LAUNCH(k_gemm_nt_lds, dim3(H / GT, nbp / GT, INFER_SPLITS), dim3(256), 0, st, nbp, H, X, x, v->w4b,
-                     v->scratch, X / INFER_SPLITS);
+               v->scratch, X / INFER_SPLITS);
   if (read) (void)hipEventRecord(read, st);
   const long count = (long)nbp * H;
-  FSTAT_LAUNCH(k_vet_sum_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->scratch, INFER_SPLITS, count,
-                     n, H, v->theta + O_B4, v->a4b);
-  gemm(st, n, H, H, v->a4b, H, 1, v->w5b, 1, H, v->z5, H);
-  FSTAT_LAUNCH(k_vet_bias_relu, blocks_for((long)n * H), dim3(256), 0, st, v->z5, (long)n, H, v->theta + O_B5,
-                     (uint16_t*)nullptr, v->a5);
-  FSTAT_LAUNCH(k_vet_fc3, blocks_for(n), dim3(256), 0, st, v->a5, n, v->theta, out);
+  // the split-K sum, the two small layers and the score in one launch
+  FSTAT_LAUNCH(k_vet_head_infer, dim3((unsigned)((n + HD_NP - 1) / HD_NP)), dim3(256), 0, st, v->scratch, INFER_SPLITS,
+               count, n, v->theta, v->w5b, out, cand);
 }
 
 // All n patches in batches of max_batch, pipelined: batch k's convolutions go to the
 // vetter's stream into buffer k % 2 (after batch k - 2's product has read it), its dense
 // layers to `st` after them; `tail(i, b, logits)` enqueues work on `st` that uses a
 // batch's logits (written to out_of(i) by the dense stage).
-template <typename OutOf, typename Tail>
+template <typename OutOf>
 static fstat_status vet_score_all(fstat_vet_t v, const float* patches, long long n, hipStream_t st, OutOf out_of,
-                                  Tail tail) {
+                                  CandEntry* cand) {
   if (!v->cstream) {
     VET_TRY(v, hipStreamCreateWithFlags(&v->cstream, hipStreamNonBlocking), "vetter stream");
     VET_TRY(v, hipEventCreateWithFlags(&v->ev_fork, hipEventDisableTiming), "vetter event");
@@ -1072,9 +1065,8 @@ static fstat_status vet_score_all(fstat_vet_t v, const float* patches, long long
     VET_TRY(v, hipEventRecord(v->ev_conv[buf], v->cstream), "vetter order");
     VET_TRY(v, hipStreamWaitEvent(st, v->ev_conv[buf], 0), "vetter join");
     float* out = out_of(i);
-    vet_dense_stage(v, x, b, out, v->ev_read[buf], st);
+    vet_dense_stage(v, x, b, out, v->ev_read[buf], st, cand ? cand + i : nullptr);
     VET_TRY(v, launch_status(), "scoring launch");
-    tail(i, b, out);
   }
   return FSTAT_OK;
 }
@@ -1165,6 +1157,12 @@ fstat_status fstat_vet_create(int32_t max_batch, fstat_vet_t* out) {
   auto v = new (std::nothrow) fstat_vet_s();
   if (!v) return vet_fail(nullptr, FSTAT_E_NOMEM, "vetter allocation");
   v->max_batch = max_batch;
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+      v->n_cu = ncu;
+  }
   const size_t nb = (size_t)max_batch, NL = nb * L;
   const size_t nbp = (nb + vet::GT - 1) / vet::GT * vet::GT;  // rows of the 8192 -> 128 product
   struct Part { void** p; size_t bytes; };
@@ -1226,7 +1224,7 @@ fstat_status fstat_vet_get_params(fstat_vet_t v, float* params, int64_t n) {
 fstat_status fstat_vet_forward(fstat_vet_t v, const float* patches, int64_t n, float* logits, void* stream) {
   if (!v || n < 0 || (n > 0 && (!patches || !logits))) return vet_fail(v, FSTAT_E_INVAL, "bad arguments");
   hipStream_t st = (hipStream_t)stream;
-  return vet_score_all(v, patches, n, st, [&](long long i) { return logits + i; }, [](long long, int, float*) {});
+  return vet_score_all(v, patches, n, st, [&](long long i) { return logits + i; }, (CandEntry*)nullptr);
 }
 
 fstat_status fstat_vet_gradient(fstat_vet_t v, const float* patches, const float* labels, int64_t n, float* loss,
@@ -1313,11 +1311,7 @@ fstat_status fstat_plan_vet_candidates(fstat_plan_t plan, void* stream) {
   const long long n = std::min<long long>({(long long)count, plan->opt.candidate_capacity, plan->patch_capacity});
   // batches of the vetter's size: logits into its own buffer, scores into the entries
   fstat_vet_t v = plan->vet;
-  const fstat_status rs = vet_score_all(
-      v, plan->d_patches, n, st, [&](long long) { return v->logit; },
-      [&](long long i, int b, float* logits) {
-        FSTAT_LAUNCH(k_vet_store_scores, blocks_for(b), dim3(256), 0, st, plan->d_cand + i, logits, (long)b);
-      });
+  const fstat_status rs = vet_score_all(v, plan->d_patches, n, st, [&](long long) { return v->logit; }, plan->d_cand);
   if (rs != FSTAT_OK) return fail(plan, rs, v->last_error);
   HIP_TRY(plan, launch_status(), "scoring launch");
   HIP_TRY(plan, hipStreamSynchronize(st), "scoring");

@@ -144,9 +144,13 @@ __global__ void __launch_bounds__(256) k_vet_colsum_part(const float* __restrict
 }
 
 // u = log(1 + 2F) - log 5 per patch bin (n * L threads)
+// Network input u = log(1 + 2F) - log 5, with the hardware logarithm (absolute error
+// about 1e-7, far below the BF16 rounding of the layers that follow).
+__device__ __forceinline__ float vet_u(float v) { return __logf(1.f + v) - 1.6094379124341003f; }
+
 __global__ void k_vet_input(const float* __restrict__ patches, long count, float* __restrict__ u) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < count) u[idx] = log1pf(patches[idx]) - 1.6094379124341003f;
+  if (idx < count) u[idx] = vet_u(patches[idx]);
 }
 
 // conv1 (one input channel): z1[n][p][c] = b1[c] + sum_t w1[c][t] u[n][p+t-3]; a1 = relu(z1)
@@ -400,15 +404,11 @@ __global__ void k_vet_prepare_frag(const float* __restrict__ theta, uint16_t* __
 // Bias, ReLU and BF16 rounding of a product tile D[co][p] (lane l: channels
 // 16 nb + 4 (l / 16) + i, i < 4, of position p0 + l % 16) into the LDS rows, four channels
 // (8 bytes) per store.
-__device__ __forceinline__ void store_tile(uint16_t* act, int pp, int p0, int nb, v4f d, const float* __restrict__ bias,
-                                           int lane) {
+__device__ __forceinline__ void store_tile(uint16_t* act, int pp, int p0, int nb, v4f d, int lane) {
   const int co0 = 16 * nb + 4 * (lane >> 4);
   uint32_t h[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const float v = d[i] + bias[co0 + i];
-    h[i] = f2bf(v > 0.f ? v : 0.f);
-  }
+  for (int i = 0; i < 4; ++i) h[i] = f2bf(d[i] > 0.f ? d[i] : 0.f);
   uint16_t* row = act + (pp * CV_R + p0 + (lane & 15) + 3) * CV_LD + co0;
   *reinterpret_cast<uint2*>(row) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
 }
@@ -422,9 +422,16 @@ __device__ __forceinline__ void store_tile(uint16_t* act, int pp, int p0, int nb
 __device__ __forceinline__ void conv_layer_lds(uint16_t* act, const uint16_t* __restrict__ wq,
                                                const float* __restrict__ bias, int w, int lane) {
   const uint16_t* in = act;
+  // the accumulators start at the bias of the lane's four output channels
   v4f acc[CV_MB][2];
+  const int cb = 4 * (lane >> 4);
+  const v4f bias0{bias[cb], bias[cb + 1], bias[cb + 2], bias[cb + 3]};
+  const v4f bias1{bias[16 + cb], bias[16 + cb + 1], bias[16 + cb + 2], bias[16 + cb + 3]};
 #pragma unroll
-  for (int m = 0; m < CV_MB; ++m) acc[m][0] = acc[m][1] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int m = 0; m < CV_MB; ++m) {
+    acc[m][0] = bias0;
+    acc[m][1] = bias1;
+  }
   const v8s* wqv = reinterpret_cast<const v8s*>(wq);   // fragments in LDS
   const int ci0 = 8 * (lane >> 4);
   for (int t = 0; t < KS; ++t) {
@@ -442,8 +449,8 @@ __device__ __forceinline__ void conv_layer_lds(uint16_t* act, const uint16_t* __
 #pragma unroll
   for (int m = 0; m < CV_MB; ++m) {
     const int mb = CV_MB * w + m, pp = mb >> 4, p0 = (mb & 15) * 16;
-    store_tile(act, pp, p0, 0, acc[m][0], bias, lane);
-    store_tile(act, pp, p0, 1, acc[m][1], bias, lane);
+    store_tile(act, pp, p0, 0, acc[m][0], lane);
+    store_tile(act, pp, p0, 1, acc[m][1], lane);
   }
 }
 
@@ -464,7 +471,7 @@ __global__ void __launch_bounds__(CV_NT) k_vet_conv_infer(const float* __restric
   for (int i = tid; i < CV_NP * CV_R; i += CV_NT) {
     const int pp = i / CV_R, r = i % CV_R, q = r - 3;
     float v = 0.f;
-    if (s0 + pp < n && q >= 0 && q < L) v = log1pf(patches[(long)(s0 + pp) * L + q]) - 1.6094379124341003f;
+    if (s0 + pp < n && q >= 0 && q < L) v = vet_u(patches[(long)(s0 + pp) * L + q]);
     su[pp][r] = v;
   }
   for (int i = tid; i < CV_NP * 6 * CV_LD; i += CV_NT) {
@@ -474,27 +481,33 @@ __global__ void __launch_bounds__(CV_NT) k_vet_conv_infer(const float* __restric
   }
   __syncthreads();
   {
-    // conv1: thread (channel c, group grp) slides along 64 positions with its channel's
-    // weights in registers and a seven-sample window, one LDS read per output
-    constexpr int PER = CV_NP * L * C / CV_NT;  // positions per thread (32)
+    // conv1: thread (channel pair c2, group grp) slides along PER positions with both
+    // channels' weights in registers and a seven-sample window, one LDS read per position
+    // and one 4-byte store of the two BF16 outputs
+    constexpr int PER = CV_NP * L * (C / 2) / CV_NT;  // positions per thread (16)
     static_assert(L % PER == 0, "conv1 work split");
-    const int c = tid & (C - 1), grp = tid >> 5;
+    const int c2 = tid & (C / 2 - 1), grp = tid / (C / 2);
     const int pp = grp / (L / PER), p0 = (grp % (L / PER)) * PER;
-    float wt[KW];
+    float wa[KW], wb[KW];
 #pragma unroll
-    for (int t = 0; t < KW; ++t) wt[t] = theta[O_W1 + c * KW + t];
-    const float bc = theta[O_B1 + c];
-    float win[KW];
+    for (int t = 0; t < KW; ++t) {
+      wa[t] = theta[O_W1 + (2 * c2) * KW + t];
+      wb[t] = theta[O_W1 + (2 * c2 + 1) * KW + t];
+    }
+    const float ba = theta[O_B1 + 2 * c2], bb = theta[O_B1 + 2 * c2 + 1];
+    float win[PER + KW - 1];
 #pragma unroll
-    for (int t = 0; t < KW - 1; ++t) win[t] = su[pp][p0 + t];
-    for (int p = p0; p < p0 + PER; ++p) {
-      win[KW - 1] = su[pp][p + KW - 1];
-      float z = bc;
+    for (int t = 0; t < PER + KW - 1; ++t) win[t] = su[pp][p0 + t];
 #pragma unroll
-      for (int t = 0; t < KW; ++t) z += wt[t] * win[t];
-      sa[(pp * CV_R + p + 3) * CV_LD + c] = f2bf(z > 0.f ? z : 0.f);
+    for (int k = 0; k < PER; ++k) {
+      float za = ba, zb = bb;
 #pragma unroll
-      for (int t = 0; t < KW - 1; ++t) win[t] = win[t + 1];
+      for (int t = 0; t < KW; ++t) {
+        za += wa[t] * win[k + t];
+        zb += wb[t] * win[k + t];
+      }
+      const uint32_t h = f2bf(za > 0.f ? za : 0.f) | ((uint32_t)f2bf(zb > 0.f ? zb : 0.f) << 16);
+      *reinterpret_cast<uint32_t*>(sa + (pp * CV_R + p0 + k + 3) * CV_LD + 2 * c2) = h;
     }
   }
   __syncthreads();
@@ -582,15 +595,73 @@ __global__ void __launch_bounds__(256) k_gemm_nt_lds(int M, int N, int K, const 
         Cz[(long)(m0 + wm + 16 * a + kq + i) * N + n0 + wn + 16 * b + r16] = acc[a][b][i];
 }
 
-// out_b[m][n] = bf16(relu(bias[n] + sum over splits z (in order) of part[z][m][n])), rows < rows
-__global__ void k_vet_sum_bias_relu(const float* __restrict__ part, int splits, long count, int rows, int N,
-                                    const float* __restrict__ bias, uint16_t* __restrict__ outb) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)rows * N) return;
-  float acc = 0.f;
-  for (int z = 0; z < splits; ++z) acc += part[(long)z * count + idx];
-  const float v = acc + bias[idx % N];
-  outb[idx] = f2bf(v > 0.f ? v : 0.f);
+// The dense layers after the 8192 -> 128 product, for HD_NP patches per workgroup: the
+// split-K partial sums added in split order, bias, ReLU and BF16 rounding (a4), the
+// 128 -> 128 layer on the matrix cores (BF16 a4 and w5, FP32 accumulation), bias and ReLU
+// (a5), and the 128 -> 1 head (logit).  With `cand`, the score sigmoid(logit) of patch i is
+// also stored in entry i (the patch store is indexed by candidate slot).  One launch
+// instead of five.  Wavefront w forms the output columns 32 w .. 32 w + 31 of both
+// sixteen-patch row blocks: lane l's A operand is eight consecutive a4 of one patch (an
+// LDS row, padded to HD_LD so that the sixteen rows fall on distinct banks), its B operand
+// eight consecutive weights of one output's w5 row (16 bytes from global memory).
+constexpr int HD_NP = 32, HD_LD = H + 8;
+__global__ void __launch_bounds__(256) k_vet_head_infer(const float* __restrict__ part, int splits, long count, int n,
+                                                        const float* __restrict__ theta,
+                                                        const uint16_t* __restrict__ w5b, float* __restrict__ logit,
+                                                        CandEntry* __restrict__ cand) {
+  __shared__ __align__(16) uint16_t sa4[HD_NP * HD_LD];   // a4 of the workgroup's patches (BF16)
+  __shared__ float sp[HD_NP][H + 1];                       // w6[o] a5[p][o]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r0 = blockIdx.x * HD_NP;
+  const float* b4 = theta + O_B4;
+  for (int i = tid; i < HD_NP * H; i += 256) {
+    const int pp = i / H, k = i % H, row = r0 + pp;
+    uint16_t v = 0;
+    if (row < n) {
+      float acc = 0.f;
+      for (int z = 0; z < splits; ++z) acc += part[(long)z * count + (long)row * H + k];
+      const float a = acc + b4[k];
+      v = f2bf(a > 0.f ? a : 0.f);
+    }
+    sa4[pp * HD_LD + k] = v;
+  }
+  __syncthreads();
+  v4f acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) acc[a][0] = acc[a][1] = v4f{0.f, 0.f, 0.f, 0.f};
+  const int r16 = lane & 15, k8 = 8 * (lane >> 4);
+#pragma unroll
+  for (int k0 = 0; k0 < H; k0 += 32) {
+    v8s fa[2], fb[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      fa[t] = *reinterpret_cast<const v8s*>(sa4 + (16 * t + r16) * HD_LD + k0 + k8);
+      fb[t] = *reinterpret_cast<const v8s*>(w5b + (long)(32 * w + 16 * t + r16) * H + k0 + k8);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = mfma32(fa[a], fb[b], acc[a][b]);
+  }
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int o = 32 * w + 16 * b + r16;
+    const float b5 = theta[O_B5 + o], w6 = theta[O_W6 + o];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float z = acc[a][b][i] + b5;
+        sp[16 * a + 4 * (lane >> 4) + i][o] = w6 * (z > 0.f ? z : 0.f);
+      }
+  }
+  __syncthreads();
+  if (tid < HD_NP && r0 + tid < n) {
+    float v = theta[O_B6];
+    for (int j = 0; j < H; ++j) v += sp[tid][j];
+    logit[r0 + tid] = v;
+    if (cand) cand[r0 + tid].pad = __float_as_int(1.f / (1.f + expf(-v)));
+  }
 }
 
 }  // namespace vet
