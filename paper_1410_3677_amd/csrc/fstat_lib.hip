@@ -97,7 +97,6 @@ struct Tables {
 
 struct fstat_vet_s {
   int max_batch = 0;
-  int n_cu = 256;                // compute units of the device
   int steps = 0;                 // Adam steps taken
   void* mem = nullptr;           // one allocation for everything below
   float *theta = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
@@ -1157,12 +1156,6 @@ fstat_status fstat_vet_create(int32_t max_batch, fstat_vet_t* out) {
   auto v = new (std::nothrow) fstat_vet_s();
   if (!v) return vet_fail(nullptr, FSTAT_E_NOMEM, "vetter allocation");
   v->max_batch = max_batch;
-  {
-    int dev = 0, ncu = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
-      v->n_cu = ncu;
-  }
   const size_t nb = (size_t)max_batch, NL = nb * L;
   const size_t nbp = (nb + vet::GT - 1) / vet::GT * vet::GT;  // rows of the 8192 -> 128 product
   struct Part { void** p; size_t bytes; };
