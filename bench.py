@@ -342,9 +342,21 @@ def vetting_leg(args, F, torch, np, dev, log):
     w2 = synth.workload("full")
     seg2 = w2.segments[0]
     cap = 1 << 21
+    # the same search without the network attached: the cost of the capture (the F kernel
+    # stores its launch's 2F rows, a gather copies each crossing's window)
+    a2, d2, f2 = dev(w2.alpha), dev(w2.delta), dev(w2.fdot)
+    p0 = F.Plan([F.segment_to_device(seg2)], candidate_capacity=cap, use_graph=0)
+    p0.search_batch(0, a2[:2], d2[:2], f2)
+    p0.candidate_count(allow_overflow=True)
+    torch.cuda.synchronize()
+    n0 = time.perf_counter()
+    p0.search_batch(0, a2, d2, f2)
+    torch.cuda.synchronize()
+    n1 = time.perf_counter()
+    p0.candidate_count(allow_overflow=True)
+    p0.destroy()
     p = F.Plan([F.segment_to_device(seg2)], candidate_capacity=cap, use_graph=0)
     p.attach_vetter(v, cap)
-    a2, d2, f2 = dev(w2.alpha), dev(w2.delta), dev(w2.fdot)
     p.search_batch(0, a2[:2], d2[:2], f2)
     p.vet_candidates()
     p.candidate_count(allow_overflow=True)
@@ -375,7 +387,8 @@ def vetting_leg(args, F, torch, np, dev, log):
             "train_s": t_train, "data_s": t_gen, "threshold_false_dismissal": st["threshold_false_dismissal"],
             "heldout_noise_kept_by_network": far, "heldout_added_false_dismissal": fdr_added,
             "heldout_noise_kept_by_threshold": 1.0,
-            "plain_search_with_capture_ms": (s1 - s0) * 1e3, "scoring_ms": (s2 - s1) * 1e3,
+            "plain_search_with_capture_ms": (s1 - s0) * 1e3, "plain_search_without_capture_ms": (n1 - n0) * 1e3,
+            "scoring_ms": (s2 - s1) * 1e3,
             "plain_crossings": int(n), "plain_crossings_kept_by_network": kept,
             "plain_crossings_near_injection": int(near.sum()),
             "plain_crossings_near_injection_kept": int(np.sum(near & (keys["vet_score"] >= 1.0 / (1.0 + np.exp(-cut))))),

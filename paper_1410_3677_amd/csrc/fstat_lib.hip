@@ -741,9 +741,13 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
     }
     HIP_TRY(p, err, "template pass B launch");
     if (capture) {
+      // the streaming second pass stores its rows transposed (k_tmpl_b_stream)
+      const bool transposed = !p->fp64 && si.ibw == 0.0 && p->variant_b == 1 && si.tP >= 64 && si.tP <= 512;
+      const bool half = (oa.k_min == 0 && oa.k_max == si.nfft / 2);
+      const int tq = transposed ? si.tQ : 0, trow = transposed ? (half ? si.tP / 2 : si.tP) : 0;
       FSTAT_LAUNCH(k_capture_patches, dim3(2048), dim3(256), 0, st, p->d_cand, p->d_spec, p->d_patches,
-                         (unsigned long long)p->patch_capacity, p->d_count, p->d_first, oa.k_min, oa.k_max, t0,
-                         nfdot, sky0);
+                   (unsigned long long)p->patch_capacity, p->d_count, p->d_first, oa.k_min, oa.k_max, t0, nfdot, sky0,
+                   tq, trow);
       HIP_TRY(p, launch_status(), "patch capture launch");
     }
   }
@@ -1283,8 +1287,10 @@ fstat_status fstat_plan_attach_vetter(fstat_plan_t plan, fstat_vet_t vet, int64_
   if (!vet) return FSTAT_OK;
   if (patch_capacity < 1 || patch_capacity > plan->opt.candidate_capacity)
     return fail(plan, FSTAT_E_INVAL, "patch_capacity outside [1, candidate_capacity]");
+  // a launch's 2F rows: bins [k_min, k_max) per template, or the streaming second pass's
+  // transposed rows (all tP outputs of each of the tQ rows)
   long nbins = 0;
-  for (auto& si : plan->segs) nbins = std::max(nbins, (long)(si.kmax - si.kmin));
+  for (auto& si : plan->segs) nbins = std::max({nbins, (long)(si.kmax - si.kmin), (long)si.tP * si.tQ});
   HIP_TRY(plan, hipMalloc((void**)&plan->d_patches, (size_t)patch_capacity * 256 * sizeof(float)), "patch store");
   HIP_TRY(plan, hipMalloc((void**)&plan->d_spec, (size_t)plan->B * nbins * sizeof(float)), "launch spectrum buffer");
   HIP_TRY(plan, hipMalloc((void**)&plan->d_first, sizeof(unsigned long long)), "count copy");

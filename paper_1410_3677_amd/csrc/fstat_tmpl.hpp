@@ -1020,18 +1020,23 @@ __global__ void __launch_bounds__(256) k_tmpl_b_stream(TmplArgs ta, int ntmpl, c
             out[k - oa.k_min] = two_f_value(fa[b][r], fb[b][r], cfa, cfb, cfab);
         }
     } else {
-      float* srow = (float*)oa.spectrum + (long)item * (long)(oa.k_max - oa.k_min);
+      // MODE 2 (patch capture) stores the launch's 2F rows transposed, [template][k2][k1]
+      // with rows of RLEN (the outputs a row forms), so that a wavefront's store is
+      // contiguous; the capture kernel reads bin k at row k % Q, column k / Q
+      constexpr int RLEN = HALF ? P / 2 : P;
+      float* srow = (float*)oa.spectrum + (long)item * ta.Q * RLEN + (long)k2 * RLEN;
       uint32_t mask = 0;
       T val[NOUT];
 #pragma unroll
       for (int b = 0; b < PBL; ++b)
 #pragma unroll
         for (int r = 0; r < ROUT; ++r) {
-          const int k = ta.Q * (g + G * b + NSL * r) + k2;
+          const int k1 = g + G * b + NSL * r;
+          const int k = ta.Q * k1 + k2;
           const T v = two_f_value(fa[b][r], fb[b][r], cfa, cfb, cfab);
           val[b * ROUT + r] = v;
           const bool inr = HALF || (k >= oa.k_min && k < oa.k_max);
-          if (MODE == 2 && inr) srow[k - oa.k_min] = (float)v;
+          if (MODE == 2) srow[k1] = (float)v;
           if (inr && v > thr) mask |= 1u << (b * ROUT + r);
         }
       stg.add<false>(oa, ta, search, lane, mask, val, item,
@@ -1305,16 +1310,19 @@ __global__ void __launch_bounds__(256) k_capture_patches(const CandEntry* __rest
                                                          unsigned long long patch_capacity,
                                                          const unsigned long long* __restrict__ count,
                                                          const unsigned long long* __restrict__ first, int k_min,
-                                                         int k_max, int t0, int nfdot, int sky0) {
+                                                         int k_max, int t0, int nfdot, int sky0, int tq, int trow) {
   unsigned long long end = count[0];
   if (end > patch_capacity) end = patch_capacity;
-  const long nb = k_max - k_min;
+  // rows of bins [k_min, k_max) per template, or (tq > 0) the transposed rows of the
+  // streaming second pass: tq rows of trow values, bin k at row k % tq, column k / tq
+  const long tlen = tq > 0 ? (long)tq * trow : (long)(k_max - k_min);
   for (unsigned long long slot = first[0] + blockIdx.x; slot < end; slot += gridDim.x) {
     const CandEntry ce = cand[slot];
     const long t_local = (long)(ce.sky - sky0) * nfdot + ce.fdot_idx - t0;
     const int k = ce.bin - 128 + (int)threadIdx.x;
     float v = 0.f;
-    if (k >= k_min && k < k_max) v = spec[t_local * nb + (k - k_min)];
+    if (k >= k_min && k < k_max)
+      v = spec[t_local * tlen + (tq > 0 ? (long)(k % tq) * trow + k / tq : (long)(k - k_min))];
     patches[slot * 256 + threadIdx.x] = v;
   }
 }
