@@ -200,14 +200,14 @@ def timed_search(args, F, torch, seg, al, de, fd, templates, nfft, log, interbin
         plan.profile_enable(False)
         plan.search_batch(0, al, de, fd)
         torch.cuda.synchronize()
-        bufs = F.candidate_buffers(max(counts[-1], 1))
+        bufs = F.candidate_buffers(max(counts[-1], 1), pinned=True)
         d0 = time.perf_counter()
         _, dkeys, nd = plan.candidates(out=bufs, allow_overflow=True)
         d1 = time.perf_counter()
         drain = {"candidates": nd, "ms": (d1 - d0) * 1e3, "entries_per_s": nd / (d1 - d0),
                  "what": "fstat_candidates after one search of the workload: device key ordering (count, scan, "
-                         "scatter, per-template order), device-to-host copy of the ordered entries, records "
-                         "and keys written by host threads"}
+                         "scatter, per-template order), records and keys formed on the device and copied into "
+                         "page-locked host arrays"}
         del bufs, dkeys
         log(f"{label}: full drain of {nd} candidates {(d1 - d0) * 1e3:.0f} ms")
     B = info["templates_per_launch"]
@@ -414,7 +414,7 @@ def plain_leg(args, F, torch, np, dev, log):
     p2.search_batch(0, a2, d2, f2)
     torch.cuda.synchronize()
     s1 = time.perf_counter()
-    bufs = F.candidate_buffers(cap)
+    bufs = F.candidate_buffers(cap, pinned=True)
     d0 = time.perf_counter()
     recs, keys, n2 = p2.candidates(out=bufs)
     d1 = time.perf_counter()
@@ -425,8 +425,8 @@ def plain_leg(args, F, torch, np, dev, log):
              "workload": f"plain FP64-phase path, one template per launch, N=86164, {len(w2.alpha)} sky x "
                          f"{len(w2.fdot)} spindown", "candidates": n2,
              "drain": {"candidates": n2, "ms": (d1 - d0) * 1e3, "ordered_by_key": ordered,
-                       "what": "fstat_candidates after the search: wait, device key ordering, device-to-host copy of "
-                               "the ordered entries, records and keys written"}}
+                       "what": "fstat_candidates after the search: wait, device key ordering, records and keys "
+                               "formed on the device and copied into page-locked host arrays"}}
     log(f"plain: {plain['value']:.4g} templates/s; full drain of {n2} candidates {(d1 - d0) * 1e3:.1f} ms")
     if not args.no_cpu:
         # F error of the plain path against the FP64 oracle: 1 sky x 16 spindowns, all bins

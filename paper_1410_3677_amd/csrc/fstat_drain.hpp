@@ -169,4 +169,56 @@ __global__ void __launch_bounds__(DRAIN_NT) k_drain_order(const CandEntry* __res
   }
 }
 
+// 5. the records and keys of the ordered entries, formed as the host would form them (the
+// paper's five numbers from the search's lists, the integer key, the vetting score), for a
+// copy straight into the caller's arrays
+struct DrainList {
+  const double* v;   // device copy: alpha[nsky], delta[nsky], then fdot[nfdot] (explicit
+                     // list) or w_freq[nsky], w_spin[nsky] (lattice grid)
+  int nsky, lattice, s_lo;
+  double m10, m11;
+};
+struct DrainSeg {
+  double f_off, dt;
+  int nfft;
+};
+
+__global__ void k_drain_records(const CandEntry* __restrict__ ent, long long n, const DrainList* __restrict__ lists,
+                                int search0, const DrainSeg* __restrict__ segs, int scored,
+                                fstat_candidate* __restrict__ out, fstat_candidate_key* __restrict__ keys) {
+#pragma clang fp contract(off)
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const CandEntry c = ent[i];
+    if (keys) {
+      fstat_candidate_key k;
+      k.search = c.search;
+      k.segment = c.segment;
+      k.sky = c.sky;
+      k.fdot_idx = c.fdot_idx;
+      k.bin = c.bin;
+      k.vet_score = scored ? __int_as_float(c.pad) : __builtin_nanf("");
+      keys[i] = k;
+    }
+    if (out) {
+      const DrainList& L = lists[c.search - search0];
+      const DrainSeg sg = segs[c.segment];
+      fstat_candidate r;
+      if (L.lattice) {
+        // the template's frequency shift and spindown, as the search kernels formed them
+        const int s = L.s_lo + c.fdot_idx;
+        const double u = lattice_shift_bins(lattice_w(s, L.m10, L.v[2 * L.nsky + c.sky]), (double)sg.nfft / (2.0 * M_PI));
+        r.f_hz = sg.f_off + ((double)c.bin + u) / ((double)sg.nfft * sg.dt);
+        r.fdot = lattice_w(s, L.m11, L.v[3 * L.nsky + c.sky]) / (M_PI * sg.dt * sg.dt);
+      } else {
+        r.f_hz = sg.f_off + (double)c.bin / ((double)sg.nfft * sg.dt);
+        r.fdot = L.v[2 * L.nsky + c.fdot_idx];
+      }
+      r.alpha = L.v[c.sky];
+      r.delta = L.v[L.nsky + c.sky];
+      r.twoF = c.twoF;
+      out[i] = r;
+    }
+  }
+}
+
 }  // namespace fstat

@@ -160,6 +160,8 @@ struct fstat_plan_s {
   // device memory of the key-ordering drain (grown on demand, kept until destroy)
   void* drain_ws = nullptr;
   size_t drain_bytes = 0;
+  void* drain_out = nullptr;     // records, keys and lists formed on the device
+  size_t drain_out_bytes = 0;
   hipStream_t last_stream = nullptr;
   bool used_stream = false;
   // profiling
@@ -1939,15 +1941,90 @@ static fstat_status order_on_device(fstat_plan_t p, long long stored, bool* done
   return FSTAT_OK;
 }
 
-// The first `nout` of the `stored` entries in key order, into `ent`.
-static fstat_status drain_in_key_order(fstat_plan_t p, long long stored, long long nout, std::vector<CandEntry>* ent) {
+// Records and keys of the first `nout` entries of d_cand (in key order) formed on the device
+// and copied straight into the caller's arrays (either may be NULL); *done is false, with
+// nothing written, when the device memory for them is not available.
+static fstat_status form_on_device(fstat_plan_t p, long long nout, fstat_candidate* out, fstat_candidate_key* keys,
+                                   bool* done) {
+  *done = false;
+  const int nsearch = (int)p->searches.size();
+  const int search0 = p->search_count - nsearch;
+  std::vector<size_t> nd((size_t)nsearch);
+  size_t ndouble = 0;
+  for (int i = 0; i < nsearch; ++i) {
+    const SearchRecord& sr = p->searches[(size_t)i];
+    nd[(size_t)i] = sr.lattice ? 4 * (size_t)sr.nsky : 2 * (size_t)sr.nsky + sr.nfdot;
+    ndouble += nd[(size_t)i];
+  }
+  size_t o = 0;
+  auto put = [&](size_t bytes) { const size_t at = o; o = align256(o + bytes); return at; };
+  const size_t o_rec = put(out ? (size_t)nout * sizeof(fstat_candidate) : 0),
+               o_key = put(keys ? (size_t)nout * sizeof(fstat_candidate_key) : 0), o_val = put(ndouble * 8),
+               o_list = put((size_t)nsearch * sizeof(DrainList)), o_seg = put(p->segs.size() * sizeof(DrainSeg));
+  if (o > p->drain_out_bytes) {
+    if (p->drain_out) (void)hipFree(p->drain_out);
+    p->drain_out = nullptr;
+    p->drain_out_bytes = 0;
+    if (hipMalloc(&p->drain_out, o) != hipSuccess) {
+      (void)launch_status();   // clear the allocation error: the host forms the records instead
+      p->drain_out = nullptr;
+      return FSTAT_OK;
+    }
+    p->drain_out_bytes = o;
+  }
+  char* w = (char*)p->drain_out;
+  double* vals = (double*)(w + o_val);
+  std::vector<DrainList> hl((size_t)nsearch);
+  size_t at = 0;
+  for (int i = 0; i < nsearch; ++i) {
+    const SearchRecord& sr = p->searches[(size_t)i];
+    HIP_TRY(p, hipMemcpy(vals + at, sr.host, nd[(size_t)i] * 8, hipMemcpyHostToDevice), "drain lists");
+    DrainList& L = hl[(size_t)i];
+    L.v = vals + at;
+    L.nsky = sr.nsky;
+    L.lattice = sr.lattice ? 1 : 0;
+    L.s_lo = sr.s_lo;
+    L.m10 = sr.m10;
+    L.m11 = sr.m11;
+    at += nd[(size_t)i];
+  }
+  std::vector<DrainSeg> hg(p->segs.size());
+  for (size_t i = 0; i < p->segs.size(); ++i) {
+    hg[i].f_off = p->segs[i].s.f_off;
+    hg[i].dt = p->segs[i].s.dt;
+    hg[i].nfft = p->segs[i].nfft;
+  }
+  DrainList* dl = (DrainList*)(w + o_list);
+  DrainSeg* dg = (DrainSeg*)(w + o_seg);
+  HIP_TRY(p, hipMemcpy(dl, hl.data(), hl.size() * sizeof(DrainList), hipMemcpyHostToDevice), "drain lists");
+  HIP_TRY(p, hipMemcpy(dg, hg.data(), hg.size() * sizeof(DrainSeg), hipMemcpyHostToDevice), "drain segments");
+  fstat_candidate* drec = out ? (fstat_candidate*)(w + o_rec) : nullptr;
+  fstat_candidate_key* dkey = keys ? (fstat_candidate_key*)(w + o_key) : nullptr;
+  const unsigned blk = (unsigned)std::min<long long>((nout + DRAIN_NT - 1) / DRAIN_NT, 1LL << 20);
+  FSTAT_LAUNCH(k_drain_records, dim3(blk), dim3(DRAIN_NT), 0, (hipStream_t)nullptr, p->d_cand, nout, dl, search0, dg,
+               p->scored ? 1 : 0, drec, dkey);
+  HIP_TRY(p, launch_status(), "drain records launch");
+  if (out) HIP_TRY(p, hipMemcpy(out, drec, (size_t)nout * sizeof(fstat_candidate), hipMemcpyDeviceToHost), "record copy");
+  if (keys)
+    HIP_TRY(p, hipMemcpy(keys, dkey, (size_t)nout * sizeof(fstat_candidate_key), hipMemcpyDeviceToHost), "key copy");
+  *done = true;
+  return FSTAT_OK;
+}
+
+// The first `nout` of the `stored` entries in key order: written to out / keys by the device
+// (*formed), or into `ent` for the host to form them.
+static fstat_status drain_in_key_order(fstat_plan_t p, long long stored, long long nout, fstat_candidate* out,
+                                       fstat_candidate_key* keys, std::vector<CandEntry>* ent, bool* formed) {
   ent->clear();
+  *formed = false;
   if (stored == 0 || nout == 0) return FSTAT_OK;
   bool done = false;
   const CandEntry* src = p->d_cand;
   fstat_status r = order_on_device(p, stored, &done, &src);
   if (r != FSTAT_OK) return r;
   if (done) {
+    r = form_on_device(p, nout, out, keys, formed);
+    if (r != FSTAT_OK || *formed) return r;
     ent->resize((size_t)nout);
     HIP_TRY(p, hipMemcpy(ent->data(), p->d_cand, (size_t)nout * sizeof(CandEntry), hipMemcpyDeviceToHost),
             "candidate copy");
@@ -1983,7 +2060,8 @@ fstat_status fstat_candidates(fstat_plan_t plan, fstat_candidate* out, fstat_can
   }
   const long long nout = std::min<long long>(stored, capacity);
   std::vector<CandEntry> ent;
-  fstat_status r = drain_in_key_order(plan, stored, nout, &ent);
+  bool formed = false;
+  fstat_status r = drain_in_key_order(plan, stored, nout, out, keys, &ent, &formed);
   if (r != FSTAT_OK) return r;
   HIP_TRY(plan, hipMemset(plan->d_count, 0, sizeof(unsigned long long)), "count reset");
   // records and keys, in threads over slices for large drains
@@ -2022,8 +2100,10 @@ fstat_status fstat_candidates(fstat_plan_t plan, fstat_candidate* out, fstat_can
   };
   const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   const long long slices = nout >= (1LL << 20) ? (long long)hw : 1;
-  if (slices == 1) {
-    fill(0, nout);
+  if (formed) {
+    // written by the device
+  } else if (slices == 1) {
+    fill(0, (long long)ent.size());
   } else {
     std::vector<std::thread> th;
     for (long long k = 0; k < slices; ++k)
@@ -2230,6 +2310,7 @@ fstat_status fstat_destroy(fstat_plan_t plan) {
   if (plan->d_spec) (void)hipFree(plan->d_spec);
   if (plan->d_first) (void)hipFree(plan->d_first);
   if (plan->drain_ws) (void)hipFree(plan->drain_ws);
+  if (plan->drain_out) (void)hipFree(plan->drain_out);
   for (auto& ge : plan->graphs) {
     if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
     if (ge.graph) (void)hipGraphDestroy(ge.graph);

@@ -308,9 +308,31 @@ class Plan:
             pass
 
 
-def candidate_buffers(capacity: int):
-    """Host arrays (records, keys) of `capacity` entries for Plan.candidates(out=...)."""
-    return np.empty(capacity, dtype=CANDIDATE_NP), np.empty(capacity, dtype=KEY_NP)
+def candidate_buffers(capacity: int, pinned: bool = False):
+    """Host arrays (records, keys) of `capacity` entries for Plan.candidates(out=...).
+    pinned=True places them in page-locked memory (allocated by PyTorch), which the
+    drain's device-to-host copies reach directly; the arrays keep that memory alive."""
+    if not pinned:
+        return np.empty(capacity, dtype=CANDIDATE_NP), np.empty(capacity, dtype=KEY_NP)
+    import torch
+    out = []
+    for dt in (CANDIDATE_NP, KEY_NP):
+        t = torch.empty(max(capacity, 1) * dt.itemsize, dtype=torch.uint8, pin_memory=True)
+        a = t.numpy().view(dt)[:capacity]
+        out.append(_Pinned(a, t))
+    return tuple(out)
+
+
+class _Pinned(np.ndarray):
+    """A numpy view of page-locked memory that holds the tensor owning it."""
+
+    def __new__(cls, arr, owner):
+        obj = arr.view(cls)
+        obj._owner = owner
+        return obj
+
+    def __array_finalize__(self, obj):
+        self._owner = getattr(obj, "_owner", None)
 
 
 def lattice_sky_range(lat: fstat_lattice):
