@@ -164,7 +164,12 @@ fstat_status fstat_search_batch(fstat_plan_t plan, int32_t segment,
  * written.  With out and keys both NULL the call only reports the count and
  * drains the buffer (FSTAT_E_OVERFLOW only if the device buffer overflowed).
  * When the device buffer overflowed, which crossings were kept is
- * unspecified. */
+ * unspecified.  The ordering and the records are formed on the device in memory the
+ * plan allocates at its first full drain and keeps until fstat_destroy (about 36 bytes
+ * per stored crossing and 12 per template of the drained searches, plus 64 per
+ * crossing copied out); if that allocation fails, or a template holds more than 4096
+ * crossings, the host orders and forms them instead (same result, slower).  Copies
+ * into page-locked host arrays are the fastest. */
 fstat_status fstat_candidates(fstat_plan_t plan, fstat_candidate* out, fstat_candidate_key* keys,
                               int64_t capacity, int64_t* n_found);
 
