@@ -119,6 +119,8 @@ def test_null_handles_are_rejected_not_crashing():
     n = ctypes.c_int64()
     assert lib.fstat_candidates(None, None, None, 0, ctypes.byref(n)) == F.E_INVAL
     assert lib.fstat_search_batch(None, 0, FAKE_PTR, FAKE_PTR, 1, FAKE_PTR, 1, None) == F.E_INVAL
+    assert lib.fstat_twoF_spectrum(None, 0, FAKE_PTR, FAKE_PTR, 1, FAKE_PTR, 1, FAKE_PTR, None) == F.E_INVAL
+    assert lib.fstat_twoF_spectrum_static(None, 0, FAKE_PTR, FAKE_PTR, 1, FAKE_PTR, 1, FAKE_PTR, None) == F.E_INVAL
     assert lib.fstat_profile_enable(None, 1) == F.E_INVAL
     assert lib.fstat_destroy(None) == F.OK
     sz = ctypes.c_size_t()
