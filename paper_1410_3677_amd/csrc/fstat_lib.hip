@@ -1019,6 +1019,7 @@ void vet_prepare(fstat_vet_t v, hipStream_t st) {
 // inference of n <= max_batch patches (logits to `out`): fused LDS convolutions, the
 // 8192 -> 128 layer as an LDS-tiled product split four ways along K, then the small layers
 constexpr int INFER_SPLITS = 4;
+static_assert((long)INFER_SPLITS * 8192 * vet::H <= VET_SCRATCH, "split-K partials of a full batch fit the scratch");
 // Scoring of n <= max_batch patches in two parts: the three convolutions into x (one
 // fused kernel, bound by the matrix cores and LDS), then the dense layers from x (the
 // 8192 -> 128 product reads x from HBM); `read` is recorded once x has been read.
@@ -1038,8 +1039,8 @@ void vet_dense_stage(fstat_vet_t v, const uint16_t* x, int n, float* out, hipEve
   if (read) (void)hipEventRecord(read, st);
   const long count = (long)nbp * H;
   // the split-K sum, the two small layers and the score in one launch
-  FSTAT_LAUNCH(k_vet_head_infer, dim3((unsigned)((n + HD_NP - 1) / HD_NP)), dim3(256), 0, st, v->scratch, INFER_SPLITS,
-               count, n, v->theta, v->w5b, out, cand);
+  FSTAT_LAUNCH(k_vet_head_infer<INFER_SPLITS>, dim3((unsigned)((n + HD_NP - 1) / HD_NP)), dim3(256), 0, st,
+               v->scratch, count, n, v->theta, v->w5b, out, cand);
 }
 
 // All n patches in batches of max_batch, pipelined: batch k's convolutions go to the

@@ -605,7 +605,8 @@ __global__ void __launch_bounds__(256) k_gemm_nt_lds(int M, int N, int K, const 
 // LDS row, padded to HD_LD so that the sixteen rows fall on distinct banks), its B operand
 // eight consecutive weights of one output's w5 row (16 bytes from global memory).
 constexpr int HD_NP = 32, HD_LD = H + 8;
-__global__ void __launch_bounds__(256) k_vet_head_infer(const float* __restrict__ part, int splits, long count, int n,
+template <int SPLITS>
+__global__ void __launch_bounds__(256) k_vet_head_infer(const float* __restrict__ part, long count, int n,
                                                         const float* __restrict__ theta,
                                                         const uint16_t* __restrict__ w5b, float* __restrict__ logit,
                                                         CandEntry* __restrict__ cand) {
@@ -614,16 +615,16 @@ __global__ void __launch_bounds__(256) k_vet_head_infer(const float* __restrict_
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int r0 = blockIdx.x * HD_NP;
   const float* b4 = theta + O_B4;
-  for (int i = tid; i < HD_NP * H; i += 256) {
-    const int pp = i / H, k = i % H, row = r0 + pp;
-    uint16_t v = 0;
-    if (row < n) {
-      float acc = 0.f;
-      for (int z = 0; z < splits; ++z) acc += part[(long)z * count + (long)row * H + k];
-      const float a = acc + b4[k];
-      v = f2bf(a > 0.f ? a : 0.f);
-    }
-    sa4[pp * HD_LD + k] = v;
+  // the partial sums of rows r0 .. r0 + HD_NP - 1 (all within the product's padded rows),
+  // every load of a thread issued before the sums
+#pragma unroll
+  for (int q = 0; q < HD_NP * H / 256; ++q) {
+    const int i = tid + 256 * q, pp = i / H, k = i % H, row = r0 + pp;
+    float acc = 0.f;
+#pragma unroll
+    for (int z = 0; z < SPLITS; ++z) acc += part[(long)z * count + (long)row * H + k];
+    const float a = acc + b4[k];
+    sa4[pp * HD_LD + k] = row < n ? f2bf(a > 0.f ? a : 0.f) : (uint16_t)0;
   }
   __syncthreads();
   v4f acc[2][2];
