@@ -167,9 +167,9 @@ fstat_status fstat_search_batch(fstat_plan_t plan, int32_t segment,
  * unspecified.  The ordering and the records are formed on the device in memory the
  * plan allocates at its first full drain and keeps until fstat_destroy (about 36 bytes
  * per stored crossing and 12 per template of the drained searches, plus 64 per
- * crossing copied out); if that allocation fails, or a template holds more than 4096
- * crossings, the host orders and forms them instead (same result, slower).  Copies
- * into page-locked host arrays are the fastest. */
+ * crossing copied out); FSTAT_E_NOMEM if it cannot, with the candidates kept for a
+ * later call (a count-only drain needs none).  Copies into page-locked host arrays are
+ * the fastest. */
 fstat_status fstat_candidates(fstat_plan_t plan, fstat_candidate* out, fstat_candidate_key* keys,
                               int64_t capacity, int64_t* n_found);
 

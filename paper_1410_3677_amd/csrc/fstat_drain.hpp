@@ -6,7 +6,8 @@
 //   2. exclusive scan of the counts: each template's offset in the output;
 //   3. write every entry to its template's range (template order);
 //   4. order each template's range by bin (bins within a template are distinct, so an
-//      entry's place is the number of entries of its template with a smaller bin).
+//      entry's place is the number of entries of its template with a smaller bin);
+//   5. form the records and keys for the copy out.
 // Templates are numbered search by search (searches since the previous drain), then
 // segment, sky, spindown: t = base[search] + (segment * nsky + sky) * nfdot + fdot_idx.
 #pragma once
@@ -26,7 +27,7 @@ struct DrainSearch {
 
 constexpr int DRAIN_NT = 256;
 constexpr int SCAN_TILE = 4096;                 // counts per workgroup of the scan (16 per thread)
-constexpr int DRAIN_SEG_MAX = 4096;             // largest template range ordered on the device
+constexpr int DRAIN_SEG_MAX = 4096;             // longest template range ordered by counting (longer: bitmap)
 
 __device__ __forceinline__ long long drain_template(const CandEntry& c, const DrainSearch* __restrict__ s,
                                                     int nsearch, int search0, int nseg, unsigned* bad) {
@@ -143,19 +144,17 @@ __global__ void k_drain_scatter(const CandEntry* __restrict__ cand, long long n,
   }
 }
 
-// 4. each template's range ordered by bin (one workgroup per template, grid-stride over
-// templates); ranges longer than DRAIN_SEG_MAX are flagged for the host instead
+// 4. each template's range ordered by bin, one workgroup per template (grid-stride over
+// templates).  Ranges of at most DRAIN_SEG_MAX entries: an entry's place is the number of
+// entries of its template with a smaller bin (the bins in LDS); longer ranges are left to
+// k_drain_order_long.
 __global__ void __launch_bounds__(DRAIN_NT) k_drain_order(const CandEntry* __restrict__ grouped,
                                                           const unsigned long long* __restrict__ off, long long ntpl,
-                                                          CandEntry* __restrict__ out, unsigned* too_long) {
+                                                          CandEntry* __restrict__ out) {
   __shared__ int sbin[DRAIN_SEG_MAX];
   for (long long t = blockIdx.x; t < ntpl; t += gridDim.x) {
     const unsigned long long a = off[t], c = off[t + 1] - a;
-    if (c == 0) continue;
-    if (c > (unsigned long long)DRAIN_SEG_MAX) {
-      if (threadIdx.x == 0) atomicOr(too_long, 1u);
-      continue;
-    }
+    if (c == 0 || c > (unsigned long long)DRAIN_SEG_MAX) continue;
     const int m = (int)c;
     __syncthreads();
     for (int j = threadIdx.x; j < m; j += DRAIN_NT) sbin[j] = grouped[a + j].bin;
@@ -165,6 +164,90 @@ __global__ void __launch_bounds__(DRAIN_NT) k_drain_order(const CandEntry* __res
       int r = 0;
       for (int k = 0; k < m; ++k) r += (sbin[k] < b) | ((sbin[k] == b) & (k < j));
       out[a + r] = grouped[a + j];
+    }
+  }
+}
+
+// 4b. ranges longer than DRAIN_SEG_MAX (thresholds low enough that a good share of a
+// template's bins cross): a bitmap of the template's bins in LDS (up to 2^20 bins, the
+// longest transform), popcounts of 32-word blocks scanned across the workgroup, and each
+// entry's place = the set bits below its bin.  Bins of one template are distinct: a
+// repeated one, or a range wider than the bitmap, sets *bad.
+constexpr int DRAIN_LONG_NT = 1024;
+constexpr int DRAIN_BITMAP_WORDS = (1 << 20) / 32;
+__global__ void __launch_bounds__(DRAIN_LONG_NT) k_drain_order_long(const CandEntry* __restrict__ grouped,
+                                                                    const unsigned long long* __restrict__ off,
+                                                                    long long ntpl, CandEntry* __restrict__ out,
+                                                                    unsigned* bad) {
+  __shared__ unsigned bits[DRAIN_BITMAP_WORDS];
+  __shared__ unsigned bpre[DRAIN_BITMAP_WORDS / 32];
+  __shared__ int rmin[DRAIN_LONG_NT / 64], rmax[DRAIN_LONG_NT / 64];
+  __shared__ unsigned wsum[DRAIN_LONG_NT / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (long long t = blockIdx.x; t < ntpl; t += gridDim.x) {
+    const unsigned long long a = off[t], c = off[t + 1] - a;
+    if (c <= (unsigned long long)DRAIN_SEG_MAX) continue;
+    // the template's bin range
+    int lo = 0x7fffffff, hi = -0x7fffffff - 1;
+    for (unsigned long long j = tid; j < c; j += DRAIN_LONG_NT) {
+      const int b = grouped[a + j].bin;
+      lo = min(lo, b);
+      hi = max(hi, b);
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+      lo = min(lo, __shfl_xor(lo, d, 64));
+      hi = max(hi, __shfl_xor(hi, d, 64));
+    }
+    __syncthreads();   // the previous template's readers of the shared arrays are done
+    if (lane == 0) {
+      rmin[wv] = lo;
+      rmax[wv] = hi;
+    }
+    __syncthreads();
+    lo = rmin[0];
+    hi = rmax[0];
+    for (int k = 1; k < DRAIN_LONG_NT / 64; ++k) {
+      lo = min(lo, rmin[k]);
+      hi = max(hi, rmax[k]);
+    }
+    if ((long long)hi - lo >= (long long)DRAIN_BITMAP_WORDS * 32) {
+      if (tid == 0) atomicOr(bad, 1u);
+      continue;
+    }
+    const int nw = ((hi - lo) >> 5) + 1, nb = (nw + 31) >> 5;
+    for (int w = tid; w < nw; w += DRAIN_LONG_NT) bits[w] = 0u;
+    __syncthreads();
+    for (unsigned long long j = tid; j < c; j += DRAIN_LONG_NT) {
+      const int d = grouped[a + j].bin - lo;
+      const unsigned m = 1u << (d & 31);
+      if (atomicOr(&bits[d >> 5], m) & m) atomicOr(bad, 1u);
+    }
+    __syncthreads();
+    // exclusive scan of the 32-word blocks' popcounts (one block per thread, nb <= 1024)
+    unsigned v = 0;
+    if (tid < nb)
+      for (int k = 0; k < 32; ++k) {
+        const int w = tid * 32 + k;
+        if (w < nw) v += __popc(bits[w]);
+      }
+    unsigned inc = v;
+    for (int d = 1; d < 64; d <<= 1) {
+      const unsigned u = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += u;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    unsigned before = 0;
+    for (int k = 0; k < wv; ++k) before += wsum[k];
+    if (tid < nb) bpre[tid] = before + inc - v;
+    __syncthreads();
+    for (unsigned long long j = tid; j < c; j += DRAIN_LONG_NT) {
+      const CandEntry e = grouped[a + j];
+      const int d = e.bin - lo, w = d >> 5;
+      unsigned r = bpre[w >> 5];
+      for (int u = w & ~31; u < w; ++u) r += __popc(bits[u]);
+      r += __popc(bits[w] & ((1u << (d & 31)) - 1u));
+      out[a + r] = e;
     }
   }
 }

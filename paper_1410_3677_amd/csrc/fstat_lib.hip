@@ -8,7 +8,6 @@
 #include <cstring>
 #include <mutex>
 #include <string>
-#include <thread>
 #include <type_traits>
 #include <unordered_map>
 #include <utility>
@@ -1858,26 +1857,13 @@ fstat_status fstat_sky_stages(fstat_plan_t plan, int32_t segment, double alpha, 
   return r;
 }
 
-static bool key_less(const CandEntry& a, const CandEntry& b) {
-  if (a.search != b.search) return a.search < b.search;
-  if (a.segment != b.segment) return a.segment < b.segment;
-  if (a.sky != b.sky) return a.sky < b.sky;
-  if (a.fdot_idx != b.fdot_idx) return a.fdot_idx < b.fdot_idx;
-  return a.bin < b.bin;
-}
-
 // Key order on the device (fstat_drain.hpp: count -> offsets -> write, then each
-// template's range by bin), leaving d_cand[0, stored) ordered.  Returns false, with the
-// entries left where they were, when the host must order them instead: more templates
-// than the counting tables take, an entry whose key lies outside its search, or the
-// device memory not available; `*from_grouped` is set when d_cand was given up for the
-// grouped copy (a template with more crossings than one workgroup orders).
-static fstat_status order_on_device(fstat_plan_t p, long long stored, bool* done, const CandEntry** src) {
-  *done = false;
-  *src = p->d_cand;
+// template's range by bin), leaving d_cand[0, stored) ordered.
+static fstat_status order_on_device(fstat_plan_t p, long long stored) {
   const int nsearch = (int)p->searches.size();
   const int search0 = p->search_count - nsearch;
   const int nseg = (int)p->segs.size();
+  if (nsearch == 0) return fail(p, FSTAT_E_STATE, "candidates without a search to drain");
   std::vector<DrainSearch> hs((size_t)nsearch);
   long long ntpl = 0;
   for (int i = 0; i < nsearch; ++i) {
@@ -1886,7 +1872,8 @@ static fstat_status order_on_device(fstat_plan_t p, long long stored, bool* done
     hs[(size_t)i].nfdot = p->searches[(size_t)i].nfdot;
     ntpl += (long long)nseg * p->searches[(size_t)i].nsky * p->searches[(size_t)i].nfdot;
   }
-  if (nsearch == 0 || ntpl > (1LL << 28)) return FSTAT_OK;
+  if (ntpl > (1LL << 31))
+    return fail(p, FSTAT_E_STATE, "more than 2^31 templates searched since the last drain: drain more often");
   const long long ntiles = (ntpl + SCAN_TILE - 1) / SCAN_TILE;
   size_t o = 0;
   auto put = [&](size_t bytes) { const size_t at = o; o = align256(o + bytes); return at; };
@@ -1897,11 +1884,7 @@ static fstat_status order_on_device(fstat_plan_t p, long long stored, bool* done
     if (p->drain_ws) (void)hipFree(p->drain_ws);
     p->drain_ws = nullptr;
     p->drain_bytes = 0;
-    if (hipMalloc(&p->drain_ws, o) != hipSuccess) {
-      (void)launch_status();   // clear the allocation error: the host orders instead
-      p->drain_ws = nullptr;
-      return FSTAT_OK;
-    }
+    HIP_TRY(p, hipMalloc(&p->drain_ws, o), "drain ordering memory");
     p->drain_bytes = o;
   }
   char* w = (char*)p->drain_ws;
@@ -1911,7 +1894,7 @@ static fstat_status order_on_device(fstat_plan_t p, long long stored, bool* done
   unsigned long long* off = (unsigned long long*)(w + o_off);
   unsigned long long* sums = (unsigned long long*)(w + o_sums);
   DrainSearch* ds = (DrainSearch*)(w + o_srch);
-  unsigned* flags = (unsigned*)(w + o_flag);   // [0] key outside its search, [1] template too long
+  unsigned* flags = (unsigned*)(w + o_flag);   // [0] key outside its search, [1] repeated bin of a template
   HIP_TRY(p, hipMemcpy(ds, hs.data(), hs.size() * sizeof(DrainSearch), hipMemcpyHostToDevice), "drain tables");
   const hipStream_t st = nullptr;
   const unsigned gblk = (unsigned)std::min<long long>((stored + DRAIN_NT - 1) / DRAIN_NT, 1LL << 20);
@@ -1923,31 +1906,25 @@ static fstat_status order_on_device(fstat_plan_t p, long long stored, bool* done
   HIP_TRY(p, launch_status(), "drain count launch");
   unsigned hf[2] = {0, 0};
   HIP_TRY(p, hipMemcpy(hf, flags, sizeof hf, hipMemcpyDeviceToHost), "drain flags");
-  if (hf[0]) return FSTAT_OK;
+  if (hf[0]) return fail(p, FSTAT_E_STATE, "a stored candidate's key lies outside its search");
   FSTAT_LAUNCH(k_scan_tile_sums, dim3((unsigned)ntiles), dim3(DRAIN_NT), 0, st, counts, ntpl, sums);
   FSTAT_LAUNCH(k_scan_sums, dim3(1), dim3(DRAIN_NT), 0, st, sums, ntiles);
   FSTAT_LAUNCH(k_scan_apply, dim3((unsigned)ntiles), dim3(DRAIN_NT), 0, st, counts, ntpl, sums, off);
   FSTAT_LAUNCH(k_drain_scatter, dim3(gblk), dim3(DRAIN_NT), 0, st, p->d_cand, stored, ds, nsearch, search0, nseg, off,
                rank, grouped, flags);
   FSTAT_LAUNCH(k_drain_order, dim3((unsigned)std::min<long long>(ntpl, 1LL << 18)), dim3(DRAIN_NT), 0, st, grouped, off,
-               ntpl, p->d_cand, flags + 1);
+               ntpl, p->d_cand);
+  FSTAT_LAUNCH(k_drain_order_long, dim3((unsigned)std::min<long long>(ntpl, 2LL * p->n_cu)), dim3(DRAIN_LONG_NT), 0,
+               st, grouped, off, ntpl, p->d_cand, flags + 1);
   HIP_TRY(p, launch_status(), "drain ordering launch");
   HIP_TRY(p, hipMemcpy(hf, flags, sizeof hf, hipMemcpyDeviceToHost), "drain flags");
-  if (hf[0]) return FSTAT_OK;        // not reached: the count pass saw the same keys
-  if (hf[1]) {
-    *src = grouped;                  // every entry, grouped by template: the host orders them
-    return FSTAT_OK;
-  }
-  *done = true;
+  if (hf[0] || hf[1]) return fail(p, FSTAT_E_STATE, "a template's candidates repeat a bin");
   return FSTAT_OK;
 }
 
 // Records and keys of the first `nout` entries of d_cand (in key order) formed on the device
-// and copied straight into the caller's arrays (either may be NULL); *done is false, with
-// nothing written, when the device memory for them is not available.
-static fstat_status form_on_device(fstat_plan_t p, long long nout, fstat_candidate* out, fstat_candidate_key* keys,
-                                   bool* done) {
-  *done = false;
+// and copied straight into the caller's arrays (either may be NULL).
+static fstat_status form_on_device(fstat_plan_t p, long long nout, fstat_candidate* out, fstat_candidate_key* keys) {
   const int nsearch = (int)p->searches.size();
   const int search0 = p->search_count - nsearch;
   std::vector<size_t> nd((size_t)nsearch);
@@ -1966,11 +1943,7 @@ static fstat_status form_on_device(fstat_plan_t p, long long nout, fstat_candida
     if (p->drain_out) (void)hipFree(p->drain_out);
     p->drain_out = nullptr;
     p->drain_out_bytes = 0;
-    if (hipMalloc(&p->drain_out, o) != hipSuccess) {
-      (void)launch_status();   // clear the allocation error: the host forms the records instead
-      p->drain_out = nullptr;
-      return FSTAT_OK;
-    }
+    HIP_TRY(p, hipMalloc(&p->drain_out, o), "drain record memory");
     p->drain_out_bytes = o;
   }
   char* w = (char*)p->drain_out;
@@ -2008,33 +1981,6 @@ static fstat_status form_on_device(fstat_plan_t p, long long nout, fstat_candida
   if (out) HIP_TRY(p, hipMemcpy(out, drec, (size_t)nout * sizeof(fstat_candidate), hipMemcpyDeviceToHost), "record copy");
   if (keys)
     HIP_TRY(p, hipMemcpy(keys, dkey, (size_t)nout * sizeof(fstat_candidate_key), hipMemcpyDeviceToHost), "key copy");
-  *done = true;
-  return FSTAT_OK;
-}
-
-// The first `nout` of the `stored` entries in key order: written to out / keys by the device
-// (*formed), or into `ent` for the host to form them.
-static fstat_status drain_in_key_order(fstat_plan_t p, long long stored, long long nout, fstat_candidate* out,
-                                       fstat_candidate_key* keys, std::vector<CandEntry>* ent, bool* formed) {
-  ent->clear();
-  *formed = false;
-  if (stored == 0 || nout == 0) return FSTAT_OK;
-  bool done = false;
-  const CandEntry* src = p->d_cand;
-  fstat_status r = order_on_device(p, stored, &done, &src);
-  if (r != FSTAT_OK) return r;
-  if (done) {
-    r = form_on_device(p, nout, out, keys, formed);
-    if (r != FSTAT_OK || *formed) return r;
-    ent->resize((size_t)nout);
-    HIP_TRY(p, hipMemcpy(ent->data(), p->d_cand, (size_t)nout * sizeof(CandEntry), hipMemcpyDeviceToHost),
-            "candidate copy");
-    return FSTAT_OK;
-  }
-  ent->resize((size_t)stored);
-  HIP_TRY(p, hipMemcpy(ent->data(), src, (size_t)stored * sizeof(CandEntry), hipMemcpyDeviceToHost), "candidate copy");
-  std::sort(ent->begin(), ent->end(), key_less);
-  ent->resize((size_t)nout);
   return FSTAT_OK;
 }
 
@@ -2059,58 +2005,14 @@ fstat_status fstat_candidates(fstat_plan_t plan, fstat_candidate* out, fstat_can
       return fail(plan, FSTAT_E_OVERFLOW, "more candidates than the device buffer holds");
     return FSTAT_OK;
   }
+  // key order, records and keys on the device; the first min(stored, capacity) copied out
   const long long nout = std::min<long long>(stored, capacity);
-  std::vector<CandEntry> ent;
-  bool formed = false;
-  fstat_status r = drain_in_key_order(plan, stored, nout, out, keys, &ent, &formed);
-  if (r != FSTAT_OK) return r;
-  HIP_TRY(plan, hipMemset(plan->d_count, 0, sizeof(unsigned long long)), "count reset");
-  // records and keys, in threads over slices for large drains
-  auto fill = [&](long long i0, long long i1) {
-    for (long long i = i0; i < i1; ++i) {
-      const CandEntry& c = ent[(size_t)i];
-      if (keys) {
-        keys[i].search = c.search;
-        keys[i].segment = c.segment;
-        keys[i].sky = c.sky;
-        keys[i].fdot_idx = c.fdot_idx;
-        keys[i].bin = c.bin;
-        float score = std::nanf("");
-        if (plan->scored) std::memcpy(&score, &c.pad, sizeof score);
-        keys[i].vet_score = score;
-      }
-      if (out) {
-        const SegInfo& si = plan->segs[c.segment];
-        const SearchRecord& sr = plan->searches[(size_t)c.search - (plan->search_count - plan->searches.size())];
-        if (sr.lattice) {
-          // the template's frequency shift and spindown, as the kernels formed them
-          const int s = sr.s_lo + c.fdot_idx;
-          const double u = lattice_shift_bins(lattice_w(s, sr.m10, sr.host[2 * sr.nsky + c.sky]),
-                                              (double)si.nfft / (2.0 * M_PI));
-          out[i].f_hz = si.s.f_off + ((double)c.bin + u) / ((double)si.nfft * si.s.dt);
-          out[i].fdot = lattice_w(s, sr.m11, sr.host[3 * sr.nsky + c.sky]) / (M_PI * si.s.dt * si.s.dt);
-        } else {
-          out[i].f_hz = si.s.f_off + (double)c.bin / ((double)si.nfft * si.s.dt);
-          out[i].fdot = sr.host[2 * sr.nsky + c.fdot_idx];
-        }
-        out[i].alpha = sr.host[c.sky];
-        out[i].delta = sr.host[sr.nsky + c.sky];
-        out[i].twoF = c.twoF;
-      }
-    }
-  };
-  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  const long long slices = nout >= (1LL << 20) ? (long long)hw : 1;
-  if (formed) {
-    // written by the device
-  } else if (slices == 1) {
-    fill(0, (long long)ent.size());
-  } else {
-    std::vector<std::thread> th;
-    for (long long k = 0; k < slices; ++k)
-      th.emplace_back(fill, nout * k / slices, nout * (k + 1) / slices);
-    for (auto& t : th) t.join();
+  if (stored > 0 && nout > 0) {
+    fstat_status r = order_on_device(plan, stored);
+    if (r == FSTAT_OK) r = form_on_device(plan, nout, out, keys);
+    if (r != FSTAT_OK) return r;
   }
+  HIP_TRY(plan, hipMemset(plan->d_count, 0, sizeof(unsigned long long)), "count reset");
   for (auto& sr : plan->searches) (void)hipHostFree(sr.host);
   plan->searches.clear();
   plan->scored = false;
