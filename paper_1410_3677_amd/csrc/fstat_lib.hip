@@ -96,6 +96,7 @@ struct Tables {
 
 struct fstat_vet_s {
   int max_batch = 0;
+  int n_cu = 256;                // compute units of the device (the convolution grid)
   int steps = 0;                 // Adam steps taken
   void* mem = nullptr;           // one allocation for everything below
   float *theta = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
@@ -104,11 +105,6 @@ struct fstat_vet_s {
   float *u, *z1, *z2, *z3, *z4, *z5, *a5, *logit, *dlogit, *lterm, *dz5, *dh4, *dx, *da, *dwm, *loss;
   float* scratch = nullptr;      // split-K partial tiles and reduction partials
   uint16_t *a1b, *a2b, *a3b, *a4b, *colA, *colB, *colC, *dz5b, *dz4b, *dzb;
-  uint16_t* a3b2 = nullptr;      // second convolution-output buffer of pipelined scoring
-  // scoring: the convolutions of the next batch run on the vetter's stream (default
-  // priority) while the current batch's dense layers run on the caller's stream
-  hipStream_t cstream = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_conv[2] = {nullptr, nullptr}, ev_read[2] = {nullptr, nullptr};
   std::string last_error;
 };
 
@@ -1015,62 +1011,43 @@ void vet_prepare(fstat_vet_t v, hipStream_t st) {
   FSTAT_LAUNCH(vet::k_vet_prepare_frag, blocks_for(vet::WQ_ELEMS), dim3(256), 0, st, v->theta, v->wq2, v->wq3);
 }
 
-// inference of n <= max_batch patches (logits to `out`): fused LDS convolutions, the
-// 8192 -> 128 layer as an LDS-tiled product split four ways along K, then the small layers
+// Scoring of n <= max_batch patches in two parts: the three convolutions into x (one
+// kernel, four 64-position items per patch spread over one workgroup per compute unit),
+// then the dense layers from x (the 8192 -> 128 product reads x from HBM, split four ways
+// along K).
 constexpr int INFER_SPLITS = 4;
 static_assert((long)INFER_SPLITS * 8192 * vet::H <= VET_SCRATCH, "split-K partials of a full batch fit the scratch");
-// Scoring of n <= max_batch patches in two parts: the three convolutions into x (one
-// fused kernel, bound by the matrix cores and LDS), then the dense layers from x (the
-// 8192 -> 128 product reads x from HBM); `read` is recorded once x has been read.
+static_assert(vet::X % (INFER_SPLITS * vet::GW_K) == 0, "K splits of whole stages");
 void vet_conv_stage(fstat_vet_t v, const float* patches, int n, uint16_t* x, hipStream_t st) {
   using namespace vet;
-  FSTAT_LAUNCH(k_vet_conv_infer, dim3((unsigned)((n + CV_NP - 1) / CV_NP)), dim3(CV_NT), 0, st, patches, n, v->theta,
-               v->wq2,
-                     v->wq3, x);
+  const long items = (long)n * CV_ITEMS;
+  const unsigned grid = (unsigned)std::max(1L, std::min<long>(v->n_cu, (items + CV_WAVES - 1) / CV_WAVES));
+  FSTAT_LAUNCH(k_vet_conv_infer, dim3(grid), dim3(CV_NT), 0, st, patches, n, v->theta, v->wq2, v->wq3, x);
 }
 
-void vet_dense_stage(fstat_vet_t v, const uint16_t* x, int n, float* out, hipEvent_t read, hipStream_t st,
-                     CandEntry* cand) {
+void vet_dense_stage(fstat_vet_t v, const uint16_t* x, int n, float* out, hipStream_t st, CandEntry* cand) {
   using namespace vet;
-  const int nbp = (n + GT - 1) / GT * GT;
-  FSTAT_LAUNCH(k_gemm_nt_lds, dim3(H / GT, nbp / GT, INFER_SPLITS), dim3(256), 0, st, nbp, H, X, x, v->w4b,
-               v->scratch, X / INFER_SPLITS);
-  if (read) (void)hipEventRecord(read, st);
+  const int nbp = (n + GW_M - 1) / GW_M * GW_M;
+  FSTAT_LAUNCH(k_gemm_nt_wide, dim3(1, nbp / GW_M, INFER_SPLITS), dim3(256), 0, st, nbp, X, x, v->w4b, v->scratch,
+               X / INFER_SPLITS);
   const long count = (long)nbp * H;
   // the split-K sum, the two small layers and the score in one launch
   FSTAT_LAUNCH(k_vet_head_infer<INFER_SPLITS>, dim3((unsigned)((n + HD_NP - 1) / HD_NP)), dim3(256), 0, st,
                v->scratch, count, n, v->theta, v->w5b, out, cand);
 }
 
-// All n patches in batches of max_batch, pipelined: batch k's convolutions go to the
-// vetter's stream into buffer k % 2 (after batch k - 2's product has read it), its dense
-// layers to `st` after them; `tail(i, b, logits)` enqueues work on `st` that uses a
-// batch's logits (written to out_of(i) by the dense stage).
+// All n patches in batches of max_batch on the caller's stream: each batch's convolutions,
+// then its dense layers (logits to out_of(i)).  The convolution kernel holds every compute
+// unit's LDS, so a second stream for the next batch's convolutions cannot run beside the
+// product: measured, it made scoring slower, not faster.
 template <typename OutOf>
 static fstat_status vet_score_all(fstat_vet_t v, const float* patches, long long n, hipStream_t st, OutOf out_of,
                                   CandEntry* cand) {
-  if (!v->cstream) {
-    VET_TRY(v, hipStreamCreateWithFlags(&v->cstream, hipStreamNonBlocking), "vetter stream");
-    VET_TRY(v, hipEventCreateWithFlags(&v->ev_fork, hipEventDisableTiming), "vetter event");
-    for (int k = 0; k < 2; ++k) {
-      VET_TRY(v, hipEventCreateWithFlags(&v->ev_conv[k], hipEventDisableTiming), "vetter event");
-      VET_TRY(v, hipEventCreateWithFlags(&v->ev_read[k], hipEventDisableTiming), "vetter event");
-    }
-  }
-  VET_TRY(v, hipEventRecord(v->ev_fork, st), "vetter fork");
-  VET_TRY(v, hipStreamWaitEvent(v->cstream, v->ev_fork, 0), "vetter fork");
-  long long k = 0;
-  for (long long i = 0; i < n; i += v->max_batch, ++k) {
+  for (long long i = 0; i < n; i += v->max_batch) {
     const int b = (int)std::min<long long>(v->max_batch, n - i);
-    const int buf = (int)(k & 1);
-    uint16_t* x = buf ? v->a3b2 : v->a3b;
-    if (k >= 2) VET_TRY(v, hipStreamWaitEvent(v->cstream, v->ev_read[buf], 0), "vetter order");
-    vet_conv_stage(v, patches + i * vet::L, b, x, v->cstream);
+    vet_conv_stage(v, patches + i * vet::L, b, v->a3b, st);
     VET_TRY(v, launch_status(), "scoring launch");
-    VET_TRY(v, hipEventRecord(v->ev_conv[buf], v->cstream), "vetter order");
-    VET_TRY(v, hipStreamWaitEvent(st, v->ev_conv[buf], 0), "vetter join");
-    float* out = out_of(i);
-    vet_dense_stage(v, x, b, out, v->ev_read[buf], st, cand ? cand + i : nullptr);
+    vet_dense_stage(v, v->a3b, b, out_of(i), st, cand ? cand + i : nullptr);
     VET_TRY(v, launch_status(), "scoring launch");
   }
   return FSTAT_OK;
@@ -1162,8 +1139,15 @@ fstat_status fstat_vet_create(int32_t max_batch, fstat_vet_t* out) {
   auto v = new (std::nothrow) fstat_vet_s();
   if (!v) return vet_fail(nullptr, FSTAT_E_NOMEM, "vetter allocation");
   v->max_batch = max_batch;
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+      v->n_cu = ncu;
+  }
   const size_t nb = (size_t)max_batch, NL = nb * L;
-  const size_t nbp = (nb + vet::GT - 1) / vet::GT * vet::GT;  // rows of the 8192 -> 128 product
+  // rows of the 8192 -> 128 products (training tiles of 64 rows, scoring tiles of 128)
+  const size_t nbp = (nb + vet::GW_M - 1) / vet::GW_M * vet::GW_M;
   struct Part { void** p; size_t bytes; };
   std::vector<Part> parts = {
       {(void**)&v->theta, N_PARAMS * 4}, {(void**)&v->grad, N_PARAMS * 4}, {(void**)&v->m1, N_PARAMS * 4},
@@ -1176,7 +1160,7 @@ fstat_status fstat_vet_create(int32_t max_batch, fstat_vet_t* out) {
       {(void**)&v->dh4, nb * H * 4}, {(void**)&v->dx, NL * C * 4}, {(void**)&v->da, NL * C * 4},
       {(void**)&v->dwm, KC * C * 4}, {(void**)&v->loss, 4}, {(void**)&v->scratch, (size_t)VET_SCRATCH * 4},
       {(void**)&v->a1b, NL * C * 2},
-      {(void**)&v->a2b, NL * C * 2}, {(void**)&v->a3b, nbp * X * 2}, {(void**)&v->a3b2, nbp * X * 2},
+      {(void**)&v->a2b, NL * C * 2}, {(void**)&v->a3b, nbp * X * 2},
       {(void**)&v->a4b, nb * H * 2},
       {(void**)&v->colA, NL * KC * 2}, {(void**)&v->colB, NL * KC * 2}, {(void**)&v->colC, NL * KC * 2},
       {(void**)&v->dz5b, nb * H * 2}, {(void**)&v->dz4b, nb * H * 2}, {(void**)&v->dzb, NL * C * 2}};
@@ -1254,12 +1238,6 @@ fstat_status fstat_vet_adam_step(fstat_vet_t v, float lr, float beta1, float bet
 fstat_status fstat_vet_destroy(fstat_vet_t v) {
   if (!v) return FSTAT_OK;
   (void)hipDeviceSynchronize();
-  for (int k = 0; k < 2; ++k) {
-    if (v->ev_conv[k]) (void)hipEventDestroy(v->ev_conv[k]);
-    if (v->ev_read[k]) (void)hipEventDestroy(v->ev_read[k]);
-  }
-  if (v->ev_fork) (void)hipEventDestroy(v->ev_fork);
-  if (v->cstream) (void)hipStreamDestroy(v->cstream);
   if (v->mem) (void)hipFree(v->mem);
   delete v;
   return FSTAT_OK;

@@ -372,20 +372,34 @@ struct PatchArgs {
 };
 
 // ------------------------------------------------------------------ inference
-// Inference runs the three convolutions of CV_NP patches in one workgroup with the
-// activations resident in one LDS buffer (position-major rows of 32 BF16 channels, padded to
-// CV_LD so that the sixteen rows one matrix-core operand spans hit distinct banks,
-// with three zero rows above and below every patch for the "same" padding), then
-// the 8192 -> 128 layer as an LDS-tiled product.  The convolutions use the training
-// forward's operands and K order (the matrix-core products transposed, so that a lane
-// holds four channels of one position), so scores agree with it.  Both layers' weight
-// fragments are staged in LDS once per workgroup.
-constexpr int CV_NP = 2;          // patches per workgroup
-constexpr int CV_NT = 512;        // threads per workgroup (8 wavefronts)
-constexpr int CV_MB = CV_NP * L / 16 / (CV_NT / 64);  // sixteen-position blocks per wavefront (4)
-constexpr int CV_R = L + 6;       // LDS rows per patch
-constexpr int CV_LD = 36;         // BF16 per LDS row
-constexpr int KS = KC / 32;       // matrix-core K steps of a convolution (7: one tap each)
+// Inference convolutions.  A work item is one 64-position segment of one patch, owned by
+// one wavefront from input to output, so that no workgroup barrier orders its layers: the
+// wavefront recomputes the three-position halos its neighbours also compute (the second
+// convolution over 80 positions, the first over 80 positions, for 64 outputs), holds the
+// item's activations in LDS rows of its own (position-major, 32 BF16 channels padded to
+// CV_LD so that the sixteen rows one matrix-core operand spans hit distinct banks), and
+// writes the third convolution's outputs straight from the accumulators to HBM.
+// Workgroups of CV_WAVES wavefronts (one per compute unit: the LDS holds one) stage the
+// second and third convolutions' weight fragments once and walk the items with a
+// stride of the grid, prefetching the next item's input during the current one.
+//
+// All three convolutions run on the matrix cores.  The second and third use the training
+// forward's BF16 operands and K order (D[co][p] = sum over taps t and input channels of
+// W[co][k] X[p][k], K step t = tap t over all 32 channels; a lane's B operand is eight
+// channels of one LDS row and its result four consecutive channels of one position).  The
+// first has one input channel: its input u and weights w are split into BF16 pairs
+// u = uh + ul, w = wh + wl (each to 2^-17 relative), and one 16 x 16 x 32 step covers all
+// seven taps (padded to eight) times the four products wh uh, wl uh, wh ul, wl ul, which
+// the accumulator sums in FP32: the FP32 convolution to about 2^-16 relative before the
+// BF16 rounding of its output.
+constexpr int CV_SEG = 64;              // third-convolution outputs of one item
+constexpr int CV_ITEMS = L / CV_SEG;    // items per patch
+constexpr int CV_WAVES = 16;            // wavefronts per workgroup
+constexpr int CV_NT = CV_WAVES * 64;
+constexpr int CV_ROWS = 86;             // LDS rows of an item: positions s0 - 11 .. s0 + 74
+constexpr int CV_LD = 36;               // BF16 per LDS row
+constexpr int CV_U = 88;                // split input entries: positions s0 - 11 .. s0 + 76
+constexpr int KS = KC / 32;             // matrix-core K steps of a convolution (7: one tap each)
 
 // Convolution weights in matrix-core fragment order: [step s][column block nb][lane][8],
 // element j of lane l = w[co = 16 nb + l % 16][ci = 8 (l / 16) + j][t = s].
@@ -401,128 +415,178 @@ __global__ void k_vet_prepare_frag(const float* __restrict__ theta, uint16_t* __
   wq3[idx] = f2bf(theta[O_W3 + (co * C + ci) * KW + t]);
 }
 
-// Bias, ReLU and BF16 rounding of a product tile D[co][p] (lane l: channels
-// 16 nb + 4 (l / 16) + i, i < 4, of position p0 + l % 16) into the LDS rows, four channels
-// (8 bytes) per store.
-__device__ __forceinline__ void store_tile(uint16_t* act, int pp, int p0, int nb, v4f d, int lane) {
-  const int co0 = 16 * nb + 4 * (lane >> 4);
-  uint32_t h[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) h[i] = f2bf(d[i] > 0.f ? d[i] : 0.f);
-  uint16_t* row = act + (pp * CV_R + p0 + (lane & 15) + 3) * CV_LD + co0;
-  *reinterpret_cast<uint2*>(row) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+// two FP32 values to BF16 (round to nearest even), packed low then high
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f){a, b}, v2bf));
+}
+// ReLU then BF16: as integers, negative floats (and -0) are below zero
+__device__ __forceinline__ uint32_t relu_bf16_pair(float a, float b) {
+  return bf16_pair(__int_as_float(max(__float_as_int(a), 0)), __int_as_float(max(__float_as_int(b), 0)));
+}
+__device__ __forceinline__ uint2 relu_bf16_tile(v4f d) {
+  return make_uint2(relu_bf16_pair(d[0], d[1]), relu_bf16_pair(d[2], d[3]));
+}
+// (hi | hi << 16, lo | lo << 16) of u = hi + lo, the first convolution's B operand entry
+__device__ __forceinline__ uint2 split_bf16(float u) {
+  const float hi = (float)(__bf16)u;
+  const uint32_t p = bf16_pair(hi, u - hi);
+  return make_uint2((p & 0xffffu) * 0x10001u, (p >> 16) * 0x10001u);
+}
+// LDS ordering between the steps of one wavefront's item: a wavefront's LDS operations
+// complete in order, so only compiler reordering must be prevented
+__device__ __forceinline__ void item_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// zero eight LDS rows from row0 (positions outside the patch)
+__device__ __forceinline__ void zero_rows8(uint16_t* buf, int row0, int lane) {
+  *reinterpret_cast<uint2*>(buf + (row0 + (lane >> 3)) * CV_LD + 4 * (lane & 7)) = make_uint2(0u, 0u);
 }
 
-// One convolution layer of the workgroup's patches, in place in LDS (the outputs wait in
-// the matrix-core accumulators until every wavefront has read the input); wavefront w
-// computes the sixteen-position blocks CV_MB w .. CV_MB w + CV_MB - 1 for all 32 output
-// channels as D[co][p] = sum_k W[co][k] X[p][k]: K step t is tap t over all 32 input
-// channels, a lane's B operand eight channels of one LDS row, and a lane's result four
-// consecutive channels of one position.
-__device__ __forceinline__ void conv_layer_lds(uint16_t* act, const uint16_t* __restrict__ wq,
-                                               const float* __restrict__ bias, int w, int lane) {
-  const uint16_t* in = act;
-  // the accumulators start at the bias of the lane's four output channels
-  v4f acc[CV_MB][2];
-  const int cb = 4 * (lane >> 4);
-  const v4f bias0{bias[cb], bias[cb + 1], bias[cb + 2], bias[cb + 3]};
-  const v4f bias1{bias[16 + cb], bias[16 + cb + 1], bias[16 + cb + 2], bias[16 + cb + 3]};
-#pragma unroll
-  for (int m = 0; m < CV_MB; ++m) {
-    acc[m][0] = bias0;
-    acc[m][1] = bias1;
-  }
-  const v8s* wqv = reinterpret_cast<const v8s*>(wq);   // fragments in LDS
-  const int ci0 = 8 * (lane >> 4);
-  for (int t = 0; t < KS; ++t) {
-    const v8s b0 = wqv[(t * 2 + 0) * 64 + lane];
-    const v8s b1 = wqv[(t * 2 + 1) * 64 + lane];
-#pragma unroll
-    for (int m = 0; m < CV_MB; ++m) {
-      const int mb = CV_MB * w + m, pp = mb >> 4, p0 = (mb & 15) * 16;
-      const v8s a = lds8(in + (pp * CV_R + p0 + (lane & 15) + t) * CV_LD + ci0);
-      acc[m][0] = mfma32(b0, a, acc[m][0]);
-      acc[m][1] = mfma32(b1, a, acc[m][1]);
-    }
-  }
-  __syncthreads();  // every wavefront has read the layer's input: overwrite it in place
-#pragma unroll
-  for (int m = 0; m < CV_MB; ++m) {
-    const int mb = CV_MB * w + m, pp = mb >> 4, p0 = (mb & 15) * 16;
-    store_tile(act, pp, p0, 0, acc[m][0], lane);
-    store_tile(act, pp, p0, 1, acc[m][1], lane);
-  }
-}
-
-// u -> conv1 -> conv2 -> conv3 for patches [CV_NP b, CV_NP b + CV_NP); x[s][p*32 + c] (BF16).
+// u -> conv1 -> conv2 -> conv3 for items [0, 4n) (item i: patch i / 4, positions 64 (i % 4)
+// .. + 63); x[s][p*32 + c] (BF16).  Every wavefront reaches the single workgroup barrier
+// (after the weight staging) before its item loop.
 __global__ void __launch_bounds__(CV_NT) k_vet_conv_infer(const float* __restrict__ patches, int n,
                                                         const float* __restrict__ theta,
                                                         const uint16_t* __restrict__ wq2,
                                                         const uint16_t* __restrict__ wq3, uint16_t* __restrict__ x) {
-  __shared__ float su[CV_NP][CV_R];
-  __shared__ __align__(16) uint16_t sa[CV_NP * CV_R * CV_LD];
-  __shared__ __align__(16) uint16_t swq[2 * WQ_ELEMS];   // conv2 and conv3 weight fragments
-  const int s0 = blockIdx.x * CV_NP;
+  __shared__ __align__(16) uint16_t swq[2 * WQ_ELEMS];                  // conv2 and conv3 fragments
+  __shared__ __align__(16) uint16_t sbuf[CV_WAVES][CV_ROWS * CV_LD];   // activations of each wavefront's item
+  __shared__ __align__(16) uint2 ssplit[CV_WAVES][CV_U];               // split input of each item
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int i = tid; i < 2 * WQ_ELEMS / 8; i += CV_NT) {
     const uint4* src = reinterpret_cast<const uint4*>(i < WQ_ELEMS / 8 ? wq2 : wq3);
     reinterpret_cast<uint4*>(swq)[i] = src[i < WQ_ELEMS / 8 ? i : i - WQ_ELEMS / 8];
   }
-  for (int i = tid; i < CV_NP * CV_R; i += CV_NT) {
-    const int pp = i / CV_R, r = i % CV_R, q = r - 3;
-    float v = 0.f;
-    if (s0 + pp < n && q >= 0 && q < L) v = vet_u(patches[(long)(s0 + pp) * L + q]);
-    su[pp][r] = v;
-  }
-  for (int i = tid; i < CV_NP * 6 * CV_LD; i += CV_NT) {
-    const int pp = i / (6 * CV_LD), rem = i % (6 * CV_LD), hr = rem / CV_LD, c = rem % CV_LD;
-    const int row = hr < 3 ? hr : L + hr;
-    sa[(pp * CV_R + row) * CV_LD + c] = 0;
-  }
+  uint16_t* buf = sbuf[w];
+  uint2* su = ssplit[w];
+  // rows 0-2 and 83-85 are never written again: the zero padding below and above the
+  // second convolution's 80 positions
+  for (int i = lane; i < CV_ROWS * CV_LD / 4; i += 64) reinterpret_cast<uint2*>(buf)[i] = make_uint2(0u, 0u);
   __syncthreads();
-  {
-    // conv1: thread (channel pair c2, group grp) slides along PER positions with both
-    // channels' weights in registers and a seven-sample window, one LDS read per position
-    // and one 4-byte store of the two BF16 outputs
-    constexpr int PER = CV_NP * L * (C / 2) / CV_NT;  // positions per thread (16)
-    static_assert(L % PER == 0, "conv1 work split");
-    const int c2 = tid & (C / 2 - 1), grp = tid / (C / 2);
-    const int pp = grp / (L / PER), p0 = (grp % (L / PER)) * PER;
-    float wa[KW], wb[KW];
+  const long items = (long)n * CV_ITEMS;
+  const long stride = (long)gridDim.x * CV_WAVES;
+  const int r16 = lane & 15, q = lane >> 4, cb = 4 * q, ci0 = 8 * q;
+  auto bias4 = [&](long o) { return v4f{theta[o + cb], theta[o + cb + 1], theta[o + cb + 2], theta[o + cb + 3]}; };
+  const v4f b10 = bias4(O_B1), b11 = bias4(O_B1 + 16), b20 = bias4(O_B2), b21 = bias4(O_B2 + 16),
+            b30 = bias4(O_B3), b31 = bias4(O_B3 + 16);
+  // first-convolution weights as the A operand: element j of lane l is product term j % 4
+  // (wh, wl, wh, wl) of tap 2 q + j / 4 (zero for the eighth tap) of channel 16 nb + l % 16
+  v8s w1f[2];
 #pragma unroll
-    for (int t = 0; t < KW; ++t) {
-      wa[t] = theta[O_W1 + (2 * c2) * KW + t];
-      wb[t] = theta[O_W1 + (2 * c2 + 1) * KW + t];
+  for (int nb = 0; nb < 2; ++nb) {
+    uint32_t d[4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int t = 2 * q + h;
+      const float wv = t < KW ? theta[O_W1 + (16 * nb + r16) * KW + t] : 0.f;
+      const float whi = (float)(__bf16)wv;
+      d[2 * h] = d[2 * h + 1] = bf16_pair(whi, wv - whi);
     }
-    const float ba = theta[O_B1 + 2 * c2], bb = theta[O_B1 + 2 * c2 + 1];
-    float win[PER + KW - 1];
+    w1f[nb] = __builtin_bit_cast(v8s, make_uint4(d[0], d[1], d[2], d[3]));
+  }
+  const v8s* wqv = reinterpret_cast<const v8s*>(swq);
+  // an item's input: lane holds positions s0 - 11 + lane and (lanes < 23) s0 + 53 + lane
+  auto load_raw = [&](long it, float& a, float& b) {
+    a = 0.f;
+    b = 0.f;
+    if (it < items) {
+      const long s = it / CV_ITEMS;
+      const int s0 = (int)(it % CV_ITEMS) * CV_SEG;
+      const int q0 = s0 - 11 + lane, q1 = s0 + 53 + lane;
+      if (q0 >= 0 && q0 < L) a = patches[s * L + q0];
+      if (lane < 23 && q1 < L) b = patches[s * L + q1];
+    }
+  };
+  long item = (long)blockIdx.x * CV_WAVES + w;
+  float ra, rb;
+  load_raw(item, ra, rb);
+  for (; item < items; item += stride) {
+    const long s = item / CV_ITEMS;
+    const int s0 = (int)(item % CV_ITEMS) * CV_SEG;
+    {
+      const int q0 = s0 - 11 + lane, q1 = s0 + 53 + lane;
+      su[lane] = split_bf16((q0 >= 0 && q0 < L) ? vet_u(ra) : 0.f);
+      if (lane < CV_U - 64) su[64 + lane] = split_bf16((lane < 23 && q1 < L) ? vet_u(rb) : 0.f);
+    }
+    load_raw(item + stride, ra, rb);
+    item_sync();
+    // conv1: output rows 3 + 16 m + r16 (position s0 - 8 + 16 m + r16); the B operand of
+    // lane l is input entries 16 m + r16 + 2 q and + 1 (taps 2 q, 2 q + 1)
 #pragma unroll
-    for (int t = 0; t < PER + KW - 1; ++t) win[t] = su[pp][p0 + t];
+    for (int m = 0; m < 5; ++m) {
+      const uint2* e = su + 16 * m + r16 + 2 * q;
+      const uint2 e0 = e[0], e1 = e[1];
+      const v8s bop = __builtin_bit_cast(v8s, make_uint4(e0.x, e0.y, e1.x, e1.y));
+      uint16_t* row = buf + (3 + 16 * m + r16) * CV_LD + cb;
+      *reinterpret_cast<uint2*>(row) = relu_bf16_tile(mfma32(w1f[0], bop, b10));
+      *reinterpret_cast<uint2*>(row + 16) = relu_bf16_tile(mfma32(w1f[1], bop, b11));
+    }
+    if (s0 == 0) zero_rows8(buf, 3, lane);               // positions -8 .. -1
+    if (s0 + CV_SEG == L) zero_rows8(buf, 75, lane);     // positions 256 .. 263
+    item_sync();
+    // conv2: output rows 3 + 16 m + r16, input rows 16 m + r16 + t; written in place once
+    // every input row has been read
+    {
+      v4f acc[5][2];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      float za = ba, zb = bb;
-#pragma unroll
-      for (int t = 0; t < KW; ++t) {
-        za += wa[t] * win[k + t];
-        zb += wb[t] * win[k + t];
+      for (int m = 0; m < 5; ++m) {
+        acc[m][0] = b20;
+        acc[m][1] = b21;
       }
-      const uint32_t h = f2bf(za > 0.f ? za : 0.f) | ((uint32_t)f2bf(zb > 0.f ? zb : 0.f) << 16);
-      *reinterpret_cast<uint32_t*>(sa + (pp * CV_R + p0 + k + 3) * CV_LD + 2 * c2) = h;
+#pragma unroll
+      for (int t = 0; t < KS; ++t) {
+        const v8s w0 = wqv[(t * 2 + 0) * 64 + lane];
+        const v8s w1 = wqv[(t * 2 + 1) * 64 + lane];
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+          const v8s a = lds8(buf + (16 * m + r16 + t) * CV_LD + ci0);
+          acc[m][0] = mfma32(w0, a, acc[m][0]);
+          acc[m][1] = mfma32(w1, a, acc[m][1]);
+        }
+      }
+      item_sync();
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        uint16_t* row = buf + (3 + 16 * m + r16) * CV_LD + cb;
+        *reinterpret_cast<uint2*>(row) = relu_bf16_tile(acc[m][0]);
+        *reinterpret_cast<uint2*>(row + 16) = relu_bf16_tile(acc[m][1]);
+      }
+      if (s0 == 0) zero_rows8(buf, 3, lane);
+      if (s0 + CV_SEG == L) zero_rows8(buf, 75, lane);
     }
-  }
-  __syncthreads();
-  conv_layer_lds(sa, swq, theta + O_B2, w, lane);
-  __syncthreads();
-  conv_layer_lds(sa, swq + WQ_ELEMS, theta + O_B3, w, lane);
-  __syncthreads();
-  // rows 3 .. L+2 of each patch to x, 16 bytes per item
-  for (int i = tid; i < CV_NP * L * (C / 8); i += CV_NT) {
-    const int pp = i / (L * (C / 8)), rem = i % (L * (C / 8)), p = rem / (C / 8), c8 = (rem % (C / 8)) * 8;
-    if (s0 + pp < n) {
-      const uint2* src = reinterpret_cast<const uint2*>(sa + (pp * CV_R + p + 3) * CV_LD + c8);
-      const uint2 lo = src[0], hi = src[1];
-      *reinterpret_cast<uint4*>(x + (long)(s0 + pp) * X + p * C + c8) = make_uint4(lo.x, lo.y, hi.x, hi.y);
+    item_sync();
+    // conv3: output position s0 + 16 m + r16 (row 11 + 16 m + r16), input rows
+    // 8 + 16 m + r16 + t; four channels (8 bytes) per lane and tile to x
+    {
+      v4f acc[4][2];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        acc[m][0] = b30;
+        acc[m][1] = b31;
+      }
+#pragma unroll
+      for (int t = 0; t < KS; ++t) {
+        const v8s w0 = wqv[((KS + t) * 2 + 0) * 64 + lane];
+        const v8s w1 = wqv[((KS + t) * 2 + 1) * 64 + lane];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const v8s a = lds8(buf + (8 + 16 * m + r16 + t) * CV_LD + ci0);
+          acc[m][0] = mfma32(w0, a, acc[m][0]);
+          acc[m][1] = mfma32(w1, a, acc[m][1]);
+        }
+      }
+      uint16_t* xs = x + s * X + (s0 + r16) * C + cb;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        *reinterpret_cast<uint2*>(xs + 16 * m * C) = relu_bf16_tile(acc[m][0]);
+        *reinterpret_cast<uint2*>(xs + 16 * m * C + 16) = relu_bf16_tile(acc[m][1]);
+      }
     }
+    item_sync();   // the next item's writes follow this item's reads
   }
 }
 
@@ -593,6 +657,75 @@ __global__ void __launch_bounds__(256) k_gemm_nt_lds(int M, int N, int K, const 
 #pragma unroll
       for (int i = 0; i < 4; ++i)
         Cz[(long)(m0 + wm + 16 * a + kq + i) * N + n0 + wn + 16 * b + r16] = acc[a][b][i];
+}
+
+// The scoring call's 8192 -> 128 product: C[m][n] (split z of K) = sum_k A[m][k] B[n][k] for
+// row-major BF16 A [M][K] and B [128][K], M a multiple of 128, K of GW_K * splits.  A
+// workgroup covers 128 rows and all 128 columns, so that each row of A is read once and B
+// once per 128 rows; four wavefronts of 64 x 64 (4 x 4 matrix-core tiles each), K in
+// stages of GW_K through LDS (rows padded by 8 BF16), the next stage loaded into registers
+// (native vector registers: arrays of the HIP vector structs are not kept in registers)
+// while the current one is multiplied.  Partial tiles of split z go to C + z * M * 128.
+constexpr int GW_M = 128, GW_K = 64, GW_LD = GW_K + 8;
+__global__ void __launch_bounds__(256) k_gemm_nt_wide(int M, int K, const uint16_t* __restrict__ A,
+                                                      const uint16_t* __restrict__ B, float* __restrict__ Cm,
+                                                      int kchunk) {
+  typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+  constexpr int PER = GW_M * GW_K / 8 / 256;   // 16-byte loads per thread per operand and stage (4)
+  constexpr int TPR = GW_K / 8;                // threads per row
+  constexpr int RPP = 256 / TPR;               // rows per pass
+  __shared__ __align__(16) uint16_t sA[GW_M * GW_LD];
+  __shared__ __align__(16) uint16_t sB[H * GW_LD];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int m0 = blockIdx.y * GW_M;
+  const int kbeg = blockIdx.z * kchunk, kend = kbeg + kchunk;
+  const int lr = tid / TPR, lc = (tid % TPR) * 8;
+  u4v ra[PER], rb[PER];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      ra[i] = *reinterpret_cast<const u4v*>(A + (long)(m0 + lr + RPP * i) * K + k0 + lc);
+      rb[i] = *reinterpret_cast<const u4v*>(B + (long)(lr + RPP * i) * K + k0 + lc);
+    }
+  };
+  v4f acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = v4f{0.f, 0.f, 0.f, 0.f};
+  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+  const int r16 = lane & 15, kq = 4 * (lane >> 4), k8 = 8 * (lane >> 4);
+  gload(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += GW_K) {
+    __syncthreads();  // the previous stage has been read
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      *reinterpret_cast<u4v*>(sA + (lr + RPP * i) * GW_LD + lc) = ra[i];
+      *reinterpret_cast<u4v*>(sB + (lr + RPP * i) * GW_LD + lc) = rb[i];
+    }
+    __syncthreads();
+    if (k0 + GW_K < kend) gload(k0 + GW_K);
+#pragma unroll
+    for (int kk = 0; kk < GW_K; kk += 32) {
+      v8s fa[4], fb[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        fa[t] = *reinterpret_cast<const v8s*>(sA + (wm + 16 * t + r16) * GW_LD + kk + k8);
+        fb[t] = *reinterpret_cast<const v8s*>(sB + (wn + 16 * t + r16) * GW_LD + kk + k8);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = mfma32(fa[a], fb[c], acc[a][c]);
+    }
+  }
+  float* Cz = Cm + (long)blockIdx.z * M * H;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Cz[(long)(m0 + wm + 16 * a + kq + i) * H + wn + 16 * c + r16] = acc[a][c][i];
 }
 
 // The dense layers after the 8192 -> 128 product, for HD_NP patches per workgroup: the
