@@ -1,7 +1,7 @@
 """The candidate drain through the C ABI: records come out in key order (search, segment,
-sky, spindown index, bin) whether the device orders them (count -> offsets -> write,
-then each template's range by bin) or, for templates with more crossings than one
-workgroup orders, the host does; the drained set equals the oracle's crossings."""
+sky, spindown index, bin), ordered on the device (count -> offsets -> write, then each
+template's range by bin: a counting rank up to 4096 crossings, an LDS bitmap of the bins
+beyond); the drained set equals the oracle's crossings."""
 import numpy as np
 import pytest
 import torch as _torch  # noqa: F401  (first import on a fresh box is slow)
@@ -62,7 +62,7 @@ def test_drain_orders_several_searches_and_segments(torch):
 
 def test_drain_of_templates_with_many_crossings(torch):
     # 2F > 1 on a full segment: about 0.91 of the 131072 bins of each template cross,
-    # more than one workgroup orders on the device: the host orders them
+    # more than the counting rank orders: the bitmap ordering takes these templates
     w = synth.workload("full", nsky=2, nfdot=2)
     seg = w.segments[0]
     nfft = synth.nfft_for(seg.n)
