@@ -59,6 +59,27 @@ def test_forward_matches_fp64_reference(torch):
     assert err.max() <= 0.02 * max(1.0, np.abs(ref).max())
 
 
+@pytest.mark.parametrize("n,batch", [(1, 8192), (3, 8192), (17, 8)])
+def test_forward_of_few_patches(torch, n, batch):
+    # fewer items than one workgroup's wavefronts (a grid of one workgroup), and a batch
+    # size that ends a batch inside a workgroup's share of items
+    from paper_1410_3677_amd import fstat as F
+    rng = np.random.default_rng(100 + n)
+    theta = _theta(7)
+    v = F.Vetter(batch)
+    v.set_params(theta.astype(np.float32))
+    x = _patches(rng, n)
+    x[0, :5] = 0.0                       # zero 2F at the left edge of the first patch
+    logits = torch.full((n + 1,), 7.5, device="cuda")
+    v.forward(torch.as_tensor(x, device="cuda"), logits[:n])
+    got = logits.cpu().numpy().astype(np.float64)
+    assert got[n] == 7.5                 # nothing written past the last patch
+    ref = vo.forward(_as_gpu_weights(theta), x.astype(np.float64))
+    err = np.abs(got[:n] - ref)
+    note(f"{n} patches, batch {batch}: logit err max {err.max():.3e}, scale {np.abs(ref).max():.3f}")
+    assert err.max() <= 0.02 * max(1.0, np.abs(ref).max())
+
+
 def test_gradients_match_fp64_reference(torch):
     from paper_1410_3677_amd import fstat as F
     rng = np.random.default_rng(12)
