@@ -79,6 +79,31 @@ def test_drain_of_templates_with_many_crossings(torch):
     assert not mism and err < 1e-4
 
 
+@pytest.mark.parametrize("nbins", [4096, 4097])
+def test_drain_at_the_ordering_switch(torch, nbins):
+    # a bin range of exactly 4096 or 4097 bins and a threshold every 2F exceeds: each
+    # template holds that many crossings, the longest range the counting rank orders and
+    # the shortest the bitmap ordering takes
+    w = synth.workload("full", nsky=2, nfdot=3)
+    seg = w.segments[0]
+    nfft = synth.nfft_for(seg.n)
+    k0 = 1000
+    plan = make_plan([seg], threshold_2F=-1.0, k_min=k0, k_max=k0 + nbins, candidate_capacity=1 << 16)
+    plan.search_batch(0, dev(w.alpha), dev(w.delta), dev(w.fdot))
+    recs, keys, n = plan.candidates()
+    note(f"{nbins} bins per template: {n} candidates")
+    assert n == 6 * nbins and _strictly_increasing(_key(keys))
+    for i in range(2):
+        for s_ in range(3):
+            m = (keys["sky"] == i) & (keys["fdot_idx"] == s_)
+            np.testing.assert_array_equal(keys["bin"][m], np.arange(k0, k0 + nbins))
+    ref = oracle_spectrum(seg, w.alpha, w.delta, w.fdot, nfft, k0, k0 + nbins)
+    got = recs["twoF"].reshape(2, 3, nbins)
+    err = np.max(np.abs(got - ref) / np.maximum(ref, 4.0))
+    note(f"max relative 2F error {err:.2e}")
+    assert err < 1e-4
+
+
 def test_partial_drain_returns_the_first_keys(torch):
     w = synth.workload("full", nsky=3, nfdot=4)
     seg = w.segments[0]
