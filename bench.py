@@ -481,10 +481,15 @@ def ragged_leg(args, F, torch, np, dev, log):
     t1 = time.perf_counter()
     plan.destroy()
     value = templates / ((t1 - t0) / steps)
+    # the two template passes' algorithmic bytes: 2 nfft x 8 B written and read per template,
+    # each segment with its own nfft (the per-sky stage and the candidates left out)
+    tbytes = sum(per_seg * 2 * 2 * synth.nfft_for(s.n) * 8 for s in w.segments)
     ns = sorted(s.n for s in w.segments)
     log(f"ragged: {len(segs)} segments, {templates} templates, {value:.4g} templates/s, "
         f"{counts[-1]} candidates/step, batches {info['templates_per_launch']} x {info['skies_per_batch']}")
     return {"value": value, "unit": "templates/s", "ms_per_step": (t1 - t0) * 1e3 / steps, "steps": steps,
+            "template_bytes_per_step": tbytes,
+            "achieved_GBs_whole_step": tbytes / ((t1 - t0) / steps) / 1e9,
             "candidates_per_step": sum(counts) / steps, "overflowed": max(counts) > cap,
             "config": {"workload": f"{len(segs)} segments, N from {ns[0]} to {ns[-1]}, nfft 2^"
                                    f"{int(math.log2(synth.nfft_for(ns[0])))}..2^{int(math.log2(synth.nfft_for(ns[-1])))}, "
@@ -672,6 +677,9 @@ def main():
                    "tuning": tuned},
         "roofline": roofline, "cpu_baseline": cpu, "plain": plain,
         "f_rel_err_vs_fp64": f_err, "candidates_per_step": n_cand / args.steps, "kernels": kernels,
+        # the two template passes' algorithmic bytes (2 nfft x 8 B written and read per
+        # template) over the whole step's time, per-sky stage and count drain included
+        "achieved_GBs_whole_step": templates * 2 * 2 * nfft * 8 / (ms_step / 1e3) / 1e9,
         "candidate_capacity": main_leg["candidate_capacity"], "full_drain": main_leg["full_drain"],
         "vetting": vetting,
         "interbinning": ib_summary(ib, templates, nfft),
