@@ -355,7 +355,10 @@ fstat_status fstat_vet_set_params(fstat_vet_t vet, const float* params, int64_t 
 fstat_status fstat_vet_get_params(fstat_vet_t vet, float* params, int64_t n);
 
 /* Logits of n patches (device [n][256] 2F values) into device logits[n]; any n
- * (processed in batches of max_batch).  Asynchronous on `stream`. */
+ * (processed in batches of max_batch).  Asynchronous on `stream`.  The first
+ * convolution runs on the matrix cores with input and weights split into BF16
+ * pairs (hi + lo, about FP32 before its output's BF16 rounding), so its outputs can
+ * differ in the last BF16 place from the FP32 first layer of fstat_vet_gradient. */
 fstat_status fstat_vet_forward(fstat_vet_t vet, const float* patches, int64_t n, float* logits, void* stream);
 
 /* Mean binary cross-entropy of n <= max_batch patches with device labels[n]
