@@ -927,6 +927,9 @@ struct WaveStage {
   }
 };
 
+// Columns per block of the 2F rows the streaming second pass stores for the patch capture.
+constexpr int CAP_BLOCK = 8;
+
 // Row units per wavefront step: RPW rows of P points.
 template <int P>
 __host__ __device__ constexpr int stream_rpw() { return 64 / groups_per_col<P>(); }
@@ -1020,11 +1023,14 @@ __global__ void __launch_bounds__(256) k_tmpl_b_stream(TmplArgs ta, int ntmpl, c
             out[k - oa.k_min] = two_f_value(fa[b][r], fb[b][r], cfa, cfb, cfab);
         }
     } else {
-      // MODE 2 (patch capture) stores the launch's 2F rows transposed, [template][k2][k1]
-      // with rows of RLEN (the outputs a row forms), so that a wavefront's store is
-      // contiguous; the capture kernel reads bin k at row k % Q, column k / Q
+      // MODE 2 (patch capture) stores the launch's 2F values in blocks of eight columns,
+      // [template][k1 / 8][k2][k1 % 8] (RLEN columns: the outputs a row forms): eight lanes
+      // store 32 contiguous bytes, the lines filled by the neighbouring rows that other
+      // wavefronts form at the same time, and a window's 256 consecutive bins (consecutive
+      // k2, one or two k1) lie four to a 128-byte line
       constexpr int RLEN = HALF ? P / 2 : P;
-      float* srow = (float*)oa.spectrum + (long)item * ta.Q * RLEN + (long)k2 * RLEN;
+      static_assert(RLEN % CAP_BLOCK == 0, "whole column blocks");
+      float* srow = (float*)oa.spectrum + (long)item * ta.Q * RLEN + (long)k2 * CAP_BLOCK;
       uint32_t mask = 0;
       T val[NOUT];
 #pragma unroll
@@ -1036,7 +1042,7 @@ __global__ void __launch_bounds__(256) k_tmpl_b_stream(TmplArgs ta, int ntmpl, c
           const T v = two_f_value(fa[b][r], fb[b][r], cfa, cfb, cfab);
           val[b * ROUT + r] = v;
           const bool inr = HALF || (k >= oa.k_min && k < oa.k_max);
-          if (MODE == 2) srow[k1] = (float)v;
+          if (MODE == 2) srow[(long)(k1 / CAP_BLOCK) * ta.Q * CAP_BLOCK + k1 % CAP_BLOCK] = (float)v;
           if (inr && v > thr) mask |= 1u << (b * ROUT + r);
         }
       stg.add<false>(oa, ta, search, lane, mask, val, item,
@@ -1313,8 +1319,9 @@ __global__ void __launch_bounds__(256) k_capture_patches(const CandEntry* __rest
                                                          int k_max, int t0, int nfdot, int sky0, int tq, int trow) {
   unsigned long long end = count[0];
   if (end > patch_capacity) end = patch_capacity;
-  // rows of bins [k_min, k_max) per template, or (tq > 0) the transposed rows of the
-  // streaming second pass: tq rows of trow values, bin k at row k % tq, column k / tq
+  // rows of bins [k_min, k_max) per template, or (tq > 0) the rows of the streaming
+  // second pass: tq rows of trow values in blocks of CAP_BLOCK columns, bin k at row
+  // k % tq, column k / tq, [column / CAP_BLOCK][row][column % CAP_BLOCK]
   const long tlen = tq > 0 ? (long)tq * trow : (long)(k_max - k_min);
   for (unsigned long long slot = first[0] + blockIdx.x; slot < end; slot += gridDim.x) {
     const CandEntry ce = cand[slot];
@@ -1322,7 +1329,9 @@ __global__ void __launch_bounds__(256) k_capture_patches(const CandEntry* __rest
     const int k = ce.bin - 128 + (int)threadIdx.x;
     float v = 0.f;
     if (k >= k_min && k < k_max)
-      v = spec[t_local * tlen + (tq > 0 ? (long)(k % tq) * trow + k / tq : (long)(k - k_min))];
+      v = spec[t_local * tlen + (tq > 0 ? (long)(k / tq / CAP_BLOCK) * tq * CAP_BLOCK + (long)(k % tq) * CAP_BLOCK +
+                                             (k / tq) % CAP_BLOCK
+                                           : (long)(k - k_min))];
     patches[slot * 256 + threadIdx.x] = v;
   }
 }
