@@ -664,8 +664,9 @@ __global__ void __launch_bounds__(256) k_gemm_nt_lds(int M, int N, int K, const 
 // workgroup covers 128 rows and all 128 columns, so that each row of A is read once and B
 // once per 128 rows; four wavefronts of 64 x 64 (4 x 4 matrix-core tiles each), K in
 // stages of GW_K through LDS (rows padded by 8 BF16), the next stage loaded into registers
-// (native vector registers: arrays of the HIP vector structs are not kept in registers)
-// while the current one is multiplied.  Partial tiles of split z go to C + z * M * 128.
+// while the current one is multiplied (arrays of native vector types: the compiler had put
+// an array of HIP's uint4 structs in scratch memory).  Partial tiles of split z go to
+// C + z * M * 128.
 constexpr int GW_M = 128, GW_K = 64, GW_LD = GW_K + 8;
 __global__ void __launch_bounds__(256) k_gemm_nt_wide(int M, int K, const uint16_t* __restrict__ A,
                                                       const uint16_t* __restrict__ B, float* __restrict__ Cm,
