@@ -184,3 +184,42 @@ def test_fused_capture_scores_equal_network_on_search_spectra(torch, precision, 
     note(f"scores: {np.mean(diff == 0):.3f} bitwise equal, max difference {diff.max():.2e}")
     assert diff.max() < 2e-3
     assert np.mean(diff == 0) > 0.5
+
+
+def test_fused_capture_on_a_bin_range(torch):
+    # a bin range other than [0, nfft/2), here across nfft/2: the capturing second pass
+    # stores all P outputs of its rows, and the capture reads bins outside the range as 0.
+    # On this range the search's and the spectrum kernel's 2F differ in the last bit on
+    # about a sixth of the bins (instantiations contracted differently), so more BF16
+    # roundings in the network flip than on the default range.
+    from paper_1410_3677_amd import fstat as F
+    w = synth.workload("full")
+    seg = w.segments[0]
+    k0, k1 = 70000, 140000
+    al, de, fd = w.alpha[:2], w.delta[:2], w.fdot[:3]
+    v = F.Vetter(512)
+    v.set_params(_theta(5).astype(np.float32))
+    plan = make_plan([seg], use_graph=0, precision=1, k_min=k0, k_max=k1)
+    plan.attach_vetter(v, 1 << 16)
+    plan.search_batch(0, dev(al), dev(de), dev(fd))
+    plan.vet_candidates()
+    recs, keys, n = plan.candidates()
+    note(f"bins [{k0}, {k1}): {n} crossings")
+    assert n > 100 and np.all(np.isfinite(keys["vet_score"]))
+    assert keys["bin"].min() >= k0 and keys["bin"].max() < k1
+    nb = k1 - k0
+    spec = torch.empty(len(al) * len(fd) * nb, dtype=torch.float32, device="cuda")
+    plain = make_plan([seg], use_graph=0, precision=1, k_min=k0, k_max=k1)
+    plain.twoF_spectrum(0, dev(al), dev(de), dev(fd), spec)
+    s = spec.view(len(al), len(fd), nb).cpu().numpy()
+    win = np.zeros((n, 256), np.float32)
+    for i, (a, f, b) in enumerate(zip(keys["sky"], keys["fdot_idx"], keys["bin"])):
+        lo, hi = max(b - 128, k0), min(b + 128, k1)
+        win[i, lo - (b - 128):hi - (b - 128)] = s[a, f, lo - k0:hi - k0]
+    lg = torch.empty(n, device="cuda")
+    v.forward(torch.as_tensor(win, device="cuda"), lg)
+    ref = 1.0 / (1.0 + np.exp(-lg.cpu().numpy()))
+    diff = np.abs(keys["vet_score"] - ref)
+    note(f"scores: {np.mean(diff == 0):.3f} bitwise equal, max difference {diff.max():.2e}")
+    assert diff.max() < 2e-3
+    assert np.mean(diff == 0) > 0.5
