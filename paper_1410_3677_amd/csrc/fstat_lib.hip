@@ -1028,7 +1028,7 @@ void vet_conv_stage(fstat_vet_t v, const float* patches, int n, uint16_t* x, hip
 void vet_dense_stage(fstat_vet_t v, const uint16_t* x, int n, float* out, hipStream_t st, CandEntry* cand) {
   using namespace vet;
   const int nbp = (n + GW_M - 1) / GW_M * GW_M;
-  FSTAT_LAUNCH(k_gemm_nt_wide, dim3(1, nbp / GW_M, INFER_SPLITS), dim3(256), 0, st, nbp, X, x, v->w4b, v->scratch,
+  FSTAT_LAUNCH(k_gemm_nt_wide, dim3(1, nbp / GW_M, INFER_SPLITS), dim3(GW_NT), 0, st, nbp, X, x, v->w4b, v->scratch,
                X / INFER_SPLITS);
   const long count = (long)nbp * H;
   // the split-K sum, the two small layers and the score in one launch

@@ -662,19 +662,21 @@ __global__ void __launch_bounds__(256) k_gemm_nt_lds(int M, int N, int K, const 
 // The scoring call's 8192 -> 128 product: C[m][n] (split z of K) = sum_k A[m][k] B[n][k] for
 // row-major BF16 A [M][K] and B [128][K], M a multiple of 128, K of GW_K * splits.  A
 // workgroup covers 128 rows and all 128 columns, so that each row of A is read once and B
-// once per 128 rows; four wavefronts of 64 x 64 (4 x 4 matrix-core tiles each), K in
-// stages of GW_K through LDS (rows padded by 8 BF16), the next stage loaded into registers
-// while the current one is multiplied (arrays of native vector types: the compiler had put
-// an array of HIP's uint4 structs in scratch memory).  Partial tiles of split z go to
-// C + z * M * 128.
-constexpr int GW_M = 128, GW_K = 64, GW_LD = GW_K + 8;
-__global__ void __launch_bounds__(256) k_gemm_nt_wide(int M, int K, const uint16_t* __restrict__ A,
-                                                      const uint16_t* __restrict__ B, float* __restrict__ Cm,
-                                                      int kchunk) {
+// once per 128 rows; eight wavefronts of 32 x 64 (2 x 4 matrix-core tiles each; four
+// wavefronts of 64 x 64 took 9% longer, fewer loads being in flight per compute unit), K
+// in stages of GW_K through LDS (rows padded by 8 BF16), the next stage loaded into
+// registers while the current one is multiplied (arrays of native vector types: the
+// compiler had put an array of HIP's uint4 structs in scratch memory).  Partial tiles of
+// split z go to C + z * M * 128.
+constexpr int GW_M = 128, GW_K = 64, GW_LD = GW_K + 8, GW_NT = 512;
+__global__ void __launch_bounds__(GW_NT) k_gemm_nt_wide(int M, int K, const uint16_t* __restrict__ A,
+                                                        const uint16_t* __restrict__ B, float* __restrict__ Cm,
+                                                        int kchunk) {
   typedef unsigned int u4v __attribute__((ext_vector_type(4)));
-  constexpr int PER = GW_M * GW_K / 8 / 256;   // 16-byte loads per thread per operand and stage (4)
-  constexpr int TPR = GW_K / 8;                // threads per row
-  constexpr int RPP = 256 / TPR;               // rows per pass
+  constexpr int PER = GW_M * GW_K / 8 / GW_NT;   // 16-byte loads per thread per operand and stage (2)
+  constexpr int TPR = GW_K / 8;                  // threads per row
+  constexpr int RPP = GW_NT / TPR;               // rows per pass
+  constexpr int TA = 2, TB = 4;                  // a wavefront's 16 x 16 tiles: 32 rows x 64 columns
   __shared__ __align__(16) uint16_t sA[GW_M * GW_LD];
   __shared__ __align__(16) uint16_t sB[H * GW_LD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -689,12 +691,12 @@ __global__ void __launch_bounds__(256) k_gemm_nt_wide(int M, int K, const uint16
       rb[i] = *reinterpret_cast<const u4v*>(B + (long)(lr + RPP * i) * K + k0 + lc);
     }
   };
-  v4f acc[4][4];
+  v4f acc[TA][TB];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < TA; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = v4f{0.f, 0.f, 0.f, 0.f};
-  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+    for (int c = 0; c < TB; ++c) acc[a][c] = v4f{0.f, 0.f, 0.f, 0.f};
+  const int wm = (w >> 1) * 16 * TA, wn = (w & 1) * 16 * TB;
   const int r16 = lane & 15, kq = 4 * (lane >> 4), k8 = 8 * (lane >> 4);
   gload(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += GW_K) {
@@ -708,23 +710,22 @@ __global__ void __launch_bounds__(256) k_gemm_nt_wide(int M, int K, const uint16
     if (k0 + GW_K < kend) gload(k0 + GW_K);
 #pragma unroll
     for (int kk = 0; kk < GW_K; kk += 32) {
-      v8s fa[4], fb[4];
+      v8s fa[TA], fb[TB];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        fa[t] = *reinterpret_cast<const v8s*>(sA + (wm + 16 * t + r16) * GW_LD + kk + k8);
-        fb[t] = *reinterpret_cast<const v8s*>(sB + (wn + 16 * t + r16) * GW_LD + kk + k8);
-      }
+      for (int t = 0; t < TA; ++t) fa[t] = *reinterpret_cast<const v8s*>(sA + (wm + 16 * t + r16) * GW_LD + kk + k8);
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int t = 0; t < TB; ++t) fb[t] = *reinterpret_cast<const v8s*>(sB + (wn + 16 * t + r16) * GW_LD + kk + k8);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = mfma32(fa[a], fb[c], acc[a][c]);
+      for (int a = 0; a < TA; ++a)
+#pragma unroll
+        for (int c = 0; c < TB; ++c) acc[a][c] = mfma32(fa[a], fb[c], acc[a][c]);
     }
   }
   float* Cz = Cm + (long)blockIdx.z * M * H;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < TA; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < TB; ++c)
 #pragma unroll
       for (int i = 0; i < 4; ++i) Cz[(long)(m0 + wm + 16 * a + kq + i) * H + wn + 16 * c + r16] = acc[a][c][i];
 }
