@@ -799,7 +799,9 @@ __device__ __forceinline__ void stage_from_lds_reg(cx<T> (&v)[PB][R], const cx<T
   }
 }
 
-template <typename T, int LEN, int G, int NS>
+// WAVE_ONLY: the rows belong to single wavefronts (otherwise a workgroup barrier orders
+// the stages of rows that span wavefronts).
+template <typename T, int LEN, int G, int NS, bool WAVE_ONLY = true>
 __device__ __forceinline__ void middle_stages_reg(cx<T>* cola, cx<T>* colb, int g, const StageTw<T, LEN, G, NS>& tw) {
   constexpr int R = stage_radix<LEN, NS>();
   if constexpr (NS * R < LEN) {
@@ -807,11 +809,11 @@ __device__ __forceinline__ void middle_stages_reg(cx<T>* cola, cx<T>* colb, int 
     cx<T> va[PB][R], vb[PB][R];
     stage_from_lds_reg<T, LEN, G, NS, R, PB, false>(va, cola, g, tw.w);
     stage_from_lds_reg<T, LEN, G, NS, R, PB, false>(vb, colb, g, tw.w);
-    stage_sync<true>();
+    stage_sync<WAVE_ONLY>();
     stage_to_lds_off<T, LEN, G, NS, R, PB>(va, cola, g);
     stage_to_lds_off<T, LEN, G, NS, R, PB>(vb, colb, g);
-    stage_sync<true>();
-    middle_stages_reg<T, LEN, G, NS * R>(cola, colb, g, tw.next);
+    stage_sync<WAVE_ONLY>();
+    middle_stages_reg<T, LEN, G, NS * R, WAVE_ONLY>(cola, colb, g, tw.next);
   }
 }
 
@@ -1050,6 +1052,117 @@ __global__ void __launch_bounds__(256) k_tmpl_b_stream(TmplArgs ta, int ntmpl, c
     }
   }
   if constexpr (MODE != 1) stg.flush(oa, ta, search, lane);
+}
+
+// ---------------------------------------------------------------- pass B, streaming, rows of 1024 points (FP32)
+// A row of P = 1024 points has 128 radix-8 butterflies per stage, so it spans two
+// wavefronts; a workgroup of 256 threads transforms the two rows k2 = 2 u and 2 u + 1 of one
+// template (row unit u) per step and walks the launch's units with the grid as stride, so
+// that the rows being read at any time form one contiguous window of HBM.  As in
+// k_tmpl_b_stream, the next unit's paired (a, b) loads are issued once the first stage is
+// in LDS and overlap the remaining stages, and the later stages' twiddles stay in
+// registers; workgroup barriers order the stages.  MODE 0: threshold and candidates
+// (staged per wavefront), MODE 1: the 2F spectrum.  With HALF (bins [0, nfft/2)) the
+// radix-2 last stage forms only the outputs k1 < P/2.
+template <int MODE, bool HALF>
+__global__ void __launch_bounds__(256) k_tmpl_b_stream2(TmplArgs ta, int ntmpl, const SkyParams* __restrict__ sp,
+                                                        const cx<float>* __restrict__ tbuf, OutArgs oa,
+                                                        const cx<float>* __restrict__ twst) {
+  using T = float;
+  constexpr int P = 1024;
+  constexpr int G = groups_per_col<P>();   // lanes per row
+  constexpr int RPB = 256 / G;              // rows per workgroup step
+  constexpr int ST = col_stride<P>(16);
+  constexpr int R1 = stage_radix<P, 1>();
+  constexpr int NB1 = P / R1, PB1 = NB1 / G;
+  static_assert(PB1 == 1 && RPB == 2, "one first-stage butterfly per lane, two rows per workgroup");
+  constexpr int NSL = last_ns<P, 1>();
+  constexpr int RL = stage_radix<P, NSL>();
+  constexpr int PBL = (P / RL) / G;
+  constexpr int ROUT = HALF ? RL / 2 : RL;
+  constexpr int NOUT = PBL * ROUT;
+  static_assert(NOUT <= 32, "output mask");
+  static_assert(MODE == 0 || MODE == 1, "threshold or spectrum");
+  __shared__ cx<T> lds[2 * RPB * ST];
+  // per-wavefront candidate staging: (template of the launch, bin, 2F)
+  __shared__ int st_item[4][STAGE_CAP];
+  __shared__ int st_bin[4][STAGE_CAP];
+  __shared__ float st_val[4][STAGE_CAP];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int sub = threadIdx.x / G, g = threadIdx.x % G;
+  const int units = ta.Q / RPB;        // row units of one template
+  const int total = ntmpl * units;     // row units of the launch
+  const int nwg = gridDim.x;
+  cx<T>* cola = lds + (2 * sub) * ST;
+  cx<T>* colb = cola + ST;
+  const T thr = (T)oa.threshold;
+  const int search = oa.search_next[0] - 1;
+  StageTw<T, P, G, R1> tw;
+  tw.load(twst, g);
+  const auto& twl = last_stage_tw<T, P, G, R1>(tw);
+
+  // unit U of the launch: template U / units, rows (U % units) RPB + sub
+  auto load_unit = [&](cx<T> (&ca)[PB1][R1], cx<T> (&cb)[PB1][R1], int U) {
+    const int item = U / units, u = U - item * units;
+    const cx<T>* p = tbuf + (long)(2 * item) * ta.L + 2 * (long)(u * RPB + sub) * P;
+#pragma unroll
+    for (int r = 0; r < R1; ++r) load_stream(p + 2 * (g + NB1 * r), ca[0][r], cb[0][r]);
+  };
+
+  WaveStage stg{st_item[wave], st_bin[wave], st_val[wave]};
+
+  int U = blockIdx.x;
+  if (U >= total) return;   // the same for the whole workgroup
+  cx<T> xa[PB1][R1], xb[PB1][R1];
+  load_unit(xa, xb, U);
+  for (; U < total; U += nwg) {
+    const int item = U / units;
+    const int u = U - item * units;
+    const int t = ta.t0 + item;
+    const int skyl = t / ta.nfdot, sidx = t - skyl * ta.nfdot;
+    const SkyParams& pr = sp[skyl];
+    const T cfa = (T)pr.cfa, cfb = (T)pr.cfb, cfab = (T)pr.cfab;
+    dftr<T, R1, false>(xa[0]);
+    dftr<T, R1, false>(xb[0]);
+    __syncthreads();  // the previous unit's last stage has read the tile
+    stage_to_lds_off<T, P, G, 1, R1, PB1>(xa, cola, g);
+    stage_to_lds_off<T, P, G, 1, R1, PB1>(xb, colb, g);
+    __syncthreads();
+    // the next unit's loads go into the registers just freed and overlap the rest
+    if (U + nwg < total) load_unit(xa, xb, U + nwg);
+    middle_stages_reg<T, P, G, R1, false>(cola, colb, g, tw);
+    cx<T> fa[PBL][RL], fb[PBL][RL];
+    stage_from_lds_reg<T, P, G, NSL, RL, PBL, HALF>(fa, cola, g, twl.w);
+    stage_from_lds_reg<T, P, G, NSL, RL, PBL, HALF>(fb, colb, g, twl.w);
+    const int k2 = u * RPB + sub;
+    if constexpr (MODE == 1) {
+      T* out = (T*)oa.spectrum + ((long)(ta.sky0 + skyl) * ta.nfdot + sidx) * (long)(oa.k_max - oa.k_min);
+#pragma unroll
+      for (int b = 0; b < PBL; ++b)
+#pragma unroll
+        for (int r = 0; r < ROUT; ++r) {
+          const int k = ta.Q * (g + G * b + NSL * r) + k2;
+          if (HALF || (k >= oa.k_min && k < oa.k_max))
+            out[k - oa.k_min] = two_f_value(fa[b][r], fb[b][r], cfa, cfb, cfab);
+        }
+    } else {
+      uint32_t mask = 0;
+      T val[NOUT];
+#pragma unroll
+      for (int b = 0; b < PBL; ++b)
+#pragma unroll
+        for (int r = 0; r < ROUT; ++r) {
+          const int k = ta.Q * (g + G * b + NSL * r) + k2;
+          const T v = two_f_value(fa[b][r], fb[b][r], cfa, cfb, cfab);
+          val[b * ROUT + r] = v;
+          if ((HALF || (k >= oa.k_min && k < oa.k_max)) && v > thr) mask |= 1u << (b * ROUT + r);
+        }
+      stg.add<false>(oa, ta, search, lane, mask, val, item,
+                     [&](int q) { return ta.Q * (g + G * (q / ROUT) + NSL * (q % ROUT)) + k2; });
+    }
+  }
+  if constexpr (MODE == 0) stg.flush(oa, ta, search, lane);
 }
 
 // ---------------------------------------------------------------- pass B with interbinning (FP32)

@@ -381,6 +381,51 @@ def test_kernel_variants_give_identical_candidates(torch, full, tmp_path):
         np.testing.assert_allclose(r0["twoF"], r1["twoF"], rtol=2e-6, atol=0)
 
 
+def test_rows_of_1024_points_streaming_equals_tiled(torch, tmp_path):
+    """nfft = 2^19 (rows of P = 1024 points, two wavefronts each in the streaming second
+    pass): the streaming and the tiled second pass find the same candidates with the same
+    2F, and the streaming pass's spectrum of a bin range (every output formed) and of the
+    bins [0, nfft/2) (half the outputs) match the oracle."""
+    from paper_1410_3677_amd import fstat as F
+    from tests.gpu_util import dev
+    n = 150000
+    rng = np.random.default_rng(1024)
+    injs = synth.draw_injections(rng, 1, 15.0, 15.0)
+    seg = synth.make_segment(n, 2.0, 100.0, 1.0, 6150, injs)
+    nfft = synth.nfft_for(n)
+    assert nfft == 1 << 19
+    note(f"rows of 1024 points: n={n} nfft={nfft}")
+    al, de = np.array([0.3, injs[0].alpha, -1.1]), np.array([-0.2, injs[0].delta, 0.7])
+    fd = np.array([0.0, injs[0].fdot])
+    probe = str(tmp_path / "probe.txt")
+    p0 = F.Plan([F.segment_to_device(seg)], workspace_from_torch=False, tuning_cache_path=probe)
+    p0.autotune(0, budget_ms=50.0)
+    tag = open(probe).read().split()[0]
+    found = []
+    for v in (0, 2):   # second pass variant 0 (tiled) and 1 (streaming)
+        cache = tmp_path / f"v{v}.txt"
+        cache.write_text(f"{tag} {nfft} 1 64 8 {v}\n")
+        plan = F.Plan([F.segment_to_device(seg)], tuning_cache_path=str(cache), use_graph=0)
+        inf = plan.info(0)
+        assert inf["p"] == 1024 and inf["pass_b_variant"] == v >> 1
+        plan.search_batch(0, dev(al), dev(de), dev(fd))
+        found.append(plan.candidates())
+    (r0, k0, n0), (r1, k1, n1) = found
+    assert n0 > 0 and n1 == n0
+    assert_keys_equal(k0, k1)
+    np.testing.assert_allclose(r0["twoF"], r1["twoF"], rtol=2e-6, atol=0)
+    cache = tmp_path / "v2.txt"
+    for k_min, k_max in ((0, nfft // 2), (1000, 200001)):
+        plan = F.Plan([F.segment_to_device(seg)], tuning_cache_path=str(cache), use_graph=0, k_min=k_min,
+                      k_max=k_max)
+        assert plan.info(0)["pass_b_variant"] == 1
+        got = gpu_spectrum(plan, 0, al, de, fd, k_max - k_min, False)
+        ref = oracle_spectrum(seg, al, de, fd, nfft, k_min, k_max)
+        err = rel_err_floor(got, ref)
+        note(f"bins [{k_min}, {k_max}): max rel err {err:.3e}")
+        assert err < TOL_MIXED
+
+
 @pytest.fixture(scope="module")
 def ragged():
     return synth.workload("ragged", nsky=3, nfdot=4)
