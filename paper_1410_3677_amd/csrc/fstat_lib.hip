@@ -581,9 +581,11 @@ constexpr int STREAM_WG_PER_CU = 3;
 // (half the outputs) it needs 135-165 VGPRs and three workgroups per CU are resident, with
 // other bin ranges 190-225 and two
 constexpr int IB_WG_PER_CU_HALF = 3, IB_WG_PER_CU_FULL = 2;
-// workgroups per compute unit of the streaming second pass for rows of 1024 points (its
-// 141-155 VGPRs leave three wavefronts per SIMD)
-constexpr int STREAM2_WG_PER_CU = 3;
+// the streaming second pass for rows of 1024 points: one row (two wavefronts) per
+// workgroup, and six workgroups per compute unit (its 141-155 VGPRs leave three wavefronts
+// per SIMD; two rows per 256-thread workgroup ran 1% slower)
+constexpr int STREAM2_NT = 128;
+constexpr int STREAM2_WG_PER_CU = 3 * 256 / STREAM2_NT;
 
 template <typename T>
 static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo& si, int sky0, int nb,
@@ -705,14 +707,15 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
           if (si.ibw == 0.0 && p->variant_b == 1 && !capture) {
             // rows of 1024 points, two wavefronts each: about one resident round of
             // workgroups walks the launch's units of two rows
-            const long units = (long)nt * (si.tQ / 2);
+            constexpr int NT2 = STREAM2_NT;
+            const long units = (long)nt * (si.tQ / (NT2 / groups_per_col<PP>()));
             const long wgs = std::min(units, (long)p->n_cu * STREAM2_WG_PER_CU);
             const bool half = (oa.k_min == 0 && oa.k_max == si.nfft / 2);
             auto go = [&](auto mode_c, auto half_c) {
               constexpr int MD = decltype(mode_c)::value;
               constexpr bool HF = decltype(half_c)::value;
-              FSTAT_LAUNCH((k_tmpl_b_stream2<MD, HF>), dim3((unsigned)wgs), dim3(256), 0, st, ta, nt, d.sp(), tbuf,
-                           oa, d.twst);
+              FSTAT_LAUNCH((k_tmpl_b_stream2<MD, HF, NT2>), dim3((unsigned)wgs), dim3(NT2), 0, st, ta, nt, d.sp(),
+                           tbuf, oa, d.twst);
             };
             using I0 = std::integral_constant<int, 0>;
             using I1 = std::integral_constant<int, 1>;

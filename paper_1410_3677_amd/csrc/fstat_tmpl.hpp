@@ -1056,26 +1056,27 @@ __global__ void __launch_bounds__(256) k_tmpl_b_stream(TmplArgs ta, int ntmpl, c
 
 // ---------------------------------------------------------------- pass B, streaming, rows of 1024 points (FP32)
 // A row of P = 1024 points has 128 radix-8 butterflies per stage, so it spans two
-// wavefronts; a workgroup of 256 threads transforms the two rows k2 = 2 u and 2 u + 1 of one
-// template (row unit u) per step and walks the launch's units with the grid as stride, so
-// that the rows being read at any time form one contiguous window of HBM.  As in
+// wavefronts; a workgroup of NT threads transforms the NT / 128 rows k2 = u NT / 128 + i of
+// one template (row unit u) per step and walks the launch's units with the grid as stride,
+// so that the rows being read at any time form one contiguous window of HBM.  As in
 // k_tmpl_b_stream, the next unit's paired (a, b) loads are issued once the first stage is
 // in LDS and overlap the remaining stages, and the later stages' twiddles stay in
 // registers; workgroup barriers order the stages.  MODE 0: threshold and candidates
 // (staged per wavefront), MODE 1: the 2F spectrum.  With HALF (bins [0, nfft/2)) the
 // radix-2 last stage forms only the outputs k1 < P/2.
-template <int MODE, bool HALF>
-__global__ void __launch_bounds__(256) k_tmpl_b_stream2(TmplArgs ta, int ntmpl, const SkyParams* __restrict__ sp,
+template <int MODE, bool HALF, int NT>
+__global__ void __launch_bounds__(NT) k_tmpl_b_stream2(TmplArgs ta, int ntmpl, const SkyParams* __restrict__ sp,
                                                         const cx<float>* __restrict__ tbuf, OutArgs oa,
                                                         const cx<float>* __restrict__ twst) {
   using T = float;
   constexpr int P = 1024;
   constexpr int G = groups_per_col<P>();   // lanes per row
-  constexpr int RPB = 256 / G;              // rows per workgroup step
+  constexpr int RPB = NT / G;               // rows per workgroup step
+  constexpr int NWV = NT / 64;               // wavefronts per workgroup
   constexpr int ST = col_stride<P>(16);
   constexpr int R1 = stage_radix<P, 1>();
   constexpr int NB1 = P / R1, PB1 = NB1 / G;
-  static_assert(PB1 == 1 && RPB == 2, "one first-stage butterfly per lane, two rows per workgroup");
+  static_assert(PB1 == 1 && RPB >= 1 && RPB * G == NT, "one first-stage butterfly per lane, whole rows per workgroup");
   constexpr int NSL = last_ns<P, 1>();
   constexpr int RL = stage_radix<P, NSL>();
   constexpr int PBL = (P / RL) / G;
@@ -1085,9 +1086,9 @@ __global__ void __launch_bounds__(256) k_tmpl_b_stream2(TmplArgs ta, int ntmpl, 
   static_assert(MODE == 0 || MODE == 1, "threshold or spectrum");
   __shared__ cx<T> lds[2 * RPB * ST];
   // per-wavefront candidate staging: (template of the launch, bin, 2F)
-  __shared__ int st_item[4][STAGE_CAP];
-  __shared__ int st_bin[4][STAGE_CAP];
-  __shared__ float st_val[4][STAGE_CAP];
+  __shared__ int st_item[NWV][STAGE_CAP];
+  __shared__ int st_bin[NWV][STAGE_CAP];
+  __shared__ float st_val[NWV][STAGE_CAP];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int sub = threadIdx.x / G, g = threadIdx.x % G;
