@@ -85,7 +85,9 @@ typedef struct {
   int64_t candidate_capacity;     /* entries of the device candidate buffer, >= 1 */
   size_t workspace_budget_bytes;  /* admission limit for the workspace; 0 = no limit */
   int32_t templates_per_launch;   /* spindown templates per FFT launch; 1 = one template per
-                                     launch; 0 = the library's choice */
+                                     launch; 0 = the library's choice (sized for the plan's
+                                     longest transform: a segment with a shorter one takes
+                                     proportionally more per launch, at most 4096) */
   int32_t skies_per_batch;        /* sky positions prepared together; 0 = the library's choice */
   int32_t use_graph;              /* 1: capture each search call as a HIP graph and replay it while
                                      the call's arguments are unchanged */

@@ -114,6 +114,7 @@ struct fstat_plan_s {
   bool fp64 = false;
   int device = 0;
   int Sb = 1, B = 1;           // skies per batch, templates per launch
+  bool scale_B = true;         // B chosen by the library: shorter transforms take more per launch
   int variant_a = 1;           // pass A kernel variant (0 sequential series, 1 paired; the autotuner may pick 0)
   int variant_b = 1;           // pass B kernel variant (0 row tiles, 1 streaming wavefronts)
   int n_cu = 256;              // compute units of the device
@@ -611,8 +612,13 @@ static fstat_status run_templates(fstat_plan_t p, const Dev<T>& d, const SegInfo
   ta.nfft = si.nfft;
   const int total = nb * nfdot;
   cx<T>* tbuf = d.tmpl();
-  for (int t0 = 0; t0 < total; t0 += p->B) {
-    const int nt = std::min(p->B, total - t0);
+  // the plan's B templates per launch are sized for its longest transform; when the
+  // library chose B, a segment with a shorter transform fits proportionally more templates
+  // in the same intermediate memory (and in the launch-sized 2F rows of the patch capture),
+  // so it takes fewer, fuller launches
+  const int Bs = p->scale_B ? (int)std::min<long>((long)p->B * (p->TL_max / si.tL), 4096L) : p->B;
+  for (int t0 = 0; t0 < total; t0 += Bs) {
+    const int nt = std::min(Bs, total - t0);
     ta.t0 = t0;
     hipError_t err = hipSuccess;
     {
@@ -1492,6 +1498,7 @@ fstat_status fstat_plan(const fstat_segment* segs, int32_t nseg, const fstat_opt
   }
   p->Sb = Sb;
   p->B = B;
+  p->scale_B = (opt.templates_per_launch == 0);
   layout(p, Sb, B, true);
 
   // device resources

@@ -223,3 +223,36 @@ def test_fused_capture_on_a_bin_range(torch):
     note(f"scores: {np.mean(diff == 0):.3f} bitwise equal, max difference {diff.max():.2e}")
     assert diff.max() < 2e-3
     assert np.mean(diff == 0) > 0.5
+
+
+def test_capture_in_a_plan_of_two_lengths_equals_a_plan_of_one(torch):
+    """With the library's batch sizes, a plan's launches hold more templates for a segment
+    whose transform is shorter than the plan's longest (the same intermediate memory and
+    launch-sized 2F rows): here one launch of 512 templates instead of two of 256.  That
+    segment's candidates, 2F and captured-patch scores equal those of a plan of the
+    segment alone."""
+    from paper_1410_3677_amd import fstat as F
+    w = synth.workload("full")
+    long_seg = w.segments[0]
+    rng = np.random.default_rng(31)
+    injs = synth.draw_injections(rng, 1, 15.0, 15.0)
+    short = synth.make_segment(30000, 2.0, 100.0, 1.0, 7031, injs)
+    assert 4 * synth.nfft_for(short.n) == synth.nfft_for(long_seg.n)
+    al, de, fd = w.alpha[:8], w.delta[:8], w.fdot[:64]
+    v = F.Vetter(512)
+    v.set_params(_theta(5).astype(np.float32))
+    found = []
+    for segs, s in (([long_seg, short], 1), ([short], 0)):
+        plan = make_plan(segs, use_graph=0, precision=1)   # the library's batch sizes
+        plan.attach_vetter(v, 1 << 16)
+        plan.search_batch(s, dev(al), dev(de), dev(fd))
+        plan.vet_candidates()
+        found.append(plan.candidates())
+    (r0, k0, n0), (r1, k1, n1) = found
+    note(f"short segment in a plan of two lengths: {n0} crossings, alone: {n1}")
+    assert n0 == n1 and n0 > 100
+    for f in ("sky", "fdot_idx", "bin"):
+        np.testing.assert_array_equal(k0[f], k1[f])
+    np.testing.assert_array_equal(r0["twoF"], r1["twoF"])
+    assert np.all(np.isfinite(k0["vet_score"]))
+    np.testing.assert_array_equal(k0["vet_score"], k1["vet_score"])
