@@ -401,19 +401,22 @@ def test_rows_of_1024_points_streaming_equals_tiled(torch, tmp_path):
     p0 = F.Plan([F.segment_to_device(seg)], workspace_from_torch=False, tuning_cache_path=probe)
     p0.autotune(0, budget_ms=50.0)
     tag = open(probe).read().split()[0]
-    found = []
     for v in (0, 2):   # second pass variant 0 (tiled) and 1 (streaming)
-        cache = tmp_path / f"v{v}.txt"
-        cache.write_text(f"{tag} {nfft} 1 64 8 {v}\n")
-        plan = F.Plan([F.segment_to_device(seg)], tuning_cache_path=str(cache), use_graph=0)
-        inf = plan.info(0)
-        assert inf["p"] == 1024 and inf["pass_b_variant"] == v >> 1
-        plan.search_batch(0, dev(al), dev(de), dev(fd))
-        found.append(plan.candidates())
-    (r0, k0, n0), (r1, k1, n1) = found
-    assert n0 > 0 and n1 == n0
-    assert_keys_equal(k0, k1)
-    np.testing.assert_allclose(r0["twoF"], r1["twoF"], rtol=2e-6, atol=0)
+        (tmp_path / f"v{v}.txt").write_text(f"{tag} {nfft} 1 64 8 {v}\n")
+    for k_min, k_max in ((0, 0), (1000, 200001)):   # all outputs of a row formed on the second range
+        found = []
+        for v in (0, 2):
+            plan = F.Plan([F.segment_to_device(seg)], tuning_cache_path=str(tmp_path / f"v{v}.txt"), use_graph=0,
+                          k_min=k_min, k_max=k_max)
+            inf = plan.info(0)
+            assert inf["p"] == 1024 and inf["pass_b_variant"] == v >> 1
+            plan.search_batch(0, dev(al), dev(de), dev(fd))
+            found.append(plan.candidates())
+        (r0, k0, n0), (r1, k1, n1) = found
+        note(f"bins [{k_min}, {k_max or nfft // 2}): {n0} candidates")
+        assert n0 > 0 and n1 == n0
+        assert_keys_equal(k0, k1)
+        np.testing.assert_allclose(r0["twoF"], r1["twoF"], rtol=2e-6, atol=0)
     cache = tmp_path / "v2.txt"
     for k_min, k_max in ((0, nfft // 2), (1000, 200001)):
         plan = F.Plan([F.segment_to_device(seg)], tuning_cache_path=str(cache), use_graph=0, k_min=k_min,
